@@ -1,0 +1,95 @@
+"""Closed forms of the paper used as test oracles -- TEST INFRASTRUCTURE ONLY.
+
+Each function states the passage it follows.  Strength gamma in (0, 1) is
+the fraction of rows with Y_i = X_ij X_ik (eq. (3)), related to the
+inner-product scale by 2 gamma - 1 = Y^T(X_j o X_k)/n (eq. (4)).
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+
+def gamma_from_stat(stat: float) -> float:
+    """eq. (4): gamma = (1 + s/n) / 2."""
+    return 0.5 * (1.0 + stat)
+
+
+def eta(gamma: float, M: int, L: int) -> float:
+    """eq. (9): probability that a pair of strength gamma is found in L repetitions."""
+    return 1.0 - (1.0 - gamma ** M) ** L
+
+
+def L_for(eta_target: float, beta: float) -> int:
+    """eq. (15): the smallest L with 1 - (1 - beta)^L >= eta_target (beta = gamma^M)."""
+    if beta >= 1.0:
+        return 1
+    if beta <= 0.0:
+        raise ValueError("beta must be positive")
+    return int(math.ceil(math.log(1.0 - eta_target) / math.log(1.0 - beta)))
+
+
+def exponent(gamma: float, gamma0: float) -> float:
+    """Theorem 2 / eq. (10): the run time grows like p^(1 + log(gamma)/log(gamma0))."""
+    return 1.0 + math.log(gamma) / math.log(gamma0)
+
+
+def gamma0(p: int, M: int) -> float:
+    """Theorem 2: gamma_0 = p^(-1/M)."""
+    return p ** (-1.0 / M)
+
+
+def naive_miss(p: int, L: int) -> float:
+    """Section 5.3: chance that p*L uniformly drawn pairs all miss one given pair."""
+    return (1.0 - 2.0 / (p * (p - 1.0))) ** (L * p)
+
+
+def cost(M: int, L: int, n: int, p: int, sum_gamma_M: float) -> float:
+    """eq. (8): C(M, L) = np + L {M p + p log p + n E|E_1|}, E|E_1| = sum_jk gamma_jk^M."""
+    return n * p + L * (M * p + p * math.log(p) + n * sum_gamma_M)
+
+
+def sum_gamma_pow(gammas_sample: np.ndarray, total_pairs: float, M: int) -> float:
+    """Plug-in estimate of sum over all pairs of gamma_jk^M from uniformly sampled
+    strengths (Section 2.3: 'estimated by sampling from {gamma_jk}')."""
+    g = np.asarray(gammas_sample, dtype=np.float64)
+    return float(total_pairs * np.mean(g ** M))
+
+
+def objective(M: int, gamma: float, n: int, p: int, sum_gamma_M: float) -> float:
+    """The quantity minimised in eq. (11)."""
+    b = gamma ** M
+    if b >= 1.0:
+        return M * p + p * math.log(p) + n * sum_gamma_M
+    return -(M * p + p * math.log(p) + n * sum_gamma_M) / math.log(1.0 - b)
+
+
+def M_star(gamma: float, n: int, p: int, gammas_sample: np.ndarray, total_pairs: float,
+           M_max: int = 64) -> int:
+    """eq. (11): the subsample size minimising cost per unit of -log(miss probability)."""
+    best, best_v = 1, math.inf
+    for M in range(1, M_max + 1):
+        v = objective(M, gamma, n, p, sum_gamma_pow(gammas_sample, total_pairs, M))
+        if v < best_v:
+            best, best_v = M, v
+    return best
+
+
+def expected_candidates(gammas: np.ndarray, M: int) -> float:
+    """Proof of Theorem 2: E|E_1| = sum over pairs of gamma_jk^M."""
+    return float(np.sum(np.asarray(gammas, dtype=np.float64) ** M))
+
+
+def gamma_tilde(XsT: np.ndarray, Y: np.ndarray, j: int, k: int) -> float:
+    """Section 3.1: |Y|-weighted strength, the sum of |Y_i| over rows with
+    sgn(Y_i) = X_ij X_ik, divided by ||Y||_1.  XsT: (p, n) +-1 signs."""
+    Y = np.asarray(Y, dtype=np.float64)
+    sg = np.where(Y < 0, -1, 1)
+    agree = sg == (XsT[j].astype(np.int64) * XsT[k].astype(np.int64))
+    return float(np.abs(Y)[agree].sum() / np.abs(Y).sum())
+
+
+def gamma_example_unweighted(sigma2: float) -> float:
+    """Section 3.1 example, Y = X_1 X_2 + eps with eps ~ N(0, sigma^2):
+    1/2 (1 + P(|eps| < 1)), the quantity the paper's sigma^2 table lists."""
+    return 0.5 * (1.0 + math.erf(1.0 / math.sqrt(2.0 * sigma2)))

@@ -1,0 +1,330 @@
+"""Seeded synthetic inputs for the xyz interaction search.
+
+This module only *draws data*: predictor matrices X, responses Y and the list
+of planted column pairs.  It holds none of the search's arithmetic (no keys,
+no strengths, no thresholds), so that the CPU oracle and the GPU library can
+both consume the same inputs without sharing any of the method's code.
+
+Conventions
+-----------
+* ``XT`` is the transpose of X, shape ``(p, n)`` and C-contiguous, i.e. X in
+  column-major order: column j of X is ``XT[j]``.  Binary data is int8 in
+  {-1, +1}; continuous data is float32.
+* ``bits`` (large binary inputs only) is X already bit-packed column-major:
+  ``(p, ceil(n/64))`` uint64, bit ``i % 64`` of word ``i // 64`` of row j is
+  1 exactly when ``X[i, j] == -1``; bits past row n are 0.
+* Every generator takes an integer ``seed`` and uses ``numpy.random.PCG64``.
+
+The shapes and distributions follow the workloads the paper measures on:
+Rademacher designs (Section 5.2), genotype-like binary SNP data (Section 5.3,
+where the real data set is not available and a minor-allele-frequency model
+stands in for it) and Gaussian continuous designs (Section 5.4).
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+__all__ = [
+    "Dataset", "rademacher", "genotype", "gaussian",
+    "config1", "config2", "config3", "config4", "config5_shared", "config5_requests",
+    "config5_fresh", "small_binary", "small_continuous", "rows_table", "pack_bits_colmajor",
+]
+
+
+@dataclasses.dataclass
+class Dataset:
+    """One synthetic search problem."""
+    n: int
+    p: int
+    XT: np.ndarray | None          # (p, n) int8 or float32, or None when only bits are held
+    Y: np.ndarray                  # (n,) int8 (+-1) or float32
+    planted: list                  # list of (j, k) with j < k (0-based)
+    params: dict                   # search parameters of the workload (L, m, kappa, seed, ...)
+    bits: np.ndarray | None = None  # (p, ceil(n/64)) uint64 column-major bits, large inputs only
+    meta: dict = dataclasses.field(default_factory=dict)
+
+
+def _rng(seed: int, stream: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([int(seed), int(stream), 0x5eed]))
+
+
+def rademacher(n: int, p: int, seed: int) -> np.ndarray:
+    """(p, n) int8 matrix of i.i.d. uniform {-1, +1} entries (X in column-major order)."""
+    r = _rng(seed, 1)
+    b = r.integers(0, 2, size=(p, n), dtype=np.int8)
+    return (2 * b - 1).astype(np.int8)
+
+
+def genotype(n: int, p: int, seed: int, f_lo: float = 0.05, f_hi: float = 0.5):
+    """(p, n) int8 genotype-shaped matrix and its minor-allele frequencies.
+
+    Column j has frequency f_j ~ U[f_lo, f_hi]; X_ij = +1 when a Binomial(2, f_j)
+    draw is positive (at least one minor allele), else -1.
+    """
+    r = _rng(seed, 2)
+    f = r.uniform(f_lo, f_hi, size=p)
+    XT = np.empty((p, n), dtype=np.int8)
+    chunk = max(1, (1 << 24) // max(n, 1))
+    for j0 in range(0, p, chunk):
+        j1 = min(p, j0 + chunk)
+        g = r.binomial(2, f[j0:j1, None], size=(j1 - j0, n))
+        XT[j0:j1] = np.where(g > 0, 1, -1).astype(np.int8)
+    return XT, f
+
+
+def gaussian(n: int, p: int, seed: int) -> np.ndarray:
+    """(p, n) float32 matrix of i.i.d. N(0, 1) entries."""
+    r = _rng(seed, 3)
+    XT = np.empty((p, n), dtype=np.float32)
+    chunk = max(1, (1 << 24) // max(n, 1))
+    for j0 in range(0, p, chunk):
+        j1 = min(p, j0 + chunk)
+        XT[j0:j1] = r.standard_normal(size=(j1 - j0, n), dtype=np.float32)
+    return XT
+
+
+def pack_bits_colmajor(XT: np.ndarray) -> np.ndarray:
+    """Pack a (p, n) +-1 int8 matrix into (p, ceil(n/64)) uint64 words, bit = [x == -1].
+
+    This is an input-format conversion (the same information in another
+    layout), used to hand large binary inputs over in packed form.
+    """
+    p, n = XT.shape
+    w = (n + 63) // 64
+    b = (XT == -1)
+    pad = w * 64 - n
+    if pad:
+        b = np.concatenate([b, np.zeros((p, pad), dtype=bool)], axis=1)
+    packed8 = np.packbits(b.reshape(p, w * 8, 8), axis=2, bitorder="little").reshape(p, w * 8)
+    return packed8.view(np.uint64).reshape(p, w).copy()
+
+
+def _distinct_columns(r: np.random.Generator, p: int, count: int) -> np.ndarray:
+    return r.choice(p, size=count, replace=False)
+
+
+def config1(seed: int = 0) -> Dataset:
+    """Plain single-instance workload: n=200, p=2000, Rademacher X.
+
+    Each row's response is driven by one of three planted pairs chosen
+    uniformly at random, (3,7), (50,900) and (1200,1999), as Y_i = X_ia X_ib,
+    then flipped with probability 0.1 for the first pair and 0.25 for the
+    other two.  Search parameters: L=20, m=10, kappa=0.3, sampler seed 0.
+    """
+    n, p = 200, 2000
+    XT = rademacher(n, p, seed)
+    r = _rng(seed, 11)
+    pairs = [(3, 7), (50, 900), (1200, 1999)]
+    flips = [0.1, 0.25, 0.25]
+    drv = r.integers(0, 3, size=n)
+    u = r.random(n)
+    Y = np.empty(n, dtype=np.int8)
+    for i in range(n):
+        a, b = pairs[drv[i]]
+        y = int(XT[a, i]) * int(XT[b, i])
+        if u[i] < flips[drv[i]]:
+            y = -y
+        Y[i] = y
+    return Dataset(n, p, XT, Y, pairs, dict(L=20, m=10, kappa=0.3, seed=0, two_sided=False))
+
+
+def config2(seed: int = 0, n: int = 2000, p: int = 100_000) -> Dataset:
+    """Genotype-shaped binary workload (stands in for the SNP data of Section 5.3).
+
+    X from the minor-allele-frequency model; Y = +-1 drawn from a logistic model
+    with 20 main effects of 0.3 and 10 planted pairs with coefficients
+    theta ~ U[0.2, 0.6], on 40 distinct random columns; intercept 0.
+    Search parameters: L=200, m=12; kappa is set by the caller so that about
+    1e4 pairs exceed it.
+    """
+    XT, f = genotype(n, p, seed)
+    r = _rng(seed, 12)
+    cols = _distinct_columns(r, p, 40)
+    mains = cols[:20]
+    pc = cols[20:]
+    pairs = [tuple(sorted((int(pc[2 * q]), int(pc[2 * q + 1])))) for q in range(10)]
+    theta = r.uniform(0.2, 0.6, size=10)
+    eta = np.zeros(n, dtype=np.float64)
+    for j in mains:
+        eta += 0.3 * XT[j].astype(np.float64)
+    for q, (a, b) in enumerate(pairs):
+        eta += theta[q] * (XT[a].astype(np.float64) * XT[b].astype(np.float64))
+    prob = 1.0 / (1.0 + np.exp(-eta))
+    Y = np.where(r.random(n) < prob, 1, -1).astype(np.int8)
+    return Dataset(n, p, XT, Y, pairs, dict(L=200, m=12, kappa=None, seed=seed, two_sided=False),
+                   meta=dict(maf=f, mains=[int(j) for j in mains], theta=theta.tolist()))
+
+
+def config3(seed: int = 0, n: int = 5000, p: int = 1_000_000, npairs: int = 20,
+            s_lo: float = 0.15, s_hi: float = 0.5, signed: bool = False) -> Dataset:
+    """Large Rademacher workload handed over bit-packed (about 625 MB at full size).
+
+    Y is Rademacher.  Each of ``npairs`` planted pairs (j, k) on distinct
+    columns gets a target strength s ~ U[s_lo, s_hi]: column k is rewritten as
+    Y o X_j and then exactly round(n (1 - s) / 2) of its rows, chosen at
+    random, are negated.  With ``signed`` each planted pair's sign is random
+    (column k is negated as a whole with probability 1/2).
+    Search parameters: L=500, m=14, kappa=0.12.
+    """
+    r = _rng(seed, 13)
+    w = (n + 63) // 64
+    bits = r.integers(0, np.iinfo(np.uint64).max, size=(p, w), dtype=np.uint64, endpoint=True)
+    tail = n - (w - 1) * 64
+    if tail < 64:
+        bits[:, w - 1] &= np.uint64((1 << tail) - 1)
+    yb = r.integers(0, 2, size=n, dtype=np.int8)
+    Y = (1 - 2 * yb).astype(np.int8)
+    ybits = pack_bits_colmajor(Y[None, :])[0]
+    cols = _distinct_columns(r, p, 2 * npairs)
+    pairs, targets, signs = [], [], []
+    for q in range(npairs):
+        j, k = int(cols[2 * q]), int(cols[2 * q + 1])
+        s = float(r.uniform(s_lo, s_hi))
+        nflip = int(round(n * (1.0 - s) / 2.0))
+        col = bits[j] ^ ybits
+        flip = r.choice(n, size=nflip, replace=False)
+        fb = np.zeros(w * 64, dtype=bool)
+        fb[flip] = True
+        fw = np.packbits(fb.reshape(w * 8, 8), axis=1, bitorder="little").reshape(w * 8).view(np.uint64)
+        col = col ^ fw
+        sg = 1
+        if signed and r.random() < 0.5:
+            col = ~col
+            if tail < 64:
+                col[w - 1] &= np.uint64((1 << tail) - 1)
+            sg = -1
+        bits[k] = col
+        pairs.append((min(j, k), max(j, k)))
+        targets.append(s)
+        signs.append(sg)
+    return Dataset(n, p, None, Y, pairs, dict(L=500, m=14, kappa=0.12, seed=seed, two_sided=signed),
+                   bits=bits, meta=dict(target_s=targets, signs=signs))
+
+
+def config4(seed: int = 0, n: int = 1000, p: int = 200_000) -> Dataset:
+    """Continuous workload: X ~ N(0,1) float32, real-valued Y.
+
+    Y = sum over 5 planted pairs of X_j X_k + 0.5 * sum over 10 main effects
+    of X_j + N(0,1), on 20 distinct random columns.  Hashing uses the signs of
+    X and |Y|-weighted row sampling.  Search parameters: L=300, m=12, kappa=0.5.
+    """
+    XT = gaussian(n, p, seed)
+    r = _rng(seed, 14)
+    cols = _distinct_columns(r, p, 20)
+    pc, mains = cols[:10], cols[10:]
+    pairs = [tuple(sorted((int(pc[2 * q]), int(pc[2 * q + 1])))) for q in range(5)]
+    y = r.standard_normal(n)
+    for a, b in pairs:
+        y += XT[a].astype(np.float64) * XT[b].astype(np.float64)
+    for j in mains:
+        y += 0.5 * XT[j].astype(np.float64)
+    Y = y.astype(np.float32)
+    return Dataset(n, p, XT, Y, pairs, dict(L=300, m=12, kappa=0.5, seed=seed, two_sided=False),
+                   meta=dict(mains=[int(j) for j in mains]))
+
+
+def config5_shared(seed: int = 0, n: int = 2000, p: int = 200_000):
+    """Shared resident X of the serving workload (genotype model as in config 2)."""
+    XT, f = genotype(n, p, seed + 1000)
+    return XT, f
+
+
+def _mixture_response(r: np.random.Generator, XT: np.ndarray, pairs, strengths) -> np.ndarray:
+    """Row mixture: row i copies X_ia X_ib of planted pair q with probability s_q,
+    otherwise it is a fair coin.  sum(s_q) must be at most 1."""
+    n = XT.shape[1]
+    u = r.random(n)
+    Y = np.where(r.random(n) < 0.5, 1, -1).astype(np.int8)
+    acc = 0.0
+    for (a, b), s in zip(pairs, strengths):
+        sel = (u >= acc) & (u < acc + s)
+        Y[sel] = (XT[a, sel].astype(np.int16) * XT[b, sel].astype(np.int16)).astype(np.int8)
+        acc += s
+    return Y
+
+
+def config5_requests(XT: np.ndarray, count: int = 256, seed: int = 0, rate: float = 50.0):
+    """Response vectors arriving for the shared X: Poisson arrivals at ``rate`` per s.
+
+    Each request plants 1-3 pairs with strengths U[0.2, 0.5] (total at most 0.9)
+    through a row mixture; its repetition count is drawn from {50, 200, 500};
+    kappa = 0.15.  Returns a list of dicts (arrival time, Y, planted, L, kappa).
+    """
+    r = _rng(seed, 15)
+    p = XT.shape[0]
+    t = 0.0
+    out = []
+    for q in range(count):
+        t += r.exponential(1.0 / rate)
+        k = int(r.integers(1, 4))
+        while True:
+            s = r.uniform(0.2, 0.5, size=k)
+            if s.sum() <= 0.9:
+                break
+        cols = _distinct_columns(r, p, 2 * k)
+        pairs = [tuple(sorted((int(cols[2 * i]), int(cols[2 * i + 1])))) for i in range(k)]
+        Y = _mixture_response(r, XT, pairs, s)
+        L = int(r.choice([50, 200, 500]))
+        out.append(dict(t=t, Y=Y, planted=pairs, strengths=s.tolist(), L=L, kappa=0.15))
+    return out
+
+
+def config5_fresh(count: int = 32, seed: int = 0, n: int = 1000, sizes=(10_000, 100_000, 500_000),
+                  rate: float = 50.0 / 8.0):
+    """Requests on fresh data sets (Rademacher X, n=1000, p from ``sizes``)."""
+    r = _rng(seed, 16)
+    t = 0.0
+    out = []
+    for q in range(count):
+        t += r.exponential(1.0 / rate)
+        p = int(r.choice(sizes))
+        XT = rademacher(n, p, seed * 1000 + q + 7)
+        k = int(r.integers(1, 4))
+        s = r.uniform(0.2, 0.3, size=k)
+        cols = _distinct_columns(r, p, 2 * k)
+        pairs = [tuple(sorted((int(cols[2 * i]), int(cols[2 * i + 1])))) for i in range(k)]
+        Y = _mixture_response(r, XT, pairs, s)
+        L = int(r.choice([50, 200, 500]))
+        out.append(dict(t=t, XT=XT, Y=Y, planted=pairs, strengths=s.tolist(), L=L, kappa=0.15))
+    return out
+
+
+def small_binary(n: int, p: int, seed: int, planted=(), flip: float = 0.0, y_bias: float = 0.5) -> Dataset:
+    """Small Rademacher problem for parity tests.
+
+    Without planted pairs Y is Bernoulli(y_bias) on {+1, -1}.  Each planted
+    pair (a, b) drives an equal share of the rows as Y_i = X_ia X_ib, flipped
+    with probability ``flip``.
+    """
+    XT = rademacher(n, p, seed)
+    r = _rng(seed, 21)
+    Y = np.where(r.random(n) < y_bias, 1, -1).astype(np.int8)
+    if planted:
+        drv = r.integers(0, len(planted), size=n)
+        u = r.random(n)
+        for i in range(n):
+            a, b = planted[drv[i]]
+            y = int(XT[a, i]) * int(XT[b, i])
+            Y[i] = -y if u[i] < flip else y
+    return Dataset(n, p, XT, Y, [tuple(sorted(pq)) for pq in planted], {})
+
+
+def small_continuous(n: int, p: int, seed: int, planted=(), noise: float = 1.0) -> Dataset:
+    """Small Gaussian problem: Y = sum of planted X_a X_b + noise * N(0,1)."""
+    XT = gaussian(n, p, seed)
+    r = _rng(seed, 22)
+    y = noise * r.standard_normal(n)
+    for a, b in planted:
+        y += XT[a].astype(np.float64) * XT[b].astype(np.float64)
+    return Dataset(n, p, XT, y.astype(np.float32), [tuple(sorted(pq)) for pq in planted], {})
+
+
+def rows_table(n: int, L: int, m: int, seed: int) -> np.ndarray:
+    """An explicit (L, m) int32 table of i.i.d. uniform row indices.
+
+    Used to hand the same row draws to both sides directly, independently of
+    any sampler either side implements.
+    """
+    r = _rng(seed, 31)
+    return r.integers(0, n, size=(L, m), dtype=np.int32)

@@ -1,0 +1,365 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine, an exhaustive enumeration, a closed form of the paper, a value the
+paper prints, or a published reference output.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import theory
+import synthgen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _pairset(arr):
+    return {(int(a), int(b)) for a, b in zip(arr["j"], arr["k"])}
+
+
+# ----------------------------------------------------------------- sampler --
+
+def test_splitmix64_published_outputs():
+    g = _gold("splitmix64_reference.json")
+    got = [oracle.splitmix64(g["seed"], k) for k in range(1, 6)]
+    assert got == [int(v) for v in g["outputs"]]
+
+
+def test_uniform_rows_chi2():
+    n, m = 13, 8
+    counts = np.zeros(n)
+    for l in range(3000):
+        r = oracle.draw_rows(n, 7, l, m)
+        assert r.min() >= 0 and r.max() < n
+        np.add.at(counts, r, 1)
+    exp = counts.sum() / n
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    # 12 degrees of freedom: P(chi2 > 40) < 1e-4
+    assert chi2 < 40.0
+
+
+def test_weighted_rows_follow_abs_y():
+    Y = np.array([0.0, 3.0, -1.0, 0.0, 0.5, -2.5, 1.0, 0.0], dtype=np.float64)
+    n = len(Y)
+    counts = np.zeros(n)
+    for l in range(4000):
+        np.add.at(counts, oracle.draw_rows(n, 3, l, 5, Y=Y), 1)
+    assert counts[Y == 0].sum() == 0, "rows with Y_i = 0 have weight 0 (Section 3.1)"
+    w = np.abs(Y) / np.abs(Y).sum()
+    nz = w > 0
+    exp = counts.sum() * w[nz]
+    chi2 = ((counts[nz] - exp) ** 2 / exp).sum()
+    assert chi2 < 30.0   # 4 degrees of freedom
+
+
+def test_weighted_rows_reject_all_zero():
+    with pytest.raises(oracle.OracleError):
+        oracle.draw_rows(4, 0, 0, 3, Y=np.zeros(4))
+
+
+# ---------------------------------------------------------- inner products --
+
+def test_inner_products_match_numpy_gemm_and_distance_identity():
+    d = synthgen.small_binary(37, 23, seed=5)
+    X = d.XT.T.astype(np.int64)                # n x p
+    Y = d.Y.astype(np.int64)
+    G = X.T @ (Y[:, None] * X)                 # library GEMM: Y^T (X_j o X_k)
+    allp = oracle.brute(d.XT, d.Y, kappa=-2.0)  # every pair passes
+    assert len(allp) == 23 * 22 // 2
+    for rec in allp:
+        assert rec["s"] == G[rec["j"], rec["k"]]
+        assert rec["stat"] == rec["s"] / 37
+    # eq. (4): 2 gamma - 1 = s/n = Z_j^T X_k / n = 1 - ||Z_j - X_k||^2 / (2n)
+    Z = Y[:, None] * X
+    for rec in allp[:50]:
+        j, k = int(rec["j"]), int(rec["k"])
+        dist2 = int(((Z[:, j] - X[:, k]) ** 2).sum())
+        assert Fraction(int(rec["s"]), 37) == 1 - Fraction(dist2, 2 * 37)
+        gamma = Fraction(int((Y == X[:, j] * X[:, k]).sum()), 37)
+        assert 2 * gamma - 1 == Fraction(int(rec["s"]), 37)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.11, 0.21, 0.31, -0.16])
+def test_threshold_equals_distance_form(kappa):
+    """eqs. (1)/(2): s/n > kappa  <=>  ||X_j - Z_k||_2 < kappa' with kappa'^2 = 2n(1-kappa).
+
+    kappa is kept off the grid of attainable s/n values (multiples of 1/20
+    here) so that exact rational comparison and the binary64 division agree."""
+    d = synthgen.small_binary(40, 30, seed=11)
+    X = d.XT.T.astype(np.int64)
+    Z = d.Y.astype(np.int64)[:, None] * X
+    kq = Fraction(kappa)
+    want = set()
+    for j in range(30):
+        for k in range(j + 1, 30):
+            dist2 = int(((X[:, j] - Z[:, k]) ** 2).sum())
+            if dist2 < 2 * 40 * (1 - kq):
+                want.add((j, k))
+    assert _pairset(oracle.brute(d.XT, d.Y, kappa)) == want
+
+
+def test_ties_at_threshold_are_excluded():
+    """eq. (1) keeps s/n strictly above kappa; s/n is the binary64 quotient."""
+    d = synthgen.small_binary(40, 30, seed=11)
+    allp = oracle.brute(d.XT, d.Y, -2.0)
+    for kappa in (0.1, 0.2, 0.3):
+        kept = _pairset(oracle.brute(d.XT, d.Y, kappa))
+        tied = {(int(r["j"]), int(r["k"])) for r in allp if int(r["s"]) / 40 == kappa}
+        above = {(int(r["j"]), int(r["k"])) for r in allp if int(r["s"]) / 40 > kappa}
+        assert tied and not (tied & kept)
+        assert kept == above
+
+
+def test_continuous_value_matches_numpy_dot():
+    d = synthgen.small_continuous(50, 12, seed=3, planted=[(1, 4)])
+    X = d.XT.astype(np.float64)
+    Y = d.Y.astype(np.float64)
+    for j, k in [(0, 1), (1, 4), (5, 11), (3, 3)]:
+        v = oracle.pair_value(d.XT, d.Y, j, k)
+        ref = float(np.dot(Y * X[j], X[k]))
+        assert abs(v - ref) <= 1e-12 * (1 + np.abs(Y * X[j] * X[k]).sum())
+
+
+# ------------------------------------------------------------- equal pairs --
+
+def _direct_E(Xs, Zs, rows, two_sided):
+    """E_l by direct O(p^2 m) enumeration: ordered (j, k), j != k, with
+    X_j and Z_k equal on every sampled row; returned as unordered pairs."""
+    p = Xs.shape[1]
+    xs = Xs[rows]          # m x p
+    zs = Zs[rows]
+    out = set()
+    for j in range(p):
+        for k in range(p):
+            if j == k:
+                continue
+            if np.all(xs[:, j] == zs[:, k]) or (two_sided and np.all(xs[:, j] == -zs[:, k])):
+                out.add((min(j, k), max(j, k)))
+    return out
+
+
+@pytest.mark.parametrize("two_sided", [False, True])
+@pytest.mark.parametrize("m", [1, 2, 4])
+def test_equal_pairs_match_direct_enumeration(m, two_sided):
+    d = synthgen.small_binary(24, 35, seed=m + 10 * two_sided)
+    X = d.XT.T.astype(np.int64)
+    Z = d.Y.astype(np.int64)[:, None] * X
+    L = 6
+    rows = synthgen.rows_table(24, L, m, seed=99 + m)
+    for l in range(L):
+        pairs, reps = oracle.search(d.XT, d.Y, m, 1, -2.0, rows=rows[l:l + 1], two_sided=two_sided)
+        want = _direct_E(X, Z, rows[l], two_sided)
+        assert _pairset(pairs) == want
+        assert reps["candidates"][0] == len(want)
+        assert reps["passed"][0] == len(want)
+        cm = sum(1 << t for t in range(m) if d.Y[rows[l][t]] < 0)
+        assert int(reps["cmask"][0]) == cm
+
+
+def test_sampler_rows_are_used():
+    """Without a rows table the oracle uses its own sampler: same E_l as
+    passing the sampler's rows explicitly."""
+    d = synthgen.small_binary(30, 25, seed=2)
+    a, ra = oracle.search(d.XT, d.Y, 3, 5, -2.0, seed=42)
+    rows = np.stack([oracle.draw_rows(30, 42, l, 3) for l in range(5)])
+    b, rb = oracle.search(d.XT, d.Y, 3, 5, -2.0, rows=rows)
+    assert np.array_equal(a, b) and np.array_equal(ra, rb)
+
+
+def test_m0_reduces_to_brute_force():
+    """With no sampled rows every pair collides, so xyz returns T(kappa) exactly."""
+    d = synthgen.small_binary(60, 40, seed=4, planted=[(2, 9)], flip=0.2)
+    for kappa in (0.1, 0.25):
+        pairs, reps = oracle.search(d.XT, d.Y, 0, 3, kappa)
+        br = oracle.brute(d.XT, d.Y, kappa)
+        assert _pairset(pairs) == _pairset(br)
+        assert np.array_equal(pairs["s"], br["s"])
+        assert np.all(pairs["hits"] == 3) and np.all(pairs["first_rep"] == 0)
+        assert np.all(reps["candidates"] == 40 * 39 // 2)
+
+
+def test_perfect_pair_found_in_every_repetition():
+    """Y = X_a o X_b gives X_a = Z_b exactly, so every projection collides (Section 2.1)."""
+    d = synthgen.small_binary(80, 30, seed=6)
+    Y = (d.XT[4].astype(np.int16) * d.XT[17].astype(np.int16)).astype(np.int8)
+    pairs, reps = oracle.search(d.XT, Y, 10, 25, 0.5, seed=1)
+    rec = pairs[(pairs["j"] == 4) & (pairs["k"] == 17)]
+    assert len(rec) == 1 and rec["hits"][0] == 25 and rec["s"][0] == 80 and rec["first_rep"][0] == 0
+
+
+def test_anti_perfect_pair_only_two_sided():
+    d = synthgen.small_binary(80, 30, seed=8)
+    Y = (-d.XT[3].astype(np.int16) * d.XT[20].astype(np.int16)).astype(np.int8)
+    one, _ = oracle.search(d.XT, Y, 8, 30, -2.0, seed=5)
+    assert (3, 20) not in _pairset(one)
+    two, _ = oracle.search(d.XT, Y, 8, 30, 0.5, seed=5, two_sided=True)
+    rec = two[(two["j"] == 3) & (two["k"] == 20)]
+    assert len(rec) == 1 and rec["hits"][0] == 30 and rec["s"][0] == -80
+
+
+def test_collision_probability_is_gamma_pow_m():
+    """Section 2.3: a pair of strength gamma is in E_1 with probability gamma^M."""
+    n, p, m, L = 40, 7, 3, 6000
+    d = synthgen.small_binary(n, p, seed=12, planted=[(0, 1), (2, 5)], flip=0.1)
+    pairs, reps = oracle.search(d.XT, d.Y, m, L, -2.0, seed=77)
+    X = d.XT.astype(np.int64)
+    got = {(int(r["j"]), int(r["k"])): int(r["hits"]) for r in pairs}
+    gammas = []
+    for j in range(p):
+        for k in range(j + 1, p):
+            g = float(np.mean(d.Y == X[j] * X[k]))
+            gammas.append(g)
+            pr = g ** m
+            h = got.get((j, k), 0)
+            z = (h - L * pr) / math.sqrt(L * pr * (1 - pr)) if 0 < pr < 1 else 0.0
+            assert abs(z) < 5.0, (j, k, g, h / L, pr)
+    # proof of Theorem 2: E|E_1| = sum_jk gamma_jk^M
+    exp = theory.expected_candidates(np.array(gammas), m)
+    c = reps["candidates"].astype(np.float64)
+    z = (c.mean() - exp) / (c.std(ddof=1) / math.sqrt(L))
+    assert abs(z) < 5.0
+
+
+def test_weighted_collision_probability_is_gamma_tilde_pow_m():
+    """Section 3.1: with |Y|-weighted rows the collision probability is gamma~^M."""
+    n, p, m, L = 30, 6, 2, 6000
+    d = synthgen.small_continuous(n, p, seed=13, planted=[(1, 3)], noise=0.7)
+    pairs, _ = oracle.search(d.XT, d.Y, m, L, -1e300, seed=9)
+    Xs = np.where(d.XT < 0, -1, 1)
+    got = {(int(r["j"]), int(r["k"])): int(r["hits"]) for r in pairs}
+    for j in range(p):
+        for k in range(j + 1, p):
+            g = theory.gamma_tilde(Xs, d.Y, j, k)
+            pr = g ** m
+            h = got.get((j, k), 0)
+            z = (h - L * pr) / math.sqrt(L * pr * (1 - pr)) if 0 < pr < 1 else 0.0
+            assert abs(z) < 5.0, (j, k, g, h / L, pr)
+
+
+def test_paper_worked_example_miss_rate():
+    """Section 5.3: strength 0.85, M = 21, L = 100 -> missed with probability about 0.03."""
+    g = _gold("paper_numbers.json")["worked_example_miss"]
+    gamma, M, L = g["gamma"], g["M"], g["L"]
+    exact = 1.0 - theory.eta(gamma, M, L)
+    assert abs(exact - g["printed"]) < 0.01       # printed as "approximately 0.03"
+    n = 200
+    agree = int(round(gamma * n))      # exactly 85% of the rows agree
+    d = synthgen.small_binary(n, 4, seed=21)
+    X = d.XT
+    Y = (X[0].astype(np.int16) * X[1].astype(np.int16)).astype(np.int8)
+    Y[agree:] = -Y[agree:]
+    assert np.mean(Y == X[0] * X[1]) == gamma
+    runs, missed = 1500, 0
+    for seed in range(runs):
+        pairs, _ = oracle.search(X, Y, M, L, 0.5, seed=seed)
+        if (0, 1) not in _pairset(pairs):
+            missed += 1
+    sd = math.sqrt(exact * (1 - exact) / runs)
+    assert abs(missed / runs - exact) < 5 * sd
+
+
+def test_split_repetitions_union_equals_full_run():
+    d = synthgen.small_binary(50, 40, seed=14, planted=[(1, 2), (5, 30)], flip=0.15)
+    full, rf = oracle.search(d.XT, d.Y, 4, 12, 0.2, seed=3)
+    a, ra = oracle.search(d.XT, d.Y, 4, 5, 0.2, seed=3, rep_offset=0)
+    b, rb = oracle.search(d.XT, d.Y, 4, 7, 0.2, seed=3, rep_offset=5)
+    assert np.array_equal(rf["candidates"], np.concatenate([ra["candidates"], rb["candidates"]]))
+    merged = {}
+    for arr in (a, b):
+        for r in arr:
+            key = (int(r["j"]), int(r["k"]))
+            h, f = merged.get(key, (0, 10 ** 9))
+            merged[key] = (h + int(r["hits"]), min(f, int(r["first_rep"])))
+    assert merged == {(int(r["j"]), int(r["k"])): (int(r["hits"]), int(r["first_rep"])) for r in full}
+
+
+def test_sign_transform_maps_zero_to_plus_one():
+    d = synthgen.small_continuous(30, 10, seed=15, planted=[(0, 2)])
+    XT = d.XT.copy()
+    XT[:, ::4] = 0.0
+    XT[1, 1] = -0.0
+    a, _ = oracle.search(XT, d.Y, 3, 8, -1e300, seed=2)
+    XT2 = XT.copy()
+    XT2[XT2 == 0] = 1e-30     # same signs, same hashing
+    b, _ = oracle.search(XT2, d.Y, 3, 8, -1e300, seed=2)
+    assert _pairset(a) == _pairset(b)
+    assert np.array_equal(a["hits"], b["hits"])
+
+
+def test_invalid_inputs_rejected():
+    d = synthgen.small_binary(10, 5, seed=0)
+    Y = d.Y.copy()
+    Y[3] = 0
+    with pytest.raises(oracle.OracleError):
+        oracle.search(d.XT, Y, 2, 2, 0.1)
+    with pytest.raises(oracle.OracleError):
+        oracle.search(d.XT, d.Y, 2, 2, float("nan"))
+    Xf = d.XT.astype(np.float32)
+    Xf[0, 0] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.search(Xf, d.Y.astype(np.float32), 2, 2, 0.1)
+
+
+# ------------------------------------------------------------ closed forms --
+
+def test_printed_exponents_and_break_even():
+    g = _gold("paper_numbers.json")
+    for gamma, g0, printed in g["exponents"]["cases"]:
+        # printed as "around" two digits (1.1762 appears as 1.17): within 0.01
+        assert abs(theory.exponent(gamma, g0) - printed) < 0.01
+    mm = g["matrix_multiplication_break_even"]
+    gam = mm["gamma0"] ** (mm["exponent"] - 1.0)   # solves 1 + log(g)/log(g0) = exponent
+    assert abs(theory.exponent(gam, mm["gamma0"]) - mm["exponent"]) < 1e-12
+    assert abs(gam - mm["printed_gamma"]) <= 0.01
+
+
+def test_printed_naive_miss():
+    g = _gold("paper_numbers.json")["naive_miss"]
+    # printed as "about 0.999" for the value 0.99971
+    assert abs(theory.naive_miss(g["p"], g["L"]) - g["printed"]) < 10 ** -g["printed_digits"]
+
+
+def test_sigma2_table_is_the_unweighted_strength():
+    """Section 3.1's table equals 1/2 (1 + P(|eps| < 1)) to the printed digits
+    (the unweighted agreement probability; see the readings of the paper)."""
+    g = _gold("paper_numbers.json")["sigma2_table"]
+    for s2, printed in zip(g["sigma2"], g["gamma"]):
+        assert abs(theory.gamma_example_unweighted(s2) - printed) <= 0.011
+
+
+def test_L_for_is_minimal():
+    for eta_t in (0.5, 0.9, 0.95, 0.99):
+        for beta in (0.5, 0.1, 0.01, 1e-4):
+            L = theory.L_for(eta_t, beta)
+            assert 1 - (1 - beta) ** L >= eta_t - 1e-12
+            assert L == 1 or 1 - (1 - beta) ** (L - 1) < eta_t
+
+
+def test_M_star_is_pareto_optimal():
+    """Proposition 2: no (M', L') with at least M*'s power costs less."""
+    r = np.random.default_rng(0)
+    n, p = 1000, 20000
+    sample = np.clip(r.normal(0.5, 0.02, size=20000), 0, 1)
+    total = p * (p - 1) / 2
+    for gamma in (0.6, 0.7, 0.85):
+        Ms = theory.M_star(gamma, n, p, sample, total)
+        for L in (1, 5, 30):
+            e_star = theory.eta(gamma, Ms, L)
+            c_star = theory.cost(Ms, L, n, p, theory.sum_gamma_pow(sample, total, Ms))
+            for M2 in range(1, 40):
+                L2 = theory.L_for(e_star, gamma ** M2) if gamma ** M2 < 1 else 1
+                if theory.eta(gamma, M2, L2) < e_star - 1e-12:
+                    L2 += 1
+                c2 = theory.cost(M2, L2, n, p, theory.sum_gamma_pow(sample, total, M2))
+                assert c2 >= c_star * (1 - 1e-9) or M2 == Ms
