@@ -1,0 +1,326 @@
+"""Python binding of libxyz, the gfx950 implementation of the xyz interaction search.
+
+Argument marshalling only: every function below forwards to the C ABI of
+``include/xyz.h`` (same names) through ctypes, and every step of the search
+runs in the library's HIP kernels.  The library must be built in-tree
+(``paper_1610_05108_amd/libxyz.so``); importing a function that needs it
+raises when it is missing -- there is no CPU fallback.
+
+PyTorch is used only as plumbing: a CUDA (HIP) tensor's ``data_ptr()`` is
+passed as a device pointer and the current torch stream as the HIP stream.
+numpy arrays are passed as host pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxyz.so")
+
+XYZ_OK, XYZ_EINVAL, XYZ_ENOMEM, XYZ_EDEVICE, XYZ_EAGAIN, XYZ_ECANCELED, XYZ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+XYZ_MEM_HOST, XYZ_MEM_DEVICE = 0, 1
+XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32 = 0, 1, 2
+XYZ_Y_I8_PM1, XYZ_Y_F32, XYZ_Y_F64 = 0, 1, 2
+XYZ_TWO_SIDED, XYZ_PROFILE = 1, 2
+XYZ_MAX_M = 30
+
+PAIR_DTYPE = np.dtype([("j", np.int32), ("k", np.int32), ("s", np.int64), ("value", np.float64),
+                       ("stat", np.float64), ("first_rep", np.int32), ("hits", np.int32)])
+REP_DTYPE = np.dtype([("candidates", np.int64), ("passed", np.int64), ("fresh", np.int64),
+                      ("cmask", np.uint64), ("max_bucket", np.int32), ("reserved", np.int32)])
+
+EXPORTS = [
+    "xyz_version", "xyz_last_error", "xyz_init", "xyz_fini", "xyz_ctx_bytes", "xyz_x_create", "xyz_x_destroy",
+    "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_bruteforce", "xyz_result_npairs",
+    "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_free", "xyz_smin",
+]
+
+
+class XyzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libxyz error {code}: {msg}")
+        self.code = code
+
+
+class xyz_params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("L", ctypes.c_int32), ("kappa", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("rep_offset", ctypes.c_int32),
+                ("rows", ctypes.c_void_p)]
+
+
+class xyz_timing(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in
+                ("total_ms", "pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms",
+                 "dedup_ms", "brute_ms")] + [("verify_launches", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                                             ("tiles", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libxyz.so.  Raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    try:  # load torch's HIP runtime first so that the process holds a single one
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "xyz_version": (ctypes.c_char_p, []),
+        "xyz_last_error": (ctypes.c_char_p, []),
+        "xyz_init": (I32, [ctypes.c_int, U64, ctypes.POINTER(P)]),
+        "xyz_fini": (None, [P]),
+        "xyz_ctx_bytes": (U64, [P]),
+        "xyz_x_create": (I32, [P, P, ctypes.c_int, ctypes.c_int, I64, I64, I64, P, ctypes.POINTER(P)]),
+        "xyz_x_destroy": (None, [P]),
+        "xyz_x_n": (I64, [P]),
+        "xyz_x_p": (I64, [P]),
+        "xyz_search": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(xyz_params), P, ctypes.POINTER(P)]),
+        "xyz_search_batch": (I32, [P, P, I32, ctypes.POINTER(P), ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(xyz_params), P, ctypes.POINTER(P)]),
+        "xyz_bruteforce": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, D, U32, P, I64, P, I64, P, ctypes.POINTER(P)]),
+        "xyz_result_npairs": (I64, [P]),
+        "xyz_result_pairs": (P, [P]),
+        "xyz_result_nreps": (I32, [P]),
+        "xyz_result_reps": (P, [P]),
+        "xyz_result_timing": (ctypes.POINTER(xyz_timing), [P]),
+        "xyz_result_free": (None, [P]),
+        "xyz_smin": (I64, [I64, D, ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != XYZ_OK:
+        raise XyzError(code, (lib().xyz_last_error() or b"").decode())
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, memory kind, keep-alive object) of a numpy array or torch tensor."""
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), (XYZ_MEM_DEVICE if a.is_cuda else XYZ_MEM_HOST), a
+    arr = np.ascontiguousarray(a)
+    return arr.ctypes.data, XYZ_MEM_HOST, arr
+
+
+def _stream(stream, *tensors):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    for t in tensors:
+        if _is_torch(t) and t.is_cuda:
+            import torch
+            return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def _x_format(a) -> int:
+    dt = str(a.dtype)
+    if dt.endswith("int8"):
+        return XYZ_X_I8_PM1
+    if dt.endswith("uint64") or dt.endswith("int64"):
+        return XYZ_X_BITS
+    if dt.endswith("float32"):
+        return XYZ_X_F32
+    raise ValueError(f"unsupported X dtype {dt}")
+
+
+def _y_format(a) -> int:
+    dt = str(a.dtype)
+    if dt.endswith("int8"):
+        return XYZ_Y_I8_PM1
+    if dt.endswith("float32"):
+        return XYZ_Y_F32
+    if dt.endswith("float64"):
+        return XYZ_Y_F64
+    raise ValueError(f"unsupported Y dtype {dt}")
+
+
+# ------------------------------------------------------------- C-ABI names --
+
+def xyz_version() -> str:
+    return lib().xyz_version().decode()
+
+
+def xyz_smin(n: int, kappa: float, two_sided: bool = False) -> int:
+    return int(lib().xyz_smin(n, float(kappa), int(bool(two_sided))))
+
+
+def xyz_init(device: int = 0, hbm_budget_bytes: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib().xyz_init(device, hbm_budget_bytes, ctypes.byref(h)))
+    return h
+
+
+def xyz_fini(ctx) -> None:
+    lib().xyz_fini(ctx)
+
+
+def xyz_ctx_bytes(ctx) -> int:
+    return int(lib().xyz_ctx_bytes(ctx))
+
+
+def xyz_x_create(ctx, XT, n: int | None = None, stream=None):
+    """Make X resident.  XT is X in column-major order, shape (p, n) for int8 +-1 or
+    float32, or (p, ceil(n/64)) uint64 packed bits (then n must be given)."""
+    fmt = _x_format(XT)
+    p = int(XT.shape[0])
+    if fmt == XYZ_X_BITS:
+        if n is None:
+            raise ValueError("n is required for packed bits")
+        ld = int(XT.shape[1])
+    else:
+        n = int(XT.shape[1]) if n is None else n
+        ld = int(XT.shape[1])
+    ptr, mem, keep = _ptr(XT)
+    h = ctypes.c_void_p()
+    _check(lib().xyz_x_create(ctx, ptr, fmt, mem, n, p, ld, _stream(stream, XT), ctypes.byref(h)))
+    del keep
+    return h
+
+
+def xyz_x_destroy(x) -> None:
+    lib().xyz_x_destroy(x)
+
+
+def _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile):
+    prm = xyz_params()
+    prm.m, prm.L, prm.kappa, prm.seed = int(m), int(L), float(kappa), int(seed) & (2 ** 64 - 1)
+    prm.flags = (XYZ_TWO_SIDED if two_sided else 0) | (XYZ_PROFILE if profile else 0)
+    prm.rep_offset = int(rep_offset)
+    keep = None
+    if rows is not None:
+        keep = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1)
+        if keep.size != int(L) * int(m):
+            raise ValueError("rows must hold L*m entries")
+        prm.rows = keep.ctypes.data
+    return prm, keep
+
+
+def _take_result(h):
+    L = lib()
+    npairs = int(L.xyz_result_npairs(h))
+    pairs = np.zeros(npairs, dtype=PAIR_DTYPE)
+    if npairs:
+        ctypes.memmove(pairs.ctypes.data, L.xyz_result_pairs(h), npairs * PAIR_DTYPE.itemsize)
+    nreps = int(L.xyz_result_nreps(h))
+    reps = np.zeros(nreps, dtype=REP_DTYPE)
+    if nreps:
+        ctypes.memmove(reps.ctypes.data, L.xyz_result_reps(h), nreps * REP_DTYPE.itemsize)
+    t = L.xyz_result_timing(h).contents
+    timing = {name: getattr(t, name) for name, _ in xyz_timing._fields_}
+    L.xyz_result_free(h)
+    return {"pairs": pairs, "reps": reps, "timing": timing}
+
+
+def xyz_search(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
+               rep_offset: int = 0, rows=None, profile: bool = False, stream=None):
+    """Algorithm 2 on resident X.  Returns {'pairs', 'reps', 'timing'}."""
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile)
+    ptr, mem, keep = _ptr(Y)
+    h = ctypes.c_void_p()
+    _check(lib().xyz_search(ctx, x, ptr, _y_format(Y), mem, ctypes.byref(prm), _stream(stream, Y), ctypes.byref(h)))
+    del keep, keep_rows
+    return _take_result(h)
+
+
+def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
+    """Several searches on one X; params[q] is a dict of xyz_search keywords."""
+    nY = len(Ys)
+    if nY == 0:
+        return []
+    fmts = {_y_format(Y) for Y in Ys}
+    if len(fmts) != 1:
+        raise ValueError("all Y must share one format")
+    ptrs, keeps, mems = [], [], set()
+    for Y in Ys:
+        ptr, mem, keep = _ptr(Y)
+        ptrs.append(ptr)
+        keeps.append(keep)
+        mems.add(mem)
+    if len(mems) != 1:
+        raise ValueError("all Y must live in the same memory")
+    arr = (xyz_params * nY)()
+    keep_rows = []
+    for q, kw in enumerate(params):
+        prm, kr = _params(kw["m"], kw["L"], kw["kappa"], kw.get("seed", 0), kw.get("two_sided", False),
+                          kw.get("rep_offset", 0), kw.get("rows"), kw.get("profile", False))
+        arr[q] = prm
+        keep_rows.append(kr)
+    yp = (ctypes.c_void_p * nY)(*ptrs)
+    outs = (ctypes.c_void_p * nY)()
+    _check(lib().xyz_search_batch(ctx, x, nY, yp, fmts.pop(), mems.pop(), arr, _stream(stream, *Ys), outs))
+    del keeps, keep_rows
+    return [_take_result(outs[q]) for q in range(nY)]
+
+
+def xyz_bruteforce(ctx, x, Y, kappa: float, colsA=None, colsB=None, two_sided: bool = False,
+                   profile: bool = False, stream=None):
+    """Exact eq. (1) over colsA x colsB (all columns when None)."""
+    ptr, mem, keep = _ptr(Y)
+    a = None if colsA is None else np.ascontiguousarray(colsA, dtype=np.int32)
+    b = None if colsB is None else np.ascontiguousarray(colsB, dtype=np.int32)
+    flags = (XYZ_TWO_SIDED if two_sided else 0) | (XYZ_PROFILE if profile else 0)
+    h = ctypes.c_void_p()
+    _check(lib().xyz_bruteforce(ctx, x, ptr, _y_format(Y), mem, float(kappa), flags,
+                                None if a is None else a.ctypes.data, 0 if a is None else a.size,
+                                None if b is None else b.ctypes.data, 0 if b is None else b.size,
+                                _stream(stream, Y), ctypes.byref(h)))
+    del keep
+    return _take_result(h)
+
+
+class Context:
+    """Convenience owner of a context and its resident matrices."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.h = xyz_init(device, hbm_budget_bytes)
+        self._xs = []
+
+    def x_create(self, XT, n=None, stream=None):
+        x = xyz_x_create(self.h, XT, n=n, stream=stream)
+        self._xs.append(x)
+        return x
+
+    def search(self, x, Y, **kw):
+        return xyz_search(self.h, x, Y, **kw)
+
+    def search_batch(self, x, Ys, params, stream=None):
+        return xyz_search_batch(self.h, x, Ys, params, stream=stream)
+
+    def bruteforce(self, x, Y, kappa, **kw):
+        return xyz_bruteforce(self.h, x, Y, kappa, **kw)
+
+    def close(self):
+        for x in self._xs:
+            xyz_x_destroy(x)
+        self._xs = []
+        if self.h:
+            xyz_fini(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

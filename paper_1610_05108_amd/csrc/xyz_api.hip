@@ -1,0 +1,692 @@
+// xyz_api.hip -- host runtime and C ABI of libxyz (see include/xyz.h).
+//
+// The host side validates arguments, converts the threshold kappa of eq. (1)
+// into the integer threshold used for +-1 data, owns device memory, splits
+// the repetitions of Algorithm 2 into chunks that fit the workspace, and
+// enqueues the kernels of xyz_kernels.hip.  Every step of the search itself
+// (packing, row sampling, projection, bucket sort, candidate expansion,
+// verification, merging) runs on the GPU.
+#include "xyz.h"
+#include "xyz_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace xyz;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+xyz_status fail(xyz_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+xyz_status fail(xyz_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                       \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess) return fail(XYZ_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                              \
+    } while (0)
+
+#define XYZ_TRY(expr)                  \
+    do {                               \
+        xyz_status s_ = (expr);        \
+        if (s_ != XYZ_OK) return s_;   \
+    } while (0)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+enum Slot {
+    WS_XIN, WS_YIN, WS_YB, WS_YD, WS_CDF, WS_LAST, WS_ERR, WS_ROWS, WS_INFO, WS_KEYS, WS_OFFS, WS_PERM, WS_BASE,
+    WS_TILES, WS_SURV, WS_SURV2, WS_SCNT, WS_SMIN, WS_KAPPA, WS_DKEYS, WS_DVALS, WS_DKEYS2, WS_DVALS2, WS_HIST,
+    WS_HEADS, WS_OUT, WS_NOUT, WS_YCNT, NWS
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// HIP events around the stages of one call, summed after the final sync.
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    hipStream_t st = nullptr;
+    int open_stage = -1;
+    hipEvent_t open_ev = nullptr;
+    hipEvent_t get()
+    {
+        hipEvent_t e;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            return nullptr;
+        }
+        return e;
+    }
+    void begin(int stage)
+    {
+        if (!on) return;
+        open_stage = stage;
+        open_ev = get();
+        if (open_ev) (void)hipEventRecord(open_ev, st);
+    }
+    void end()
+    {
+        if (!on || !open_ev) return;
+        hipEvent_t e = get();
+        if (!e) return;
+        (void)hipEventRecord(e, st);
+        marks.push_back({open_stage, {open_ev, e}});
+        open_ev = nullptr;
+    }
+    // stage ids: 0 pack, 1 sample, 2 hash, 3 bucket, 4 tiles, 5 verify, 6 dedup, 7 brute
+    void collect(xyz_timing &t)
+    {
+        for (auto &m : marks) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, m.second.first, m.second.second);
+            double *dst[8] = {&t.pack_ms, &t.sample_ms, &t.hash_ms, &t.bucket_ms,
+                              &t.tiles_ms, &t.verify_ms, &t.dedup_ms, &t.brute_ms};
+            if (m.first >= 0 && m.first < 8) *dst[m.first] += ms;
+            pool.push_back(m.second.first);
+            pool.push_back(m.second.second);
+        }
+        marks.clear();
+    }
+    ~Timer()
+    {
+        for (auto &m : marks) {
+            (void)hipEventDestroy(m.second.first);
+            (void)hipEventDestroy(m.second.second);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+struct xyz_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    int cu_count = 256;
+    DevBuf ws[NWS];
+};
+
+struct xyz_x {
+    xyz_ctx *ctx = nullptr;
+    int64_t n = 0, p = 0;
+    int fmt = 0;
+    int W32p = 0;
+    int64_t P64 = 0;
+    int64_t nF = 0;
+    uint32_t *XC = nullptr;
+    uint64_t *XR = nullptr;
+    float *XF = nullptr;
+    size_t bytes = 0;
+};
+
+struct xyz_result {
+    std::vector<xyz_pair> pairs;
+    std::vector<xyz_rep_stats> reps;
+    xyz_timing timing{};
+};
+
+namespace {
+
+xyz_status dev_alloc(xyz_ctx *c, size_t bytes, void **out)
+{
+    bytes = (size_t)round_up((int64_t)std::max<size_t>(bytes, 256), 256);
+    if (c->budget && c->used + bytes > c->budget)
+        return fail(XYZ_ENOMEM, "device memory budget exceeded: %llu in use + %zu requested > %llu",
+                    (unsigned long long)c->used, bytes, (unsigned long long)c->budget);
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) return fail(XYZ_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    c->used += bytes;
+    return XYZ_OK;
+}
+
+void dev_free(xyz_ctx *c, void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    bytes = (size_t)round_up((int64_t)std::max<size_t>(bytes, 256), 256);
+    c->used -= std::min<uint64_t>(c->used, bytes);
+}
+
+// Grow-only workspace slot.
+xyz_status ws_get(xyz_ctx *c, int slot, size_t bytes, void **out)
+{
+    DevBuf &b = c->ws[slot];
+    if (b.p && b.bytes >= bytes) {
+        *out = b.p;
+        return XYZ_OK;
+    }
+    size_t want = std::max(bytes, b.bytes + b.bytes / 4);
+    want = (size_t)round_up((int64_t)std::max<size_t>(want, 256), 256);
+    dev_free(c, b.p, b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+    void *p = nullptr;
+    xyz_status s = dev_alloc(c, want, &p);
+    if (s != XYZ_OK && want > bytes) s = dev_alloc(c, bytes, &p), want = bytes;
+    if (s != XYZ_OK) return s;
+    b.p = p;
+    b.bytes = (size_t)round_up((int64_t)std::max<size_t>(want, 256), 256);
+    *out = p;
+    return XYZ_OK;
+}
+
+template <class T>
+xyz_status ws(xyz_ctx *c, int slot, size_t count, T **out)
+{
+    void *p = nullptr;
+    XYZ_TRY(ws_get(c, slot, std::max<size_t>(count, 1) * sizeof(T), &p));
+    *out = static_cast<T *>(p);
+    return XYZ_OK;
+}
+
+xyz_status check_err_flag(int *d_err, hipStream_t st)
+{
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h & 1) return fail(XYZ_EINVAL, "X holds a value other than -1 or +1");
+    if (h & 2) return fail(XYZ_EINVAL, "X holds NaN or Inf");
+    if (h & 4) return fail(XYZ_EINVAL, "Y holds an invalid value (not +-1 for the +-1 format, or NaN/Inf)");
+    if (h & 8) return fail(XYZ_EINVAL, "Y is zero everywhere: the |Y|-weighted sampler has no row to draw");
+    return XYZ_OK;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI --
+
+extern "C" const char *xyz_version(void) { return "libxyz 0.1 (gfx950)"; }
+
+extern "C" const char *xyz_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int64_t xyz_smin(int64_t n, double kappa, int two_sided)
+{
+    if (n <= 0) return 1;
+    const double dn = (double)n;
+    int64_t lo = two_sided ? 0 : -n, hi = n;
+    if (!((double)hi / dn > kappa)) return n + 1;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((double)mid / dn > kappa) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+extern "C" xyz_status xyz_init(int device, uint64_t hbm_budget_bytes, xyz_ctx **out)
+{
+    if (!out) return fail(XYZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(XYZ_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(XYZ_EUNSUPPORTED, "libxyz is built for gfx950; device %d is %s", device, prop.gcnArchName);
+    HIP_TRY(kernels_init());
+    xyz_ctx *c = new xyz_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return XYZ_OK;
+}
+
+extern "C" void xyz_fini(xyz_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    for (auto &b : c->ws) dev_free(c, b.p, b.bytes);
+    delete c;
+}
+
+extern "C" uint64_t xyz_ctx_bytes(const xyz_ctx *c) { return c ? c->used : 0; }
+
+extern "C" xyz_status xyz_x_create(xyz_ctx *c, const void *X, int fmt, int mem, int64_t n, int64_t p, int64_t ld,
+                                   void *stream, xyz_x **out)
+{
+    if (!c || !out || !X) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (n < 1 || n >= (1ll << 31) || p < 1 || p >= (1ll << 31))
+        return fail(XYZ_EINVAL, "shape n=%lld p=%lld out of range", (long long)n, (long long)p);
+    if (fmt != XYZ_X_I8_PM1 && fmt != XYZ_X_BITS && fmt != XYZ_X_F32) return fail(XYZ_EINVAL, "unknown X format %d", fmt);
+    if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
+    const int64_t minld = fmt == XYZ_X_BITS ? (n + 63) / 64 : n;
+    if (ld < minld) return fail(XYZ_EINVAL, "ld=%lld < %lld", (long long)ld, (long long)minld);
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    xyz_x *x = new xyz_x();
+    x->ctx = c;
+    x->n = n;
+    x->p = p;
+    x->fmt = fmt;
+    x->W32p = (int)round_up((n + 31) / 32, 4);
+    x->P64 = (p + 63) / 64;
+    x->nF = round_up(n, 32);
+    auto cleanup = [&](xyz_status s) {
+        xyz_x_destroy(x);
+        return s;
+    };
+    const size_t xc_bytes = (size_t)p * x->W32p * 4, xr_bytes = (size_t)n * x->P64 * 8;
+    void *pc = nullptr, *pr = nullptr, *pf = nullptr;
+    xyz_status s = dev_alloc(c, xc_bytes, &pc);
+    if (s != XYZ_OK) return cleanup(s);
+    x->XC = (uint32_t *)pc;
+    x->bytes += xc_bytes;
+    s = dev_alloc(c, xr_bytes, &pr);
+    if (s != XYZ_OK) return cleanup(s);
+    x->XR = (uint64_t *)pr;
+    x->bytes += xr_bytes;
+    if (fmt == XYZ_X_F32) {
+        const size_t xf_bytes = (size_t)p * x->nF * 4;
+        s = dev_alloc(c, xf_bytes, &pf);
+        if (s != XYZ_OK) return cleanup(s);
+        x->XF = (float *)pf;
+        x->bytes += xf_bytes;
+    }
+    // source on the device
+    const size_t esz = fmt == XYZ_X_BITS ? 8 : (fmt == XYZ_X_F32 ? 4 : 1);
+    const size_t src_bytes = ((size_t)(p - 1) * ld + minld) * esz;
+    const void *src = X;
+    if (mem == XYZ_MEM_HOST) {
+        void *tmp = nullptr;
+        s = ws_get(c, WS_XIN, src_bytes, &tmp);
+        if (s != XYZ_OK) return cleanup(s);
+        if (hipMemcpyAsync(tmp, X, src_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+            return cleanup(fail(XYZ_EDEVICE, "copying X to the device failed"));
+        src = tmp;
+    }
+    int *err = nullptr;
+    s = ws(c, WS_ERR, 4, &err);
+    if (s != XYZ_OK) return cleanup(s);
+    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) return cleanup(fail(XYZ_EDEVICE, "memset failed"));
+    hipError_t e;
+    if (fmt == XYZ_X_I8_PM1) e = launch_pack_x_i8((const int8_t *)src, ld, n, p, x->W32p, x->XC, err, st);
+    else if (fmt == XYZ_X_F32) e = launch_pack_x_f32((const float *)src, ld, n, p, x->W32p, x->XC, x->XF, x->nF, err, st);
+    else e = launch_pack_x_bits((const uint64_t *)src, ld, n, p, x->W32p, x->XC, st);
+    if (e == hipSuccess) e = launch_transpose(x->XC, n, p, x->W32p, x->XR, x->P64, st);
+    if (e != hipSuccess) return cleanup(fail(XYZ_EDEVICE, "packing X failed: %s", hipGetErrorString(e)));
+    s = check_err_flag(err, st);
+    if (s != XYZ_OK) return cleanup(s);
+    *out = x;
+    return XYZ_OK;
+}
+
+extern "C" void xyz_x_destroy(xyz_x *x)
+{
+    if (!x) return;
+    xyz_ctx *c = x->ctx;
+    (void)hipSetDevice(c->device);
+    dev_free(c, x->XC, (size_t)x->p * x->W32p * 4);
+    dev_free(c, x->XR, (size_t)x->n * x->P64 * 8);
+    if (x->XF) dev_free(c, x->XF, (size_t)x->p * x->nF * 4);
+    delete x;
+}
+
+extern "C" int64_t xyz_x_n(const xyz_x *x) { return x ? x->n : 0; }
+extern "C" int64_t xyz_x_p(const xyz_x *x) { return x ? x->p : 0; }
+
+namespace {
+
+xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt)
+{
+    if (!P) return fail(XYZ_EINVAL, "params is NULL");
+    if (P->m < 0 || P->m > XYZ_MAX_M) return fail(XYZ_EINVAL, "m=%d out of range [0, %d]", P->m, XYZ_MAX_M);
+    if (P->m > MAX_M_LDS)
+        return fail(XYZ_EUNSUPPORTED, "m=%d: this build sorts keys of at most %d bits", P->m, MAX_M_LDS);
+    if (P->L < 1) return fail(XYZ_EINVAL, "L=%d < 1", P->L);
+    if (!std::isfinite(P->kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
+    if (P->rep_offset < 0) return fail(XYZ_EINVAL, "rep_offset < 0");
+    if ((int64_t)P->rep_offset + P->L > (1ll << 31)) return fail(XYZ_EINVAL, "repetition index overflow");
+    if (P->flags & ~(uint32_t)(XYZ_TWO_SIDED | XYZ_PROFILE)) return fail(XYZ_EINVAL, "unknown flags 0x%x", P->flags);
+    if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
+    if (P->rows) {
+        const int64_t cnt = (int64_t)P->L * P->m;
+        for (int64_t q = 0; q < cnt; ++q)
+            if (P->rows[q] < 0 || P->rows[q] >= x->n)
+                return fail(XYZ_EINVAL, "rows[%lld]=%d out of range [0, %lld)", (long long)q, P->rows[q], (long long)x->n);
+    }
+    return XYZ_OK;
+}
+
+size_t y_bytes(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 1 : (yfmt == XYZ_Y_F32 ? 4 : 8)); }
+
+// One group of searches sharing X, m, L, seed, rep_offset and flags.  With
+// nys > 1 every Y must be +-1 and no row table may be given, so the row draws,
+// projections and bucket sort are shared (Z = Y o X changes only the partner mask).
+xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
+                     const xyz_params *const *Ps, hipStream_t st, xyz_result **outs)
+{
+    const double t0 = now_ms();
+    const xyz_params &P = *Ps[0];
+    const int64_t n = x->n, p = x->p;
+    const int m = P.m, L = P.L;
+    const int two = (P.flags & XYZ_TWO_SIDED) ? 1 : 0;
+    const bool real_y = yfmt != XYZ_Y_I8_PM1;
+    const bool real_x = x->fmt == XYZ_X_F32;
+    const bool real = real_x || real_y;
+    Timer tm;
+    tm.on = (P.flags & XYZ_PROFILE) != 0;
+    tm.st = st;
+    xyz_timing timing{};
+
+    // ---- Y
+    uint32_t *yb = nullptr;
+    double *yd = nullptr;
+    int *err = nullptr;
+    XYZ_TRY(ws(c, WS_YB, (size_t)nys * x->W32p, &yb));
+    XYZ_TRY(ws(c, WS_YD, (size_t)nys * x->nF, &yd));
+    XYZ_TRY(ws(c, WS_ERR, 1, &err));
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
+    tm.begin(0);
+    for (int y = 0; y < nys; ++y) {
+        const void *src = Ys[y];
+        if (mem == XYZ_MEM_HOST) {
+            void *tmp = nullptr;
+            XYZ_TRY(ws_get(c, WS_YIN, y_bytes(yfmt, n), &tmp));
+            HIP_TRY(hipMemcpyAsync(tmp, Ys[y], y_bytes(yfmt, n), hipMemcpyHostToDevice, st));
+            src = tmp;
+        }
+        HIP_TRY(launch_pack_y(src, yfmt, n, x->W32p, yb + (size_t)y * x->W32p, yd + (size_t)y * x->nF, x->nF, err, st));
+    }
+    double *cdf = nullptr;
+    int64_t *last = nullptr;
+    if (real_y && m > 0) {
+        XYZ_TRY(ws(c, WS_CDF, (size_t)n, &cdf));
+        XYZ_TRY(ws(c, WS_LAST, 1, &last));
+        HIP_TRY(launch_cdf(yd, n, cdf, last, err, st));
+    }
+    tm.end();
+    // thresholds
+    std::vector<int64_t> hsmin(nys);
+    std::vector<double> hkap(nys);
+    for (int y = 0; y < nys; ++y) {
+        hkap[y] = Ps[y]->kappa;
+        hsmin[y] = xyz_smin(n, Ps[y]->kappa, two);
+    }
+    int64_t *dsmin = nullptr;
+    double *dkap = nullptr;
+    XYZ_TRY(ws(c, WS_SMIN, nys, &dsmin));
+    XYZ_TRY(ws(c, WS_KAPPA, nys, &dkap));
+    HIP_TRY(hipMemcpyAsync(dsmin, hsmin.data(), sizeof(int64_t) * nys, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dkap, hkap.data(), sizeof(double) * nys, hipMemcpyHostToDevice, st));
+    XYZ_TRY(check_err_flag(err, st));
+
+    // ---- repetitions, in chunks
+    const int nb = 1 << m;
+    int64_t chunk = std::min<int64_t>(L, 4096);
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((1ll << 32) - 1) / p));      // u32 positions
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / (8 * p + 4 * (nb + 1))));
+    chunk = std::min<int64_t>(chunk, 65535);
+    RepInfo *info = nullptr;
+    XYZ_TRY(ws(c, WS_INFO, (size_t)L * nys, &info));
+    int32_t *rows = nullptr;
+    uint32_t *keys = nullptr, *offs = nullptr, *perm = nullptr;
+    unsigned long long *base = nullptr, *scnt = nullptr;
+    XYZ_TRY(ws(c, WS_ROWS, (size_t)chunk * std::max(m, 1), &rows));
+    XYZ_TRY(ws(c, WS_KEYS, (size_t)chunk * p, &keys));
+    XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
+    XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
+    XYZ_TRY(ws(c, WS_BASE, (size_t)chunk * nys + 1, &base));
+    XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
+    HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
+    uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
+    Survivor *surv = nullptr;
+    XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
+    uint64_t surv_done = 0;
+    const int grid = std::max(1, c->cu_count * 24);
+
+    for (int64_t r0 = 0; r0 < L; r0 += chunk) {
+        const int R = (int)std::min<int64_t>(chunk, L - r0);
+        const int64_t rep_abs0 = (int64_t)P.rep_offset + r0;
+        RepInfo *cinfo = info + (size_t)r0 * nys;
+        tm.begin(1);
+        if (m > 0) {
+            if (P.rows) {
+                HIP_TRY(hipMemcpyAsync(rows, P.rows + (size_t)r0 * m, sizeof(int32_t) * R * m, hipMemcpyHostToDevice, st));
+            } else {
+                HIP_TRY(launch_sample(P.seed, rep_abs0, R, m, n, real_y ? 1 : 0, cdf, last, rows, st));
+            }
+        }
+        HIP_TRY(launch_cmask(rows, R, m, nys, yb, x->W32p, cinfo, st));
+        tm.end();
+        tm.begin(2);
+        HIP_TRY(launch_hash(x->XR, x->P64, p, m, R, rows, keys, st));
+        tm.end();
+        bool redo = true;
+        while (redo) {
+            redo = false;
+            tm.begin(3);
+            HIP_TRY(launch_bucket(keys, p, m, R, nys, cinfo, two, offs, perm, st));
+            tm.end();
+            tm.begin(4);
+            HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
+            unsigned long long ntiles = 0;
+            HIP_TRY(hipMemcpyAsync(&ntiles, base + (size_t)R * nys, sizeof ntiles, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            Tile *tiles = nullptr;
+            XYZ_TRY(ws(c, WS_TILES, (size_t)ntiles, &tiles));
+            HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, base, tiles, st));
+            tm.end();
+            VerifyArgs va{};
+            va.tiles = tiles;
+            va.ntiles = ntiles;
+            va.perm = perm;
+            va.XC = x->XC;
+            va.W32p = x->W32p;
+            va.XF = x->XF;
+            va.nF = x->nF;
+            va.yb = yb;
+            va.yd = yd;
+            va.n = n;
+            va.smin = dsmin;
+            va.kappa = dkap;
+            va.two_sided = two;
+            va.nys = nys;
+            va.rep_abs0 = rep_abs0;
+            va.surv = surv;
+            va.surv_count = scnt;
+            va.surv_cap = surv_cap;
+            va.info = cinfo;
+            const int g = (int)std::min<unsigned long long>(ntiles ? ntiles : 1, (unsigned long long)grid);
+            tm.begin(5);
+            if (real) HIP_TRY(launch_verify_real(va, real_x ? 1 : 0, g, st));
+            else HIP_TRY(launch_verify_bin(va, g, st));
+            tm.end();
+            timing.verify_launches += ntiles ? 1 : 0;
+            timing.tiles += (int64_t)ntiles;
+            unsigned long long cnt = 0;
+            HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (cnt > surv_cap) {
+                // grow the survivor buffer, keep what earlier chunks found, and redo this chunk
+                uint64_t ncap = std::max<uint64_t>(cnt + cnt / 2, surv_cap * 2);
+                Survivor *tmp = nullptr;
+                XYZ_TRY(ws(c, WS_SURV2, surv_done, &tmp));
+                if (surv_done) HIP_TRY(hipMemcpyAsync(tmp, surv, surv_done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                XYZ_TRY(ws(c, WS_SURV, ncap, &surv));
+                if (surv_done) HIP_TRY(hipMemcpyAsync(surv, tmp, surv_done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
+                surv_cap = ncap;
+                const unsigned long long keep = surv_done;
+                HIP_TRY(hipMemcpyAsync(scnt, &keep, sizeof keep, hipMemcpyHostToDevice, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                redo = true;
+            } else {
+                surv_done = cnt;
+            }
+        }
+    }
+
+    // ---- merge repetitions
+    const uint64_t S = surv_done;
+    uint64_t *dk = nullptr, *dk2 = nullptr;
+    uint32_t *dv = nullptr, *dv2 = nullptr, *hist = nullptr, *heads = nullptr;
+    OutPair *dout = nullptr;
+    unsigned long long *nout = nullptr, *ycnt = nullptr;
+    XYZ_TRY(ws(c, WS_DKEYS, S, &dk));
+    XYZ_TRY(ws(c, WS_DKEYS2, S, &dk2));
+    XYZ_TRY(ws(c, WS_DVALS, S, &dv));
+    XYZ_TRY(ws(c, WS_DVALS2, S, &dv2));
+    XYZ_TRY(ws(c, WS_HIST, radix_hist_entries(S), &hist));
+    XYZ_TRY(ws(c, WS_HEADS, S + 1, &heads));
+    XYZ_TRY(ws(c, WS_OUT, S, &dout));
+    XYZ_TRY(ws(c, WS_NOUT, 1, &nout));
+    XYZ_TRY(ws(c, WS_YCNT, nys, &ycnt));
+    HIP_TRY(hipMemsetAsync(ycnt, 0, sizeof(unsigned long long) * nys, st));
+    tm.begin(6);
+    HIP_TRY(launch_dedup(surv, S, p, n, nys, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info,
+                         (int64_t)P.rep_offset, st));
+    tm.end();
+    unsigned long long U = 0;
+    std::vector<unsigned long long> hy(nys);
+    HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hy.data(), ycnt, sizeof(unsigned long long) * nys, hipMemcpyDeviceToHost, st));
+    std::vector<RepInfo> hinfo((size_t)L * nys);
+    HIP_TRY(hipMemcpyAsync(hinfo.data(), info, sizeof(RepInfo) * hinfo.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<xyz_pair> all(U);
+    if (U) HIP_TRY(hipMemcpyAsync(all.data(), dout, sizeof(xyz_pair) * U, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    tm.collect(timing);
+    int64_t cand_total = 0;
+    for (auto &ri : hinfo) cand_total += (int64_t)ri.candidates;
+    timing.candidates = cand_total;
+    timing.total_ms = now_ms() - t0;
+
+    size_t off = 0;
+    for (int y = 0; y < nys; ++y) {
+        xyz_result *r = new xyz_result();
+        r->pairs.assign(all.begin() + off, all.begin() + off + hy[y]);
+        off += hy[y];
+        r->reps.resize(L);
+        for (int l = 0; l < L; ++l) {
+            const RepInfo &ri = hinfo[(size_t)l * nys + y];
+            xyz_rep_stats &o = r->reps[l];
+            o.candidates = (int64_t)ri.candidates;
+            o.passed = (int64_t)ri.passed;
+            o.fresh = (int64_t)ri.fresh;
+            o.cmask = ri.cmask;
+            o.max_bucket = (int32_t)ri.max_bucket;
+            o.reserved = 0;
+        }
+        r->timing = timing;
+        outs[y] = r;
+    }
+    return XYZ_OK;
+}
+
+}  // namespace
+
+extern "C" xyz_status xyz_search(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem,
+                                 const xyz_params *params, void *stream, xyz_result **out)
+{
+    if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
+    XYZ_TRY(validate_params(x, params, yfmt));
+    HIP_TRY(hipSetDevice(c->device));
+    const void *ys[1] = {Y};
+    const xyz_params *ps[1] = {params};
+    return run_group(c, x, 1, ys, yfmt, mem, ps, (hipStream_t)stream, out);
+}
+
+extern "C" xyz_status xyz_search_batch(xyz_ctx *c, const xyz_x *x, int32_t nY, const void *const *Y, int yfmt,
+                                       int mem, const xyz_params *params, void *stream, xyz_result **outs)
+{
+    if (!c || !x || !Y || !outs || !params) return fail(XYZ_EINVAL, "NULL argument");
+    if (nY < 0) return fail(XYZ_EINVAL, "nY < 0");
+    if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
+    for (int q = 0; q < nY; ++q) {
+        outs[q] = nullptr;
+        if (!Y[q]) return fail(XYZ_EINVAL, "Y[%d] is NULL", q);
+        XYZ_TRY(validate_params(x, &params[q], yfmt));
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<char> done(nY, 0);
+    for (int q = 0; q < nY; ++q) {
+        if (done[q]) continue;
+        std::vector<int> grp{q};
+        const xyz_params &a = params[q];
+        const bool shareable = yfmt == XYZ_Y_I8_PM1 && !a.rows;
+        if (shareable)
+            for (int r = q + 1; r < nY && grp.size() < 255; ++r) {
+                const xyz_params &b = params[r];
+                if (!done[r] && !b.rows && b.m == a.m && b.L == a.L && b.seed == a.seed &&
+                    b.rep_offset == a.rep_offset && b.flags == a.flags)
+                    grp.push_back(r);
+            }
+        std::vector<const void *> ys;
+        std::vector<const xyz_params *> ps;
+        for (int g : grp) {
+            ys.push_back(Y[g]);
+            ps.push_back(&params[g]);
+            done[g] = 1;
+        }
+        std::vector<xyz_result *> res(grp.size(), nullptr);
+        xyz_status s = run_group(c, x, (int)grp.size(), ys.data(), yfmt, mem, ps.data(), st, res.data());
+        if (s != XYZ_OK) {
+            for (int r = 0; r < nY; ++r) {
+                if (outs[r]) xyz_result_free(outs[r]);
+                outs[r] = nullptr;
+            }
+            return s;
+        }
+        for (size_t g = 0; g < grp.size(); ++g) outs[grp[g]] = res[g];
+    }
+    return XYZ_OK;
+}
+
+extern "C" int64_t xyz_result_npairs(const xyz_result *r) { return r ? (int64_t)r->pairs.size() : 0; }
+extern "C" const xyz_pair *xyz_result_pairs(const xyz_result *r) { return r && !r->pairs.empty() ? r->pairs.data() : nullptr; }
+extern "C" int32_t xyz_result_nreps(const xyz_result *r) { return r ? (int32_t)r->reps.size() : 0; }
+extern "C" const xyz_rep_stats *xyz_result_reps(const xyz_result *r) { return r && !r->reps.empty() ? r->reps.data() : nullptr; }
+extern "C" const xyz_timing *xyz_result_timing(const xyz_result *r) { return r ? &r->timing : nullptr; }
+extern "C" void xyz_result_free(xyz_result *r) { delete r; }
+
+extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
+                                     uint32_t flags, const int32_t *colsA, int64_t nA, const int32_t *colsB,
+                                     int64_t nB, void *stream, xyz_result **out)
+{
+    (void)c; (void)x; (void)Y; (void)yfmt; (void)mem; (void)kappa; (void)flags;
+    (void)colsA; (void)nA; (void)colsB; (void)nB; (void)stream;
+    if (out) *out = nullptr;
+    return fail(XYZ_EUNSUPPORTED, "xyz_bruteforce is not built yet");
+}

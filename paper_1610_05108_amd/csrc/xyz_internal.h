@@ -1,0 +1,136 @@
+// Internal declarations shared by the libxyz sources (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace xyz {
+
+// Verification tiles cover at most TILE columns per side (Algorithm 2's
+// E_l is a union of Cartesian products of two buckets; each product is cut
+// into TILE x TILE blocks).
+constexpr int TILE = 32;
+// Largest m handled by the single-pass LDS bucket sort (2^m counters in LDS).
+constexpr int MAX_M_LDS = 15;
+
+struct Tile {            // 16 bytes
+    uint32_t rep;        // repetition index relative to the launch's first repetition
+    uint32_t a0;         // first position of the A block in perm (absolute)
+    uint32_t b0;         // first position of the B block in perm (absolute)
+    uint8_t na, nb;      // block sizes (1..TILE)
+    uint8_t diag;        // 1: A and B are the same block of one bucket; keep positions a < b only
+    uint8_t ysel;        // response index within a batch
+};
+
+struct Survivor {        // 32 bytes
+    uint32_t j, k;       // j < k
+    uint32_t rep;        // absolute repetition index
+    int32_t s;           // exact Y^T(X_j o X_k) for +-1 data
+    double value;        // inner product as double (binary64 sum for real data)
+    uint32_t ysel;       // response index within a batch
+    uint32_t pad;
+};
+
+struct OutPair {         // layout of xyz_pair
+    int32_t j, k;
+    int64_t s;
+    double value;
+    double stat;
+    int32_t first_rep, hits;
+};
+
+struct RepInfo {         // per repetition and response, filled on the device
+    unsigned long long candidates;
+    unsigned long long tiles;
+    unsigned long long passed;
+    unsigned long long fresh;
+    unsigned long long cmask;
+    unsigned int max_bucket;
+    unsigned int pad;
+};
+
+// ------------------------------------------------------------ launchers --
+// All launchers enqueue on `st` and return the hipError_t of the launch.
+
+// X (int8 +-1, column-major, ld) -> XC bits [p][W32p] u32.  err |= 1 on a bad value.
+hipError_t launch_pack_x_i8(const int8_t *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC,
+                            int *err, hipStream_t st);
+// X (float32, column-major, ld) -> sign bits XC and the zero-padded copy XF [p][nF].  err |= 2 on NaN/Inf.
+hipError_t launch_pack_x_f32(const float *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC,
+                             float *XF, int64_t nF, int *err, hipStream_t st);
+// X (uint64 bits, column-major, ld words) -> XC (tail bits past n cleared).
+hipError_t launch_pack_x_bits(const uint64_t *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC,
+                              hipStream_t st);
+// XC [p][W32p] -> XR [n][P64] (row-major bits, bit j%64 of word j/64).
+hipError_t launch_transpose(const uint32_t *XC, int64_t n, int64_t p, int W32p, uint64_t *XR, int64_t P64,
+                            hipStream_t st);
+// X (float32) -> int8 +-1 of the signs, or int8 copy, for matrix-core brute force (not used yet).
+
+// Y -> yb bits [W32p] u32, yd binary64 [nF] (zero padded).  yfmt: 0 int8, 1 f32, 2 f64.  err |= 4 bad value.
+hipError_t launch_pack_y(const void *Y, int yfmt, int64_t n, int W32p, uint32_t *yb, double *yd, int64_t nF,
+                         int *err, hipStream_t st);
+// Running sum of |Y| in binary64, left to right (one thread); last[0] = largest i with Y_i != 0.  err |= 8 if all zero.
+hipError_t launch_cdf(const double *yd, int64_t n, double *cdf, int64_t *last, int *err, hipStream_t st);
+// Row draws for repetitions [rep0, rep0 + nrep): rows [nrep][m].  weighted: cdf/last used.
+hipError_t launch_sample(uint64_t seed, int64_t rep0, int nrep, int m, int64_t n, int weighted, const double *cdf,
+                         const int64_t *last, int32_t *rows, hipStream_t st);
+// cmask of every (repetition, response): info[r * nys + y].cmask from rows and yb + y * yb_stride.
+hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uint32_t *yb, int yb_stride,
+                        RepInfo *info, hipStream_t st);
+// keys[r][j] for r < nrep (projection of column j on the sampled rows).
+hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nrep, const int32_t *rows,
+                       uint32_t *keys, hipStream_t st);
+// Bucket sort of each repetition's keys (one workgroup per repetition) plus the histogram-only
+// statistics of nys responses (info[r * nys + y]): candidates, tiles, max bucket.
+// offs [nrep][2^m + 1], perm [nrep][p].
+hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info,
+                         int two_sided, uint32_t *offs, uint32_t *perm, hipStream_t st);
+// Exclusive scan of info[...].tiles over nrep*nys entries into base [nrep*nys + 1] (u64).
+hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st);
+// Emit the tiles of every (repetition, response) at base[r * nys + y].
+hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
+                        int two_sided, const unsigned long long *base, Tile *tiles, hipStream_t st);
+
+// Shared arguments of the verification kernels.
+struct VerifyArgs {
+    const Tile *tiles;
+    uint64_t ntiles;
+    const uint32_t *perm;
+    const uint32_t *XC;      // [p][W32p] bits
+    int W32p;
+    const float *XF;         // [p][nF] values (continuous X) or null
+    int64_t nF;
+    const uint32_t *yb;      // [nys][W32p] bits of Y
+    const double *yd;        // [nys][nF] values of Y
+    int64_t n;
+    const int64_t *smin;     // [nys] integer thresholds (binary data)
+    const double *kappa;     // [nys] thresholds (real data)
+    int two_sided;
+    int nys;
+    int64_t rep_abs0;        // absolute index of relative repetition 0
+    Survivor *surv;
+    unsigned long long *surv_count;
+    uint64_t surv_cap;
+    RepInfo *info;           // [nrep][nys]
+};
+// Popcount-XOR verification of +-1 candidates: s = n - 2 popcount(y ^ x_j ^ x_k).
+hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st);
+// Binary64 verification of real-valued candidates (x_real: values from XF, else +-1 from XC).
+hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStream_t st);
+
+// Merge S survivors into unique pairs sorted by (ysel, j, k).  Scratch: keys/keys2 (u64) and
+// vals/vals2 (u32) of S entries, hist of radix_hist_entries(S) u32, heads of S + 1 u32.
+// out: unique pairs (ysel in the pad word of first_rep's neighbour is not kept: pairs of one
+// response are contiguous and their count per response goes to ycount[y]).  nout: device count.
+// Fresh counts go to info[(first_rep - rep_abs0) * nys + ysel].fresh.
+hipError_t launch_dedup(const Survivor *surv, uint64_t S, int64_t p, int64_t n, int nys, uint64_t *keys,
+                        uint32_t *vals, uint64_t *keys2, uint32_t *vals2, uint32_t *hist, uint32_t *heads,
+                        OutPair *out, unsigned long long *nout, unsigned long long *ycount, RepInfo *info,
+                        int64_t rep_abs0, hipStream_t st);
+
+// Radix histogram scratch size (u32 entries) for S items.
+size_t radix_hist_entries(uint64_t S);
+// Set kernel attributes (large dynamic LDS); called once per device.
+hipError_t kernels_init();
+
+}  // namespace xyz

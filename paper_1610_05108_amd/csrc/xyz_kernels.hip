@@ -1,0 +1,1111 @@
+// xyz_kernels.hip -- gfx950 kernels of the xyz interaction search.
+//
+// Data layout in HBM (per resident X):
+//   XC [p][W32p] u32  column-major bits, bit (i % 32) of word i / 32 = [X_ij = -1] (sign of real X),
+//                     W32p = ceil(n/32) rounded up to a multiple of 4 (16-byte rows), zero padded.
+//   XR [n][P64]   u64 row-major bits, bit (j % 64) of word j / 64 = [X_ij = -1].
+//   XF [p][nF]    f32 values of real X, nF = n rounded up to 32, zero padded.
+// Per search: yb [W32p] bits of Y (sign for real Y), yd [nF] values of Y.
+//
+// Paper mapping (Thanei, Meinshausen & Shah):
+//   k_pack_*       term (i) of eq. (8), forming the data Z is reduced to one XOR per word;
+//   k_sample       eq. (6) with tau = 0 (minimal subsampling, Section 2.1), |Y|-weighted for real Y (Section 3.1);
+//   k_hash         Algorithm 2's projection x = X^T R, z = Z^T R: with tau = 0 a column's projection is
+//                  determined by its entries on the sampled rows, packed here into an m-bit key;
+//                  z_k's key equals x_k's key XOR the bits of Y on the sampled rows (Z = Y o X);
+//   k_bucket       the equal-pairs search of Section 2.2 (Figure 2), as a counting sort of the p keys;
+//   k_tiles        E_l as a union of Cartesian products of a bucket b and its partner b ^ c;
+//   k_verify_*     the strength check of Algorithm 2 / eq. (1), term (iv) of eq. (8);
+//   k_rs_*, dedup  "add to I": the union over repetitions.
+#include "xyz_internal.h"
+
+namespace xyz {
+
+#define XYZ_DEV __device__ __forceinline__
+
+XYZ_DEV unsigned lane_id() { return threadIdx.x & 63u; }
+
+XYZ_DEV unsigned long long lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// v_bcnt_u32_b32 with accumulate: popcount(x) + acc in one VALU op.
+XYZ_DEV uint32_t bcnt_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+XYZ_DEV uint64_t cdiv_u64(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Exclusive scan of one value per thread over a block of NT threads.
+template <int NT>
+XYZ_DEV unsigned long long block_scan_excl(unsigned long long v, unsigned long long *shm, unsigned long long *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned long long x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        unsigned long long y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) shm[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long acc = 0;
+        for (int i = 0; i < NT / 64; ++i) {
+            unsigned long long t = shm[i];
+            shm[i] = acc;
+            acc += t;
+        }
+        shm[NT / 64] = acc;
+    }
+    __syncthreads();
+    unsigned long long res = shm[w] + x - v;
+    *total = shm[NT / 64];
+    __syncthreads();
+    return res;
+}
+
+template <int NT>
+XYZ_DEV unsigned long long block_sum(unsigned long long v, unsigned long long *shm)
+{
+    unsigned long long t;
+    block_scan_excl<NT>(v, shm, &t);
+    return t;
+}
+
+template <int NT>
+XYZ_DEV unsigned block_max(unsigned v, unsigned *shm)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (unsigned)__shfl_xor(v, d, 64));
+    if (lane == 0) shm[w] = v;
+    __syncthreads();
+    unsigned r = 0;
+    for (int i = 0; i < NT / 64; ++i) r = max(r, shm[i]);
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- packing --
+
+// One wave per column: each lane reads one entry of 64 consecutive rows, a
+// ballot forms the 64-bit word; lane c keeps word c of a group of 64 words.
+__global__ __launch_bounds__(256) void k_pack_x_i8(const int8_t *__restrict__ X, int64_t ld, int64_t n, int64_t p,
+                                                   int W32p, uint32_t *__restrict__ XC, int *__restrict__ err)
+{
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= p) return;
+    const unsigned lane = lane_id();
+    const int W64p = W32p / 2;
+    const int8_t *col = X + j * ld;
+    uint64_t *dst = reinterpret_cast<uint64_t *>(XC + j * (int64_t)W32p);
+    bool bad = false;
+    for (int g = 0; g < W64p; g += 64) {
+        uint64_t mine = 0;
+        const int gend = min(W64p, g + 64);
+        for (int c = g; c < gend; ++c) {
+            const int64_t i = (int64_t)c * 64 + lane;
+            int8_t v = 1;
+            if (i < n) {
+                v = col[i];
+                bad |= (v != 1 && v != -1);
+            }
+            unsigned long long w = __ballot(v == -1);
+            if ((int)lane == c - g) mine = w;
+        }
+        if (g + (int)lane < W64p) dst[g + lane] = mine;
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(err, 1);
+}
+
+__global__ __launch_bounds__(256) void k_pack_x_f32(const float *__restrict__ X, int64_t ld, int64_t n, int64_t p,
+                                                    int W32p, uint32_t *__restrict__ XC, float *__restrict__ XF,
+                                                    int64_t nF, int *__restrict__ err)
+{
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= p) return;
+    const unsigned lane = lane_id();
+    const int W64p = W32p / 2;
+    const float *col = X + j * ld;
+    uint64_t *dst = reinterpret_cast<uint64_t *>(XC + j * (int64_t)W32p);
+    float *fdst = XF + j * nF;
+    bool bad = false;
+    for (int g = 0; g < W64p; g += 64) {
+        uint64_t mine = 0;
+        const int gend = min(W64p, g + 64);
+        for (int c = g; c < gend; ++c) {
+            const int64_t i = (int64_t)c * 64 + lane;
+            float v = 0.0f;
+            if (i < n) {
+                v = col[i];
+                bad |= !isfinite(v);
+            }
+            if (i < nF) fdst[i] = v;
+            unsigned long long w = __ballot(v < 0.0f);
+            if ((int)lane == c - g) mine = w;
+        }
+        if (g + (int)lane < W64p) dst[g + lane] = mine;
+    }
+    for (int64_t i = (int64_t)W64p * 64 + lane; i < nF; i += 64) fdst[i] = 0.0f;
+    if (__ballot(bad) && lane == 0) atomicOr(err, 2);
+}
+
+__global__ __launch_bounds__(256) void k_pack_x_bits(const uint64_t *__restrict__ X, int64_t ld, int64_t n,
+                                                     int64_t p, int W32p, uint32_t *__restrict__ XC)
+{
+    const int W64p = W32p / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= p * W64p) return;
+    const int64_t j = gid / W64p;
+    const int w = (int)(gid % W64p);
+    const int64_t nw = (n + 63) / 64;
+    uint64_t v = 0;
+    if (w < nw) {
+        v = X[j * ld + w];
+        const int64_t tail = n - (int64_t)w * 64;
+        if (tail < 64) v &= (1ull << tail) - 1ull;
+    }
+    reinterpret_cast<uint64_t *>(XC)[j * W64p + w] = v;
+}
+
+// Bit transpose XC -> XR.  One wave takes 64 columns and 4 words (128 rows):
+// lane l holds 4 words of column 64g + l; 128 ballots produce the 64-column
+// words of 128 rows; lane l writes rows l and l + 64.
+__global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ XC, int64_t n, int64_t p, int W32p,
+                                                   uint64_t *__restrict__ XR, int64_t P64)
+{
+    const int W4 = W32p / 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t ngroups = (p + 63) / 64;
+    if (wave >= ngroups * W4) return;
+    const int64_t g = wave / W4;
+    const int q = (int)(wave % W4);
+    const unsigned lane = lane_id();
+    const int64_t j = g * 64 + lane;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (j < p) v = reinterpret_cast<const uint4 *>(XC + j * (int64_t)W32p)[q];
+    uint64_t lo = 0, hi = 0;
+    const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int b = 0; b < 32; ++b) {
+            unsigned long long m = __ballot((words[e] >> b) & 1u);
+            const int row = e * 32 + b;
+            if (row < 64) {
+                if ((int)lane == row) lo = m;
+            } else {
+                if ((int)lane == row - 64) hi = m;
+            }
+        }
+    }
+    const int64_t r0 = (int64_t)q * 128 + lane;
+    if (r0 < n) XR[r0 * P64 + g] = lo;
+    if (r0 + 64 < n) XR[(r0 + 64) * P64 + g] = hi;
+}
+
+__global__ __launch_bounds__(256) void k_pack_y(const void *__restrict__ Y, int yfmt, int64_t n, int W32p,
+                                                uint32_t *__restrict__ yb, double *__restrict__ yd, int64_t nF,
+                                                int *__restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = (int64_t)W32p * 32;
+    const int64_t lim = nb > nF ? nb : nF;
+    if (i >= lim) return;
+    double v = 0.0;
+    bool bad = false;
+    if (i < n) {
+        if (yfmt == 0) {
+            const int8_t y = static_cast<const int8_t *>(Y)[i];
+            bad = (y != 1 && y != -1);
+            v = (double)y;
+        } else if (yfmt == 1) {
+            v = (double)static_cast<const float *>(Y)[i];
+            bad = !isfinite(v);
+        } else {
+            v = static_cast<const double *>(Y)[i];
+            bad = !isfinite(v);
+        }
+    }
+    if (i < nF) yd[i] = v;
+    const unsigned long long m = __ballot(v < 0.0);
+    const unsigned lane = lane_id();
+    if (i < nb && (lane & 31) == 0) yb[i >> 5] = (lane == 0) ? (uint32_t)m : (uint32_t)(m >> 32);
+    if (__ballot(bad) && lane == 0) atomicOr(err, 4);
+}
+
+// Running sum of |Y_i| in binary64, in the order i = 0, 1, ..., n-1.
+__global__ void k_cdf(const double *__restrict__ yd, int64_t n, double *__restrict__ cdf, int64_t *__restrict__ last,
+                      int *__restrict__ err)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    int64_t lst = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double y = yd[i];
+        acc = __dadd_rn(acc, fabs(y));
+        cdf[i] = acc;
+        if (y != 0.0) lst = i;
+    }
+    *last = lst;
+    if (!(acc > 0.0)) atomicOr(err, 8);
+}
+
+// ----------------------------------------------------------------- sampler --
+
+// SplitMix64 (Steele, Lea & Flood 2014): output number k of the generator seeded with `seed`.
+XYZ_DEV uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Row draw t of repetition l is output 1 + l * 2^16 + t.  Uniform rows map u to
+// floor(u n / 2^64); weighted rows take the first i with cdf[i] > (u >> 11) 2^-53 cdf[n-1].
+__global__ __launch_bounds__(256) void k_sample(uint64_t seed, int64_t rep0, int nrep, int m, int64_t n,
+                                                int weighted, const double *__restrict__ cdf,
+                                                const int64_t *__restrict__ last, int32_t *__restrict__ rows)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)nrep * m) return;
+    const int64_t r = gid / m;
+    const int t = (int)(gid % m);
+    const uint64_t l = (uint64_t)(rep0 + r);
+    const uint64_t u = splitmix64_at(seed, 1ull + l * 65536ull + (uint64_t)t);
+    int64_t row;
+    if (!weighted) {
+        row = (int64_t)__umul64hi(u, (uint64_t)n);
+    } else {
+        const double v = __dmul_rn((double)(u >> 11) * 0x1p-53, cdf[n - 1]);
+        int64_t lo = 0, hi = n;   // first i in [lo, hi) with cdf[i] > v; n if none
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (cdf[mid] > v) hi = mid; else lo = mid + 1;
+        }
+        row = lo < n ? lo : *last;
+    }
+    rows[gid] = (int32_t)row;
+}
+
+__global__ __launch_bounds__(256) void k_cmask(const int32_t *__restrict__ rows, int nrep, int m, int nys,
+                                               const uint32_t *__restrict__ yb, int yb_stride,
+                                               RepInfo *__restrict__ info)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)nrep * nys) return;
+    const int64_t r = gid / nys;
+    const int y = (int)(gid % nys);
+    const uint32_t *yy = yb + (int64_t)y * yb_stride;
+    unsigned long long c = 0;
+    for (int t = 0; t < m; ++t) {
+        const int32_t i = rows[r * m + t];
+        c |= (unsigned long long)((yy[i >> 5] >> (i & 31)) & 1u) << t;
+    }
+    info[gid].cmask = c;
+}
+
+// ------------------------------------------------------------------- hash --
+
+// key_j = sum_t bit(X_{r_t, j}) << t.  One thread per column; the row words
+// are shared by the 64 lanes of a wave (one broadcast load per row).
+__global__ __launch_bounds__(256) void k_hash(const uint64_t *__restrict__ XR, int64_t P64, int64_t p, int m,
+                                              const int32_t *__restrict__ rows, uint32_t *__restrict__ keys)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    __shared__ int32_t rr[32];
+    if (threadIdx.x < (unsigned)m) rr[threadIdx.x] = rows[(int64_t)r * m + threadIdx.x];
+    __syncthreads();
+    if (j >= p) return;
+    const int64_t w = j >> 6;
+    const unsigned sh = (unsigned)(j & 63);
+    uint32_t key = 0;
+    for (int t = 0; t < m; ++t) {
+        const uint64_t word = XR[(int64_t)rr[t] * P64 + w];
+        key |= (uint32_t)((word >> sh) & 1ull) << t;
+    }
+    keys[(int64_t)r * p + j] = key;
+}
+
+// ----------------------------------------------------------------- bucket --
+
+// Bucket pair (b, b2) of a repetition: b < b2 -> all pairs of the two buckets;
+// b == b2 (partner mask 0) -> pairs inside the bucket.  Adds candidates and tiles.
+XYZ_DEV void pair_stats(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, unsigned long long &cand,
+                        unsigned long long &tiles)
+{
+    if (b < b2) {
+        cand += (unsigned long long)a * a2;
+        tiles += cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
+    } else if (b == b2 && a >= 2) {
+        cand += (unsigned long long)a * (a - 1) / 2;
+        const unsigned long long T = cdiv_u64(a, TILE);
+        tiles += T * (T + 1) / 2;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ keys, int64_t p, int m, int nys,
+                                                 RepInfo *__restrict__ info, int two_sided,
+                                                 uint32_t *__restrict__ offs, uint32_t *__restrict__ perm)
+{
+    extern __shared__ uint32_t cnt[];
+    __shared__ unsigned long long shm[17];
+    __shared__ unsigned shmax[16];
+    const int nb = 1 << m;
+    const uint32_t mask = (uint32_t)(nb - 1);
+    const int r = blockIdx.x;
+    const uint32_t *kr = keys + (int64_t)r * p;
+    for (int b = threadIdx.x; b < nb; b += 1024) cnt[b] = 0;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < p; j += 1024) atomicAdd(&cnt[kr[j]], 1u);
+    __syncthreads();
+    for (int y = 0; y < nys; ++y) {
+        RepInfo *inf = info + (int64_t)r * nys + y;
+        const uint32_t c = (uint32_t)inf->cmask & mask;
+        const uint32_t cn = (~c) & mask;
+        unsigned long long cand = 0, tiles = 0;
+        unsigned mx = 0;
+        for (int b = threadIdx.x; b < nb; b += 1024) {
+            const uint32_t a = cnt[b];
+            mx = max(mx, a);
+            pair_stats((uint32_t)b, (uint32_t)b ^ c, a, cnt[b ^ c], cand, tiles);
+            if (two_sided && cn != c) pair_stats((uint32_t)b, (uint32_t)b ^ cn, a, cnt[b ^ cn], cand, tiles);
+        }
+        cand = block_sum<1024>(cand, shm);
+        tiles = block_sum<1024>(tiles, shm);
+        mx = block_max<1024>(mx, shmax);
+        if (threadIdx.x == 0) {
+            inf->candidates = cand;
+            inf->tiles = tiles;
+            inf->max_bucket = mx;
+            inf->passed = 0;
+            inf->fresh = 0;
+        }
+    }
+    // exclusive scan of the histogram: each thread owns a contiguous segment
+    const int seg = (nb + 1023) / 1024;
+    const int b0 = min(nb, (int)threadIdx.x * seg), b1 = min(nb, b0 + seg);
+    unsigned long long loc = 0;
+    for (int b = b0; b < b1; ++b) loc += cnt[b];
+    unsigned long long tot;
+    unsigned long long pre = block_scan_excl<1024>(loc, shm, &tot);
+    uint32_t *of = offs + (int64_t)r * (nb + 1);
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c0 = cnt[b];
+        cnt[b] = (uint32_t)pre;
+        of[b] = (uint32_t)pre;
+        pre += c0;
+    }
+    if (threadIdx.x == 0) of[nb] = (uint32_t)p;
+    __syncthreads();
+    uint32_t *pr = perm + (int64_t)r * p;
+    for (int64_t j = threadIdx.x; j < p; j += 1024) {
+        const uint32_t pos = atomicAdd(&cnt[kr[j]], 1u);
+        pr[pos] = (uint32_t)j;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_tile_scan(const RepInfo *__restrict__ info, int count,
+                                                    unsigned long long *__restrict__ base)
+{
+    __shared__ unsigned long long shm[17];
+    const int seg = (count + 1023) / 1024;
+    const int i0 = min(count, (int)threadIdx.x * seg), i1 = min(count, i0 + seg);
+    unsigned long long loc = 0;
+    for (int i = i0; i < i1; ++i) loc += info[i].tiles;
+    unsigned long long tot;
+    unsigned long long pre = block_scan_excl<1024>(loc, shm, &tot);
+    for (int i = i0; i < i1; ++i) {
+        base[i] = pre;
+        pre += info[i].tiles;
+    }
+    if (threadIdx.x == 0) base[count] = tot;
+}
+
+XYZ_DEV unsigned long long pair_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2)
+{
+    if (b < b2) return cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
+    if (b == b2 && a >= 2) {
+        const unsigned long long T = cdiv_u64(a, TILE);
+        return T * (T + 1) / 2;
+    }
+    return 0;
+}
+
+XYZ_DEV void emit_pair(Tile *__restrict__ tiles, unsigned long long &pos, uint32_t r, uint32_t ysel, uint32_t pbase,
+                       uint32_t b, uint32_t b2, const uint32_t *of)
+{
+    const uint32_t o1 = of[b], a = of[b + 1] - o1;
+    const uint32_t o2 = of[b2], a2 = of[b2 + 1] - o2;
+    if (b < b2) {
+        const uint32_t nA = (a + TILE - 1) / TILE, nB = (a2 + TILE - 1) / TILE;
+        for (uint32_t ia = 0; ia < nA; ++ia)
+            for (uint32_t ib = 0; ib < nB; ++ib) {
+                Tile t;
+                t.rep = r;
+                t.a0 = pbase + o1 + ia * TILE;
+                t.b0 = pbase + o2 + ib * TILE;
+                t.na = (uint8_t)min((uint32_t)TILE, a - ia * TILE);
+                t.nb = (uint8_t)min((uint32_t)TILE, a2 - ib * TILE);
+                t.diag = 0;
+                t.ysel = (uint8_t)ysel;
+                tiles[pos++] = t;
+            }
+    } else if (b == b2 && a >= 2) {
+        const uint32_t T = (a + TILE - 1) / TILE;
+        for (uint32_t ia = 0; ia < T; ++ia)
+            for (uint32_t ib = ia; ib < T; ++ib) {
+                Tile t;
+                t.rep = r;
+                t.a0 = pbase + o1 + ia * TILE;
+                t.b0 = pbase + o1 + ib * TILE;
+                t.na = (uint8_t)min((uint32_t)TILE, a - ia * TILE);
+                t.nb = (uint8_t)min((uint32_t)TILE, a - ib * TILE);
+                t.diag = (uint8_t)(ia == ib);
+                t.ysel = (uint8_t)ysel;
+                tiles[pos++] = t;
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs, int64_t p, int m, int nys,
+                                               const RepInfo *__restrict__ info, int two_sided,
+                                               const unsigned long long *__restrict__ base, Tile *__restrict__ tiles)
+{
+    __shared__ unsigned long long shm[5];
+    const int ry = blockIdx.x;
+    const int r = ry / nys, y = ry % nys;
+    const int nb = 1 << m;
+    const uint32_t mask = (uint32_t)(nb - 1);
+    const uint32_t *of = offs + (int64_t)r * (nb + 1);
+    const uint32_t c = (uint32_t)info[ry].cmask & mask;
+    const uint32_t cn = (~c) & mask;
+    const bool second = two_sided && cn != c;
+    const int seg = (nb + 255) / 256;
+    const int b0 = min(nb, (int)threadIdx.x * seg), b1 = min(nb, b0 + seg);
+    unsigned long long loc = 0;
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t a = of[b + 1] - of[b];
+        loc += pair_tiles(b, b ^ c, a, of[(b ^ c) + 1] - of[b ^ c]);
+        if (second) loc += pair_tiles(b, b ^ cn, a, of[(b ^ cn) + 1] - of[b ^ cn]);
+    }
+    unsigned long long tot;
+    unsigned long long pos = base[ry] + block_scan_excl<256>(loc, shm, &tot);
+    const uint32_t pbase = (uint32_t)((int64_t)r * p);
+    for (int b = b0; b < b1; ++b) {
+        emit_pair(tiles, pos, (uint32_t)r, (uint32_t)y, pbase, b, b ^ c, of);
+        if (second) emit_pair(tiles, pos, (uint32_t)r, (uint32_t)y, pbase, b, b ^ cn, of);
+    }
+}
+
+// ------------------------------------------------------------ verification --
+//
+// One wave per tile (<= 32 x 32 column pairs).  Lane (ia, ib) = (lane & 7,
+// lane >> 3) owns the RA x RB block of pairs (ia + 8u, ib + 8v).  Columns are
+// staged through LDS in chunks of 32 words (1024 rows): A holds z_a = y ^ x_a,
+// B holds x_b, so the inner loop is one XOR and one popcount-accumulate per
+// pair and 32-bit word.  RA = ceil(na/8), RB = ceil(nb/8) are wave-uniform.
+
+constexpr int CW4 = 8;       // uint4 per column per chunk (32 words)
+constexpr int LDS4 = CW4 + 1;  // padded row length (uint4) against bank conflicts
+
+template <int RA, int RB>
+XYZ_DEV void verify_bin_tile(const Tile &t, const uint32_t *colA, const uint32_t *colB, uint4 (*As)[LDS4],
+                             uint4 (*Bs)[LDS4], const VerifyArgs &a)
+{
+    const unsigned lane = lane_id();
+    const int ia = lane & 7, ib = lane >> 3;
+    const int q = lane & 7, rc = lane >> 3;
+    const int W4 = a.W32p >> 2;
+    const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
+    const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
+    uint32_t acc[RA][RB];
+#pragma unroll
+    for (int u = 0; u < RA; ++u)
+#pragma unroll
+        for (int v = 0; v < RB; ++v) acc[u][v] = 0;
+    const int nchunk = (W4 + CW4 - 1) / CW4;
+    for (int c = 0; c < nchunk; ++c) {
+        const int gq = c * CW4 + q;
+        const bool inw = gq < W4;
+        const uint4 yv = inw ? y4[gq] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < RA; ++u) {
+            const int ci = rc + 8 * u;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (ci < t.na && inw) {
+                v = XC4[(int64_t)colA[ci] * W4 + gq];
+                v.x ^= yv.x; v.y ^= yv.y; v.z ^= yv.z; v.w ^= yv.w;
+            }
+            As[ci][q] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int ci = rc + 8 * u;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (ci < t.nb && inw) v = XC4[(int64_t)colB[ci] * W4 + gq];
+            Bs[ci][q] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < CW4; ++w) {
+            uint4 av[RA], bv[RB];
+#pragma unroll
+            for (int u = 0; u < RA; ++u) av[u] = As[ia + 8 * u][w];
+#pragma unroll
+            for (int v = 0; v < RB; ++v) bv[v] = Bs[ib + 8 * v][w];
+#pragma unroll
+            for (int u = 0; u < RA; ++u)
+#pragma unroll
+                for (int v = 0; v < RB; ++v) {
+                    uint32_t x = acc[u][v];
+                    x = bcnt_acc(av[u].x ^ bv[v].x, x);
+                    x = bcnt_acc(av[u].y ^ bv[v].y, x);
+                    x = bcnt_acc(av[u].z ^ bv[v].z, x);
+                    x = bcnt_acc(av[u].w ^ bv[v].w, x);
+                    acc[u][v] = x;
+                }
+        }
+        __syncthreads();
+    }
+    const int64_t smin = a.smin[t.ysel];
+#pragma unroll
+    for (int u = 0; u < RA; ++u)
+#pragma unroll
+        for (int v = 0; v < RB; ++v) {
+            const int pa = ia + 8 * u, pb = ib + 8 * v;
+            if (pa < t.na && pb < t.nb && (!t.diag || pa < pb)) {
+                const int64_t s = a.n - 2 * (int64_t)acc[u][v];
+                const bool pass = a.two_sided ? ((s < 0 ? -s : s) >= smin) : (s >= smin);
+                if (pass) {
+                    const uint32_t j = colA[pa], k = colB[pb];
+                    Survivor sv;
+                    sv.j = min(j, k);
+                    sv.k = max(j, k);
+                    sv.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                    sv.s = (int32_t)s;
+                    sv.value = (double)s;
+                    sv.ysel = t.ysel;
+                    sv.pad = 0;
+                    const unsigned long long idx = atomicAdd(a.surv_count, 1ull);
+                    if (idx < a.surv_cap) a.surv[idx] = sv;
+                    atomicAdd(&a.info[(int64_t)t.rep * a.nys + t.ysel].passed, 1ull);
+                }
+            }
+        }
+}
+
+__global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
+{
+    __shared__ uint4 As[TILE][LDS4];
+    __shared__ uint4 Bs[TILE][LDS4];
+    __shared__ uint32_t colA[TILE], colB[TILE];
+    const unsigned lane = lane_id();
+    for (uint64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+        const Tile t = a.tiles[ti];
+        if (lane < t.na) colA[lane] = a.perm[t.a0 + lane];
+        if (lane >= 32 && lane - 32 < t.nb) colB[lane - 32] = a.perm[t.b0 + lane - 32];
+        __syncthreads();
+        const int ra = (t.na + 7) >> 3, rb = (t.nb + 7) >> 3;
+        switch (ra * 4 + rb) {
+        case 5: verify_bin_tile<1, 1>(t, colA, colB, As, Bs, a); break;
+        case 6: verify_bin_tile<1, 2>(t, colA, colB, As, Bs, a); break;
+        case 7: verify_bin_tile<1, 3>(t, colA, colB, As, Bs, a); break;
+        case 8: verify_bin_tile<1, 4>(t, colA, colB, As, Bs, a); break;
+        case 9: verify_bin_tile<2, 1>(t, colA, colB, As, Bs, a); break;
+        case 10: verify_bin_tile<2, 2>(t, colA, colB, As, Bs, a); break;
+        case 11: verify_bin_tile<2, 3>(t, colA, colB, As, Bs, a); break;
+        case 12: verify_bin_tile<2, 4>(t, colA, colB, As, Bs, a); break;
+        case 13: verify_bin_tile<3, 1>(t, colA, colB, As, Bs, a); break;
+        case 14: verify_bin_tile<3, 2>(t, colA, colB, As, Bs, a); break;
+        case 15: verify_bin_tile<3, 3>(t, colA, colB, As, Bs, a); break;
+        case 16: verify_bin_tile<3, 4>(t, colA, colB, As, Bs, a); break;
+        case 17: verify_bin_tile<4, 1>(t, colA, colB, As, Bs, a); break;
+        case 18: verify_bin_tile<4, 2>(t, colA, colB, As, Bs, a); break;
+        case 19: verify_bin_tile<4, 3>(t, colA, colB, As, Bs, a); break;
+        case 20: verify_bin_tile<4, 4>(t, colA, colB, As, Bs, a); break;
+        default: break;
+        }
+        __syncthreads();
+    }
+}
+
+// Real-valued verification: v = sum_i (Y_i X_ij) X_ik in binary64.  Rows are
+// staged in chunks of 32: A holds Y_i X_ia (exact in binary64 for float
+// inputs), B holds X_ib; each lane accumulates its RA x RB block with FMAs.
+constexpr int CR = 32;
+
+template <int RA, int RB>
+XYZ_DEV void verify_real_tile(const Tile &t, const uint32_t *colA, const uint32_t *colB, double (*As)[CR + 1],
+                              double (*Bs)[CR + 1], const VerifyArgs &a, int x_real)
+{
+    const unsigned lane = lane_id();
+    const int ia = lane & 7, ib = lane >> 3;
+    const double *yd = a.yd + (int64_t)t.ysel * a.nF;
+    double acc[RA][RB];
+#pragma unroll
+    for (int u = 0; u < RA; ++u)
+#pragma unroll
+        for (int v = 0; v < RB; ++v) acc[u][v] = 0.0;
+    const int64_t nchunk = (a.n + CR - 1) / CR;
+    const int row = lane & 31, half = lane >> 5;
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const int64_t i = c * CR + row;
+        const bool inr = i < a.n;
+        const double yv = inr ? yd[i] : 0.0;
+        // each lane stages row `row` of columns half, half + 2, ...
+        for (int ci = half; ci < 8 * RA; ci += 2) {
+            double v = 0.0;
+            if (ci < t.na && inr) {
+                double x;
+                if (x_real) x = (double)a.XF[(int64_t)colA[ci] * a.nF + i];
+                else x = ((a.XC[(int64_t)colA[ci] * a.W32p + (i >> 5)] >> (i & 31)) & 1u) ? -1.0 : 1.0;
+                v = yv * x;
+            }
+            As[ci][row] = v;
+        }
+        for (int ci = half; ci < 8 * RB; ci += 2) {
+            double v = 0.0;
+            if (ci < t.nb && inr) {
+                if (x_real) v = (double)a.XF[(int64_t)colB[ci] * a.nF + i];
+                else v = ((a.XC[(int64_t)colB[ci] * a.W32p + (i >> 5)] >> (i & 31)) & 1u) ? -1.0 : 1.0;
+            }
+            Bs[ci][row] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < CR; ++rr) {
+            double av[RA], bv[RB];
+#pragma unroll
+            for (int u = 0; u < RA; ++u) av[u] = As[ia + 8 * u][rr];
+#pragma unroll
+            for (int v = 0; v < RB; ++v) bv[v] = Bs[ib + 8 * v][rr];
+#pragma unroll
+            for (int u = 0; u < RA; ++u)
+#pragma unroll
+                for (int v = 0; v < RB; ++v) acc[u][v] = __fma_rn(av[u], bv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+    const double kappa = a.kappa[t.ysel];
+    const double dn = (double)a.n;
+#pragma unroll
+    for (int u = 0; u < RA; ++u)
+#pragma unroll
+        for (int v = 0; v < RB; ++v) {
+            const int pa = ia + 8 * u, pb = ib + 8 * v;
+            if (pa < t.na && pb < t.nb && (!t.diag || pa < pb)) {
+                const double val = acc[u][v];
+                const double st = __ddiv_rn(val, dn);
+                const bool pass = a.two_sided ? (fabs(st) > kappa) : (st > kappa);
+                if (pass) {
+                    const uint32_t j = colA[pa], k = colB[pb];
+                    Survivor sv;
+                    sv.j = min(j, k);
+                    sv.k = max(j, k);
+                    sv.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                    sv.s = 0;
+                    sv.value = val;
+                    sv.ysel = t.ysel;
+                    sv.pad = 0;
+                    const unsigned long long idx = atomicAdd(a.surv_count, 1ull);
+                    if (idx < a.surv_cap) a.surv[idx] = sv;
+                    atomicAdd(&a.info[(int64_t)t.rep * a.nys + t.ysel].passed, 1ull);
+                }
+            }
+        }
+}
+
+__global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
+{
+    __shared__ double As[TILE][CR + 1];
+    __shared__ double Bs[TILE][CR + 1];
+    __shared__ uint32_t colA[TILE], colB[TILE];
+    const unsigned lane = lane_id();
+    for (uint64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+        const Tile t = a.tiles[ti];
+        if (lane < t.na) colA[lane] = a.perm[t.a0 + lane];
+        if (lane >= 32 && lane - 32 < t.nb) colB[lane - 32] = a.perm[t.b0 + lane - 32];
+        __syncthreads();
+        const int ra = (t.na + 7) >> 3, rb = (t.nb + 7) >> 3;
+        switch (ra * 4 + rb) {
+        case 5: verify_real_tile<1, 1>(t, colA, colB, As, Bs, a, x_real); break;
+        case 6: verify_real_tile<1, 2>(t, colA, colB, As, Bs, a, x_real); break;
+        case 7: verify_real_tile<1, 3>(t, colA, colB, As, Bs, a, x_real); break;
+        case 8: verify_real_tile<1, 4>(t, colA, colB, As, Bs, a, x_real); break;
+        case 9: verify_real_tile<2, 1>(t, colA, colB, As, Bs, a, x_real); break;
+        case 10: verify_real_tile<2, 2>(t, colA, colB, As, Bs, a, x_real); break;
+        case 11: verify_real_tile<2, 3>(t, colA, colB, As, Bs, a, x_real); break;
+        case 12: verify_real_tile<2, 4>(t, colA, colB, As, Bs, a, x_real); break;
+        case 13: verify_real_tile<3, 1>(t, colA, colB, As, Bs, a, x_real); break;
+        case 14: verify_real_tile<3, 2>(t, colA, colB, As, Bs, a, x_real); break;
+        case 15: verify_real_tile<3, 3>(t, colA, colB, As, Bs, a, x_real); break;
+        case 16: verify_real_tile<3, 4>(t, colA, colB, As, Bs, a, x_real); break;
+        case 17: verify_real_tile<4, 1>(t, colA, colB, As, Bs, a, x_real); break;
+        case 18: verify_real_tile<4, 2>(t, colA, colB, As, Bs, a, x_real); break;
+        case 19: verify_real_tile<4, 3>(t, colA, colB, As, Bs, a, x_real); break;
+        case 20: verify_real_tile<4, 4>(t, colA, colB, As, Bs, a, x_real); break;
+        default: break;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------- scan, radix sort --
+
+constexpr int RS_NT = 256, RS_IPT = 8, RS_TILE = RS_NT * RS_IPT;
+
+__global__ __launch_bounds__(RS_NT) void k_scan_reduce(const uint32_t *__restrict__ in, uint64_t cnt,
+                                                       uint32_t *__restrict__ partial)
+{
+    __shared__ unsigned long long shm[RS_NT / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+    unsigned long long s = 0;
+    for (int e = 0; e < RS_IPT; ++e) {
+        const uint64_t i = base + (uint64_t)e * RS_NT + threadIdx.x;
+        if (i < cnt) s += in[i];
+    }
+    s = block_sum<RS_NT>(s, shm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = (uint32_t)s;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_single(uint32_t *__restrict__ v, uint64_t cnt)
+{
+    __shared__ unsigned long long shm[17];
+    const uint64_t seg = (cnt + 1023) / 1024;
+    const uint64_t i0 = min(cnt, (uint64_t)threadIdx.x * seg), i1 = min(cnt, i0 + seg);
+    unsigned long long loc = 0;
+    for (uint64_t i = i0; i < i1; ++i) loc += v[i];
+    unsigned long long tot;
+    unsigned long long pre = block_scan_excl<1024>(loc, shm, &tot);
+    for (uint64_t i = i0; i < i1; ++i) {
+        const uint32_t x = v[i];
+        v[i] = (uint32_t)pre;
+        pre += x;
+    }
+}
+
+// Exclusive scan of in[0..cnt) into out (may alias in), given exclusive block offsets.
+__global__ __launch_bounds__(RS_NT) void k_scan_apply(const uint32_t *in, uint64_t cnt, const uint32_t *partial,
+                                                      uint32_t *out)
+{
+    __shared__ unsigned long long shm[RS_NT / 64 + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)threadIdx.x * RS_IPT;
+    uint32_t vals[RS_IPT];
+    unsigned long long s = 0;
+    for (int e = 0; e < RS_IPT; ++e) {
+        const uint64_t i = base + e;
+        vals[e] = i < cnt ? in[i] : 0;
+        s += vals[e];
+    }
+    unsigned long long tot;
+    unsigned long long pre = block_scan_excl<RS_NT>(s, shm, &tot) + partial[blockIdx.x];
+    for (int e = 0; e < RS_IPT; ++e) {
+        const uint64_t i = base + e;
+        if (i < cnt) out[i] = (uint32_t)pre;
+        pre += vals[e];
+    }
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t *__restrict__ keys, uint64_t S, int shift,
+                                                   uint32_t *__restrict__ hist, uint32_t nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+    for (int e = 0; e < RS_IPT; ++e) {
+        const uint64_t i = base + (uint64_t)e * RS_NT + threadIdx.x;
+        if (i < S) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: items are taken in index order, 256 per step; within a step
+// the rank of an item among equal digits is (count in earlier waves) + (rank
+// among its wave's peers, found by 8 ballots on the digit bits).
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                      const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+                                                      uint32_t *__restrict__ vout, uint64_t S, int shift,
+                                                      const uint32_t *__restrict__ hist, uint32_t nblocks)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[RS_NT / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6;
+    run[tid] = hist[(uint64_t)tid * nblocks + blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+    for (int e = 0; e < RS_IPT; ++e) {
+#pragma unroll
+        for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
+        __syncthreads();
+        const uint64_t i = base + (uint64_t)e * RS_NT + tid;
+        const bool valid = i < S;
+        uint64_t k = 0;
+        uint32_t v = 0, d = 0;
+        if (valid) {
+            k = kin[i];
+            v = vin[i];
+            d = (uint32_t)(k >> shift) & 255u;
+        }
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bal = __ballot(valid && bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dedup_keys(const Survivor *__restrict__ surv, uint64_t S, int64_t p,
+                                                    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const Survivor s = surv[i];
+    keys[i] = ((uint64_t)s.ysel * (uint64_t)p + s.j) * (uint64_t)p + s.k;
+    vals[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_dedup_heads(const uint64_t *__restrict__ keys, uint64_t S,
+                                                     uint32_t *__restrict__ heads)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    heads[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_dedup_emit(const uint64_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ vals,
+                                                    const Survivor *__restrict__ surv, uint64_t S,
+                                                    const uint32_t *__restrict__ heads_scan, int64_t n, int nys,
+                                                    OutPair *__restrict__ out, unsigned long long *__restrict__ ycount,
+                                                    RepInfo *__restrict__ info, int64_t rep_abs0)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    if (i != 0 && keys[i] == keys[i - 1]) return;
+    const Survivor s0 = surv[vals[i]];
+    uint32_t first = s0.rep;
+    int32_t hits = 0;
+    for (uint64_t q = i; q < S && keys[q] == keys[i]; ++q) {
+        first = min(first, surv[vals[q]].rep);
+        ++hits;
+    }
+    OutPair o;
+    o.j = (int32_t)s0.j;
+    o.k = (int32_t)s0.k;
+    o.s = s0.s;
+    o.value = s0.value;
+    o.stat = __ddiv_rn(s0.value, (double)n);
+    o.first_rep = (int32_t)first;
+    o.hits = hits;
+    const uint32_t u = heads_scan[i];
+    out[u] = o;
+    atomicAdd(&ycount[s0.ysel], 1ull);
+    atomicAdd(&info[((int64_t)first - rep_abs0) * nys + s0.ysel].fresh, 1ull);
+}
+
+__global__ void k_dedup_count(const uint32_t *__restrict__ heads_scan, const uint64_t *__restrict__ keys, uint64_t S,
+                              unsigned long long *__restrict__ nout)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (S == 0) {
+        *nout = 0;
+        return;
+    }
+    const bool last_head = (S == 1) || keys[S - 1] != keys[S - 2];
+    *nout = (unsigned long long)heads_scan[S - 1] + (last_head ? 1ull : 0ull);
+}
+
+// ------------------------------------------------------------- launchers --
+
+static inline unsigned grid1(uint64_t work, unsigned per) { return (unsigned)((work + per - 1) / per); }
+
+hipError_t kernels_init()
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (1 << MAX_M_LDS) * 4);
+    return e;
+}
+
+hipError_t launch_pack_x_i8(const int8_t *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC, int *err,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_x_i8, dim3(grid1(p, 4)), dim3(256), 0, st, X, ld, n, p, W32p, XC, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_x_f32(const float *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC, float *XF,
+                             int64_t nF, int *err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_x_f32, dim3(grid1(p, 4)), dim3(256), 0, st, X, ld, n, p, W32p, XC, XF, nF, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_x_bits(const uint64_t *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_x_bits, dim3(grid1((uint64_t)p * (W32p / 2), 256)), dim3(256), 0, st, X, ld, n, p,
+                       W32p, XC);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const uint32_t *XC, int64_t n, int64_t p, int W32p, uint64_t *XR, int64_t P64,
+                            hipStream_t st)
+{
+    const uint64_t waves = (uint64_t)((p + 63) / 64) * (uint64_t)(W32p / 4);
+    hipLaunchKernelGGL(k_transpose, dim3(grid1(waves, 4)), dim3(256), 0, st, XC, n, p, W32p, XR, P64);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_y(const void *Y, int yfmt, int64_t n, int W32p, uint32_t *yb, double *yd, int64_t nF,
+                         int *err, hipStream_t st)
+{
+    const int64_t nb = (int64_t)W32p * 32;
+    const int64_t lim = nb > nF ? nb : nF;
+    hipLaunchKernelGGL(k_pack_y, dim3(grid1(lim, 256)), dim3(256), 0, st, Y, yfmt, n, W32p, yb, yd, nF, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_cdf(const double *yd, int64_t n, double *cdf, int64_t *last, int *err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cdf, dim3(1), dim3(64), 0, st, yd, n, cdf, last, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(uint64_t seed, int64_t rep0, int nrep, int m, int64_t n, int weighted, const double *cdf,
+                         const int64_t *last, int32_t *rows, hipStream_t st)
+{
+    if (m == 0 || nrep == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample, dim3(grid1((uint64_t)nrep * m, 256)), dim3(256), 0, st, seed, rep0, nrep, m, n,
+                       weighted, cdf, last, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uint32_t *yb, int yb_stride,
+                        RepInfo *info, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cmask, dim3(grid1((uint64_t)nrep * nys, 256)), dim3(256), 0, st, rows, nrep, m, nys, yb,
+                       yb_stride, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nrep, const int32_t *rows,
+                       uint32_t *keys, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hash, dim3(grid1(p, 256), nrep), dim3(256), 0, st, XR, P64, p, m, rows, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info, int two_sided,
+                         uint32_t *offs, uint32_t *perm, hipStream_t st)
+{
+    const size_t lds = (size_t)4 << m;
+    hipLaunchKernelGGL(k_bucket, dim3(nrep), dim3(1024), lds, st, keys, p, m, nys, info, two_sided, offs, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, info, count, base);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
+                        int two_sided, const unsigned long long *base, Tile *tiles, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tiles, dim3(nrep * nys), dim3(256), 0, st, offs, p, m, nys, info, two_sided, base, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
+{
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_verify_bin, dim3(grid), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStream_t st)
+{
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_verify_real, dim3(grid), dim3(64), 0, st, a, x_real);
+    return hipGetLastError();
+}
+
+size_t radix_hist_entries(uint64_t S)
+{
+    const uint64_t nb = (S + RS_TILE - 1) / RS_TILE;
+    const uint64_t h = 256 * (nb ? nb : 1);
+    return (size_t)(h + (h + RS_TILE - 1) / RS_TILE + 16);
+}
+
+// Exclusive scan in place of v[0..cnt) using partial (cdiv(cnt, RS_TILE) entries).
+static hipError_t scan_u32(uint32_t *v, uint64_t cnt, uint32_t *partial, hipStream_t st)
+{
+    const uint64_t nb = (cnt + RS_TILE - 1) / RS_TILE;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(RS_NT), 0, st, v, cnt, partial);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, partial, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(RS_NT), 0, st, v, cnt, partial, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_dedup(const Survivor *surv, uint64_t S, int64_t p, int64_t n, int nys, uint64_t *keys,
+                        uint32_t *vals, uint64_t *keys2, uint32_t *vals2, uint32_t *hist, uint32_t *heads,
+                        OutPair *out, unsigned long long *nout, unsigned long long *ycount, RepInfo *info,
+                        int64_t rep_abs0, hipStream_t st)
+{
+    if (S == 0) {
+        hipLaunchKernelGGL(k_dedup_count, dim3(1), dim3(64), 0, st, heads, keys, (uint64_t)0, nout);
+        return hipGetLastError();
+    }
+    const unsigned g = grid1(S, 256);
+    hipLaunchKernelGGL(k_dedup_keys, dim3(g), dim3(256), 0, st, surv, S, p, keys, vals);
+    // number of key bits: ceil(log2(nys * p * p))
+    const double span = (double)nys * (double)p * (double)p;
+    int bits = 1;
+    while (bits < 64 && (double)(1ull << bits) < span) ++bits;
+    const uint32_t nb = (uint32_t)((S + RS_TILE - 1) / RS_TILE);
+    const uint64_t hent = 256ull * nb;
+    uint32_t *partial = hist + hent;
+    uint64_t *ka = keys, *kb = keys2;
+    uint32_t *va = vals, *vb = vals2;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_NT), 0, st, ka, S, shift, hist, nb);
+        hipError_t e = scan_u32(hist, hent, partial, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_NT), 0, st, ka, va, kb, vb, S, shift, hist, nb);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    hipLaunchKernelGGL(k_dedup_heads, dim3(g), dim3(256), 0, st, ka, S, heads);
+    hipError_t e = scan_u32(heads, S, hist, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dedup_emit, dim3(g), dim3(256), 0, st, ka, va, surv, S, heads, n, nys, out, ycount, info,
+                       rep_abs0);
+    hipLaunchKernelGGL(k_dedup_count, dim3(1), dim3(64), 0, st, heads, ka, S, nout);
+    return hipGetLastError();
+}
+
+}  // namespace xyz

@@ -1,0 +1,239 @@
+"""GPU parity: libxyz against the CPU oracle on the same seeded inputs.
+
++-1 data: pair sets, every pair statistic (s, stat, first_rep, hits) and every
+per-repetition statistic (candidates, passed, fresh, cmask, max_bucket) must be
+bit-identical.  Real data: the same pair set and values within 1e-12 relative
+of the binary64 oracle (both sides decide membership in binary64; only pairs
+whose value lies within that rounding band of kappa may differ).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthgen
+import paper_1610_05108_amd as xyz
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = xyz.Context(0)
+    yield c
+    c.close()
+
+
+def assert_same_binary(res, ref_pairs, ref_reps):
+    got = res["pairs"]
+    assert len(got) == len(ref_pairs), (len(got), len(ref_pairs))
+    for f in ("j", "k", "s", "first_rep", "hits"):
+        assert np.array_equal(got[f], ref_pairs[f]), f
+    assert np.array_equal(got["stat"], ref_pairs["stat"])
+    reps = res["reps"]
+    assert len(reps) == len(ref_reps)
+    for f in ("candidates", "passed", "fresh", "cmask", "max_bucket"):
+        assert np.array_equal(reps[f], ref_reps[f]), f
+
+
+def run_both(ctx, XT, Y, m, L, kappa, seed=0, two_sided=False, rep_offset=0, rows=None, n=None, x=None):
+    xh = x if x is not None else ctx.x_create(XT if n is None else synthgen.pack_bits_colmajor(XT), n=n)
+    _log(f"case n={XT.shape[1]} p={XT.shape[0]} m={m} L={L} kappa={kappa} seed={seed} two={two_sided}")
+    res = ctx.search(xh, Y, m=m, L=L, kappa=kappa, seed=seed, two_sided=two_sided, rep_offset=rep_offset, rows=rows)
+    ref_pairs, ref_reps = oracle.search(XT, Y, m, L, kappa, seed=seed, two_sided=two_sided,
+                                        rep_offset=rep_offset, rows=rows)
+    return res, ref_pairs, ref_reps
+
+
+def test_config1_bit_exact(ctx):
+    d = synthgen.config1()
+    p = d.params
+    res, rp, rr = run_both(ctx, d.XT, d.Y, p["m"], p["L"], p["kappa"], seed=p["seed"])
+    assert_same_binary(res, rp, rr)
+    assert res["reps"]["candidates"].mean() > 1000
+
+
+CASES = [
+    # n, p, m, L, kappa, two_sided, seed
+    (37, 33, 3, 7, 0.1, False, 1),
+    (64, 64, 4, 5, -2.0, False, 2),
+    (100, 257, 5, 9, 0.2, True, 3),
+    (1000, 3000, 7, 6, 0.12, False, 4),
+    (1025, 1500, 9, 4, -2.0, False, 5),     # every candidate survives: large merge
+    (4097, 700, 6, 5, 0.05, True, 6),
+    (33, 2, 1, 3, -2.0, False, 7),
+    (200, 1, 2, 3, 0.0, False, 8),
+    (500, 2000, 15, 30, 0.1, False, 9),
+    (300, 800, 0, 2, 0.15, False, 10),       # m = 0: every pair collides
+    (300, 800, 0, 2, 0.15, True, 11),
+]
+
+
+@pytest.mark.parametrize("n,p,m,L,kappa,two,seed", CASES)
+def test_random_binary_bit_exact(ctx, n, p, m, L, kappa, two, seed):
+    d = synthgen.small_binary(n, p, seed=seed, y_bias=0.4 + 0.05 * (seed % 3))
+    res, rp, rr = run_both(ctx, d.XT, d.Y, m, L, kappa, seed=seed, two_sided=two)
+    assert_same_binary(res, rp, rr)
+
+
+def test_packed_bits_input(ctx):
+    d = synthgen.small_binary(130, 400, seed=12)
+    res, rp, rr = run_both(ctx, d.XT, d.Y, 5, 6, 0.1, seed=3, n=130)
+    assert_same_binary(res, rp, rr)
+
+
+def test_genotype_skewed_buckets(ctx):
+    """Genotype-shaped columns give a few buckets far larger than the mean,
+    so bucket products are split into many tiles."""
+    XT, _ = synthgen.genotype(600, 5000, seed=13)
+    r = np.random.default_rng(1)
+    Y = np.where(r.random(600) < 0.45, 1, -1).astype(np.int8)
+    res, rp, rr = run_both(ctx, XT, Y, 10, 6, 0.15, seed=2)
+    assert_same_binary(res, rp, rr)
+    assert res["reps"]["max_bucket"].max() > 8 * 5000 / 1024
+
+
+def test_rows_table(ctx):
+    d = synthgen.small_binary(150, 600, seed=14, planted=[(3, 9)], flip=0.2)
+    rows = synthgen.rows_table(150, 8, 6, seed=5)
+    res, rp, rr = run_both(ctx, d.XT, d.Y, 6, 8, 0.2, rows=rows)
+    assert_same_binary(res, rp, rr)
+
+
+def test_survivor_buffer_growth(ctx):
+    """More survivors than the initial buffer: the library grows it and redoes the chunk."""
+    d = synthgen.small_binary(64, 2600, seed=15)
+    res, rp, rr = run_both(ctx, d.XT, d.Y, 3, 2, -2.0, seed=1)
+    assert len(rp) > 1 << 17
+    assert_same_binary(res, rp, rr)
+
+
+def test_split_repetitions_match_full_run(ctx):
+    d = synthgen.small_binary(300, 1200, seed=16, planted=[(1, 2)], flip=0.1)
+    x = ctx.x_create(d.XT)
+    full = ctx.search(x, d.Y, m=6, L=10, kappa=0.12, seed=9)
+    a = ctx.search(x, d.Y, m=6, L=4, kappa=0.12, seed=9, rep_offset=0)
+    b = ctx.search(x, d.Y, m=6, L=6, kappa=0.12, seed=9, rep_offset=4)
+    for f in ("candidates", "passed", "cmask", "max_bucket"):
+        assert np.array_equal(full["reps"][f], np.concatenate([a["reps"][f], b["reps"][f]]))
+    merged = {}
+    for part in (a, b):
+        for rec in part["pairs"]:
+            key = (int(rec["j"]), int(rec["k"]))
+            h, f = merged.get(key, (0, 1 << 30))
+            merged[key] = (h + int(rec["hits"]), min(f, int(rec["first_rep"])))
+    assert merged == {(int(r["j"]), int(r["k"])): (int(r["hits"]), int(r["first_rep"])) for r in full["pairs"]}
+
+
+def test_batch_matches_single_searches(ctx):
+    """Several responses against one X share projections and bucket sort; each
+    result must equal its stand-alone search (and the oracle)."""
+    XT = synthgen.rademacher(400, 1500, seed=17)
+    r = np.random.default_rng(3)
+    Ys = [np.where(r.random(400) < 0.5, 1, -1).astype(np.int8) for _ in range(5)]
+    x = ctx.x_create(XT)
+    params = [dict(m=7, L=6, kappa=0.1 + 0.01 * q, seed=4) for q in range(5)]
+    params[3] = dict(m=5, L=6, kappa=0.1, seed=4)            # a different group
+    params[4] = dict(m=7, L=6, kappa=0.1, seed=4, two_sided=True)
+    batch = ctx.search_batch(x, Ys, params)
+    for q in range(5):
+        kw = params[q]
+        single = ctx.search(x, Ys[q], **kw)
+        assert np.array_equal(batch[q]["pairs"], single["pairs"]), q
+        assert np.array_equal(batch[q]["reps"], single["reps"]), q
+        rp, rr = oracle.search(XT, Ys[q], kw["m"], kw["L"], kw["kappa"], seed=kw["seed"],
+                               two_sided=kw.get("two_sided", False))
+        assert_same_binary(batch[q], rp, rr)
+
+
+def test_device_tensor_inputs(ctx):
+    torch = pytest.importorskip("torch")
+    d = synthgen.small_binary(257, 900, seed=18, planted=[(5, 6)], flip=0.15)
+    XT_d = torch.from_numpy(d.XT).cuda()
+    Y_d = torch.from_numpy(d.Y).cuda()
+    x = ctx.x_create(XT_d)
+    res = ctx.search(x, Y_d, m=6, L=5, kappa=0.15, seed=2)
+    rp, rr = oracle.search(d.XT, d.Y, 6, 5, 0.15, seed=2)
+    assert_same_binary(res, rp, rr)
+
+
+def assert_same_real(res, rp, rr, kappa, n, tol=1e-12):
+    got = res["pairs"]
+    gk = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(got["j"], got["k"]))}
+    rk = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(rp["j"], rp["k"]))}
+    for key in set(gk) ^ set(rk):
+        src = got[gk[key]] if key in gk else rp[rk[key]]
+        assert abs(src["value"] / n - kappa) <= tol * (1 + abs(src["value"]) / n), key
+    for key in set(gk) & set(rk):
+        g, r = got[gk[key]], rp[rk[key]]
+        assert abs(g["value"] - r["value"]) <= tol * max(1.0, abs(r["value"])) * n
+        assert g["hits"] == r["hits"] and g["first_rep"] == r["first_rep"]
+    for f in ("candidates", "cmask", "max_bucket"):
+        assert np.array_equal(res["reps"][f], rr[f]), f
+
+
+@pytest.mark.parametrize("n,p,m,L,kappa,two,seed", [
+    (300, 400, 6, 8, 0.2, False, 1),
+    (1000, 1200, 8, 5, 0.3, False, 2),
+    (97, 150, 3, 6, -1e300, False, 3),
+    (513, 600, 7, 4, 0.25, True, 4),
+])
+def test_continuous_x_and_y(ctx, n, p, m, L, kappa, two, seed):
+    d = synthgen.small_continuous(n, p, seed=seed, planted=[(0, 1), (7, 40)], noise=0.8)
+    x = ctx.x_create(d.XT)
+    _log(f"continuous n={n} p={p} m={m} L={L}")
+    res = ctx.search(x, d.Y, m=m, L=L, kappa=kappa, seed=seed, two_sided=two)
+    rp, rr = oracle.search(d.XT, d.Y, m, L, kappa, seed=seed, two_sided=two)
+    assert_same_real(res, rp, rr, kappa, n)
+
+
+@pytest.mark.parametrize("ydtype", [np.float32, np.float64])
+def test_binary_x_real_y(ctx, ydtype):
+    d = synthgen.small_binary(400, 900, seed=19)
+    r = np.random.default_rng(7)
+    Y = (d.XT[2].astype(np.float64) * d.XT[11] + r.standard_normal(400)).astype(ydtype)
+    Y[::17] = 0.0
+    x = ctx.x_create(d.XT)
+    res = ctx.search(x, Y, m=6, L=7, kappa=0.2, seed=5)
+    rp, rr = oracle.search(d.XT, Y, 6, 7, 0.2, seed=5)
+    assert_same_real(res, rp, rr, 0.2, 400)
+
+
+def test_real_x_binary_y(ctx):
+    d = synthgen.small_continuous(350, 500, seed=20)
+    Y = np.where(np.random.default_rng(2).random(350) < 0.5, 1, -1).astype(np.int8)
+    x = ctx.x_create(d.XT)
+    res = ctx.search(x, Y, m=5, L=6, kappa=0.15, seed=1)
+    rp, rr = oracle.search(d.XT, Y, 5, 6, 0.15, seed=1)
+    assert_same_real(res, rp, rr, 0.15, 350)
+
+
+def test_invalid_inputs_raise(ctx):
+    d = synthgen.small_binary(40, 20, seed=21)
+    x = ctx.x_create(d.XT)
+    Y = d.Y.copy()
+    Y[5] = 0
+    with pytest.raises(xyz.XyzError) as e:
+        ctx.search(x, Y, m=2, L=2, kappa=0.1)
+    assert e.value.code == xyz.XYZ_EINVAL
+    bad = d.XT.copy()
+    bad[3, 4] = 3
+    with pytest.raises(xyz.XyzError):
+        ctx.x_create(bad)
+    with pytest.raises(xyz.XyzError):
+        ctx.search(x, d.Y, m=31, L=2, kappa=0.1)
+    with pytest.raises(xyz.XyzError):
+        ctx.search(x, d.Y, m=2, L=0, kappa=0.1)
+    with pytest.raises(xyz.XyzError):
+        ctx.search(x, d.Y, m=2, L=2, kappa=float("nan"))
+    with pytest.raises(xyz.XyzError):
+        ctx.search(x, np.zeros(40, dtype=np.float32), m=2, L=2, kappa=0.1)
+    # the context stays usable after rejected calls
+    res = ctx.search(x, d.Y, m=2, L=2, kappa=0.1)
+    rp, rr = oracle.search(d.XT, d.Y, 2, 2, 0.1)
+    assert_same_binary(res, rp, rr)
