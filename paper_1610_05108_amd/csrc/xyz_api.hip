@@ -385,6 +385,35 @@ xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt)
 
 size_t y_bytes(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 1 : (yfmt == XYZ_Y_F32 ? 4 : 8)); }
 
+// Pack nys responses into yb [nys][W32p] bits and yd [nys][nF] values; err is
+// the device error flag (zeroed here, checked by the caller).
+xyz_status pack_ys(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem, hipStream_t st,
+                   uint32_t **yb_out, double **yd_out, int **err_out)
+{
+    uint32_t *yb = nullptr;
+    double *yd = nullptr;
+    int *err = nullptr;
+    XYZ_TRY(ws(c, WS_YB, (size_t)nys * x->W32p, &yb));
+    XYZ_TRY(ws(c, WS_YD, (size_t)nys * x->nF, &yd));
+    XYZ_TRY(ws(c, WS_ERR, 1, &err));
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
+    for (int y = 0; y < nys; ++y) {
+        const void *src = Ys[y];
+        if (mem == XYZ_MEM_HOST) {
+            void *tmp = nullptr;
+            XYZ_TRY(ws_get(c, WS_YIN, y_bytes(yfmt, x->n), &tmp));
+            HIP_TRY(hipMemcpyAsync(tmp, Ys[y], y_bytes(yfmt, x->n), hipMemcpyHostToDevice, st));
+            src = tmp;
+        }
+        HIP_TRY(launch_pack_y(src, yfmt, x->n, x->W32p, yb + (size_t)y * x->W32p, yd + (size_t)y * x->nF, x->nF,
+                              err, st));
+    }
+    *yb_out = yb;
+    *yd_out = yd;
+    *err_out = err;
+    return XYZ_OK;
+}
+
 // One group of searches sharing X, m, L, seed, rep_offset and flags.  With
 // nys > 1 every Y must be +-1 and no row table may be given, so the row draws,
 // projections and bucket sort are shared (Z = Y o X changes only the partner mask).
@@ -408,21 +437,8 @@ xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys,
     uint32_t *yb = nullptr;
     double *yd = nullptr;
     int *err = nullptr;
-    XYZ_TRY(ws(c, WS_YB, (size_t)nys * x->W32p, &yb));
-    XYZ_TRY(ws(c, WS_YD, (size_t)nys * x->nF, &yd));
-    XYZ_TRY(ws(c, WS_ERR, 1, &err));
-    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
     tm.begin(0);
-    for (int y = 0; y < nys; ++y) {
-        const void *src = Ys[y];
-        if (mem == XYZ_MEM_HOST) {
-            void *tmp = nullptr;
-            XYZ_TRY(ws_get(c, WS_YIN, y_bytes(yfmt, n), &tmp));
-            HIP_TRY(hipMemcpyAsync(tmp, Ys[y], y_bytes(yfmt, n), hipMemcpyHostToDevice, st));
-            src = tmp;
-        }
-        HIP_TRY(launch_pack_y(src, yfmt, n, x->W32p, yb + (size_t)y * x->W32p, yd + (size_t)y * x->nF, x->nF, err, st));
-    }
+    XYZ_TRY(pack_ys(c, x, nys, Ys, yfmt, mem, st, &yb, &yd, &err));
     double *cdf = nullptr;
     int64_t *last = nullptr;
     if (real_y && m > 0) {
@@ -685,8 +701,152 @@ extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, 
                                      uint32_t flags, const int32_t *colsA, int64_t nA, const int32_t *colsB,
                                      int64_t nB, void *stream, xyz_result **out)
 {
-    (void)c; (void)x; (void)Y; (void)yfmt; (void)mem; (void)kappa; (void)flags;
-    (void)colsA; (void)nA; (void)colsB; (void)nB; (void)stream;
-    if (out) *out = nullptr;
-    return fail(XYZ_EUNSUPPORTED, "xyz_bruteforce is not built yet");
+    if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
+    if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
+    if (!std::isfinite(kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
+    if (flags & ~(uint32_t)(XYZ_TWO_SIDED | XYZ_PROFILE)) return fail(XYZ_EINVAL, "unknown flags 0x%x", flags);
+    const int64_t p = x->p, n = x->n;
+    if (!colsA) nA = p;
+    if (!colsB) nB = p;
+    if (nA < 0 || nB < 0) return fail(XYZ_EINVAL, "negative column count");
+    for (int64_t q = 0; colsA && q < nA; ++q)
+        if (colsA[q] < 0 || colsA[q] >= p) return fail(XYZ_EINVAL, "colsA[%lld] out of range", (long long)q);
+    for (int64_t q = 0; colsB && q < nB; ++q)
+        if (colsB[q] < 0 || colsB[q] >= p) return fail(XYZ_EINVAL, "colsB[%lld] out of range", (long long)q);
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const bool real = x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1;
+    if (real) {
+        // real-valued data: the exhaustive search (m = 0, every pair collides) verified in binary64
+        if (colsA || colsB) return fail(XYZ_EUNSUPPORTED, "column lists are supported for +-1 data only");
+        xyz_params P{};
+        P.m = 0;
+        P.L = 1;
+        P.kappa = kappa;
+        P.flags = flags;
+        const void *ys[1] = {Y};
+        const xyz_params *ps[1] = {&P};
+        xyz_result *r = nullptr;
+        XYZ_TRY(run_group(c, x, 1, ys, yfmt, mem, ps, st, &r));
+        for (auto &pr : r->pairs) {
+            pr.first_rep = -1;
+            pr.hits = 0;
+        }
+        r->reps.clear();
+        r->timing.brute_ms = r->timing.verify_ms;
+        *out = r;
+        return XYZ_OK;
+    }
+    const double t0 = now_ms();
+    Timer tm;
+    tm.on = (flags & XYZ_PROFILE) != 0;
+    tm.st = st;
+    xyz_timing timing{};
+    const int two = (flags & XYZ_TWO_SIDED) ? 1 : 0;
+    uint32_t *yb = nullptr;
+    double *yd = nullptr;
+    int *err = nullptr;
+    const void *ys[1] = {Y};
+    tm.begin(0);
+    XYZ_TRY(pack_ys(c, x, 1, ys, yfmt, mem, st, &yb, &yd, &err));
+    tm.end();
+    XYZ_TRY(check_err_flag(err, st));
+    int32_t *dA = nullptr, *dB = nullptr;
+    if (colsA) {
+        XYZ_TRY(ws(c, WS_ROWS, (size_t)nA + (colsB ? nB : 0), &dA));
+        HIP_TRY(hipMemcpyAsync(dA, colsA, sizeof(int32_t) * nA, hipMemcpyHostToDevice, st));
+    }
+    if (colsB) {
+        if (!dA) {
+            XYZ_TRY(ws(c, WS_ROWS, (size_t)nB, &dA));
+            dB = dA;
+        } else {
+            dB = dA + nA;
+        }
+        HIP_TRY(hipMemcpyAsync(dB, colsB, sizeof(int32_t) * nB, hipMemcpyHostToDevice, st));
+    }
+    RepInfo *info = nullptr;
+    unsigned long long *scnt = nullptr;
+    XYZ_TRY(ws(c, WS_INFO, 1, &info));
+    XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
+    uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
+    Survivor *surv = nullptr;
+    XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
+    BruteArgs ba{};
+    ba.XC = x->XC;
+    ba.W32p = x->W32p;
+    ba.nw = (int)((n + 31) / 32);
+    ba.yb = yb;
+    ba.colsA = colsA ? dA : nullptr;
+    ba.nA = nA;
+    ba.colsB = colsB ? dB : nullptr;
+    ba.nB = nB;
+    ba.tri = (!colsA && !colsB) ? 1 : 0;
+    ba.nbA = (nA + BF_TILE - 1) / BF_TILE;
+    ba.nbB = (nB + BF_TILE - 1) / BF_TILE;
+    ba.ntiles = ba.tri ? (uint64_t)ba.nbA * (ba.nbA + 1) / 2 : (uint64_t)ba.nbA * ba.nbB;
+    ba.n = n;
+    ba.smin = xyz_smin(n, kappa, two);
+    ba.two_sided = two;
+    ba.surv_count = scnt;
+    ba.info = info;
+    if (ba.ntiles > 0x7fffffffull) return fail(XYZ_EUNSUPPORTED, "too many column blocks for one launch");
+    uint64_t S = 0;
+    for (;;) {
+        HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
+        HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo), st));
+        ba.surv = surv;
+        ba.surv_cap = surv_cap;
+        tm.begin(7);
+        HIP_TRY(launch_brute(ba, st));
+        tm.end();
+        timing.verify_launches += 1;
+        unsigned long long cnt = 0;
+        HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (cnt <= surv_cap) {
+            S = cnt;
+            break;
+        }
+        surv_cap = cnt + cnt / 2;
+        XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
+    }
+    uint64_t *dk = nullptr, *dk2 = nullptr;
+    uint32_t *dv = nullptr, *dv2 = nullptr, *hist = nullptr, *heads = nullptr;
+    OutPair *dout = nullptr;
+    unsigned long long *nout = nullptr, *ycnt = nullptr;
+    XYZ_TRY(ws(c, WS_DKEYS, S, &dk));
+    XYZ_TRY(ws(c, WS_DKEYS2, S, &dk2));
+    XYZ_TRY(ws(c, WS_DVALS, S, &dv));
+    XYZ_TRY(ws(c, WS_DVALS2, S, &dv2));
+    XYZ_TRY(ws(c, WS_HIST, radix_hist_entries(S), &hist));
+    XYZ_TRY(ws(c, WS_HEADS, S + 1, &heads));
+    XYZ_TRY(ws(c, WS_OUT, S, &dout));
+    XYZ_TRY(ws(c, WS_NOUT, 1, &nout));
+    XYZ_TRY(ws(c, WS_YCNT, 1, &ycnt));
+    HIP_TRY(hipMemsetAsync(ycnt, 0, sizeof(unsigned long long), st));
+    tm.begin(6);
+    HIP_TRY(launch_dedup(surv, S, p, n, 1, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info, 0, st));
+    tm.end();
+    unsigned long long U = 0;
+    HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    xyz_result *r = new xyz_result();
+    r->pairs.resize(U);
+    if (U) HIP_TRY(hipMemcpyAsync(r->pairs.data(), dout, sizeof(xyz_pair) * U, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (auto &pr : r->pairs) {
+        pr.first_rep = -1;
+        pr.hits = 0;
+    }
+    tm.collect(timing);
+    timing.candidates = ba.tri ? (int64_t)(nA * (nA - 1) / 2) : (int64_t)nA * nB;
+    timing.tiles = (int64_t)ba.ntiles;
+    timing.total_ms = now_ms() - t0;
+    r->timing = timing;
+    *out = r;
+    return XYZ_OK;
 }

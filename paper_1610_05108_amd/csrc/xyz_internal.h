@@ -128,6 +128,30 @@ hipError_t launch_dedup(const Survivor *surv, uint64_t S, int64_t p, int64_t n, 
                         OutPair *out, unsigned long long *nout, unsigned long long *ycount, RepInfo *info,
                         int64_t rep_abs0, hipStream_t st);
 
+// Exact search of eq. (1) over column blocks with int8 matrix cores.
+struct BruteArgs {
+    const uint32_t *XC;      // [p][W32p] bits
+    int W32p;
+    int nw;                  // ceil(n / 32) words holding data
+    const uint32_t *yb;      // bits of Y
+    const int32_t *colsA;    // column ids of the A side (null: identity)
+    int64_t nA;
+    const int32_t *colsB;    // column ids of the B side (null: identity)
+    int64_t nB;
+    int tri;                 // A and B are the same list: only block pairs bi <= bj, and a < b on the diagonal
+    int64_t nbA, nbB;        // number of 256-column blocks per side
+    uint64_t ntiles;         // block pairs
+    int64_t n;
+    int64_t smin;
+    int two_sided;
+    Survivor *surv;
+    unsigned long long *surv_count;
+    uint64_t surv_cap;
+    RepInfo *info;           // one entry: passed counts
+};
+constexpr int BF_TILE = 256;
+hipError_t launch_brute(const BruteArgs &a, hipStream_t st);
+
 // Radix histogram scratch size (u32 entries) for S items.
 size_t radix_hist_entries(uint64_t S);
 // Set kernel attributes (large dynamic LDS); called once per device.

@@ -436,47 +436,64 @@ XYZ_DEV unsigned long long pair_tiles(uint32_t b, uint32_t b2, uint32_t a, uint3
     return 0;
 }
 
-XYZ_DEV void emit_pair(Tile *__restrict__ tiles, unsigned long long &pos, uint32_t r, uint32_t ysel, uint32_t pbase,
-                       uint32_t b, uint32_t b2, const uint32_t *of)
+// Tile (ia, ib) number t of a bucket's own product (ia <= ib < T), in row order:
+// row ia starts at S(ia) = ia T - ia (ia - 1) / 2.
+XYZ_DEV void tri_index(uint64_t t, uint64_t T, uint32_t &ia, uint32_t &ib)
+{
+    const double b = 2.0 * (double)T + 1.0;
+    double r = 0.5 * (b - sqrt(b * b - 8.0 * (double)t));
+    int64_t i = (int64_t)r;
+    if (i < 0) i = 0;
+    if (i > (int64_t)T - 1) i = (int64_t)T - 1;
+    auto S = [T](int64_t q) { return (uint64_t)q * T - (uint64_t)q * (uint64_t)(q - 1) / 2; };
+    while (i > 0 && S(i) > t) --i;
+    while (i + 1 < (int64_t)T && S(i + 1) <= t) ++i;
+    ia = (uint32_t)i;
+    ib = (uint32_t)(i + (int64_t)(t - S(i)));
+}
+
+XYZ_DEV Tile make_tile(uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1, uint32_t a, uint32_t o2, uint32_t a2,
+                       uint32_t ia, uint32_t ib, uint8_t diag)
+{
+    Tile t;
+    t.rep = r;
+    t.a0 = pbase + o1 + ia * TILE;
+    t.b0 = pbase + o2 + ib * TILE;
+    t.na = (uint8_t)min((uint32_t)TILE, a - ia * TILE);
+    t.nb = (uint8_t)min((uint32_t)TILE, a2 - ib * TILE);
+    t.diag = diag;
+    t.ysel = (uint8_t)ysel;
+    return t;
+}
+
+// Tile number t of the product of bucket b and its partner b2.
+XYZ_DEV Tile pair_tile(uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t b, uint32_t b2,
+                       const uint32_t *of)
 {
     const uint32_t o1 = of[b], a = of[b + 1] - o1;
     const uint32_t o2 = of[b2], a2 = of[b2 + 1] - o2;
-    if (b < b2) {
-        const uint32_t nA = (a + TILE - 1) / TILE, nB = (a2 + TILE - 1) / TILE;
-        for (uint32_t ia = 0; ia < nA; ++ia)
-            for (uint32_t ib = 0; ib < nB; ++ib) {
-                Tile t;
-                t.rep = r;
-                t.a0 = pbase + o1 + ia * TILE;
-                t.b0 = pbase + o2 + ib * TILE;
-                t.na = (uint8_t)min((uint32_t)TILE, a - ia * TILE);
-                t.nb = (uint8_t)min((uint32_t)TILE, a2 - ib * TILE);
-                t.diag = 0;
-                t.ysel = (uint8_t)ysel;
-                tiles[pos++] = t;
-            }
-    } else if (b == b2 && a >= 2) {
-        const uint32_t T = (a + TILE - 1) / TILE;
-        for (uint32_t ia = 0; ia < T; ++ia)
-            for (uint32_t ib = ia; ib < T; ++ib) {
-                Tile t;
-                t.rep = r;
-                t.a0 = pbase + o1 + ia * TILE;
-                t.b0 = pbase + o1 + ib * TILE;
-                t.na = (uint8_t)min((uint32_t)TILE, a - ia * TILE);
-                t.nb = (uint8_t)min((uint32_t)TILE, a - ib * TILE);
-                t.diag = (uint8_t)(ia == ib);
-                t.ysel = (uint8_t)ysel;
-                tiles[pos++] = t;
-            }
+    if (b != b2) {
+        const uint32_t nB = (a2 + TILE - 1) / TILE;
+        return make_tile(r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
     }
+    const uint32_t T = (a + TILE - 1) / TILE;
+    uint32_t ia, ib;
+    tri_index(t, T, ia, ib);
+    return make_tile(r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
 }
+
+// Bucket products with more tiles than this are emitted by the whole block.
+constexpr unsigned HEAVY_TILES = 64;
+constexpr int HEAVY_CAP = 512;
 
 __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs, int64_t p, int m, int nys,
                                                const RepInfo *__restrict__ info, int two_sided,
                                                const unsigned long long *__restrict__ base, Tile *__restrict__ tiles)
 {
     __shared__ unsigned long long shm[5];
+    __shared__ uint32_t hb[HEAVY_CAP], hb2[HEAVY_CAP];
+    __shared__ unsigned long long hpos[HEAVY_CAP], hcnt_t[HEAVY_CAP];
+    __shared__ int hcnt;
     const int ry = blockIdx.x;
     const int r = ry / nys, y = ry % nys;
     const int nb = 1 << m;
@@ -485,6 +502,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     const uint32_t c = (uint32_t)info[ry].cmask & mask;
     const uint32_t cn = (~c) & mask;
     const bool second = two_sided && cn != c;
+    if (threadIdx.x == 0) hcnt = 0;
     const int seg = (nb + 255) / 256;
     const int b0 = min(nb, (int)threadIdx.x * seg), b1 = min(nb, b0 + seg);
     unsigned long long loc = 0;
@@ -497,8 +515,31 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     unsigned long long pos = base[ry] + block_scan_excl<256>(loc, shm, &tot);
     const uint32_t pbase = (uint32_t)((int64_t)r * p);
     for (int b = b0; b < b1; ++b) {
-        emit_pair(tiles, pos, (uint32_t)r, (uint32_t)y, pbase, b, b ^ c, of);
-        if (second) emit_pair(tiles, pos, (uint32_t)r, (uint32_t)y, pbase, b, b ^ cn, of);
+        for (int side = 0; side < (second ? 2 : 1); ++side) {
+            const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
+            const unsigned long long T = pair_tiles(b, b2, of[b + 1] - of[b], of[b2 + 1] - of[b2]);
+            if (T == 0) continue;
+            int h = -1;
+            if (T > HEAVY_TILES) {
+                h = atomicAdd(&hcnt, 1);
+                if (h < HEAVY_CAP) {
+                    hb[h] = b;
+                    hb2[h] = b2;
+                    hpos[h] = pos;
+                    hcnt_t[h] = T;
+                }
+            }
+            if (h < 0 || h >= HEAVY_CAP)
+                for (unsigned long long t = 0; t < T; ++t) tiles[pos + t] = pair_tile(t, r, y, pbase, b, b2, of);
+            pos += T;
+        }
+    }
+    __syncthreads();
+    const int nh = min(hcnt, HEAVY_CAP);
+    for (int h = 0; h < nh; ++h) {
+        const unsigned long long T = hcnt_t[h], p0 = hpos[h];
+        for (unsigned long long t = threadIdx.x; t < T; t += 256)
+            tiles[p0 + t] = pair_tile(t, r, y, pbase, hb[h], hb2[h], of);
     }
 }
 
@@ -512,6 +553,30 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
 
 constexpr int CW4 = 8;       // uint4 per column per chunk (32 words)
 constexpr int LDS4 = CW4 + 1;  // padded row length (uint4) against bank conflicts
+
+
+// Reserve room for the survivors of one tile: one atomic per wave (also
+// counting them as passed for the tile's repetition).  Returns the index of
+// this lane's first survivor, or ~0 when the wave has none.
+XYZ_DEV unsigned long long reserve_survivors(const VerifyArgs &a, const Tile &t, int mine)
+{
+    const unsigned lane = lane_id();
+    int incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if ((int)lane >= d) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) return ~0ull;
+    unsigned long long base = 0;
+    if (lane == 0) {
+        base = atomicAdd(a.surv_count, (unsigned long long)total);
+        atomicAdd(&a.info[(int64_t)t.rep * a.nys + t.ysel].passed, (unsigned long long)total);
+    }
+    base = __shfl(base, 0, 64);
+    return base + (unsigned long long)(incl - mine);
+}
 
 template <int RA, int RB>
 XYZ_DEV void verify_bin_tile(const Tile &t, const uint32_t *colA, const uint32_t *colB, uint4 (*As)[LDS4],
@@ -573,16 +638,26 @@ XYZ_DEV void verify_bin_tile(const Tile &t, const uint32_t *colA, const uint32_t
         __syncthreads();
     }
     const int64_t smin = a.smin[t.ysel];
+    uint32_t passmask = 0;
 #pragma unroll
     for (int u = 0; u < RA; ++u)
 #pragma unroll
         for (int v = 0; v < RB; ++v) {
             const int pa = ia + 8 * u, pb = ib + 8 * v;
-            if (pa < t.na && pb < t.nb && (!t.diag || pa < pb)) {
+            const int64_t s = a.n - 2 * (int64_t)acc[u][v];
+            const bool pass = a.two_sided ? ((s < 0 ? -s : s) >= smin) : (s >= smin);
+            if (pa < t.na && pb < t.nb && (!t.diag || pa < pb) && pass) passmask |= 1u << (u * RB + v);
+        }
+    unsigned long long idx = reserve_survivors(a, t, __popc(passmask));
+    if (idx == ~0ull) return;
+#pragma unroll
+    for (int u = 0; u < RA; ++u)
+#pragma unroll
+        for (int v = 0; v < RB; ++v)
+            if ((passmask >> (u * RB + v)) & 1u) {
+                const uint32_t j = colA[ia + 8 * u], k = colB[ib + 8 * v];
                 const int64_t s = a.n - 2 * (int64_t)acc[u][v];
-                const bool pass = a.two_sided ? ((s < 0 ? -s : s) >= smin) : (s >= smin);
-                if (pass) {
-                    const uint32_t j = colA[pa], k = colB[pb];
+                if (idx < a.surv_cap) {
                     Survivor sv;
                     sv.j = min(j, k);
                     sv.k = max(j, k);
@@ -591,12 +666,10 @@ XYZ_DEV void verify_bin_tile(const Tile &t, const uint32_t *colA, const uint32_t
                     sv.value = (double)s;
                     sv.ysel = t.ysel;
                     sv.pad = 0;
-                    const unsigned long long idx = atomicAdd(a.surv_count, 1ull);
-                    if (idx < a.surv_cap) a.surv[idx] = sv;
-                    atomicAdd(&a.info[(int64_t)t.rep * a.nys + t.ysel].passed, 1ull);
+                    a.surv[idx] = sv;
                 }
+                ++idx;
             }
-        }
 }
 
 __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
@@ -693,31 +766,37 @@ XYZ_DEV void verify_real_tile(const Tile &t, const uint32_t *colA, const uint32_
     }
     const double kappa = a.kappa[t.ysel];
     const double dn = (double)a.n;
+    uint32_t passmask = 0;
 #pragma unroll
     for (int u = 0; u < RA; ++u)
 #pragma unroll
         for (int v = 0; v < RB; ++v) {
             const int pa = ia + 8 * u, pb = ib + 8 * v;
-            if (pa < t.na && pb < t.nb && (!t.diag || pa < pb)) {
-                const double val = acc[u][v];
-                const double st = __ddiv_rn(val, dn);
-                const bool pass = a.two_sided ? (fabs(st) > kappa) : (st > kappa);
-                if (pass) {
-                    const uint32_t j = colA[pa], k = colB[pb];
+            const double st = __ddiv_rn(acc[u][v], dn);
+            const bool pass = a.two_sided ? (fabs(st) > kappa) : (st > kappa);
+            if (pa < t.na && pb < t.nb && (!t.diag || pa < pb) && pass) passmask |= 1u << (u * RB + v);
+        }
+    unsigned long long idx = reserve_survivors(a, t, __popc(passmask));
+    if (idx == ~0ull) return;
+#pragma unroll
+    for (int u = 0; u < RA; ++u)
+#pragma unroll
+        for (int v = 0; v < RB; ++v)
+            if ((passmask >> (u * RB + v)) & 1u) {
+                const uint32_t j = colA[ia + 8 * u], k = colB[ib + 8 * v];
+                if (idx < a.surv_cap) {
                     Survivor sv;
                     sv.j = min(j, k);
                     sv.k = max(j, k);
                     sv.rep = (uint32_t)(a.rep_abs0 + t.rep);
                     sv.s = 0;
-                    sv.value = val;
+                    sv.value = acc[u][v];
                     sv.ysel = t.ysel;
                     sv.pad = 0;
-                    const unsigned long long idx = atomicAdd(a.surv_count, 1ull);
-                    if (idx < a.surv_cap) a.surv[idx] = sv;
-                    atomicAdd(&a.info[(int64_t)t.rep * a.nys + t.ysel].passed, 1ull);
+                    a.surv[idx] = sv;
                 }
+                ++idx;
             }
-        }
 }
 
 __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
@@ -753,6 +832,183 @@ __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
         }
         __syncthreads();
     }
+}
+
+
+// ------------------------------------------------------- exact brute force --
+//
+// G = Z_A^T X_B for +-1 data on int8 matrix cores.  With bits z = [Y_i X_ia = -1]
+// and x = [X_ib = -1], Y_i X_ia X_ib = (1 - 2z)(1 - 2x), so
+//   s = n - 2|z| - 2|x| + 4 C,   C = #{i : z_i = x_i = 1},
+// and C is a dot product of 0/1 int8 vectors.  A workgroup of 8 waves owns a
+// 256 x 256 block of column pairs; each K step expands one 32-row word of each
+// of its 512 columns into 32 bytes of 0/1 in LDS (double buffered), and each
+// wave runs 2 x 4 v_mfma_i32_32x32x32_i8 on its 64 x 128 sub-block.  A and B
+// fragments take the same 16 rows per lane, so the dot products are over the
+// same rows whatever order the instruction pairs them in.
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// 4 bits -> 4 bytes of 0/1 (bit q of the nibble to byte q).
+XYZ_DEV uint32_t spread4(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
+
+__global__ __launch_bounds__(512) void k_brute(BruteArgs a)
+{
+    __shared__ uint4 As[2][BF_TILE][2];
+    __shared__ uint4 Bs[2][BF_TILE][2];
+    __shared__ uint32_t popA[BF_TILE], popB[BF_TILE];
+    __shared__ int32_t colA[BF_TILE], colB[BF_TILE];
+    // give each XCD (blocks g = x mod 8 run on XCD x) a contiguous range of block
+    // pairs; the grid is a multiple of 8, so g -> t is a bijection onto [0, grid)
+    const uint64_t G = gridDim.x, g = blockIdx.x;
+    const uint64_t per = G / 8;
+    const uint64_t t = (g % 8) * per + g / 8;
+    if (t >= a.ntiles) return;
+    uint64_t bi, bj;
+    if (a.tri) {
+        uint32_t i0, j0;
+        tri_index(t, (uint64_t)a.nbA, i0, j0);
+        bi = i0;
+        bj = j0;
+    } else {
+        bi = t / (uint64_t)a.nbB;
+        bj = t % (uint64_t)a.nbB;
+    }
+    const int tid = threadIdx.x;
+    const int side = tid >> 8, cc = tid & 255;
+    {
+        const int64_t ci = (int64_t)(side ? bj : bi) * BF_TILE + cc;
+        const int64_t lim = side ? a.nB : a.nA;
+        const int32_t *lst = side ? a.colsB : a.colsA;
+        const int32_t col = ci < lim ? (lst ? lst[ci] : (int32_t)ci) : -1;
+        if (side) colB[cc] = col; else colA[cc] = col;
+    }
+    __syncthreads();
+    const int32_t mycol = side ? colB[cc] : colA[cc];
+    const uint4 *src = mycol >= 0 ? reinterpret_cast<const uint4 *>(a.XC + (int64_t)mycol * a.W32p) : nullptr;
+    const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb);
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wa = wave >> 1, wb = wave & 1;     // wave sub-block: rows wa*64.., columns wb*128..
+    v16i acc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = v16i{};
+    uint32_t pc = 0;
+    const int nq = a.W32p >> 2;   // uint4 per column
+    // one quad (128 rows) of this thread's column is loaded ahead of its use
+    uint4 cur = make_uint4(0, 0, 0, 0), ycur = make_uint4(0, 0, 0, 0);
+    uint4 nxt = src ? src[0] : make_uint4(0, 0, 0, 0);
+    uint4 ynxt = side ? make_uint4(0, 0, 0, 0) : y4[0];
+    for (int w = 0; w < a.nw; ++w) {
+        if ((w & 3) == 0) {
+            cur = nxt;
+            ycur = ynxt;
+            const int qn = (w >> 2) + 1;
+            if (qn < nq) {
+                nxt = src ? src[qn] : make_uint4(0, 0, 0, 0);
+                if (!side) ynxt = y4[qn];
+            }
+        }
+        const int e = w & 3;
+        uint32_t word = e == 0 ? cur.x : (e == 1 ? cur.y : (e == 2 ? cur.z : cur.w));
+        if (!side && src) word ^= (e == 0 ? ycur.x : (e == 1 ? ycur.y : (e == 2 ? ycur.z : ycur.w)));
+        pc += __popc(word);
+        uint4 lo, hi;
+        lo.x = spread4(word & 15u);
+        lo.y = spread4((word >> 4) & 15u);
+        lo.z = spread4((word >> 8) & 15u);
+        lo.w = spread4((word >> 12) & 15u);
+        hi.x = spread4((word >> 16) & 15u);
+        hi.y = spread4((word >> 20) & 15u);
+        hi.z = spread4((word >> 24) & 15u);
+        hi.w = spread4(word >> 28);
+        const int buf = w & 1;
+        if (side) {
+            Bs[buf][cc][0] = lo;
+            Bs[buf][cc][1] = hi;
+        } else {
+            As[buf][cc][0] = lo;
+            As[buf][cc][1] = hi;
+        }
+        __syncthreads();
+        v4i fa[2], fb[4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint4 q = As[buf][wa * 64 + u * 32 + (lane & 31)][lane >> 5];
+            fa[u] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint4 q = Bs[buf][wb * 128 + v * 32 + (lane & 31)][lane >> 5];
+            fb[v] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[v], acc[u][v], 0, 0, 0);
+    }
+    if (side) popB[cc] = pc; else popA[cc] = pc;
+    __syncthreads();
+    // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32;
+    // survivors are reserved one 32 x 32 fragment at a time (one atomic per wave and fragment)
+    const bool diag = a.tri && bi == bj;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int cb = wb * 128 + v * 32 + (lane & 31);
+            const int32_t gb = colB[cb];
+            const uint32_t pb = popB[cb];
+            uint32_t passmask = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const int32_t ga = colA[ra];
+                const int64_t sv = a.n - 2 * (int64_t)(popA[ra] + pb) + 4 * (int64_t)acc[u][v][r];
+                const bool pass = a.two_sided ? ((sv < 0 ? -sv : sv) >= a.smin) : (sv >= a.smin);
+                if (ga >= 0 && gb >= 0 && ga != gb && (!diag || ra < cb) && pass) passmask |= 1u << r;
+            }
+            const int mine = __popc(passmask);
+            int incl = mine;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int yv = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += yv;
+            }
+            const int total = __shfl(incl, 63, 64);
+            if (total == 0) continue;
+            unsigned long long base = 0;
+            if (lane == 0) {
+                base = atomicAdd(a.surv_count, (unsigned long long)total);
+                atomicAdd(&a.info[0].passed, (unsigned long long)total);
+            }
+            base = __shfl(base, 0, 64);
+            unsigned long long idx = base + (unsigned long long)(incl - mine);
+            while (passmask) {
+                const int r = __ffs(passmask) - 1;
+                passmask &= passmask - 1;
+                const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const int32_t ga = colA[ra];
+                if (idx < a.surv_cap) {
+                    int32_t cval = 0;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        if (q == r) cval = acc[u][v][q];
+                    Survivor s;
+                    s.j = (uint32_t)min(ga, gb);
+                    s.k = (uint32_t)max(ga, gb);
+                    s.rep = 0;
+                    s.s = (int32_t)(a.n - 2 * (int64_t)(popA[ra] + pb) + 4 * (int64_t)cval);
+                    s.value = (double)s.s;
+                    s.ysel = 0;
+                    s.pad = 0;
+                    a.surv[idx] = s;
+                }
+                ++idx;
+            }
+        }
 }
 
 // ------------------------------------------------------- scan, radix sort --
@@ -922,8 +1178,28 @@ __global__ __launch_bounds__(256) void k_dedup_emit(const uint64_t *__restrict__
     o.hits = hits;
     const uint32_t u = heads_scan[i];
     out[u] = o;
-    atomicAdd(&ycount[s0.ysel], 1ull);
-    atomicAdd(&info[((int64_t)first - rep_abs0) * nys + s0.ysel].fresh, 1ull);
+    // per-response and per-repetition counters: lanes with equal targets add once
+    unsigned long long todo = __ballot(1);
+    const unsigned long long key_y = s0.ysel;
+    const unsigned long long key_f = ((unsigned long long)(first - rep_abs0) << 8) | s0.ysel;
+    const unsigned lane = lane_id();
+    unsigned long long left = todo;
+    while (left) {
+        const int leader = __ffsll((long long)left) - 1;
+        const unsigned long long v = __shfl(key_y, leader, 64);
+        const unsigned long long same = __ballot(key_y == v) & left;
+        if ((int)lane == leader) atomicAdd(&ycount[v], (unsigned long long)__popcll(same));
+        left &= ~same;
+    }
+    left = todo;
+    while (left) {
+        const int leader = __ffsll((long long)left) - 1;
+        const unsigned long long v = __shfl(key_f, leader, 64);
+        const unsigned long long same = __ballot(key_f == v) & left;
+        if ((int)lane == leader)
+            atomicAdd(&info[(int64_t)(v >> 8) * nys + (int64_t)(v & 255)].fresh, (unsigned long long)__popcll(same));
+        left &= ~same;
+    }
 }
 
 __global__ void k_dedup_count(const uint32_t *__restrict__ heads_scan, const uint64_t *__restrict__ keys, uint64_t S,
@@ -1050,6 +1326,14 @@ hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStre
 {
     if (a.ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_verify_real, dim3(grid), dim3(64), 0, st, a, x_real);
+    return hipGetLastError();
+}
+
+hipError_t launch_brute(const BruteArgs &a, hipStream_t st)
+{
+    if (a.ntiles == 0) return hipSuccess;
+    const uint64_t grid = (a.ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 

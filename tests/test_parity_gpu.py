@@ -237,3 +237,91 @@ def test_invalid_inputs_raise(ctx):
     res = ctx.search(x, d.Y, m=2, L=2, kappa=0.1)
     rp, rr = oracle.search(d.XT, d.Y, 2, 2, 0.1)
     assert_same_binary(res, rp, rr)
+
+
+# ------------------------------------------------------------- brute force --
+
+def _brute_ref(XT, Y, kappa, colsA=None, colsB=None, two_sided=False):
+    """Expected exact result over colsA x colsB from the oracle's brute force."""
+    p = XT.shape[0]
+    full = oracle.brute(XT, Y, -2.0)
+    val = {(int(r["j"]), int(r["k"])): int(r["s"]) for r in full}
+    A = range(p) if colsA is None else colsA
+    B = range(p) if colsB is None else colsB
+    n = XT.shape[1]
+    keep = set()
+    for a in A:
+        for b in B:
+            if a == b:
+                continue
+            key = (min(a, b), max(a, b))
+            sv = val[key]
+            st = sv / n
+            if (abs(st) > kappa) if two_sided else (st > kappa):
+                keep.add(key)
+    return {k: val[k] for k in keep}
+
+
+@pytest.mark.parametrize("n,p,kappa,two,seed", [
+    (77, 300, 0.1, False, 1),
+    (1000, 700, 0.08, False, 2),
+    (4097, 520, 0.03, True, 3),
+    (32, 257, 0.2, False, 4),
+    (2000, 256, 0.0, False, 5),
+    (64, 2400, 0.25, False, 6),       # 55 block pairs: grid not a multiple of 8
+    (150, 3100, 0.3, True, 7),
+])
+def test_bruteforce_all_pairs_exact(ctx, n, p, kappa, two, seed):
+    d = synthgen.small_binary(n, p, seed=seed, planted=[(1, 2)], flip=0.3)
+    x = ctx.x_create(d.XT)
+    _log(f"brute n={n} p={p} kappa={kappa} two={two}")
+    res = ctx.bruteforce(x, d.Y, kappa, two_sided=two)
+    ref = oracle.brute(d.XT, d.Y, kappa, two_sided=two)
+    got = res["pairs"]
+    assert len(got) == len(ref)
+    for f in ("j", "k", "s", "stat"):
+        assert np.array_equal(got[f], ref[f]), f
+    assert np.all(got["first_rep"] == -1) and np.all(got["hits"] == 0)
+
+
+def test_bruteforce_column_lists(ctx):
+    d = synthgen.small_binary(300, 400, seed=6)
+    x = ctx.x_create(d.XT)
+    r = np.random.default_rng(0)
+    A = r.choice(400, size=90, replace=False).astype(np.int32)
+    B = np.concatenate([A[:20], r.choice(400, size=300, replace=True)]).astype(np.int32)  # overlap + repeats
+    res = ctx.bruteforce(x, d.Y, 0.05, colsA=A, colsB=B)
+    want = _brute_ref(d.XT, d.Y, 0.05, list(A), list(B))
+    got = {(int(a), int(b)): int(s) for a, b, s in zip(res["pairs"]["j"], res["pairs"]["k"], res["pairs"]["s"])}
+    assert got == want
+    assert list(zip(res["pairs"]["j"], res["pairs"]["k"])) == sorted(got)
+
+
+def test_bruteforce_many_survivors(ctx):
+    d = synthgen.small_binary(100, 600, seed=7)
+    x = ctx.x_create(d.XT)
+    res = ctx.bruteforce(x, d.Y, -2.0)
+    ref = oracle.brute(d.XT, d.Y, -2.0)
+    assert len(ref) == 600 * 599 // 2
+    assert np.array_equal(res["pairs"]["s"], ref["s"]) and np.array_equal(res["pairs"]["j"], ref["j"])
+
+
+def test_bruteforce_equals_exhaustive_search(ctx):
+    """The matrix-core brute force and the popcount search with m = 0 compute
+    the same set (two independent GPU routes to eq. (1))."""
+    XT, _ = synthgen.genotype(2000, 3000, seed=8)
+    Y = np.where(np.random.default_rng(5).random(2000) < 0.45, 1, -1).astype(np.int8)
+    x = ctx.x_create(XT)
+    b = ctx.bruteforce(x, Y, 0.06)
+    s = ctx.search(x, Y, m=0, L=1, kappa=0.06)
+    assert np.array_equal(b["pairs"][["j", "k", "s"]], s["pairs"][["j", "k", "s"]])
+    assert len(b["pairs"]) > 100
+
+
+def test_bruteforce_real_data(ctx):
+    d = synthgen.small_continuous(200, 150, seed=9, planted=[(3, 4)])
+    x = ctx.x_create(d.XT)
+    res = ctx.bruteforce(x, d.Y, 0.2)
+    ref = oracle.brute(d.XT, d.Y, 0.2)
+    assert np.array_equal(res["pairs"][["j", "k"]], ref[["j", "k"]])
+    assert np.allclose(res["pairs"]["value"], ref["value"], rtol=1e-12, atol=1e-9)
