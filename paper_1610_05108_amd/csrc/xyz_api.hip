@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -719,6 +720,7 @@ extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, 
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     const bool real = x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1;
+    if (!real && n >= (1ll << 29)) return fail(XYZ_EUNSUPPORTED, "brute force needs n < 2^29 (32-bit counts)");
     if (real) {
         // real-valued data: the exhaustive search (m = 0, every pair collides) verified in binary64
         if (colsA || colsB) return fail(XYZ_EUNSUPPORTED, "column lists are supported for +-1 data only");
@@ -793,6 +795,7 @@ extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, 
     ba.two_sided = two;
     ba.surv_count = scnt;
     ba.info = info;
+    ba.grid_blocks = std::max(8, c->cu_count / 8 * 8);
     if (ba.ntiles > 0x7fffffffull) return fail(XYZ_EUNSUPPORTED, "too many column blocks for one launch");
     uint64_t S = 0;
     for (;;) {

@@ -148,6 +148,7 @@ struct BruteArgs {
     unsigned long long *surv_count;
     uint64_t surv_cap;
     RepInfo *info;           // one entry: passed counts
+    int grid_blocks;         // persistent grid (a multiple of 8)
 };
 constexpr int BF_TILE = 256;
 hipError_t launch_brute(const BruteArgs &a, hipStream_t st);

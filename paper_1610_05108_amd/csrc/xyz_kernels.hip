@@ -19,6 +19,8 @@
 //   k_rs_*, dedup  "add to I": the union over repetitions.
 #include "xyz_internal.h"
 
+#include <algorithm>
+
 namespace xyz {
 
 #define XYZ_DEV __device__ __forceinline__
@@ -36,6 +38,16 @@ XYZ_DEV uint32_t bcnt_acc(uint32_t x, uint32_t acc)
 }
 
 XYZ_DEV uint64_t cdiv_u64(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits for every outstanding global load (its fence covers all address
+// spaces), which would drain the prefetches issued ahead of the barrier.
+XYZ_DEV void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Exclusive scan of one value per thread over a block of NT threads.
 template <int NT>
@@ -853,163 +865,209 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // 4 bits -> 4 bytes of 0/1 (bit q of the nibble to byte q).
 XYZ_DEV uint32_t spread4(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
 
-__global__ __launch_bounds__(512) void k_brute(BruteArgs a)
+// XC4 and y4 are kernel arguments of their own so that the compiler sees
+// global, read-only pointers (global loads for the columns, scalar loads for
+// Y's words, which every lane shares).
+__global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint4 *__restrict__ XC4,
+                                               const uint4 *__restrict__ y4)
 {
-    __shared__ uint4 As[2][BF_TILE][2];
-    __shared__ uint4 Bs[2][BF_TILE][2];
-    __shared__ uint32_t popA[BF_TILE], popB[BF_TILE];
+    // LDS: [buffer][word of the step][16-row half][column] -> 16 bytes of 0/1.
+    // Consecutive lanes read consecutive columns of one half: conflict-free.
+    __shared__ uint4 As[2][2][2][BF_TILE];
+    __shared__ uint4 Bs[2][2][2][BF_TILE];
+    __shared__ __align__(16) uint32_t popA[BF_TILE];
+    __shared__ __align__(16) uint32_t popB[BF_TILE];
     __shared__ int32_t colA[BF_TILE], colB[BF_TILE];
-    // give each XCD (blocks g = x mod 8 run on XCD x) a contiguous range of block
-    // pairs; the grid is a multiple of 8, so g -> t is a bijection onto [0, grid)
-    const uint64_t G = gridDim.x, g = blockIdx.x;
-    const uint64_t per = G / 8;
-    const uint64_t t = (g % 8) * per + g / 8;
-    if (t >= a.ntiles) return;
-    uint64_t bi, bj;
-    if (a.tri) {
-        uint32_t i0, j0;
-        tri_index(t, (uint64_t)a.nbA, i0, j0);
-        bi = i0;
-        bj = j0;
-    } else {
-        bi = t / (uint64_t)a.nbB;
-        bj = t % (uint64_t)a.nbB;
-    }
     const int tid = threadIdx.x;
     const int side = tid >> 8, cc = tid & 255;
-    {
-        const int64_t ci = (int64_t)(side ? bj : bi) * BF_TILE + cc;
-        const int64_t lim = side ? a.nB : a.nA;
-        const int32_t *lst = side ? a.colsB : a.colsA;
-        const int32_t col = ci < lim ? (lst ? lst[ci] : (int32_t)ci) : -1;
-        if (side) colB[cc] = col; else colA[cc] = col;
-    }
-    __syncthreads();
-    const int32_t mycol = side ? colB[cc] : colA[cc];
-    const uint4 *src = mycol >= 0 ? reinterpret_cast<const uint4 *>(a.XC + (int64_t)mycol * a.W32p) : nullptr;
-    const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb);
     const int wave = tid >> 6, lane = tid & 63;
     const int wa = wave >> 1, wb = wave & 1;     // wave sub-block: rows wa*64.., columns wb*128..
-    v16i acc[2][4];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = v16i{};
-    uint32_t pc = 0;
-    const int nq = a.W32p >> 2;   // uint4 per column
-    // one quad (128 rows) of this thread's column is loaded ahead of its use
-    uint4 cur = make_uint4(0, 0, 0, 0), ycur = make_uint4(0, 0, 0, 0);
-    uint4 nxt = src ? src[0] : make_uint4(0, 0, 0, 0);
-    uint4 ynxt = side ? make_uint4(0, 0, 0, 0) : y4[0];
-    for (int w = 0; w < a.nw; ++w) {
-        if ((w & 3) == 0) {
-            cur = nxt;
-            ycur = ynxt;
-            const int qn = (w >> 2) + 1;
-            if (qn < nq) {
-                nxt = src ? src[qn] : make_uint4(0, 0, 0, 0);
-                if (!side) ynxt = y4[qn];
-            }
-        }
-        const int e = w & 3;
-        uint32_t word = e == 0 ? cur.x : (e == 1 ? cur.y : (e == 2 ? cur.z : cur.w));
-        if (!side && src) word ^= (e == 0 ? ycur.x : (e == 1 ? ycur.y : (e == 2 ? ycur.z : ycur.w)));
-        pc += __popc(word);
-        uint4 lo, hi;
-        lo.x = spread4(word & 15u);
-        lo.y = spread4((word >> 4) & 15u);
-        lo.z = spread4((word >> 8) & 15u);
-        lo.w = spread4((word >> 12) & 15u);
-        hi.x = spread4((word >> 16) & 15u);
-        hi.y = spread4((word >> 20) & 15u);
-        hi.z = spread4((word >> 24) & 15u);
-        hi.w = spread4(word >> 28);
-        const int buf = w & 1;
-        if (side) {
-            Bs[buf][cc][0] = lo;
-            Bs[buf][cc][1] = hi;
+    const int nq = a.W32p >> 2;                   // uint4 per column
+    // blocks g = x mod 8 run on XCD x; G and the grid are multiples of 8, so
+    // t(g) is a bijection onto [0, G) and each XCD gets a contiguous range
+    const uint64_t G = (a.ntiles + 7) / 8 * 8;
+    const uint64_t per = G / 8;
+    for (uint64_t g = blockIdx.x; g < G; g += gridDim.x) {
+        const uint64_t t = (g % 8) * per + g / 8;
+        if (t >= a.ntiles) continue;
+        uint64_t bi, bj;
+        if (a.tri) {
+            uint32_t i0, j0;
+            tri_index(t, (uint64_t)a.nbA, i0, j0);
+            bi = i0;
+            bj = j0;
         } else {
-            As[buf][cc][0] = lo;
-            As[buf][cc][1] = hi;
+            bi = t / (uint64_t)a.nbB;
+            bj = t % (uint64_t)a.nbB;
         }
-        __syncthreads();
-        v4i fa[2], fb[4];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const uint4 q = As[buf][wa * 64 + u * 32 + (lane & 31)][lane >> 5];
-            fa[u] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+        {
+            const int64_t ci = (int64_t)(side ? bj : bi) * BF_TILE + cc;
+            const int64_t lim = side ? a.nB : a.nA;
+            const int32_t *lst = side ? a.colsB : a.colsA;
+            const int32_t col = ci < lim ? (lst ? lst[ci] : (int32_t)ci) : -1;
+            if (side) colB[cc] = col; else colA[cc] = col;
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const uint4 q = Bs[buf][wb * 128 + v * 32 + (lane & 31)][lane >> 5];
-            fb[v] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
-        }
+        lds_barrier();
+        const int32_t mycol = side ? colB[cc] : colA[cc];
+        const bool live = mycol >= 0;               // padding columns read column 0 and use zeros
+        const uint4 *src = XC4 + (int64_t)(live ? mycol : 0) * nq;
+        v16i acc[2][4];
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[v], acc[u][v], 0, 0, 0);
-    }
-    if (side) popB[cc] = pc; else popA[cc] = pc;
-    __syncthreads();
-    // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32;
-    // survivors are reserved one 32 x 32 fragment at a time (one atomic per wave and fragment)
-    const bool diag = a.tri && bi == bj;
+            for (int v = 0; v < 4; ++v) acc[u][v] = v16i{};
+        uint32_t pc = 0;
+        // one step: expand two 32-row words into LDS buffer `buf`, then 16 MFMAs
+        auto step = [&](uint32_t w0, uint32_t w1, int buf) {
+            const uint32_t wd[2] = {w0, w1};
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int cb = wb * 128 + v * 32 + (lane & 31);
-            const int32_t gb = colB[cb];
-            const uint32_t pb = popB[cb];
-            uint32_t passmask = 0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                const int32_t ga = colA[ra];
-                const int64_t sv = a.n - 2 * (int64_t)(popA[ra] + pb) + 4 * (int64_t)acc[u][v][r];
-                const bool pass = a.two_sided ? ((sv < 0 ? -sv : sv) >= a.smin) : (sv >= a.smin);
-                if (ga >= 0 && gb >= 0 && ga != gb && (!diag || ra < cb) && pass) passmask |= 1u << r;
-            }
-            const int mine = __popc(passmask);
-            int incl = mine;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int yv = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += yv;
-            }
-            const int total = __shfl(incl, 63, 64);
-            if (total == 0) continue;
-            unsigned long long base = 0;
-            if (lane == 0) {
-                base = atomicAdd(a.surv_count, (unsigned long long)total);
-                atomicAdd(&a.info[0].passed, (unsigned long long)total);
-            }
-            base = __shfl(base, 0, 64);
-            unsigned long long idx = base + (unsigned long long)(incl - mine);
-            while (passmask) {
-                const int r = __ffs(passmask) - 1;
-                passmask &= passmask - 1;
-                const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                const int32_t ga = colA[ra];
-                if (idx < a.surv_cap) {
-                    int32_t cval = 0;
-#pragma unroll
-                    for (int q = 0; q < 16; ++q)
-                        if (q == r) cval = acc[u][v][q];
-                    Survivor s;
-                    s.j = (uint32_t)min(ga, gb);
-                    s.k = (uint32_t)max(ga, gb);
-                    s.rep = 0;
-                    s.s = (int32_t)(a.n - 2 * (int64_t)(popA[ra] + pb) + 4 * (int64_t)cval);
-                    s.value = (double)s.s;
-                    s.ysel = 0;
-                    s.pad = 0;
-                    a.surv[idx] = s;
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t word = wd[k];
+                pc += __popc(word);
+                uint4 lo, hi;
+                lo.x = spread4(word & 15u);
+                lo.y = spread4((word >> 4) & 15u);
+                lo.z = spread4((word >> 8) & 15u);
+                lo.w = spread4((word >> 12) & 15u);
+                hi.x = spread4((word >> 16) & 15u);
+                hi.y = spread4((word >> 20) & 15u);
+                hi.z = spread4((word >> 24) & 15u);
+                hi.w = spread4(word >> 28);
+                if (side) {
+                    Bs[buf][k][0][cc] = lo;
+                    Bs[buf][k][1][cc] = hi;
+                } else {
+                    As[buf][k][0][cc] = lo;
+                    As[buf][k][1][cc] = hi;
                 }
-                ++idx;
+            }
+            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                v4i fa[2], fb[4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const uint4 q = As[buf][k][lane >> 5][wa * 64 + u * 32 + (lane & 31)];
+                    fa[u] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint4 q = Bs[buf][k][lane >> 5][wb * 128 + v * 32 + (lane & 31)];
+                    fb[v] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[v], acc[u][v], 0, 0, 0);
+            }
+        };
+        // quads of 4 words (128 rows): the next quad is loaded while this one is used;
+        // Y's words are the same for every lane (scalar loads)
+        const int nquad = (a.nw + 3) >> 2;
+        const uint4 zero4 = make_uint4(0, 0, 0, 0);
+        uint4 q = src[0];
+        if (!live) q = zero4;
+        for (int qi = 0; qi < nquad; ++qi) {
+            uint4 qn = src[min(qi + 1, nq - 1)];
+            if (!live || qi + 1 >= nq) qn = zero4;
+            if (!side && live) {
+                const uint4 yq = y4[qi];
+                q.x ^= yq.x;
+                q.y ^= yq.y;
+                q.z ^= yq.z;
+                q.w ^= yq.w;
+            }
+            const int w = qi * 4;   // words past nw are zero (padding), so they add nothing
+            step(q.x, w + 1 < a.nw ? q.y : 0u, 0);
+            if (w + 2 < a.nw) step(q.z, w + 3 < a.nw ? q.w : 0u, 1);
+            q = qn;
+        }
+        if (side) popB[cc] = pc; else popA[cc] = pc;
+        lds_barrier();
+        // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
+        // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b| (32-bit: 4n < 2^31);
+        // the cheap test runs on every pair, the validity checks only on the few that pass.
+        const bool diag = a.tri && bi == bj;
+        const int32_t n32 = (int32_t)a.n, smin32 = (int32_t)a.smin;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int32_t pa16[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 v4 = *reinterpret_cast<const uint4 *>(&popA[wa * 64 + u * 32 + q * 8 + (lane >> 5) * 4]);
+                pa16[4 * q + 0] = 2 * (int32_t)v4.x;
+                pa16[4 * q + 1] = 2 * (int32_t)v4.y;
+                pa16[4 * q + 2] = 2 * (int32_t)v4.z;
+                pa16[4 * q + 3] = 2 * (int32_t)v4.w;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int cb = wb * 128 + v * 32 + (lane & 31);
+                const int32_t pb2 = 2 * (int32_t)popB[cb];
+                const int32_t hi = smin32 - n32 + pb2;         // s >= smin
+                const int32_t lo = -smin32 - n32 + pb2;        // s <= -smin (two-sided)
+                uint32_t passmask = 0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t x = 4 * acc[u][v][r] - pa16[r];
+                    const bool pass = x >= hi || (a.two_sided && x <= lo);
+                    passmask |= (pass ? 1u : 0u) << r;
+                }
+                if (__ballot(passmask != 0) == 0) continue;
+                const int32_t gb = colB[cb];
+                uint32_t m = passmask;
+                while (m) {
+                    const int r = __ffs(m) - 1;
+                    m &= m - 1;
+                    const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                    const int32_t ga = colA[ra];
+                    if (!(ga >= 0 && gb >= 0 && ga != gb && (!diag || ra < cb))) passmask &= ~(1u << r);
+                }
+                const int mine = __popc(passmask);
+                int incl = mine;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int yv = __shfl_up(incl, d, 64);
+                    if (lane >= d) incl += yv;
+                }
+                const int total = __shfl(incl, 63, 64);
+                if (total == 0) continue;
+                unsigned long long base = 0;
+                if (lane == 0) {
+                    base = atomicAdd(a.surv_count, (unsigned long long)total);
+                    atomicAdd(&a.info[0].passed, (unsigned long long)total);
+                }
+                base = __shfl(base, 0, 64);
+                unsigned long long idx = base + (unsigned long long)(incl - mine);
+                while (passmask) {
+                    const int r = __ffs(passmask) - 1;
+                    passmask &= passmask - 1;
+                    const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                    const int32_t ga = colA[ra];
+                    if (idx < a.surv_cap) {
+                        int32_t cval = 0;
+#pragma unroll
+                        for (int q = 0; q < 16; ++q)
+                            if (q == r) cval = acc[u][v][q];
+                        Survivor sv;
+                        sv.j = (uint32_t)min(ga, gb);
+                        sv.k = (uint32_t)max(ga, gb);
+                        sv.rep = 0;
+                        sv.s = n32 - 2 * (int32_t)(popA[ra] + popB[cb]) + 4 * cval;
+                        sv.value = (double)sv.s;
+                        sv.ysel = 0;
+                        sv.pad = 0;
+                        a.surv[idx] = sv;
+                    }
+                    ++idx;
+                }
             }
         }
+        lds_barrier();   // colA/colB/popA/popB are rewritten by the next block pair
+    }
 }
+
 
 // ------------------------------------------------------- scan, radix sort --
 
@@ -1332,8 +1390,10 @@ hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStre
 hipError_t launch_brute(const BruteArgs &a, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
-    const uint64_t grid = (a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a);
+    const uint64_t G = (a.ntiles + 7) / 8 * 8;
+    const uint64_t grid = std::min<uint64_t>(G, (uint64_t)a.grid_blocks);
+    hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a, reinterpret_cast<const uint4 *>(a.XC),
+                       reinterpret_cast<const uint4 *>(a.yb));
     return hipGetLastError();
 }
 
