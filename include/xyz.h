@@ -167,6 +167,87 @@ xyz_status xyz_bruteforce(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt,
                           uint32_t flags, const int32_t *colsA, int64_t nA, const int32_t *colsB,
                           int64_t nB, void *stream, xyz_result **out);
 
+/* ---------------------------------------------------- parameter choice --
+ * Section 2.3: a pair of strength gamma (eq. (3); gamma = (1 + s/n)/2 by
+ * eq. (4)) lands in E_l with probability gamma^m, so it is found within L
+ * repetitions with probability eta = 1 - (1 - gamma^m)^L (eq. (9)). */
+
+/* eq. (9). */
+double xyz_eta(double gamma, int32_t m, int64_t L);
+/* eq. (15): the smallest L with 1 - (1 - beta)^L >= eta, beta = gamma^m in (0, 1]; -1 if beta <= 0 or eta
+ * not in (0, 1). */
+int64_t xyz_L_for(double eta, double beta);
+/* The largest m in [0, m_max] with eta(gamma, m, L) >= eta, or -1 (the rule for a request with fixed L). */
+int32_t xyz_m_for_L(double gamma, int64_t L, double eta, int32_t m_max);
+/* eq. (11): M* = argmin over M in [1, m_max] of -(M p + p log p + n S(M)) / log(1 - gamma^M), with
+ * S(M) = total_pairs * mean(gammas^M) estimated from ns sampled strengths (Section 2.3: "estimated by
+ * sampling"); returns -1 on invalid input. */
+int32_t xyz_mstar(double gamma, int64_t n, int64_t p, const double *gammas, int64_t ns, double total_pairs,
+                  int32_t m_max);
+
+/* Strengths of npairs column pairs drawn uniformly (j != k) with SplitMix64(seed): gamma = fraction of rows
+ * with sgn(Y_i) = X~_ij X~_ik, weighted by |Y_i|/||Y||_1 for real Y (the collision probability of one row
+ * draw, Section 3.1).  out: host array of npairs doubles. */
+xyz_status xyz_sample_strengths(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem, int64_t npairs,
+                                uint64_t seed, void *stream, double *out);
+
+#define XYZ_PLAN_XYZ   0
+#define XYZ_PLAN_BRUTE 1
+typedef struct {
+    int32_t method;             /* XYZ_PLAN_XYZ or XYZ_PLAN_BRUTE */
+    int32_t m, L;               /* the xyz parameters (m = 0, L = 1 for brute force) */
+    int32_t mstar;              /* eq. (11) under the paper's cost model, for reference */
+    double predicted_ms;        /* predicted GPU time of the chosen plan */
+    double predicted_recall;    /* eq. (9) at gamma_target (1 for brute force) */
+    double expected_candidates; /* sum over repetitions of E|E_l| (unordered pairs) */
+    double brute_ms;            /* predicted time of the exact search */
+} xyz_plan_info;
+
+/* Autotuner: choose brute force or xyz (m, L) for a search at threshold kappa that must find pairs of
+ * strength >= gamma_target (gamma scale) with probability >= eta_target.  Samples pair strengths to predict
+ * E|E_l| per m, takes L from eq. (15), times short runs of the candidate plans on this X and Y, and picks
+ * the fastest.  flags: XYZ_TWO_SIDED. */
+xyz_status xyz_plan(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
+                    double gamma_target, double eta_target, uint32_t flags, void *stream, xyz_plan_info *out);
+
+/* -------------------------------------------------------------- serving --
+ * A server owns `workers` threads, each with its own context (workspaces) and
+ * HIP stream on the device of ctx.  Requests on resident X (any context of the
+ * same device; X must outlive its requests) wait in one FIFO queue; a free
+ * worker takes the oldest request whose estimated device bytes fit beside the
+ * running ones within hbm_budget_bytes (0: no bound), together with up to
+ * max_batch - 1 queued requests it can share a pass with (same X, m, L, seed,
+ * rep_offset and flags, +-1 Y, no row table: one row draw, projection and
+ * bucket sort serve them all).  Groups on different workers overlap on the
+ * device.  Each result equals the request's stand-alone xyz_search.  A request
+ * larger than the budget runs fewer repetitions per chunk; if one repetition
+ * does not fit, submission fails with XYZ_ENOMEM.  All xyz_serve_* calls are
+ * thread-safe. */
+typedef struct {
+    uint64_t submitted, completed, canceled, failed;
+    uint64_t batches;           /* groups run */
+    int32_t max_batch;          /* largest group */
+    int32_t queued, inflight;   /* requests waiting / running now */
+    uint64_t bytes_inflight;    /* estimated device bytes of running groups */
+    double p50_ms, p99_ms, max_ms;  /* submit-to-completion latency of completed requests */
+} xyz_serve_stats;
+
+xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, int32_t workers, int32_t max_batch,
+                           xyz_server **out);
+/* Queue a search; Y (host memory, format yfmt) and params (including its row table) are copied. */
+xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void *Y, int yfmt, const xyz_params *params,
+                            uint64_t *ticket);
+/* XYZ_EAGAIN while the request is queued or running; otherwise the request's result (or its error, or
+ * XYZ_ECANCELED) is returned once and the ticket is forgotten. */
+xyz_status xyz_serve_poll(xyz_server *s, uint64_t ticket, xyz_result **out);
+/* Like xyz_serve_poll but blocks until the request is finished. */
+xyz_status xyz_serve_wait(xyz_server *s, uint64_t ticket, xyz_result **out);
+/* Cancel a queued request (XYZ_EAGAIN if it is already running). */
+xyz_status xyz_serve_cancel(xyz_server *s, uint64_t ticket);
+xyz_status xyz_serve_stats_get(xyz_server *s, xyz_serve_stats *out);
+/* Cancel queued requests, wait for running ones, free the server and every unclaimed result. */
+xyz_status xyz_serve_stop(xyz_server *s);
+
 int64_t xyz_result_npairs(const xyz_result *r);
 const xyz_pair *xyz_result_pairs(const xyz_result *r);      /* sorted by (j, k), unique */
 int32_t xyz_result_nreps(const xyz_result *r);

@@ -36,7 +36,11 @@ EXPORTS = [
     "xyz_version", "xyz_last_error", "xyz_init", "xyz_fini", "xyz_ctx_bytes", "xyz_x_create", "xyz_x_destroy",
     "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_bruteforce", "xyz_result_npairs",
     "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_free", "xyz_smin",
+    "xyz_eta", "xyz_L_for", "xyz_m_for_L", "xyz_mstar", "xyz_sample_strengths", "xyz_plan",
+    "xyz_serve_start", "xyz_serve_submit", "xyz_serve_poll", "xyz_serve_wait", "xyz_serve_cancel",
+    "xyz_serve_stats_get", "xyz_serve_stop",
 ]
+XYZ_PLAN_XYZ, XYZ_PLAN_BRUTE = 0, 1
 
 
 class XyzError(RuntimeError):
@@ -56,6 +60,19 @@ class xyz_timing(ctypes.Structure):
                 ("total_ms", "pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms",
                  "dedup_ms", "brute_ms")] + [("verify_launches", ctypes.c_int64), ("candidates", ctypes.c_int64),
                                              ("tiles", ctypes.c_int64)]
+
+
+class xyz_plan_info(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("m", ctypes.c_int32), ("L", ctypes.c_int32), ("mstar", ctypes.c_int32),
+                ("predicted_ms", ctypes.c_double), ("predicted_recall", ctypes.c_double),
+                ("expected_candidates", ctypes.c_double), ("brute_ms", ctypes.c_double)]
+
+
+class xyz_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("max_batch", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("inflight", ctypes.c_int32), ("bytes_inflight", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -96,6 +113,19 @@ def lib():
         "xyz_result_timing": (ctypes.POINTER(xyz_timing), [P]),
         "xyz_result_free": (None, [P]),
         "xyz_smin": (I64, [I64, D, ctypes.c_int]),
+        "xyz_eta": (D, [D, I32, I64]),
+        "xyz_L_for": (I64, [D, D]),
+        "xyz_m_for_L": (I32, [D, I64, D, I32]),
+        "xyz_mstar": (I32, [D, I64, I64, P, I64, D, I32]),
+        "xyz_sample_strengths": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, I64, U64, P, P]),
+        "xyz_plan": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, D, D, D, U32, P, ctypes.POINTER(xyz_plan_info)]),
+        "xyz_serve_start": (I32, [P, U64, I32, I32, ctypes.POINTER(P)]),
+        "xyz_serve_submit": (I32, [P, P, P, ctypes.c_int, ctypes.POINTER(xyz_params), ctypes.POINTER(U64)]),
+        "xyz_serve_poll": (I32, [P, U64, ctypes.POINTER(P)]),
+        "xyz_serve_wait": (I32, [P, U64, ctypes.POINTER(P)]),
+        "xyz_serve_cancel": (I32, [P, U64]),
+        "xyz_serve_stats_get": (I32, [P, ctypes.POINTER(xyz_serve_stats)]),
+        "xyz_serve_stop": (I32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -290,6 +320,96 @@ def xyz_bruteforce(ctx, x, Y, kappa: float, colsA=None, colsB=None, two_sided: b
     return _take_result(h)
 
 
+def xyz_eta(gamma: float, m: int, L: int) -> float:
+    return float(lib().xyz_eta(float(gamma), int(m), int(L)))
+
+
+def xyz_L_for(eta: float, beta: float) -> int:
+    return int(lib().xyz_L_for(float(eta), float(beta)))
+
+
+def xyz_m_for_L(gamma: float, L: int, eta: float, m_max: int = XYZ_MAX_M) -> int:
+    return int(lib().xyz_m_for_L(float(gamma), int(L), float(eta), int(m_max)))
+
+
+def xyz_mstar(gamma: float, n: int, p: int, gammas, total_pairs: float, m_max: int = 64) -> int:
+    g = np.ascontiguousarray(gammas, dtype=np.float64)
+    return int(lib().xyz_mstar(float(gamma), int(n), int(p), g.ctypes.data, g.size, float(total_pairs), int(m_max)))
+
+
+def xyz_sample_strengths(ctx, x, Y, npairs: int, seed: int = 0, stream=None) -> np.ndarray:
+    out = np.zeros(int(npairs), dtype=np.float64)
+    ptr, mem, keep = _ptr(Y)
+    _check(lib().xyz_sample_strengths(ctx, x, ptr, _y_format(Y), mem, int(npairs), int(seed) & (2 ** 64 - 1),
+                                      _stream(stream, Y), out.ctypes.data))
+    del keep
+    return out
+
+
+def xyz_plan(ctx, x, Y, kappa: float, gamma_target: float, eta_target: float = 0.95, two_sided: bool = False,
+             stream=None) -> dict:
+    info = xyz_plan_info()
+    ptr, mem, keep = _ptr(Y)
+    _check(lib().xyz_plan(ctx, x, ptr, _y_format(Y), mem, float(kappa), float(gamma_target), float(eta_target),
+                          XYZ_TWO_SIDED if two_sided else 0, _stream(stream, Y), ctypes.byref(info)))
+    del keep
+    return {name: getattr(info, name) for name, _ in xyz_plan_info._fields_}
+
+
+def xyz_serve_start(ctx, hbm_budget_bytes: int = 0, workers: int = 2, max_batch: int = 64):
+    h = ctypes.c_void_p()
+    _check(lib().xyz_serve_start(ctx, int(hbm_budget_bytes), int(workers), int(max_batch), ctypes.byref(h)))
+    return h
+
+
+def xyz_serve_submit(server, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
+                     rep_offset: int = 0, rows=None) -> int:
+    """Queue a search (Y is host memory: numpy array or CPU tensor); returns the ticket."""
+    if _is_torch(Y) and Y.is_cuda:
+        raise ValueError("xyz_serve_submit takes Y in host memory")
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, False)
+    ptr, _, keep = _ptr(Y)
+    t = ctypes.c_uint64()
+    _check(lib().xyz_serve_submit(server, x, ptr, _y_format(Y), ctypes.byref(prm), ctypes.byref(t)))
+    del keep, keep_rows
+    return int(t.value)
+
+
+def xyz_serve_poll(server, ticket: int):
+    """None while the request is pending, else its result dict (raises on error / cancellation)."""
+    h = ctypes.c_void_p()
+    rc = lib().xyz_serve_poll(server, int(ticket), ctypes.byref(h))
+    if rc == XYZ_EAGAIN:
+        return None
+    _check(rc)
+    return _take_result(h)
+
+
+def xyz_serve_wait(server, ticket: int):
+    h = ctypes.c_void_p()
+    _check(lib().xyz_serve_wait(server, int(ticket), ctypes.byref(h)))
+    return _take_result(h)
+
+
+def xyz_serve_cancel(server, ticket: int) -> bool:
+    """True if the request was cancelled (or had finished), False if it is already running."""
+    rc = lib().xyz_serve_cancel(server, int(ticket))
+    if rc == XYZ_EAGAIN:
+        return False
+    _check(rc)
+    return True
+
+
+def xyz_serve_stats_get(server) -> dict:
+    st = xyz_serve_stats()
+    _check(lib().xyz_serve_stats_get(server, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in xyz_serve_stats._fields_}
+
+
+def xyz_serve_stop(server) -> None:
+    _check(lib().xyz_serve_stop(server))
+
+
 class Context:
     """Convenience owner of a context and its resident matrices."""
 
@@ -310,6 +430,12 @@ class Context:
 
     def bruteforce(self, x, Y, kappa, **kw):
         return xyz_bruteforce(self.h, x, Y, kappa, **kw)
+
+    def sample_strengths(self, x, Y, npairs, seed=0, stream=None):
+        return xyz_sample_strengths(self.h, x, Y, npairs, seed=seed, stream=stream)
+
+    def plan(self, x, Y, kappa, gamma_target, eta_target=0.95, two_sided=False, stream=None):
+        return xyz_plan(self.h, x, Y, kappa, gamma_target, eta_target, two_sided=two_sided, stream=stream)
 
     def close(self):
         for x in self._xs:

@@ -6,8 +6,7 @@
 // enqueues the kernels of xyz_kernels.hip.  Every step of the search itself
 // (packing, row sampling, projection, bucket sort, candidate expansion,
 // verification, merging) runs on the GPU.
-#include "xyz.h"
-#include "xyz_internal.h"
+#include "xyz_runtime.h"
 
 #include <algorithm>
 #include <cstdarg>
@@ -21,13 +20,13 @@
 #include <vector>
 
 using namespace xyz;
+using namespace xyz_rt;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-xyz_status fail(xyz_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-xyz_status fail(xyz_status code, const char *fmt, ...)
+xyz_status xyz_rt::fail(xyz_status code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -37,6 +36,8 @@ xyz_status fail(xyz_status code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                                       \
     do {                                                                                                    \
@@ -52,17 +53,6 @@ xyz_status fail(xyz_status code, const char *fmt, ...)
     } while (0)
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
-
-enum Slot {
-    WS_XIN, WS_YIN, WS_YB, WS_YD, WS_CDF, WS_LAST, WS_ERR, WS_ROWS, WS_INFO, WS_KEYS, WS_OFFS, WS_PERM, WS_BASE,
-    WS_TILES, WS_SURV, WS_SURV2, WS_SCNT, WS_SMIN, WS_KAPPA, WS_DKEYS, WS_DVALS, WS_DKEYS2, WS_DVALS2, WS_HIST,
-    WS_HEADS, WS_OUT, WS_NOUT, WS_YCNT, NWS
-};
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
 
 // HIP events around the stages of one call, summed after the final sync.
 struct Timer {
@@ -124,33 +114,6 @@ struct Timer {
 };
 
 }  // namespace
-
-struct xyz_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    uint64_t used = 0;
-    int cu_count = 256;
-    DevBuf ws[NWS];
-};
-
-struct xyz_x {
-    xyz_ctx *ctx = nullptr;
-    int64_t n = 0, p = 0;
-    int fmt = 0;
-    int W32p = 0;
-    int64_t P64 = 0;
-    int64_t nF = 0;
-    uint32_t *XC = nullptr;
-    uint64_t *XR = nullptr;
-    float *XF = nullptr;
-    size_t bytes = 0;
-};
-
-struct xyz_result {
-    std::vector<xyz_pair> pairs;
-    std::vector<xyz_rep_stats> reps;
-    xyz_timing timing{};
-};
 
 namespace {
 
@@ -361,9 +324,27 @@ extern "C" void xyz_x_destroy(xyz_x *x)
 extern "C" int64_t xyz_x_n(const xyz_x *x) { return x ? x->n : 0; }
 extern "C" int64_t xyz_x_p(const xyz_x *x) { return x ? x->p : 0; }
 
-namespace {
+int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m)
+{
+    const int64_t nb = 1ll << m;
+    int64_t chunk = std::min<int64_t>(L, 4096);
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((1ll << 32) - 1) / p));   // u32 positions in perm
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / (8 * p + 4 * (nb + 1))));
+    chunk = std::min<int64_t>(chunk, 65535);                                           // grid y of k_hash
+    if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
+    return std::max<int64_t>(chunk, 1);
+}
 
-xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt)
+void xyz_rt::ws_release(xyz_ctx *c)
+{
+    for (auto &b : c->ws) {
+        dev_free(c, b.p, b.bytes);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+}
+
+xyz_status xyz_rt::validate_params(const xyz_x *x, const xyz_params *P, int yfmt)
 {
     if (!P) return fail(XYZ_EINVAL, "params is NULL");
     if (P->m < 0 || P->m > XYZ_MAX_M) return fail(XYZ_EINVAL, "m=%d out of range [0, %d]", P->m, XYZ_MAX_M);
@@ -383,6 +364,8 @@ xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt)
     }
     return XYZ_OK;
 }
+
+namespace {
 
 size_t y_bytes(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 1 : (yfmt == XYZ_Y_F32 ? 4 : 8)); }
 
@@ -418,8 +401,10 @@ xyz_status pack_ys(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, i
 // One group of searches sharing X, m, L, seed, rep_offset and flags.  With
 // nys > 1 every Y must be +-1 and no row table may be given, so the row draws,
 // projections and bucket sort are shared (Z = Y o X changes only the partner mask).
-xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
-                     const xyz_params *const *Ps, hipStream_t st, xyz_result **outs)
+}  // namespace
+
+xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
+                             const xyz_params *const *Ps, hipStream_t st, xyz_result **outs)
 {
     const double t0 = now_ms();
     const xyz_params &P = *Ps[0];
@@ -465,10 +450,7 @@ xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys,
 
     // ---- repetitions, in chunks
     const int nb = 1 << m;
-    int64_t chunk = std::min<int64_t>(L, 4096);
-    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((1ll << 32) - 1) / p));      // u32 positions
-    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / (8 * p + 4 * (nb + 1))));
-    chunk = std::min<int64_t>(chunk, 65535);
+    const int64_t chunk = chunk_reps(c, L, p, m);
     RepInfo *info = nullptr;
     XYZ_TRY(ws(c, WS_INFO, (size_t)L * nys, &info));
     int32_t *rows = nullptr;
@@ -626,8 +608,6 @@ xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys,
     }
     return XYZ_OK;
 }
-
-}  // namespace
 
 extern "C" xyz_status xyz_search(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem,
                                  const xyz_params *params, void *stream, xyz_result **out)
@@ -851,5 +831,187 @@ extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, 
     timing.total_ms = now_ms() - t0;
     r->timing = timing;
     *out = r;
+    return XYZ_OK;
+}
+
+// ------------------------------------------------------- parameter choice --
+
+extern "C" double xyz_eta(double gamma, int32_t m, int64_t L)
+{
+    if (!(gamma >= 0.0 && gamma <= 1.0) || m < 0 || L < 0) return NAN;
+    return 1.0 - std::pow(1.0 - std::pow(gamma, (double)m), (double)L);
+}
+
+extern "C" int64_t xyz_L_for(double eta, double beta)
+{
+    if (!(eta > 0.0 && eta < 1.0) || !(beta > 0.0) || beta > 1.0) return -1;
+    if (beta >= 1.0) return 1;
+    const double L = std::ceil(std::log(1.0 - eta) / std::log1p(-beta));
+    int64_t Li = (int64_t)std::max(1.0, L);
+    // guard against rounding on either side of the exact boundary: 1 - (1 - beta)^L >= eta
+    auto found = [beta](int64_t l) { return 1.0 - std::pow(1.0 - beta, (double)l); };
+    while (Li > 1 && found(Li - 1) >= eta) --Li;
+    while (found(Li) < eta) ++Li;
+    return Li;
+}
+
+extern "C" int32_t xyz_m_for_L(double gamma, int64_t L, double eta, int32_t m_max)
+{
+    if (!(gamma > 0.0 && gamma <= 1.0) || L < 1 || !(eta > 0.0 && eta < 1.0) || m_max < 0) return -1;
+    int32_t best = -1;
+    for (int32_t m = 0; m <= m_max; ++m)
+        if (xyz_eta(gamma, m, L) >= eta) best = m;
+    return best;
+}
+
+extern "C" int32_t xyz_mstar(double gamma, int64_t n, int64_t p, const double *gammas, int64_t ns,
+                             double total_pairs, int32_t m_max)
+{
+    if (!(gamma > 0.0 && gamma < 1.0) || n < 1 || p < 2 || !gammas || ns < 1 || m_max < 1) return -1;
+    int32_t best = -1;
+    double best_v = INFINITY;
+    const double lp = std::log((double)p);
+    for (int32_t M = 1; M <= m_max; ++M) {
+        double acc = 0.0;
+        for (int64_t q = 0; q < ns; ++q) acc += std::pow(gammas[q], (double)M);
+        const double S = total_pairs * acc / (double)ns;
+        const double b = std::pow(gamma, (double)M);
+        const double cost = (double)M * p + p * lp + (double)n * S;
+        const double v = b >= 1.0 ? cost : -cost / std::log1p(-b);
+        if (v < best_v) {
+            best_v = v;
+            best = M;
+        }
+    }
+    return best;
+}
+
+extern "C" xyz_status xyz_sample_strengths(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem,
+                                           int64_t npairs, uint64_t seed, void *stream, double *out)
+{
+    if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
+    if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    if (npairs < 0) return fail(XYZ_EINVAL, "npairs < 0");
+    if (x->p < 2) return fail(XYZ_EINVAL, "X has fewer than two columns");
+    if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
+    if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
+    if (npairs == 0) return XYZ_OK;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *yb = nullptr;
+    double *yd = nullptr;
+    int *err = nullptr;
+    const void *ys[1] = {Y};
+    XYZ_TRY(pack_ys(c, x, 1, ys, yfmt, mem, st, &yb, &yd, &err));
+    XYZ_TRY(check_err_flag(err, st));
+    double *g = nullptr;
+    XYZ_TRY(ws(c, WS_CDF, (size_t)npairs, &g));
+    HIP_TRY(launch_pair_strengths(x->XC, x->W32p, yb, yd, x->n, x->p, yfmt != XYZ_Y_I8_PM1 ? 1 : 0, seed, npairs, g, st));
+    HIP_TRY(hipMemcpyAsync(out, g, sizeof(double) * npairs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return XYZ_OK;
+}
+
+extern "C" xyz_status xyz_plan(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
+                               double gamma_target, double eta_target, uint32_t flags, void *stream,
+                               xyz_plan_info *out)
+{
+    if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
+    if (!(gamma_target > 0.0 && gamma_target <= 1.0)) return fail(XYZ_EINVAL, "gamma_target must be in (0, 1]");
+    if (!(eta_target > 0.0 && eta_target < 1.0)) return fail(XYZ_EINVAL, "eta_target must be in (0, 1)");
+    if (!std::isfinite(kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
+    if (flags & ~(uint32_t)XYZ_TWO_SIDED) return fail(XYZ_EINVAL, "unknown flags 0x%x", flags);
+    const int64_t n = x->n, p = x->p;
+    if (p < 2) return fail(XYZ_EINVAL, "X has fewer than two columns");
+    const double P = (double)p * (double)(p - 1) / 2.0;
+    const bool two = (flags & XYZ_TWO_SIDED) != 0;
+    // 1. sampled strengths -> expected candidates per repetition for each m
+    const int64_t ns = std::min<int64_t>(1 << 16, (int64_t)std::max(2.0, P));
+    std::vector<double> g(ns);
+    XYZ_TRY(xyz_sample_strengths(c, x, Y, yfmt, mem, ns, 0x5eed5eedull, stream, g.data()));
+    std::vector<double> cand(MAX_M_LDS + 1, 0.0);
+    for (int m = 0; m <= MAX_M_LDS; ++m) {
+        double acc = 0.0;
+        for (double gq : g) acc += std::pow(gq, (double)m) + (two && m > 0 ? std::pow(1.0 - gq, (double)m) : 0.0);
+        cand[m] = m == 0 ? P : P * acc / (double)ns;
+    }
+    xyz_plan_info best{};
+    best.mstar = xyz_mstar(std::min(gamma_target, 1.0 - 1e-12), n, p, g.data(), ns, (double)p * (double)p, 64);
+    // 2. brute force: time a square block of up to 4096 x 4096 columns
+    const int64_t nb = std::min<int64_t>(p, 4096);
+    std::vector<int32_t> cols(nb);
+    for (int64_t q = 0; q < nb; ++q) cols[q] = (int32_t)q;
+    double brute_ms = INFINITY;
+    {
+        xyz_result *r = nullptr;
+        const bool real = x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1;
+        if (!real) {
+            for (int rep = 0; rep < 2; ++rep) {
+                XYZ_TRY(xyz_bruteforce(c, x, Y, yfmt, mem, 1.0, XYZ_PROFILE, cols.data(), nb, cols.data(), nb, stream, &r));
+                const double ms = r->timing.brute_ms;
+                xyz_result_free(r);
+                brute_ms = ms * P / ((double)nb * (double)nb);
+            }
+        } else {
+            xyz_params P0{};
+            P0.m = 0;
+            P0.L = 1;
+            P0.kappa = 1e300;
+            P0.flags = XYZ_PROFILE;
+            // real data: exhaustive search on the first nb columns is not available through
+            // column lists; time the exhaustive search on the whole X only when it is small
+            if (p <= 8192) {
+                XYZ_TRY(xyz_search(c, x, Y, yfmt, mem, &P0, stream, &r));
+                brute_ms = r->timing.total_ms;
+                xyz_result_free(r);
+            }
+        }
+    }
+    best.method = XYZ_PLAN_BRUTE;
+    best.m = 0;
+    best.L = 1;
+    best.predicted_ms = brute_ms;
+    best.predicted_recall = 1.0;
+    best.expected_candidates = P;
+    best.brute_ms = brute_ms;
+    // 3. xyz: L from eq. (15); rank m by the analytic work, time the most promising ones
+    struct Cand {
+        int m;
+        int64_t L;
+        double work;
+    };
+    std::vector<Cand> cs;
+    for (int m = 1; m <= MAX_M_LDS; ++m) {
+        const int64_t L = xyz_L_for(eta_target, std::pow(gamma_target, (double)m));
+        if (L < 1 || L > 2000000) continue;
+        const double work = (double)L * (cand[m] * std::ceil(n / 32.0) * 2.0 / 1.5e13 + (double)p * 2e-10);
+        cs.push_back({m, L, work});
+    }
+    std::sort(cs.begin(), cs.end(), [](const Cand &a, const Cand &b) { return a.work < b.work; });
+    if (cs.size() > 4) cs.resize(4);
+    for (const Cand &cd : cs) {
+        xyz_params Pc{};
+        Pc.m = cd.m;
+        Pc.L = (int32_t)std::min<int64_t>(cd.L, 32);
+        Pc.kappa = kappa;
+        Pc.seed = 0x9a1ull;
+        Pc.flags = XYZ_PROFILE | (two ? XYZ_TWO_SIDED : 0);
+        xyz_result *r = nullptr;
+        XYZ_TRY(xyz_search(c, x, Y, yfmt, mem, &Pc, stream, &r));
+        const xyz_timing &t = r->timing;
+        const double per_rep = (t.sample_ms + t.hash_ms + t.bucket_ms + t.tiles_ms + t.verify_ms) / Pc.L;
+        const double fixed = t.pack_ms + t.dedup_ms;
+        xyz_result_free(r);
+        const double pred = fixed + per_rep * (double)cd.L;
+        if (pred < best.predicted_ms) {
+            best.method = XYZ_PLAN_XYZ;
+            best.m = cd.m;
+            best.L = (int32_t)std::min<int64_t>(cd.L, 0x7fffffff);
+            best.predicted_ms = pred;
+            best.predicted_recall = xyz_eta(gamma_target, cd.m, cd.L);
+            best.expected_candidates = cand[cd.m] * (double)cd.L;
+        }
+    }
+    *out = best;
     return XYZ_OK;
 }

@@ -153,6 +153,15 @@ struct BruteArgs {
 constexpr int BF_TILE = 256;
 hipError_t launch_brute(const BruteArgs &a, hipStream_t st);
 
+// Collision strengths of uniformly drawn column pairs (for the planner).
+// Pair q: draws u = SplitMix64(seed, 2q+1), v = SplitMix64(seed, 2q+2);
+// j = floor(u p / 2^64), k = floor(v (p-1) / 2^64), k += (k >= j).  gamma[q] is
+// the probability that one sampled row agrees: the fraction of rows with
+// sgn(Y_i) = X~_ij X~_ik, weighted by |Y_i| / ||Y||_1 for real Y.
+hipError_t launch_pair_strengths(const uint32_t *XC, int W32p, const uint32_t *yb, const double *yd, int64_t n,
+                                 int64_t p, int real_y, uint64_t seed, int64_t npairs, double *gamma,
+                                 hipStream_t st);
+
 // Radix histogram scratch size (u32 entries) for S items.
 size_t radix_hist_entries(uint64_t S);
 // Set kernel attributes (large dynamic LDS); called once per device.

@@ -1069,6 +1069,46 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint4 *__restr
 }
 
 
+// ---------------------------------------------------------------- planner --
+
+// One wave per pair.  Binary Y: gamma = 1 - popcount(y ^ x_j ^ x_k) / n.
+// Real Y: gamma = sum of |Y_i| over agreeing rows / ||Y||_1 (the collision
+// probability of one |Y|-weighted row draw, Section 3.1).
+__global__ __launch_bounds__(256) void k_pair_strengths(const uint32_t *__restrict__ XC, int W32p,
+                                                        const uint32_t *__restrict__ yb,
+                                                        const double *__restrict__ yd, int64_t n, int64_t p,
+                                                        int real_y, uint64_t seed, int64_t npairs,
+                                                        double *__restrict__ gamma)
+{
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= npairs) return;
+    const unsigned lane = lane_id();
+    const uint64_t u = splitmix64_at(seed, 2ull * q + 1), v = splitmix64_at(seed, 2ull * q + 2);
+    const int64_t j = (int64_t)__umul64hi(u, (uint64_t)p);
+    int64_t k = (int64_t)__umul64hi(v, (uint64_t)(p - 1));
+    k += (k >= j) ? 1 : 0;
+    const uint32_t *xj = XC + j * (int64_t)W32p, *xk = XC + k * (int64_t)W32p;
+    if (!real_y) {
+        uint32_t c = 0;
+        for (int w = lane; w < W32p; w += 64) c += __popc(yb[w] ^ xj[w] ^ xk[w]);
+        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+        if (lane == 0) gamma[q] = 1.0 - (double)c / (double)n;
+        return;
+    }
+    double agree = 0.0, tot = 0.0;
+    for (int64_t i = lane; i < n; i += 64) {
+        const double a = fabs(yd[i]);
+        const uint32_t bit = ((yb[i >> 5] ^ xj[i >> 5] ^ xk[i >> 5]) >> (i & 31)) & 1u;
+        tot += a;
+        if (!bit) agree += a;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        agree += __shfl_xor(agree, d, 64);
+        tot += __shfl_xor(tot, d, 64);
+    }
+    if (lane == 0) gamma[q] = tot > 0.0 ? agree / tot : 0.0;
+}
+
 // ------------------------------------------------------- scan, radix sort --
 
 constexpr int RS_NT = 256, RS_IPT = 8, RS_TILE = RS_NT * RS_IPT;
@@ -1394,6 +1434,16 @@ hipError_t launch_brute(const BruteArgs &a, hipStream_t st)
     const uint64_t grid = std::min<uint64_t>(G, (uint64_t)a.grid_blocks);
     hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a, reinterpret_cast<const uint4 *>(a.XC),
                        reinterpret_cast<const uint4 *>(a.yb));
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_strengths(const uint32_t *XC, int W32p, const uint32_t *yb, const double *yd, int64_t n,
+                                 int64_t p, int real_y, uint64_t seed, int64_t npairs, double *gamma,
+                                 hipStream_t st)
+{
+    if (npairs <= 0 || p < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_strengths, dim3(grid1((uint64_t)npairs, 4)), dim3(256), 0, st, XC, W32p, yb, yd, n, p,
+                       real_y, seed, npairs, gamma);
     return hipGetLastError();
 }
 

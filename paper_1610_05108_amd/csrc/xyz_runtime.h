@@ -1,0 +1,67 @@
+// xyz_runtime.h -- host-runtime internals shared by the libxyz sources (not part of the ABI).
+#pragma once
+#include "xyz.h"
+#include "xyz_internal.h"
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace xyz_rt {
+
+enum Slot {
+    WS_XIN, WS_YIN, WS_YB, WS_YD, WS_CDF, WS_LAST, WS_ERR, WS_ROWS, WS_INFO, WS_KEYS, WS_OFFS, WS_PERM, WS_BASE,
+    WS_TILES, WS_SURV, WS_SURV2, WS_SCNT, WS_SMIN, WS_KAPPA, WS_DKEYS, WS_DVALS, WS_DKEYS2, WS_DVALS2, WS_HIST,
+    WS_HEADS, WS_OUT, WS_NOUT, WS_YCNT, NWS
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace xyz_rt
+
+struct xyz_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    int cu_count = 256;
+    int64_t max_chunk = 0;   // repetitions per chunk (0: the default bound); the server lowers it to fit its budget
+    xyz_rt::DevBuf ws[xyz_rt::NWS];
+};
+
+struct xyz_x {
+    xyz_ctx *ctx = nullptr;
+    int64_t n = 0, p = 0;
+    int fmt = 0;
+    int W32p = 0;
+    int64_t P64 = 0;
+    int64_t nF = 0;
+    uint32_t *XC = nullptr;
+    uint64_t *XR = nullptr;
+    float *XF = nullptr;
+    size_t bytes = 0;
+};
+
+struct xyz_result {
+    std::vector<xyz_pair> pairs;
+    std::vector<xyz_rep_stats> reps;
+    xyz_timing timing{};
+};
+
+namespace xyz_rt {
+
+// Sets the thread's last error and returns code.
+xyz_status fail(xyz_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt);
+// Searches sharing X, m, L, seed, rep_offset and flags (nys > 1 requires +-1 Y and no row table).
+// X may belong to another context on the same device.
+xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
+                     const xyz_params *const *Ps, hipStream_t st, xyz_result **outs);
+// Repetitions per chunk for p columns and 2^m buckets under the context's limits.
+int64_t chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m);
+// Frees every workspace of the context.
+void ws_release(xyz_ctx *c);
+
+}  // namespace xyz_rt

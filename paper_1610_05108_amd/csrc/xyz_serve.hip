@@ -1,0 +1,342 @@
+// xyz_serve.hip -- serving loop of libxyz (xyz_serve_* in include/xyz.h).
+//
+// Requests arrive from any thread and wait in one FIFO queue.  Each worker
+// thread owns a context (its own workspaces) and a HIP stream on the server's
+// device.  A free worker takes the oldest request that fits the memory budget
+// together with every queued request it can share a pass with (same resident
+// X, m, L, seed, first repetition and flags, +-1 responses, no row table:
+// these share the row draws, projections and bucket sort, Section 2.2), runs
+// them as one group, and publishes each result.  Workers run concurrently, so
+// groups overlap on the device.  A request's result never depends on what it
+// was grouped with: every per-response quantity is computed from its own Y.
+#include "xyz_runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace xyz_rt;
+
+namespace {
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    const xyz_x *x = nullptr;
+    std::vector<uint8_t> y;      // host copy of Y
+    int yfmt = 0;
+    xyz_params params{};
+    std::vector<int32_t> rows;   // host copy of the row table, if any
+    double t_submit = 0.0;
+    uint64_t bytes = 0;          // estimated device bytes while running
+    int64_t chunk = 0;           // repetitions per chunk that keep it within budget
+    bool running = false, done = false, canceled = false;
+    xyz_status status = XYZ_OK;
+    xyz_result *result = nullptr;
+};
+
+size_t y_size(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 1 : (yfmt == XYZ_Y_F32 ? 4 : 8)); }
+
+// Device bytes of one search with `chunk` repetitions per chunk: keys and
+// permutation (8p per repetition), bucket offsets, the tile list (about one
+// 16-byte tile per 24 x 24 candidates, at least p/24 per repetition), the
+// initial survivor buffer and merge scratch, and packed Y.
+uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk)
+{
+    const double p = (double)x->p, nb = std::ldexp(1.0, P.m);
+    const double cand = p * (p - 1) / 2 / nb;
+    const double tiles = std::max(p / 24.0, cand / 576.0);
+    const double per_rep = 8 * p + 4 * (nb + 1) + 16 * tiles + 64;
+    const double fixed = (double)(1 << 16) * 32 * 2 + (double)x->W32p * 4 + (double)x->nF * 8 + (double)P.L * 48;
+    return (uint64_t)(per_rep * (double)chunk + fixed);
+}
+
+bool same_group(const Request &a, const Request &b)
+{
+    return a.x == b.x && a.yfmt == XYZ_Y_I8_PM1 && b.yfmt == XYZ_Y_I8_PM1 && a.rows.empty() && b.rows.empty() &&
+           a.params.m == b.params.m && a.params.L == b.params.L && a.params.seed == b.params.seed &&
+           a.params.rep_offset == b.params.rep_offset && a.params.flags == b.params.flags && a.chunk == b.chunk;
+}
+
+}  // namespace
+
+struct xyz_server {
+    int device = 0;
+    uint64_t budget = 0;
+    int max_batch = 64;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, Request *> reqs;
+    std::vector<std::thread> threads;
+    std::vector<xyz_ctx *> wctx;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    uint64_t bytes_inflight = 0;
+    int inflight = 0;
+    xyz_serve_stats st{};
+    std::vector<double> lat;
+};
+
+namespace {
+
+void worker_loop(xyz_server *s, int w)
+{
+    (void)hipSetDevice(s->device);
+    hipStream_t stream = nullptr;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    xyz_ctx *ctx = s->wctx[w];
+    for (;;) {
+        std::vector<Request *> batch;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [s] {
+                if (s->stopping) return true;
+                if (s->queue.empty()) return false;
+                const Request *h = s->queue.front();
+                return s->inflight == 0 || s->budget == 0 || s->bytes_inflight + h->bytes <= s->budget;
+            });
+            if (s->stopping) break;
+            Request *h = s->queue.front();
+            s->queue.pop_front();
+            batch.push_back(h);
+            uint64_t bytes = h->bytes;
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->max_batch;) {
+                Request *r = *it;
+                // a group shares its workspace: extra members add only their response buffers
+                if (same_group(*h, *r)) {
+                    batch.push_back(r);
+                    it = s->queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            for (Request *r : batch) r->running = true;
+            s->bytes_inflight += bytes;
+            s->inflight += (int)batch.size();
+            s->st.batches += 1;
+            s->st.max_batch = std::max<int32_t>(s->st.max_batch, (int32_t)batch.size());
+        }
+        std::vector<const void *> ys;
+        std::vector<const xyz_params *> ps;
+        for (Request *r : batch) {
+            ys.push_back(r->y.data());
+            r->params.rows = r->rows.empty() ? nullptr : r->rows.data();
+            ps.push_back(&r->params);
+        }
+        std::vector<xyz_result *> outs(batch.size(), nullptr);
+        ctx->max_chunk = batch[0]->chunk;
+        const xyz_status rc = run_group(ctx, batch[0]->x, (int)batch.size(), ys.data(), batch[0]->yfmt,
+                                        XYZ_MEM_HOST, ps.data(), stream, outs.data());
+        if (s->budget && ctx->used > s->budget) ws_release(ctx);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            const double t = now_ms();
+            for (size_t q = 0; q < batch.size(); ++q) {
+                Request *r = batch[q];
+                r->running = false;
+                r->done = true;
+                r->status = rc;
+                r->result = rc == XYZ_OK ? outs[q] : nullptr;
+                if (rc == XYZ_OK) {
+                    s->st.completed += 1;
+                    s->lat.push_back(t - r->t_submit);
+                } else {
+                    s->st.failed += 1;
+                    if (outs[q]) xyz_result_free(outs[q]);
+                }
+            }
+            s->bytes_inflight -= batch[0]->bytes;
+            s->inflight -= (int)batch.size();
+        }
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace
+
+extern "C" xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, int32_t workers, int32_t max_batch,
+                                      xyz_server **out)
+{
+    if (!ctx || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (workers < 1 || workers > 16) return fail(XYZ_EINVAL, "workers=%d out of range [1, 16]", workers);
+    if (max_batch < 1 || max_batch > 255) return fail(XYZ_EINVAL, "max_batch=%d out of range [1, 255]", max_batch);
+    xyz_server *s = new xyz_server();
+    s->device = ctx->device;
+    s->budget = hbm_budget_bytes;
+    s->max_batch = max_batch;
+    for (int w = 0; w < workers; ++w) {
+        xyz_ctx *c = nullptr;
+        const xyz_status rc = xyz_init(ctx->device, 0, &c);
+        if (rc != XYZ_OK) {
+            for (auto *q : s->wctx) xyz_fini(q);
+            delete s;
+            return rc;
+        }
+        s->wctx.push_back(c);
+    }
+    for (int w = 0; w < workers; ++w) s->threads.emplace_back(worker_loop, s, w);
+    *out = s;
+    return XYZ_OK;
+}
+
+extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void *Y, int yfmt,
+                                       const xyz_params *params, uint64_t *ticket)
+{
+    if (!s || !x || !Y || !params || !ticket) return fail(XYZ_EINVAL, "NULL argument");
+    if (x->ctx->device != s->device) return fail(XYZ_EINVAL, "X lives on another device");
+    {
+        const xyz_status v = validate_params(x, params, yfmt);
+        if (v != XYZ_OK) return v;
+    }
+    Request *r = new Request();
+    r->x = x;
+    r->yfmt = yfmt;
+    r->y.resize(y_size(yfmt, x->n));
+    std::memcpy(r->y.data(), Y, r->y.size());
+    r->params = *params;
+    if (params->rows) r->rows.assign(params->rows, params->rows + (size_t)params->L * params->m);
+    r->params.rows = nullptr;
+    // repetitions per chunk: as many as the budget allows (at least one)
+    xyz_ctx probe{};
+    int64_t chunk = chunk_reps(&probe, params->L, x->p, params->m);
+    if (s->budget) {
+        while (chunk > 1 && estimate_bytes(x, r->params, chunk) > s->budget) chunk = (chunk + 1) / 2;
+        if (estimate_bytes(x, r->params, chunk) > s->budget) {
+            delete r;
+            return fail(XYZ_ENOMEM, "request needs about %llu bytes even one repetition at a time, budget %llu",
+                        (unsigned long long)estimate_bytes(x, *params, 1), (unsigned long long)s->budget);
+        }
+    }
+    r->chunk = chunk;
+    r->bytes = estimate_bytes(x, r->params, chunk);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) {
+            delete r;
+            return fail(XYZ_ECANCELED, "server is stopping");
+        }
+        r->ticket = s->next_ticket++;
+        r->t_submit = now_ms();
+        s->reqs[r->ticket] = r;
+        s->queue.push_back(r);
+        s->st.submitted += 1;
+        *ticket = r->ticket;
+    }
+    s->cv_work.notify_one();
+    return XYZ_OK;
+}
+
+namespace {
+
+// Hands out a finished request's outcome and forgets the ticket (lock held).
+xyz_status claim(xyz_server *s, Request *r, xyz_result **out)
+{
+    xyz_status rc = r->canceled ? fail(XYZ_ECANCELED, "request %llu was cancelled", (unsigned long long)r->ticket)
+                                : r->status;
+    if (rc == XYZ_OK) *out = r->result;
+    else if (r->status != XYZ_OK && !r->canceled) fail(r->status, "request %llu failed", (unsigned long long)r->ticket);
+    s->reqs.erase(r->ticket);
+    delete r;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" xyz_status xyz_serve_poll(xyz_server *s, uint64_t ticket, xyz_result **out)
+{
+    if (!s || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(XYZ_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second->done) return XYZ_EAGAIN;
+    return claim(s, it->second, out);
+}
+
+extern "C" xyz_status xyz_serve_wait(xyz_server *s, uint64_t ticket, xyz_result **out)
+{
+    if (!s || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(XYZ_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    s->cv_done.wait(lk, [r] { return r->done; });
+    return claim(s, r, out);
+}
+
+extern "C" xyz_status xyz_serve_cancel(xyz_server *s, uint64_t ticket)
+{
+    if (!s) return fail(XYZ_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(XYZ_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    if (r->done) return XYZ_OK;
+    if (r->running) return XYZ_EAGAIN;
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+    r->canceled = true;
+    r->done = true;
+    s->st.canceled += 1;
+    s->cv_done.notify_all();
+    return XYZ_OK;
+}
+
+extern "C" xyz_status xyz_serve_stats_get(xyz_server *s, xyz_serve_stats *out)
+{
+    if (!s || !out) return fail(XYZ_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    out->queued = (int32_t)s->queue.size();
+    out->inflight = s->inflight;
+    out->bytes_inflight = s->bytes_inflight;
+    if (!s->lat.empty()) {
+        std::vector<double> v = s->lat;
+        std::sort(v.begin(), v.end());
+        auto q = [&v](double f) { return v[std::min(v.size() - 1, (size_t)std::floor(f * (double)(v.size() - 1) + 0.5))]; };
+        out->p50_ms = q(0.50);
+        out->p99_ms = q(0.99);
+        out->max_ms = v.back();
+    }
+    return XYZ_OK;
+}
+
+extern "C" xyz_status xyz_serve_stop(xyz_server *s)
+{
+    if (!s) return fail(XYZ_EINVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        for (Request *r : s->queue) {
+            r->canceled = true;
+            r->done = true;
+            s->st.canceled += 1;
+        }
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+    for (auto &t : s->threads) t.join();
+    for (auto &kv : s->reqs) {
+        if (kv.second->result) xyz_result_free(kv.second->result);
+        delete kv.second;
+    }
+    for (auto *c : s->wctx) xyz_fini(c);
+    delete s;
+    return XYZ_OK;
+}

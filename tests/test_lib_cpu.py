@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "xyz.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(xyz_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(xyz_[A-Za-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_function():
@@ -56,3 +56,38 @@ def test_init_without_gpu_fails_cleanly():
         pass
     with pytest.raises(xyz.XyzError):
         xyz.xyz_init(0)
+
+
+# ------------------------------------------------ parameter choice (host) --
+from oracle import theory  # noqa: E402
+
+
+@pytest.mark.parametrize("gamma,m,L", [(0.85, 21, 100), (0.6, 12, 200), (0.55, 0, 3), (1.0, 7, 1), (0.0, 3, 5)])
+def test_eta_matches_closed_form(gamma, m, L):
+    assert abs(xyz.xyz_eta(gamma, m, L) - theory.eta(gamma, m, L)) < 1e-12
+
+
+def test_L_for_matches_oracle():
+    for eta in (0.5, 0.9, 0.95, 0.99, 0.999):
+        for beta in (1.0, 0.5, 0.1, 1e-2, 1e-4, 3.7e-7):
+            assert xyz.xyz_L_for(eta, beta) == theory.L_for(eta, beta), (eta, beta)
+    assert xyz.xyz_L_for(0.95, 0.0) == -1 and xyz.xyz_L_for(1.0, 0.5) == -1
+
+
+def test_m_for_L_is_the_largest_admissible():
+    for gamma in (0.55, 0.575, 0.6, 0.8):
+        for L in (1, 50, 200, 500):
+            m = xyz.xyz_m_for_L(gamma, L, 0.95, 30)
+            ok = [mm for mm in range(31) if theory.eta(gamma, mm, L) >= 0.95]
+            assert m == (max(ok) if ok else -1)
+    # the serving rule of kappa = 0.15 (gamma = 0.575): 5 / 7 / 9 rows for L = 50 / 200 / 500
+    assert [xyz.xyz_m_for_L(0.575, L, 0.95, 30) for L in (50, 200, 500)] == [5, 7, 9]
+
+
+def test_mstar_matches_oracle():
+    r = np.random.default_rng(1)
+    for n, p in ((859, 687_253), (2000, 100_000), (1000, 20_000)):
+        g = np.clip(r.normal(0.5, 0.02 + 0.01 * r.random(), size=4000), 0, 1)
+        for gamma in (0.6, 0.75, 0.85, 0.95):
+            total = float(p) * p
+            assert xyz.xyz_mstar(gamma, n, p, g, total) == theory.M_star(gamma, n, p, g, total, M_max=64)

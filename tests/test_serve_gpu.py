@@ -1,0 +1,137 @@
+"""GPU checks of the serving loop: results in the mix equal stand-alone searches."""
+import threading
+
+import numpy as np
+import pytest
+
+import synthgen
+import paper_1610_05108_amd as xyz
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = xyz.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def shared(ctx):
+    XT, _ = synthgen.genotype(500, 3000, seed=31)
+    x = ctx.x_create(XT)
+    return XT, x
+
+
+def _requests(XT, count, seed):
+    r = np.random.default_rng(seed)
+    n = XT.shape[1]
+    reqs = []
+    for q in range(count):
+        kind = q % 6
+        if kind == 5:
+            Y = (XT[q].astype(np.float64) * XT[q + 7] + r.standard_normal(n)).astype(np.float32)
+        else:
+            Y = np.where(r.random(n) < 0.45, 1, -1).astype(np.int8)
+        kw = dict(m=6 if kind < 3 else 8, L=6 if kind % 2 == 0 else 9, kappa=0.1 + 0.01 * (q % 4), seed=q % 2)
+        if kind == 4:
+            kw["two_sided"] = True
+        if kind == 3:
+            kw["rows"] = synthgen.rows_table(n, kw["L"], kw["m"], seed=q)
+        reqs.append((Y, kw))
+    return reqs
+
+
+def _same(a, b):
+    assert np.array_equal(a["pairs"], b["pairs"])
+    assert np.array_equal(a["reps"], b["reps"])
+
+
+def test_results_in_the_mix_equal_standalone(ctx, shared):
+    XT, x = shared
+    reqs = _requests(XT, 18, seed=1)
+    srv = xyz.xyz_serve_start(ctx.h, 0, workers=3, max_batch=8)
+    try:
+        tickets = [xyz.xyz_serve_submit(srv, x, Y, **kw) for Y, kw in reqs]
+        outs = [xyz.xyz_serve_wait(srv, t) for t in tickets]
+        st = xyz.xyz_serve_stats_get(srv)
+    finally:
+        xyz.xyz_serve_stop(srv)
+    for (Y, kw), o in zip(reqs, outs):
+        _same(o, ctx.search(x, Y, **kw))
+    assert st["completed"] == 18 and st["failed"] == 0
+    assert st["batches"] < 18 and st["max_batch"] > 1          # compatible requests were grouped
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+
+
+def test_tight_budget_serialises_but_keeps_results(ctx, shared):
+    XT, x = shared
+    reqs = _requests(XT, 8, seed=2)
+    # room for one small request at a time: each request runs in small chunks
+    srv = xyz.xyz_serve_start(ctx.h, 12 << 20, workers=2, max_batch=1)
+    try:
+        tickets = [xyz.xyz_serve_submit(srv, x, Y, **kw) for Y, kw in reqs]
+        outs = [xyz.xyz_serve_wait(srv, t) for t in tickets]
+        st = xyz.xyz_serve_stats_get(srv)
+    finally:
+        xyz.xyz_serve_stop(srv)
+    for (Y, kw), o in zip(reqs, outs):
+        _same(o, ctx.search(x, Y, **kw))
+    assert st["batches"] == 8 and st["bytes_inflight"] == 0
+
+
+def test_request_larger_than_budget_is_rejected(ctx, shared):
+    XT, x = shared
+    srv = xyz.xyz_serve_start(ctx.h, 4096, workers=1)
+    try:
+        with pytest.raises(xyz.XyzError) as e:
+            xyz.xyz_serve_submit(srv, x, np.ones(XT.shape[1], dtype=np.int8), m=5, L=3, kappa=0.1)
+        assert e.value.code == xyz.XYZ_ENOMEM
+    finally:
+        xyz.xyz_serve_stop(srv)
+
+
+def test_cancel_queued_requests(ctx, shared):
+    XT, x = shared
+    reqs = _requests(XT, 12, seed=3)
+    srv = xyz.xyz_serve_start(ctx.h, 0, workers=1, max_batch=1)
+    try:
+        tickets = [xyz.xyz_serve_submit(srv, x, Y, **kw) for Y, kw in reqs]
+        cancelled = [t for t in tickets[6:] if xyz.xyz_serve_cancel(srv, t)]
+        for t in tickets:
+            if t in cancelled:
+                with pytest.raises(xyz.XyzError) as e:
+                    xyz.xyz_serve_wait(srv, t)
+                assert e.value.code == xyz.XYZ_ECANCELED
+            else:
+                xyz.xyz_serve_wait(srv, t)
+        assert len(cancelled) >= 3
+    finally:
+        xyz.xyz_serve_stop(srv)
+
+
+def test_concurrent_submitters_and_polling(ctx, shared):
+    XT, x = shared
+    reqs = _requests(XT, 16, seed=4)
+    srv = xyz.xyz_serve_start(ctx.h, 0, workers=2, max_batch=16)
+    got = {}
+    try:
+        def client(lo, hi):
+            ts = [(q, xyz.xyz_serve_submit(srv, x, reqs[q][0], **reqs[q][1])) for q in range(lo, hi)]
+            for q, t in ts:
+                while True:
+                    o = xyz.xyz_serve_poll(srv, t)
+                    if o is not None:
+                        got[q] = o
+                        break
+        th = [threading.Thread(target=client, args=(4 * i, 4 * i + 4)) for i in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+    finally:
+        xyz.xyz_serve_stop(srv)
+    assert sorted(got) == list(range(16))
+    for q, (Y, kw) in enumerate(reqs):
+        _same(got[q], ctx.search(x, Y, **kw))
