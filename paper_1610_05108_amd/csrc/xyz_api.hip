@@ -460,7 +460,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     XYZ_TRY(ws(c, WS_KEYS, (size_t)chunk * p, &keys));
     XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
     XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
-    XYZ_TRY(ws(c, WS_BASE, (size_t)chunk * nys + 1, &base));
+    XYZ_TRY(ws(c, WS_BASE, 2 * ((size_t)chunk * nys + 1), &base));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
     HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
     uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
@@ -494,16 +494,19 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             tm.end();
             tm.begin(4);
             HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
-            unsigned long long ntiles = 0;
+            // large-tile total at base[R nys], small-tile total at base[2 R nys + 1]
+            unsigned long long ntiles = 0, nsmall = 0;
             HIP_TRY(hipMemcpyAsync(&ntiles, base + (size_t)R * nys, sizeof ntiles, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * (size_t)R * nys + 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             Tile *tiles = nullptr;
-            XYZ_TRY(ws(c, WS_TILES, (size_t)ntiles, &tiles));
+            XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall), &tiles));
             HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, base, tiles, st));
             tm.end();
             VerifyArgs va{};
             va.tiles = tiles;
             va.ntiles = ntiles;
+            va.nsmall = nsmall;
             va.perm = perm;
             va.XC = x->XC;
             va.W32p = x->W32p;
@@ -521,13 +524,13 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             va.surv_count = scnt;
             va.surv_cap = surv_cap;
             va.info = cinfo;
-            const int g = (int)std::min<unsigned long long>(ntiles ? ntiles : 1, (unsigned long long)grid);
+            const int g = (int)std::min<unsigned long long>(std::max(ntiles + nsmall, 1ull), (unsigned long long)grid);
             tm.begin(5);
             if (real) HIP_TRY(launch_verify_real(va, real_x ? 1 : 0, g, st));
             else HIP_TRY(launch_verify_bin(va, g, st));
             tm.end();
-            timing.verify_launches += ntiles ? 1 : 0;
-            timing.tiles += (int64_t)ntiles;
+            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0);
+            timing.tiles += (int64_t)(ntiles + nsmall);
             unsigned long long cnt = 0;
             HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));

@@ -12,6 +12,9 @@ namespace xyz {
 constexpr int TILE = 32;
 // Largest m handled by the single-pass LDS bucket sort (2^m counters in LDS).
 constexpr int MAX_M_LDS = 15;
+// A bucket product that fits one tile and has at most this many candidate
+// pairs goes to the small-tile list (verified many tiles per wave).
+constexpr uint32_t SMALL_TILE_PAIRS = 96;
 
 struct Tile {            // 16 bytes
     uint32_t rep;        // repetition index relative to the launch's first repetition
@@ -46,7 +49,7 @@ struct RepInfo {         // per repetition and response, filled on the device
     unsigned long long fresh;
     unsigned long long cmask;
     unsigned int max_bucket;
-    unsigned int pad;
+    unsigned int small_tiles; // one-tile bucket products with at most SMALL_TILE_PAIRS pairs
 };
 
 // ------------------------------------------------------------ launchers --
@@ -85,16 +88,19 @@ hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nr
 // offs [nrep][2^m + 1], perm [nrep][p].
 hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info,
                          int two_sided, uint32_t *offs, uint32_t *perm, hipStream_t st);
-// Exclusive scan of info[...].tiles over nrep*nys entries into base [nrep*nys + 1] (u64).
+// Exclusive scans over count = nrep*nys entries into base [2 count + 2] (u64): base[0..count]
+// of info[].tiles (large tiles), base[count+1 .. 2 count+1] of info[].small_tiles.
 hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st);
-// Emit the tiles of every (repetition, response) at base[r * nys + y].
+// Emit the tiles of every (repetition, response): large tiles at base[r * nys + y], small
+// ones after all large tiles, at base[count] + base[count + 1 + r * nys + y].
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
                         int two_sided, const unsigned long long *base, Tile *tiles, hipStream_t st);
 
 // Shared arguments of the verification kernels.
 struct VerifyArgs {
     const Tile *tiles;
-    uint64_t ntiles;
+    uint64_t ntiles;         // large tiles: tiles[0, ntiles)
+    uint64_t nsmall;         // small tiles: tiles[ntiles, ntiles + nsmall)
     const uint32_t *perm;
     const uint32_t *XC;      // [p][W32p] bits
     int W32p;

@@ -346,18 +346,32 @@ __global__ __launch_bounds__(256) void k_hash(const uint64_t *__restrict__ XR, i
 // ----------------------------------------------------------------- bucket --
 
 // Bucket pair (b, b2) of a repetition: b < b2 -> all pairs of the two buckets;
-// b == b2 (partner mask 0) -> pairs inside the bucket.  Adds candidates and tiles.
-XYZ_DEV void pair_stats(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, unsigned long long &cand,
-                        unsigned long long &tiles)
+// b == b2 (partner mask 0) -> pairs inside the bucket.  Returns the candidate
+// count; T is the number of TILE x TILE tiles, or 0 when the product is empty
+// or small (one tile with at most SMALL_TILE_PAIRS pairs: small = 1).
+XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, unsigned long long &T,
+                                         uint32_t &small)
 {
+    T = 0;
+    small = 0;
     if (b < b2) {
-        cand += (unsigned long long)a * a2;
-        tiles += cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
-    } else if (b == b2 && a >= 2) {
-        cand += (unsigned long long)a * (a - 1) / 2;
-        const unsigned long long T = cdiv_u64(a, TILE);
-        tiles += T * (T + 1) / 2;
+        const unsigned long long c = (unsigned long long)a * a2;
+        if (c == 0) return 0;
+        if (a <= (uint32_t)TILE && a2 <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) small = 1;
+        else T = cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
+        return c;
     }
+    if (b == b2 && a >= 2) {
+        const unsigned long long c = (unsigned long long)a * (a - 1) / 2;
+        if (a <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
+            small = 1;
+        } else {
+            const unsigned long long n = cdiv_u64(a, TILE);
+            T = n * (n + 1) / 2;
+        }
+        return c;
+    }
+    return 0;
 }
 
 __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ keys, int64_t p, int m, int nys,
@@ -379,20 +393,30 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
         RepInfo *inf = info + (int64_t)r * nys + y;
         const uint32_t c = (uint32_t)inf->cmask & mask;
         const uint32_t cn = (~c) & mask;
-        unsigned long long cand = 0, tiles = 0;
+        unsigned long long cand = 0, tiles = 0, small = 0;
         unsigned mx = 0;
         for (int b = threadIdx.x; b < nb; b += 1024) {
             const uint32_t a = cnt[b];
             mx = max(mx, a);
-            pair_stats((uint32_t)b, (uint32_t)b ^ c, a, cnt[b ^ c], cand, tiles);
-            if (two_sided && cn != c) pair_stats((uint32_t)b, (uint32_t)b ^ cn, a, cnt[b ^ cn], cand, tiles);
+            unsigned long long T;
+            uint32_t sm;
+            cand += product_tiles((uint32_t)b, (uint32_t)b ^ c, a, cnt[b ^ c], T, sm);
+            tiles += T;
+            small += sm;
+            if (two_sided && cn != c) {
+                cand += product_tiles((uint32_t)b, (uint32_t)b ^ cn, a, cnt[b ^ cn], T, sm);
+                tiles += T;
+                small += sm;
+            }
         }
         cand = block_sum<1024>(cand, shm);
         tiles = block_sum<1024>(tiles, shm);
+        small = block_sum<1024>(small, shm);
         mx = block_max<1024>(mx, shmax);
         if (threadIdx.x == 0) {
             inf->candidates = cand;
             inf->tiles = tiles;
+            inf->small_tiles = (unsigned)small;
             inf->max_bucket = mx;
             inf->passed = 0;
             inf->fresh = 0;
@@ -427,25 +451,19 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const RepInfo *__restrict__ 
     __shared__ unsigned long long shm[17];
     const int seg = (count + 1023) / 1024;
     const int i0 = min(count, (int)threadIdx.x * seg), i1 = min(count, i0 + seg);
-    unsigned long long loc = 0;
-    for (int i = i0; i < i1; ++i) loc += info[i].tiles;
-    unsigned long long tot;
-    unsigned long long pre = block_scan_excl<1024>(loc, shm, &tot);
-    for (int i = i0; i < i1; ++i) {
-        base[i] = pre;
-        pre += info[i].tiles;
+    for (int list = 0; list < 2; ++list) {
+        unsigned long long *bs = base + list * (count + 1);
+        unsigned long long loc = 0;
+        for (int i = i0; i < i1; ++i) loc += list ? info[i].small_tiles : info[i].tiles;
+        unsigned long long tot;
+        unsigned long long pre = block_scan_excl<1024>(loc, shm, &tot);
+        for (int i = i0; i < i1; ++i) {
+            bs[i] = pre;
+            pre += list ? info[i].small_tiles : info[i].tiles;
+        }
+        if (threadIdx.x == 0) bs[count] = tot;
+        __syncthreads();
     }
-    if (threadIdx.x == 0) base[count] = tot;
-}
-
-XYZ_DEV unsigned long long pair_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2)
-{
-    if (b < b2) return cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
-    if (b == b2 && a >= 2) {
-        const unsigned long long T = cdiv_u64(a, TILE);
-        return T * (T + 1) / 2;
-    }
-    return 0;
 }
 
 // Tile (ia, ib) number t of a bucket's own product (ia <= ib < T), in row order:
@@ -506,7 +524,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     __shared__ uint32_t hb[HEAVY_CAP], hb2[HEAVY_CAP];
     __shared__ unsigned long long hpos[HEAVY_CAP], hcnt_t[HEAVY_CAP];
     __shared__ int hcnt;
-    const int ry = blockIdx.x;
+    const int ry = blockIdx.x, count = gridDim.x;
     const int r = ry / nys, y = ry % nys;
     const int nb = 1 << m;
     const uint32_t mask = (uint32_t)(nb - 1);
@@ -517,19 +535,32 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     if (threadIdx.x == 0) hcnt = 0;
     const int seg = (nb + 255) / 256;
     const int b0 = min(nb, (int)threadIdx.x * seg), b1 = min(nb, b0 + seg);
-    unsigned long long loc = 0;
+    unsigned long long loc = 0, sloc = 0;
     for (int b = b0; b < b1; ++b) {
         const uint32_t a = of[b + 1] - of[b];
-        loc += pair_tiles(b, b ^ c, a, of[(b ^ c) + 1] - of[b ^ c]);
-        if (second) loc += pair_tiles(b, b ^ cn, a, of[(b ^ cn) + 1] - of[b ^ cn]);
+        for (int side = 0; side < (second ? 2 : 1); ++side) {
+            const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
+            unsigned long long T;
+            uint32_t sm;
+            product_tiles(b, b2, a, of[b2 + 1] - of[b2], T, sm);
+            loc += T;
+            sloc += sm;
+        }
     }
     unsigned long long tot;
     unsigned long long pos = base[ry] + block_scan_excl<256>(loc, shm, &tot);
+    unsigned long long spos = base[count] + base[count + 1 + ry] + block_scan_excl<256>(sloc, shm, &tot);
     const uint32_t pbase = (uint32_t)((int64_t)r * p);
     for (int b = b0; b < b1; ++b) {
         for (int side = 0; side < (second ? 2 : 1); ++side) {
             const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
-            const unsigned long long T = pair_tiles(b, b2, of[b + 1] - of[b], of[b2 + 1] - of[b2]);
+            unsigned long long T;
+            uint32_t sm;
+            product_tiles(b, b2, of[b + 1] - of[b], of[b2 + 1] - of[b2], T, sm);
+            if (sm) {
+                tiles[spos++] = pair_tile(0, r, y, pbase, b, b2, of);
+                continue;
+            }
             if (T == 0) continue;
             int h = -1;
             if (T > HEAVY_TILES) {
@@ -562,6 +593,25 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
 // staged through LDS in chunks of 32 words (1024 rows): A holds z_a = y ^ x_a,
 // B holds x_b, so the inner loop is one XOR and one popcount-accumulate per
 // pair and 32-bit word.  RA = ceil(na/8), RB = ceil(nb/8) are wave-uniform.
+
+// Candidate pairs of a tile (positions a < b only on a diagonal tile).
+XYZ_DEV uint32_t tile_pairs(const Tile &t)
+{
+    return t.diag ? (uint32_t)t.na * (uint32_t)(t.na - 1) / 2 : (uint32_t)t.na * (uint32_t)t.nb;
+}
+
+XYZ_DEV Tile tile_from(uint4 v)
+{
+    Tile t;
+    t.rep = v.x;
+    t.a0 = v.y;
+    t.b0 = v.z;
+    t.na = (uint8_t)(v.w & 255u);
+    t.nb = (uint8_t)((v.w >> 8) & 255u);
+    t.diag = (uint8_t)((v.w >> 16) & 255u);
+    t.ysel = (uint8_t)(v.w >> 24);
+    return t;
+}
 
 constexpr int CW4 = 8;       // uint4 per column per chunk (32 words)
 constexpr int LDS4 = CW4 + 1;  // padded row length (uint4) against bank conflicts
@@ -719,6 +769,197 @@ __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
     }
 }
 
+// Small tiles (high m: products of buckets holding a few columns each).  A
+// wave reads 64 consecutive small tiles and packs them, in order, into groups
+// of at most SG_COLS staged columns and 64 * SG_KP pairs.  The group's columns
+// go through LDS in chunks of 16 words (A-side columns already XORed with y),
+// and every lane verifies up to SG_KP of the group's pairs: two LDS reads, one
+// XOR and one popcount-accumulate per pair and word, with all lanes busy
+// whatever the tile shapes.
+constexpr int SG_COLS = 64;
+constexpr int SG_KP = 4;
+constexpr int SCW4 = 4;              // uint4 per column per chunk
+constexpr int SLDS4 = SCW4 + 1;      // padded row length
+
+// Pair number `local` of a small tile: (pa, pb) = (local / nb, local % nb), or
+// on a diagonal tile the pairs pa < pb < na in row order (row pa starts at
+// pa na - pa (pa + 1) / 2).
+XYZ_DEV void small_pair(uint32_t w, uint32_t local, uint32_t &pa, uint32_t &pb)
+{
+    const uint32_t na = w & 255u, nb = (w >> 8) & 255u, diag = (w >> 16) & 255u;
+    if (diag) {
+        pa = 0;
+        while (pa + 1 < na && (pa + 1) * na - (pa + 1) * (pa + 2) / 2 <= local) ++pa;
+        pb = pa + 1 + (local - (pa * na - pa * (pa + 1) / 2));
+    } else {
+        pa = nb ? local / nb : 0;
+        pb = nb ? local % nb : 0;
+    }
+}
+
+// Smallest lane l whose inclusive prefix v(l) exceeds x (64 if none).
+XYZ_DEV int first_above(uint32_t v, uint32_t x)
+{
+    int L = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t u = __shfl(v, L + step - 1, 64);
+        if (u <= x) L += step;
+    }
+    return L;
+}
+
+__global__ __launch_bounds__(64) void k_verify_small(VerifyArgs a)
+{
+    __shared__ uint4 Cs[SG_COLS][SLDS4];
+    const unsigned lane = lane_id();
+    const int W4 = a.W32p >> 2;
+    const int nchunk = (W4 + SCW4 - 1) / SCW4;
+    const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
+    const uint4 *Y4 = reinterpret_cast<const uint4 *>(a.yb);
+    const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles);
+    const uint64_t NS = a.nsmall;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * 64; g0 < NS; g0 += (uint64_t)gridDim.x * 64) {
+        const int cnt = (int)min<uint64_t>(64, NS - g0);
+        const bool have = (int)lane < cnt;
+        const uint4 td = have ? T4[g0 + lane] : make_uint4(0, 0, 0, 0);
+        const Tile mt = tile_from(td);
+        const uint32_t cols = have ? (uint32_t)mt.na + mt.nb : 0u;
+        const uint32_t np = have ? tile_pairs(mt) : 0u;
+        uint32_t incC = cols, incP = np;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t uc = __shfl_up(incC, d, 64), up = __shfl_up(incP, d, 64);
+            if ((int)lane >= d) {
+                incC += uc;
+                incP += up;
+            }
+        }
+        int s0 = 0;
+        uint32_t baseC = 0, baseP = 0;
+        while (s0 < cnt) {
+            // tiles [s0, e): every single tile fits (at most 64 columns, SMALL_TILE_PAIRS pairs)
+            const bool fit = (int)lane >= s0 && have && incC - baseC <= (uint32_t)SG_COLS &&
+                             incP - baseP <= 64u * SG_KP;
+            const int e = s0 + (int)__popcll(__ballot(fit));
+            const uint32_t C = __shfl(incC, e - 1, 64) - baseC;
+            const uint32_t P = __shfl(incP, e - 1, 64) - baseP;
+            // the column staged in slot `lane`
+            uint32_t mycol = 0, myA = 0, myys = 0;
+            {
+                const int t = min(first_above(incC, baseC + lane), 63);
+                const uint32_t tw = __shfl(td.w, t, 64), ta0 = __shfl(td.y, t, 64), tb0 = __shfl(td.z, t, 64);
+                const uint32_t start = __shfl(incC, t, 64) - __shfl(cols, t, 64) - baseC;
+                const uint32_t na = tw & 255u, local = lane - start;
+                if (lane < C) {
+                    if (local < na) {
+                        mycol = a.perm[ta0 + local];
+                        myA = 1;
+                    } else {
+                        mycol = a.perm[tb0 + local - na];
+                    }
+                    myys = tw >> 24;
+                }
+            }
+            // the pairs of this lane: slots in LDS and the owning tile's lane
+            uint32_t slot[SG_KP];
+#pragma unroll
+            for (int i = 0; i < SG_KP; ++i) {
+                const uint32_t q = lane + 64u * i;
+                const int t = min(first_above(incP, baseP + q), 63);
+                const uint32_t tw = __shfl(td.w, t, 64);
+                const uint32_t start = __shfl(incC, t, 64) - __shfl(cols, t, 64) - baseC;
+                const uint32_t pstart = __shfl(incP, t, 64) - __shfl(np, t, 64) - baseP;
+                uint32_t pa = 0, pb = 0;
+                if (q < P) small_pair(tw, q - pstart, pa, pb);
+                const uint32_t sa = q < P ? start + pa : 0u, sb = q < P ? start + (tw & 255u) + pb : 0u;
+                slot[i] = sa | (sb << 8) | ((uint32_t)t << 16);
+            }
+            // staging assignment: slot (lane >> 2) + 16 u, uint4 lane & 3 of the chunk
+            uint32_t scol[SG_COLS / 16], sflag[SG_COLS / 16];
+#pragma unroll
+            for (int u = 0; u < SG_COLS / 16; ++u) {
+                const int cs = (int)(lane >> 2) + 16 * u;
+                scol[u] = __shfl(mycol, cs, 64);
+                sflag[u] = (__shfl(myA, cs, 64) ? 1u : 0u) | (__shfl(myys, cs, 64) << 8) | ((uint32_t)(cs < (int)C) << 1);
+            }
+            const int kp = (int)((P + 63) / 64);
+            uint32_t acc[SG_KP];
+#pragma unroll
+            for (int i = 0; i < SG_KP; ++i) acc[i] = 0;
+            for (int c = 0; c < nchunk; ++c) {
+                const int gq = c * SCW4 + (int)(lane & 3);
+#pragma unroll
+                for (int u = 0; u < SG_COLS / 16; ++u) {
+                    if (sflag[u] & 2u) {
+                        uint4 v = make_uint4(0, 0, 0, 0);
+                        if (gq < W4) {
+                            v = XC4[(int64_t)scol[u] * W4 + gq];
+                            if (sflag[u] & 1u) {
+                                const uint4 yv = Y4[(int64_t)(sflag[u] >> 8) * W4 + gq];
+                                v.x ^= yv.x; v.y ^= yv.y; v.z ^= yv.z; v.w ^= yv.w;
+                            }
+                        }
+                        Cs[(lane >> 2) + 16 * u][lane & 3] = v;
+                    }
+                }
+                lds_barrier();
+#pragma unroll
+                for (int w = 0; w < SCW4; ++w) {
+#pragma unroll
+                    for (int i = 0; i < SG_KP; ++i) {
+                        if (i < kp) {
+                            const uint4 x = Cs[slot[i] & 255u][w], z = Cs[(slot[i] >> 8) & 255u][w];
+                            uint32_t r = acc[i];
+                            r = bcnt_acc(x.x ^ z.x, r);
+                            r = bcnt_acc(x.y ^ z.y, r);
+                            r = bcnt_acc(x.z ^ z.z, r);
+                            r = bcnt_acc(x.w ^ z.w, r);
+                            acc[i] = r;
+                        }
+                    }
+                }
+                lds_barrier();
+            }
+            // threshold and survivors
+#pragma unroll
+            for (int i = 0; i < SG_KP; ++i) {
+                const uint32_t q = lane + 64u * i;
+                const int t = (int)(slot[i] >> 16);
+                const uint32_t ys = __shfl(td.w, t, 64) >> 24, rep = __shfl(td.x, t, 64);
+                const uint32_t j = __shfl(mycol, (int)(slot[i] & 255u), 64);
+                const uint32_t k = __shfl(mycol, (int)((slot[i] >> 8) & 255u), 64);
+                const int64_t sv = a.n - 2 * (int64_t)acc[i];
+                const int64_t smin = a.smin[ys];
+                const bool pass = q < P && (a.two_sided ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin));
+                const unsigned long long bal = __ballot(pass);
+                if (bal == 0) continue;
+                unsigned long long basei = 0;
+                if (lane == 0) basei = atomicAdd(a.surv_count, (unsigned long long)__popcll(bal));
+                basei = __shfl(basei, 0, 64);
+                if (pass) {
+                    const unsigned long long idx = basei + (unsigned long long)__popcll(bal & lanemask_lt());
+                    if (idx < a.surv_cap) {
+                        Survivor sr;
+                        sr.j = min(j, k);
+                        sr.k = max(j, k);
+                        sr.rep = (uint32_t)(a.rep_abs0 + rep);
+                        sr.s = (int32_t)sv;
+                        sr.value = (double)sv;
+                        sr.ysel = ys;
+                        sr.pad = 0;
+                        a.surv[idx] = sr;
+                    }
+                    atomicAdd(&a.info[(int64_t)rep * a.nys + ys].passed, 1ull);
+                }
+            }
+            s0 = e;
+            baseC = __shfl(incC, e - 1, 64);
+            baseP = __shfl(incP, e - 1, 64);
+        }
+    }
+}
+
 // Real-valued verification: v = sum_i (Y_i X_ij) X_ik in binary64.  Rows are
 // staged in chunks of 32: A holds Y_i X_ia (exact in binary64 for float
 // inputs), B holds X_ib; each lane accumulates its RA x RB block with FMAs.
@@ -817,7 +1058,7 @@ __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
     __shared__ double Bs[TILE][CR + 1];
     __shared__ uint32_t colA[TILE], colB[TILE];
     const unsigned lane = lane_id();
-    for (uint64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+    for (uint64_t ti = blockIdx.x; ti < a.ntiles + a.nsmall; ti += gridDim.x) {
         const Tile t = a.tiles[ti];
         if (lane < t.na) colA[lane] = a.perm[t.a0 + lane];
         if (lane >= 32 && lane - 32 < t.nb) colB[lane - 32] = a.perm[t.b0 + lane - 32];
@@ -1415,14 +1656,20 @@ hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int ny
 
 hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
 {
-    if (a.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_verify_bin, dim3(grid), dim3(64), 0, st, a);
+    if (a.ntiles)
+        hipLaunchKernelGGL(k_verify_bin, dim3((unsigned)std::min<uint64_t>(a.ntiles, (uint64_t)grid)), dim3(64), 0, st,
+                           a);
+    if (a.nsmall) {
+        const uint64_t groups = (a.nsmall + 63) / 64;                  // 64 small tiles per wave step
+        hipLaunchKernelGGL(k_verify_small, dim3((unsigned)std::min<uint64_t>(groups, (uint64_t)grid)), dim3(64), 0, st,
+                           a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStream_t st)
 {
-    if (a.ntiles == 0) return hipSuccess;
+    if (a.ntiles + a.nsmall == 0) return hipSuccess;
     hipLaunchKernelGGL(k_verify_real, dim3(grid), dim3(64), 0, st, a, x_real);
     return hipGetLastError();
 }

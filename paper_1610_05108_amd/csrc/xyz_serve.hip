@@ -57,7 +57,7 @@ uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk)
     const double p = (double)x->p, nb = std::ldexp(1.0, P.m);
     const double cand = p * (p - 1) / 2 / nb;
     const double tiles = std::max(p / 24.0, cand / 576.0);
-    const double per_rep = 8 * p + 4 * (nb + 1) + 16 * tiles + 64;
+    const double per_rep = 8 * p + 4 * (nb + 1) + 16 * tiles + 80;
     const double fixed = (double)(1 << 16) * 32 * 2 + (double)x->W32p * 4 + (double)x->nF * 8 + (double)P.L * 48;
     return (uint64_t)(per_rep * (double)chunk + fixed);
 }
