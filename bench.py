@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--L", type=int, default=None, help="force L (default: eq. (15) at 95%% recall)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=None)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-fresh", type=int, default=32)
+    ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -219,12 +223,17 @@ def main():
     pairs_per_search = p * (p - 1) / 2
     value = len(data) * pairs_per_search / (ms_per_step * 1e-3)
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_leg(ctx, args.serve_requests, args.serve_fresh, args.serve_workers, seq_sample=32)
+        log(f"serving: {serving}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(data[0], plan[1], plan[2], n, p, args.cpu_reps)
 
     line = {
-        "metric": "interaction pairs screened/s at >=95% planted recall",
+        "metric": "interaction pairs screened/s at >=95% planted recall; p50/p99 request latency",
         "value": value,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -246,9 +255,160 @@ def main():
         "stages_ms_per_search": stages,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serve_leg(ctx, count, fresh_count, workers, seq_sample):
+    """The serving workload: a shared genotype-shaped X (n=2000, p=200,000)
+    resident on the GPU; `count` +-1 responses arrive as a Poisson stream at
+    50/s (1-3 planted pairs of strength 0.2-0.5, L from {50, 200, 500},
+    kappa 0.15), mixed with `fresh_count` requests on fresh Rademacher data
+    sets (n=1000, p from {1e4, 1e5, 5e5}, handed over bit-packed, made
+    resident on arrival and freed after).
+
+    Each request is routed by the cost model: xyz with the largest m that
+    keeps eq. (9) >= 0.95 at the strength kappa itself (gamma = (1 + kappa)/2)
+    for the request's L, and candidates predicted from sampled pair strengths
+    (E|E_l| = sum of gamma^m), against the exact matrix-core search; the
+    predicted faster one is submitted.  Rates for the model are measured on
+    the shared X before the stream starts.  Latency = arrival to result."""
+    import threading
+    import synthgen
+    import paper_1610_05108_amd as xyz
+    t0 = time.time()
+    XT, _ = synthgen.config5_shared(seed=0)
+    ps, ns = XT.shape
+    x = xyz.xyz_x_create(ctx.h, XT)
+    reqs = synthgen.config5_requests(XT, count=count, seed=0, rate=50.0)
+    fresh = synthgen.config5_fresh_bits(count=fresh_count, seed=0) if fresh_count else []
+    log(f"serving data ready ({time.time() - t0:.1f}s): {len(reqs)} shared-X requests, {len(fresh)} fresh")
+
+    # rates for the cost model, on the shared X
+    Y0 = reqs[0]["Y"]
+    ctx.bruteforce(x, Y0, 0.15)
+    tb = time.perf_counter()
+    ctx.bruteforce(x, Y0, 0.15)
+    t_br = time.perf_counter() - tb
+    rate_exact = ps * (ps - 1) / 2 * ns / t_br               # pair-rows / s
+    r = ctx.search(x, Y0, m=9, L=50, kappa=0.15, seed=1, profile=True)
+    tm = r["timing"]
+    words = math.ceil(ns / 32)
+    rate_verify = tm["candidates"] * words / (tm["verify_ms"] * 1e-3)   # candidate-words / s
+    rep_cost = max(tm["total_ms"] - tm["verify_ms"], 0.0) * 1e-3 / (50 * ps)   # s per repetition and column
+
+    def route(xh, Y, p, n, L, kappa):
+        g = 0.5 * (1.0 + kappa)
+        m = xyz.xyz_m_for_L(g, L, 0.95, 15)
+        t_exact = p * (p - 1) / 2 * n / rate_exact
+        if m < 1:
+            return ("exact", 0, t_exact, t_exact)
+        gs = xyz.xyz_sample_strengths(ctx.h, xh, Y, 4096, seed=7)
+        cand = p * (p - 1) / 2 * float(np.mean(gs ** m))
+        t_xyz = L * (cand * math.ceil(n / 32) / rate_verify + p * rep_cost)
+        return ("xyz", m, t_xyz, t_exact) if t_xyz < t_exact else ("exact", m, t_xyz, t_exact)
+
+    events = [dict(kind="shared", **q) for q in reqs] + [dict(kind="fresh", **q) for q in fresh]
+    events.sort(key=lambda e: e["t"])
+    srv = xyz.xyz_serve_start(ctx.h, 0, workers=workers, max_batch=16)
+    pending = {}
+    done = {}
+    lock = threading.Lock()
+    finished = threading.Event()
+
+    def collector():
+        while not finished.is_set() or pending:
+            with lock:
+                items = list(pending.items())
+            for tk, e in items:
+                try:
+                    o = xyz.xyz_serve_poll(srv, tk)
+                except xyz.XyzError as err:          # failed request: report it, keep collecting
+                    e["error"] = str(err)
+                    o = {"pairs": np.zeros(0, dtype=[("j", "i4"), ("k", "i4")])}
+                if o is not None:
+                    e["t_done"] = time.perf_counter()
+                    e["out"] = o
+                    with lock:
+                        del pending[tk]
+                        done[tk] = e
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=collector)
+    th.start()
+    start = time.perf_counter()
+    routes = {"xyz": 0, "exact": 0}
+    try:
+        for e in events:
+            wait = start + e["t"] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            e["t_arr"] = start + e["t"]
+            if e["kind"] == "fresh":
+                e["x"] = xyz.xyz_x_create(ctx.h, e["bits"], n=e["n"])
+                p, n, xh = e["bits"].shape[0], e["n"], e["x"]
+            else:
+                p, n, xh = ps, ns, x
+            kind, m, t_x, t_e = route(xh, e["Y"], p, n, e["L"], e["kappa"])
+            e.update(route=kind, m=m, p=p, n=n)
+            routes[kind] += 1
+            if kind == "exact":
+                tk = xyz.xyz_serve_submit(srv, xh, e["Y"], kappa=e["kappa"], exact=True)
+            else:
+                tk = xyz.xyz_serve_submit(srv, xh, e["Y"], m=m, L=e["L"], kappa=e["kappa"], seed=int(e["t"] * 1e6))
+            with lock:
+                pending[tk] = e
+    finally:
+        finished.set()
+        th.join()
+        st = xyz.xyz_serve_stats_get(srv)
+        xyz.xyz_serve_stop(srv)
+    end = max(e["t_done"] for e in done.values())
+    for e in events:
+        if "x" in e:
+            xyz.xyz_x_destroy(e.pop("x"))
+    lat = [(e["t_done"] - e["t_arr"]) * 1e3 for e in events]
+    screened = sum(e["p"] * (e["p"] - 1) / 2 for e in events)
+    # planted pairs reported by their request
+    found = tot = 0
+    for e in events:
+        got = {(int(a), int(b)) for a, b in zip(e["out"]["pairs"]["j"], e["out"]["pairs"]["k"])}
+        for pq in e["planted"]:
+            tot += 1
+            found += pq in got
+    # the same requests one at a time, without the server (first seq_sample shared-X requests)
+    seq = [e for e in events if e["kind"] == "shared"][:seq_sample]
+    ts = time.perf_counter()
+    for e in seq:
+        if e["route"] == "exact":
+            ctx.bruteforce(x, e["Y"], e["kappa"])
+        else:
+            ctx.search(x, e["Y"], m=e["m"], L=e["L"], kappa=e["kappa"], seed=int(e["t"] * 1e6))
+    t_seq = time.perf_counter() - ts
+    xyz.xyz_x_destroy(x)
+    return {
+        "workload": f"shared genotype X n={ns} p={ps} resident; {len(reqs)} +-1 requests at 50/s "
+                    f"(L in {{50,200,500}}, kappa 0.15) + {len(fresh)} fresh Rademacher data sets "
+                    f"(n=1000, p in {{1e4,1e5,5e5}}, bit-packed)",
+        "requests": len(events), "workers": workers,
+        "failed": sum(1 for e in events if "error" in e),
+        "routes": routes,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": max(lat),
+        "server_p50_ms": st["p50_ms"], "server_p99_ms": st["p99_ms"],
+        "batches": st["batches"], "max_batch": st["max_batch"],
+        "wall_s": end - start, "pairs_screened_per_s": screened / (end - start),
+        "planted_found": found, "planted_total": tot,
+        "sequential_pairs_per_s": sum(ps * (ps - 1) / 2 for _ in seq) / t_seq if seq else None,
+        "sequential_sample": len(seq),
+        "model": {"exact_pair_rows_per_s": rate_exact, "verify_candidate_words_per_s": rate_verify,
+                  "s_per_rep_column": rep_cost},
+    }
 
 
 def cpu_baseline(dd, m, L, n, p, reps=None):

@@ -64,6 +64,8 @@ typedef int32_t xyz_status;
 /* flags */
 #define XYZ_TWO_SIDED 1u  /* also search -Y (Section 4 runs +r and -r in turn): keep |Y^T(X_j o X_k)|/n > kappa */
 #define XYZ_PROFILE   2u  /* time the GPU stages with HIP events and report them in xyz_timing */
+#define XYZ_EXACT     4u  /* xyz_serve_submit only: answer with the exact search of eq. (1), as xyz_bruteforce
+                             over all columns; m, L, seed, rep_offset and rows are ignored */
 
 #define XYZ_MAX_M 30      /* largest supported number of sampled rows per repetition */
 
@@ -234,7 +236,9 @@ typedef struct {
 
 xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, int32_t workers, int32_t max_batch,
                            xyz_server **out);
-/* Queue a search; Y (host memory, format yfmt) and params (including its row table) are copied. */
+/* Queue a search; Y (host memory, format yfmt) and params (including its row table) are copied.
+ * With XYZ_EXACT in params->flags the request is answered by the exact search (result as from
+ * xyz_bruteforce); such requests are never grouped with others. */
 xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void *Y, int yfmt, const xyz_params *params,
                             uint64_t *ticket);
 /* XYZ_EAGAIN while the request is queued or running; otherwise the request's result (or its error, or

@@ -24,7 +24,7 @@ XYZ_OK, XYZ_EINVAL, XYZ_ENOMEM, XYZ_EDEVICE, XYZ_EAGAIN, XYZ_ECANCELED, XYZ_EUNS
 XYZ_MEM_HOST, XYZ_MEM_DEVICE = 0, 1
 XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32 = 0, 1, 2
 XYZ_Y_I8_PM1, XYZ_Y_F32, XYZ_Y_F64 = 0, 1, 2
-XYZ_TWO_SIDED, XYZ_PROFILE = 1, 2
+XYZ_TWO_SIDED, XYZ_PROFILE, XYZ_EXACT = 1, 2, 4
 XYZ_MAX_M = 30
 
 PAIR_DTYPE = np.dtype([("j", np.int32), ("k", np.int32), ("s", np.int64), ("value", np.float64),
@@ -362,12 +362,15 @@ def xyz_serve_start(ctx, hbm_budget_bytes: int = 0, workers: int = 2, max_batch:
     return h
 
 
-def xyz_serve_submit(server, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
-                     rep_offset: int = 0, rows=None) -> int:
-    """Queue a search (Y is host memory: numpy array or CPU tensor); returns the ticket."""
+def xyz_serve_submit(server, x, Y, m: int = 0, L: int = 1, kappa: float = 0.0, seed: int = 0,
+                     two_sided: bool = False, rep_offset: int = 0, rows=None, exact: bool = False) -> int:
+    """Queue a search (Y is host memory: numpy array or CPU tensor); returns the ticket.
+    exact=True asks for the exact search of eq. (1) (m, L, seed, rows ignored)."""
     if _is_torch(Y) and Y.is_cuda:
         raise ValueError("xyz_serve_submit takes Y in host memory")
-    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, False)
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, None if exact else rows, False)
+    if exact:
+        prm.flags |= XYZ_EXACT
     ptr, _, keep = _ptr(Y)
     t = ctypes.c_uint64()
     _check(lib().xyz_serve_submit(server, x, ptr, _y_format(Y), ctypes.byref(prm), ctypes.byref(t)))

@@ -688,6 +688,16 @@ extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, 
     if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
     *out = nullptr;
     if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    return brute_run(c, x, Y, yfmt, mem, kappa, flags, colsA, nA, colsB, nB, (hipStream_t)stream, out);
+}
+
+xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
+                             uint32_t flags, const int32_t *colsA, int64_t nA, const int32_t *colsB, int64_t nB,
+                             hipStream_t st, xyz_result **out)
+{
+    if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (x->ctx->device != c->device) return fail(XYZ_EINVAL, "X lives on another device");
     if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
     if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
     if (!std::isfinite(kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
@@ -701,7 +711,6 @@ extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, 
     for (int64_t q = 0; colsB && q < nB; ++q)
         if (colsB[q] < 0 || colsB[q] >= p) return fail(XYZ_EINVAL, "colsB[%lld] out of range", (long long)q);
     HIP_TRY(hipSetDevice(c->device));
-    hipStream_t st = (hipStream_t)stream;
     const bool real = x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1;
     if (!real && n >= (1ll << 29)) return fail(XYZ_EUNSUPPORTED, "brute force needs n < 2^29 (32-bit counts)");
     if (real) {

@@ -55,6 +55,11 @@ namespace xyz_rt {
 // Sets the thread's last error and returns code.
 xyz_status fail(xyz_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt);
+// Exact search of eq. (1) (xyz_bruteforce after its argument checks); x may belong to another
+// context on the same device.
+xyz_status brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa, uint32_t flags,
+                     const int32_t *colsA, int64_t nA, const int32_t *colsB, int64_t nB, hipStream_t st,
+                     xyz_result **out);
 // Searches sharing X, m, L, seed, rep_offset and flags (nys > 1 requires +-1 Y and no row table).
 // X may belong to another context on the same device.
 xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,

@@ -12,6 +12,7 @@
 #include "xyz_runtime.h"
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -54,6 +55,8 @@ size_t y_size(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 
 // initial survivor buffer and merge scratch, and packed Y.
 uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk)
 {
+    if (P.flags & XYZ_EXACT)   // survivors, merge scratch and packed Y only
+        return (uint64_t)((double)(1 << 16) * 32 * 2 + (double)x->W32p * 4 + (double)x->nF * 8 + 4096);
     const double p = (double)x->p, nb = std::ldexp(1.0, P.m);
     const double cand = p * (p - 1) / 2 / nb;
     const double tiles = std::max(p / 24.0, cand / 576.0);
@@ -64,6 +67,7 @@ uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk)
 
 bool same_group(const Request &a, const Request &b)
 {
+    if ((a.params.flags | b.params.flags) & XYZ_EXACT) return false;
     return a.x == b.x && a.yfmt == XYZ_Y_I8_PM1 && b.yfmt == XYZ_Y_I8_PM1 && a.rows.empty() && b.rows.empty() &&
            a.params.m == b.params.m && a.params.L == b.params.L && a.params.seed == b.params.seed &&
            a.params.rep_offset == b.params.rep_offset && a.params.flags == b.params.flags && a.chunk == b.chunk;
@@ -137,8 +141,13 @@ void worker_loop(xyz_server *s, int w)
         }
         std::vector<xyz_result *> outs(batch.size(), nullptr);
         ctx->max_chunk = batch[0]->chunk;
-        const xyz_status rc = run_group(ctx, batch[0]->x, (int)batch.size(), ys.data(), batch[0]->yfmt,
-                                        XYZ_MEM_HOST, ps.data(), stream, outs.data());
+        const xyz_params &P0 = batch[0]->params;
+        const xyz_status rc =
+            (P0.flags & XYZ_EXACT)
+                ? brute_run(ctx, batch[0]->x, ys[0], batch[0]->yfmt, XYZ_MEM_HOST, P0.kappa,
+                            P0.flags & ~XYZ_EXACT, nullptr, 0, nullptr, 0, stream, outs.data())
+                : run_group(ctx, batch[0]->x, (int)batch.size(), ys.data(), batch[0]->yfmt, XYZ_MEM_HOST,
+                            ps.data(), stream, outs.data());
         if (s->budget && ctx->used > s->budget) ws_release(ctx);
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -199,7 +208,13 @@ extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void
 {
     if (!s || !x || !Y || !params || !ticket) return fail(XYZ_EINVAL, "NULL argument");
     if (x->ctx->device != s->device) return fail(XYZ_EINVAL, "X lives on another device");
-    {
+    if (params->flags & XYZ_EXACT) {
+        if (!std::isfinite(params->kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
+        if (params->flags & ~(uint32_t)(XYZ_TWO_SIDED | XYZ_PROFILE | XYZ_EXACT))
+            return fail(XYZ_EINVAL, "unknown flags 0x%x", params->flags);
+        if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64)
+            return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
+    } else {
         const xyz_status v = validate_params(x, params, yfmt);
         if (v != XYZ_OK) return v;
     }
@@ -209,11 +224,12 @@ extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void
     r->y.resize(y_size(yfmt, x->n));
     std::memcpy(r->y.data(), Y, r->y.size());
     r->params = *params;
-    if (params->rows) r->rows.assign(params->rows, params->rows + (size_t)params->L * params->m);
+    if (params->rows && !(params->flags & XYZ_EXACT))
+        r->rows.assign(params->rows, params->rows + (size_t)params->L * params->m);
     r->params.rows = nullptr;
     // repetitions per chunk: as many as the budget allows (at least one)
     xyz_ctx probe{};
-    int64_t chunk = chunk_reps(&probe, params->L, x->p, params->m);
+    int64_t chunk = (params->flags & XYZ_EXACT) ? 1 : chunk_reps(&probe, params->L, x->p, params->m);
     if (s->budget) {
         while (chunk > 1 && estimate_bytes(x, r->params, chunk) > s->budget) chunk = (chunk + 1) / 2;
         if (estimate_bytes(x, r->params, chunk) > s->budget) {

@@ -290,6 +290,51 @@ def config5_fresh(count: int = 32, seed: int = 0, n: int = 1000, sizes=(10_000, 
     return out
 
 
+def unpack_column(bits: np.ndarray, n: int) -> np.ndarray:
+    """One packed column (ceil(n/64) uint64 words, bit = [x == -1]) back to +-1 int8."""
+    b = np.unpackbits(bits.view(np.uint8), bitorder="little")[:n]
+    return (1 - 2 * b.astype(np.int8)).astype(np.int8)
+
+
+def config5_fresh_bits(count: int = 32, seed: int = 0, n: int = 1000, sizes=(10_000, 100_000, 500_000),
+                       rate: float = 50.0 / 8.0):
+    """The fresh-data requests of the serving workload, with X handed over bit-packed.
+
+    Same model as ``config5_fresh`` (Rademacher X, n=1000, p from ``sizes``,
+    1-3 pairs of strength U[0.2, 0.3] planted by a row mixture, L from
+    {50, 200, 500}, kappa = 0.15); X is drawn directly as random words, which
+    is the same distribution and avoids building the int8 matrix.  Each entry
+    holds ``bits`` of shape (p, ceil(n/64)) instead of ``XT``.
+    """
+    r = _rng(seed, 17)
+    w = (n + 63) // 64
+    t = 0.0
+    out = []
+    for q in range(count):
+        t += r.exponential(1.0 / rate)
+        p = int(r.choice(sizes))
+        bits = _rng(seed * 1000 + q, 18).integers(0, np.iinfo(np.uint64).max, size=(p, w), dtype=np.uint64,
+                                                    endpoint=True)
+        tail = n - (w - 1) * 64
+        if tail < 64:
+            bits[:, w - 1] &= np.uint64((1 << tail) - 1)
+        k = int(r.integers(1, 4))
+        s = r.uniform(0.2, 0.3, size=k)
+        cols = _distinct_columns(r, p, 2 * k)
+        pairs = [tuple(sorted((int(cols[2 * i]), int(cols[2 * i + 1])))) for i in range(k)]
+        sub = {j: unpack_column(bits[j], n) for pq in pairs for j in pq}
+        u = r.random(n)
+        Y = np.where(r.random(n) < 0.5, 1, -1).astype(np.int8)
+        acc = 0.0
+        for (a, b), sq in zip(pairs, s):
+            sel = (u >= acc) & (u < acc + sq)
+            Y[sel] = (sub[a][sel].astype(np.int16) * sub[b][sel]).astype(np.int8)
+            acc += sq
+        L = int(r.choice([50, 200, 500]))
+        out.append(dict(t=t, bits=bits, n=n, Y=Y, planted=pairs, strengths=s.tolist(), L=L, kappa=0.15))
+    return out
+
+
 def small_binary(n: int, p: int, seed: int, planted=(), flip: float = 0.0, y_bias: float = 0.5) -> Dataset:
     """Small Rademacher problem for parity tests.
 

@@ -135,3 +135,25 @@ def test_concurrent_submitters_and_polling(ctx, shared):
     assert sorted(got) == list(range(16))
     for q, (Y, kw) in enumerate(reqs):
         _same(got[q], ctx.search(x, Y, **kw))
+
+
+def test_exact_requests_in_the_mix(ctx, shared):
+    """Requests flagged exact are answered by the matrix-core search of eq. (1),
+    alongside xyz requests, with the same result as a stand-alone call."""
+    XT, x = shared
+    reqs = _requests(XT, 8, seed=5)
+    r = np.random.default_rng(9)
+    exact = [(np.where(r.random(XT.shape[1]) < 0.5, 1, -1).astype(np.int8), 0.12 + 0.01 * q) for q in range(4)]
+    srv = xyz.xyz_serve_start(ctx.h, 0, workers=2, max_batch=8)
+    try:
+        te = [xyz.xyz_serve_submit(srv, x, Y, kappa=k, exact=True) for Y, k in exact]
+        tx = [xyz.xyz_serve_submit(srv, x, Y, **kw) for Y, kw in reqs]
+        oe = [xyz.xyz_serve_wait(srv, t) for t in te]
+        ox = [xyz.xyz_serve_wait(srv, t) for t in tx]
+    finally:
+        xyz.xyz_serve_stop(srv)
+    for (Y, k), o in zip(exact, oe):
+        ref = ctx.bruteforce(x, Y, k)
+        assert np.array_equal(o["pairs"], ref["pairs"]) and len(o["pairs"]) > 0
+    for (Y, kw), o in zip(reqs, ox):
+        _same(o, ctx.search(x, Y, **kw))
