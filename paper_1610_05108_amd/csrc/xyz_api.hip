@@ -712,7 +712,8 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
         if (colsB[q] < 0 || colsB[q] >= p) return fail(XYZ_EINVAL, "colsB[%lld] out of range", (long long)q);
     HIP_TRY(hipSetDevice(c->device));
     const bool real = x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1;
-    if (!real && n >= (1ll << 29)) return fail(XYZ_EUNSUPPORTED, "brute force needs n < 2^29 (32-bit counts)");
+    if (!real && n >= (1ll << 24))
+        return fail(XYZ_EUNSUPPORTED, "brute force needs n < 2^24 (exact FP32 accumulation of the matrix cores)");
     if (real) {
         // real-valued data: the exhaustive search (m = 0, every pair collides) verified in binary64
         if (colsA || colsB) return fail(XYZ_EUNSUPPORTED, "column lists are supported for +-1 data only");
@@ -763,17 +764,11 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
         HIP_TRY(hipMemcpyAsync(dB, colsB, sizeof(int32_t) * nB, hipMemcpyHostToDevice, st));
     }
     RepInfo *info = nullptr;
-    unsigned long long *scnt = nullptr;
     XYZ_TRY(ws(c, WS_INFO, 1, &info));
-    XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
-    uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
-    Survivor *surv = nullptr;
-    XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
+    HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo), st));
     BruteArgs ba{};
-    ba.XC = x->XC;
-    ba.W32p = x->W32p;
-    ba.nw = (int)((n + 31) / 32);
-    ba.yb = yb;
+    const int nw = (int)((n + 31) / 32);
+    ba.nq = x->W32p >> 2;
     ba.colsA = colsA ? dA : nullptr;
     ba.nA = nA;
     ba.colsB = colsB ? dB : nullptr;
@@ -782,33 +777,74 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     ba.nbA = (nA + BF_TILE - 1) / BF_TILE;
     ba.nbB = (nB + BF_TILE - 1) / BF_TILE;
     ba.ntiles = ba.tri ? (uint64_t)ba.nbA * (ba.nbA + 1) / 2 : (uint64_t)ba.nbA * ba.nbB;
+    {
+        // blocked copies of both sides (z = y ^ x on the A side) and their popcounts
+        uint4 *xa = nullptr, *xb = nullptr;
+        uint32_t *pops = nullptr;
+        XYZ_TRY(ws(c, WS_BXA, (size_t)ba.nbA * ba.nq * BF_TILE, &xa));
+        XYZ_TRY(ws(c, WS_BXB, (size_t)ba.nbB * ba.nq * BF_TILE, &xb));
+        XYZ_TRY(ws(c, WS_BPOP, (size_t)(ba.nbA + ba.nbB) * BF_TILE, &pops));
+        tm.begin(0);
+        HIP_TRY(launch_brute_stage(x->XC, x->W32p, nw, ba.colsA, nA, yb, xa, pops, st));
+        HIP_TRY(launch_brute_stage(x->XC, x->W32p, nw, ba.colsB, nB, nullptr, xb, pops + ba.nbA * BF_TILE, st));
+        tm.end();
+        ba.XBA = xa;
+        ba.XBB = xb;
+        ba.popA = pops;
+        ba.popB = pops + ba.nbA * BF_TILE;
+    }
     ba.n = n;
     ba.smin = xyz_smin(n, kappa, two);
     ba.two_sided = two;
-    ba.surv_count = scnt;
-    ba.info = info;
     ba.grid_blocks = std::max(8, c->cu_count / 8 * 8);
     if (ba.ntiles > 0x7fffffffull) return fail(XYZ_EUNSUPPORTED, "too many column blocks for one launch");
+    // each workgroup of the persistent launch owns cap_wg survivor slots; a workgroup that
+    // finds more reports its count, and the launch is redone with room for the largest
+    const int grid = ba.ntiles ? brute_grid(ba) : 1;
+    uint64_t cap_wg = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor) / grid, 1024);
+    unsigned int *wcnt = nullptr;
+    XYZ_TRY(ws(c, WS_BCNT, grid, &wcnt));
+    std::vector<unsigned int> hcnt(grid);
+    Survivor *surv = nullptr;
     uint64_t S = 0;
     for (;;) {
-        HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
-        HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo), st));
+        XYZ_TRY(ws(c, WS_SURV, cap_wg * grid, &surv));
+        HIP_TRY(hipMemsetAsync(wcnt, 0, sizeof(unsigned int) * grid, st));
         ba.surv = surv;
-        ba.surv_cap = surv_cap;
+        ba.cap_wg = cap_wg;
+        ba.wg_count = wcnt;
         tm.begin(7);
         HIP_TRY(launch_brute(ba, st));
         tm.end();
         timing.verify_launches += 1;
-        unsigned long long cnt = 0;
-        HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hcnt.data(), wcnt, sizeof(unsigned int) * grid, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (cnt <= surv_cap) {
-            S = cnt;
-            break;
+        uint64_t mx = 0;
+        S = 0;
+        for (unsigned int v : hcnt) {
+            mx = std::max<uint64_t>(mx, v);
+            S += v;
         }
-        surv_cap = cnt + cnt / 2;
-        XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
+        if (mx <= cap_wg) break;
+        cap_wg = mx + mx / 4 + 64;
     }
+    // dense survivor list
+    Survivor *dense = nullptr;
+    unsigned long long *doff = nullptr;
+    XYZ_TRY(ws(c, WS_SURV2, std::max<uint64_t>(S, 1), &dense));
+    XYZ_TRY(ws(c, WS_BOFF, grid, &doff));
+    std::vector<unsigned long long> hoff(grid);
+    {
+        unsigned long long acc = 0;
+        for (int g = 0; g < grid; ++g) {
+            hoff[g] = acc;
+            acc += hcnt[g];
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(doff, hoff.data(), sizeof(unsigned long long) * grid, hipMemcpyHostToDevice, st));
+    tm.begin(6);
+    if (S) HIP_TRY(launch_brute_compact(surv, cap_wg, wcnt, doff, grid, dense, st));
+    tm.end();
     uint64_t *dk = nullptr, *dk2 = nullptr;
     uint32_t *dv = nullptr, *dv2 = nullptr, *hist = nullptr, *heads = nullptr;
     OutPair *dout = nullptr;
@@ -824,7 +860,7 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     XYZ_TRY(ws(c, WS_YCNT, 1, &ycnt));
     HIP_TRY(hipMemsetAsync(ycnt, 0, sizeof(unsigned long long), st));
     tm.begin(6);
-    HIP_TRY(launch_dedup(surv, S, p, n, 1, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info, 0, st));
+    HIP_TRY(launch_dedup(dense, S, p, n, 1, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info, 0, st));
     tm.end();
     unsigned long long U = 0;
     HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));

@@ -134,12 +134,13 @@ hipError_t launch_dedup(const Survivor *surv, uint64_t S, int64_t p, int64_t n, 
                         OutPair *out, unsigned long long *nout, unsigned long long *ycount, RepInfo *info,
                         int64_t rep_abs0, hipStream_t st);
 
-// Exact search of eq. (1) over column blocks with int8 matrix cores.
+// Exact search of eq. (1) over column blocks on FP4 matrix cores.
 struct BruteArgs {
-    const uint32_t *XC;      // [p][W32p] bits
-    int W32p;
-    int nw;                  // ceil(n / 32) words holding data
-    const uint32_t *yb;      // bits of Y
+    const uint4 *XBA;        // A side staged: [nbA][nq][BF_TILE] quads of z = y ^ x (zero padded, words 0,2,1,3)
+    const uint4 *XBB;        // B side staged: [nbB][nq][BF_TILE] quads of x
+    const uint32_t *popA;    // [nbA * BF_TILE] popcounts of the staged A columns
+    const uint32_t *popB;    // [nbB * BF_TILE]
+    int nq;                  // quads (4 words, 128 rows) per column
     const int32_t *colsA;    // column ids of the A side (null: identity)
     int64_t nA;
     const int32_t *colsB;    // column ids of the B side (null: identity)
@@ -150,14 +151,24 @@ struct BruteArgs {
     int64_t n;
     int64_t smin;
     int two_sided;
-    Survivor *surv;
-    unsigned long long *surv_count;
-    uint64_t surv_cap;
-    RepInfo *info;           // one entry: passed counts
-    int grid_blocks;         // persistent grid (a multiple of 8)
+    Survivor *surv;          // [grid][cap_wg]: workgroup g writes its survivors at g * cap_wg
+    uint64_t cap_wg;
+    unsigned int *wg_count;  // [grid]: survivors found by each workgroup (may exceed cap_wg)
+    int grid_blocks;         // persistent grid bound (a multiple of 8)
 };
 constexpr int BF_TILE = 256;
+// Stage ncols columns (cols: device ids, or null for 0..ncols-1) into XB [nblk][W32p/4][BF_TILE]
+// quads (words in the order 0, 2, 1, 3), XORed with yb when yb is not null, words >= nw and
+// padding columns zero, and their
+// popcounts into pop [nblk * BF_TILE].
+hipError_t launch_brute_stage(const uint32_t *XC, int W32p, int nw, const int32_t *cols, int64_t ncols,
+                              const uint32_t *yb, uint4 *XB, uint32_t *pop, hipStream_t st);
+// Workgroups of the persistent brute-force launch (a multiple of 8, at most grid_blocks).
+int brute_grid(const BruteArgs &a);
 hipError_t launch_brute(const BruteArgs &a, hipStream_t st);
+// dense[offs[g] + i] = sparse[g * cap + i] for i < count[g], g < grid.
+hipError_t launch_brute_compact(const Survivor *sparse, uint64_t cap, const unsigned int *count,
+                                const unsigned long long *offs, int grid, Survivor *dense, hipStream_t st);
 
 // Collision strengths of uniformly drawn column pairs (for the planner).
 // Pair q: draws u = SplitMix64(seed, 2q+1), v = SplitMix64(seed, 2q+2);

@@ -1090,40 +1090,108 @@ __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
 
 // ------------------------------------------------------- exact brute force --
 //
-// G = Z_A^T X_B for +-1 data on int8 matrix cores.  With bits z = [Y_i X_ia = -1]
+// G = Z_A^T X_B for +-1 data on FP4 matrix cores.  With bits z = [Y_i X_ia = -1]
 // and x = [X_ib = -1], Y_i X_ia X_ib = (1 - 2z)(1 - 2x), so
 //   s = n - 2|z| - 2|x| + 4 C,   C = #{i : z_i = x_i = 1},
-// and C is a dot product of 0/1 int8 vectors.  A workgroup of 8 waves owns a
-// 256 x 256 block of column pairs; each K step expands one 32-row word of each
-// of its 512 columns into 32 bytes of 0/1 in LDS (double buffered), and each
-// wave runs 2 x 4 v_mfma_i32_32x32x32_i8 on its 64 x 128 sub-block.  A and B
-// fragments take the same 16 rows per lane, so the dot products are over the
-// same rows whatever order the instruction pairs them in.
+// and C is the dot product of two 0/1 vectors: exact in FP4 (e2m1 holds 0 and
+// 1) with FP32 accumulation while C < 2^24.
+//
+// Staging (per call): each side's columns are copied into a blocked layout
+// XB[block of 256 columns][quad of 4 words][column in block] (16 bytes: words
+// 0, 2, 1, 3 of the quad), z = y ^ x on the A side, zero words past the data
+// and zero padding columns, with the popcount of every staged column.  In a
+// 32 x 32 x 64 matrix instruction, lanes 0-31 feed 32 rows of one column and
+// lanes 32-63 the next 32 rows, so lane half h of a fragment reads words h and
+// h + 2 of the quad: 8 contiguous bytes, and a wave's fragment load is 512
+// contiguous bytes.
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
-// 4 bits -> 4 bytes of 0/1 (bit q of the nibble to byte q).
-XYZ_DEV uint32_t spread4(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
-
-// XC4 and y4 are kernel arguments of their own so that the compiler sees
-// global, read-only pointers (global loads for the columns, scalar loads for
-// Y's words, which every lane shares).
-__global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint4 *__restrict__ XC4,
-                                               const uint4 *__restrict__ y4)
+// One thread per (block, quad, column): XB[(blk * nq + qi) * 256 + c].
+__global__ __launch_bounds__(256) void k_brute_stage(const uint4 *__restrict__ XC4, int nq, int nw,
+                                                     const int32_t *__restrict__ cols, int64_t ncols,
+                                                     const uint4 *__restrict__ y4, int64_t nblk,
+                                                     uint4 *__restrict__ XB)
 {
-    // LDS: [buffer][word of the step][16-row half][column] -> 16 bytes of 0/1.
-    // Consecutive lanes read consecutive columns of one half: conflict-free.
-    __shared__ uint4 As[2][2][2][BF_TILE];
-    __shared__ uint4 Bs[2][2][2][BF_TILE];
-    __shared__ __align__(16) uint32_t popA[BF_TILE];
-    __shared__ __align__(16) uint32_t popB[BF_TILE];
-    __shared__ int32_t colA[BF_TILE], colB[BF_TILE];
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (uint64_t)nblk * nq * BF_TILE) return;
+    const int c = (int)(i % BF_TILE);
+    const uint64_t bq = i / BF_TILE;
+    const int qi = (int)(bq % (uint64_t)nq);
+    const int64_t ci = (int64_t)(bq / (uint64_t)nq) * BF_TILE + c;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (ci < ncols) {
+        const int64_t col = cols ? cols[ci] : ci;
+        v = XC4[col * nq + qi];
+        if (y4) {
+            const uint4 yq = y4[qi];
+            v.x ^= yq.x;
+            v.y ^= yq.y;
+            v.z ^= yq.z;
+            v.w ^= yq.w;
+        }
+        const int w = qi * 4;
+        if (w >= nw) v.x = 0;
+        if (w + 1 >= nw) v.y = 0;
+        if (w + 2 >= nw) v.z = 0;
+        if (w + 3 >= nw) v.w = 0;
+    }
+    XB[i] = make_uint4(v.x, v.z, v.y, v.w);
+}
+
+// Popcount of every staged column (one thread per column, coalesced over c).
+__global__ __launch_bounds__(256) void k_brute_pop(const uint4 *__restrict__ XB, int nq, int64_t nblk,
+                                                   uint32_t *__restrict__ pop)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (uint64_t)nblk * BF_TILE) return;
+    const uint64_t blk = i / BF_TILE, c = i % BF_TILE;
+    const uint4 *src = XB + blk * (uint64_t)nq * BF_TILE + c;
+    uint32_t pc = 0;
+    for (int qi = 0; qi < nq; ++qi) {
+        const uint4 v = src[(uint64_t)qi * BF_TILE];
+        pc += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+    }
+    pop[i] = pc;
+}
+
+// 32 bits of one column word -> 32 e2m1 nibbles (the low half of an FP4
+// operand), 1.0 (0b0010) for a set bit and 0 otherwise.  Dword d holds bits d,
+// d + 4, ..., d + 28 (nibble q <- bit 4q + d): any fixed assignment of rows to
+// nibbles works, because A and B fragments are expanded the same way and the
+// product sums over all of them.
+XYZ_DEV v8i expand_fp4(uint32_t w)
+{
+    return v8i{(int)((w << 1) & 0x22222222u), (int)(w & 0x22222222u), (int)((w >> 1) & 0x22222222u),
+               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+
+// A workgroup of 8 waves owns a 256 x 256 block of column pairs; wave (wa, wb)
+// computes the 64 x 128 sub-block of A columns wa*64.. and B columns wb*128..
+// as 2 x 4 fragments of 32 x 32.  Each lane loads its fragments' words straight
+// from the staged layout (the waves of a workgroup share them through the L1
+// cache), expands them in registers and feeds the matrix cores: no barriers,
+// and quads are loaded two steps ahead.  XA and XB are kernel
+// arguments of their own so that the compiler sees global, read-only pointers.
+struct BruteFrag {
+    uint2 a[2], b[4];        // words (h, h + 2) of quad qi for the lane's 2 A and 4 B columns
+};
+
+__global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restrict__ XA,
+                                               const uint2 *__restrict__ XB)
+{
+    __shared__ float fragbuf[8][16][64];             // per wave: one fragment of the rare pass
+    __shared__ unsigned int wg_n;                    // survivors of this workgroup so far
     const int tid = threadIdx.x;
-    const int side = tid >> 8, cc = tid & 255;
+    if (tid == 0) wg_n = 0;
+    __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
-    const int wa = wave >> 1, wb = wave & 1;     // wave sub-block: rows wa*64.., columns wb*128..
-    const int nq = a.W32p >> 2;                   // uint4 per column
+    const int wa = wave >> 1, wb = wave & 1;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int nq = a.nq;
+    const uint64_t qstride = 2 * BF_TILE;            // uint2 per quad of a block
+    const int32_t n32 = (int32_t)a.n, smin32 = (int32_t)a.smin;
     // blocks g = x mod 8 run on XCD x; G and the grid are multiples of 8, so
     // t(g) is a bijection onto [0, G) and each XCD gets a contiguous range
     const uint64_t G = (a.ntiles + 7) / 8 * 8;
@@ -1141,131 +1209,128 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint4 *__restr
             bi = t / (uint64_t)a.nbB;
             bj = t % (uint64_t)a.nbB;
         }
-        {
-            const int64_t ci = (int64_t)(side ? bj : bi) * BF_TILE + cc;
-            const int64_t lim = side ? a.nB : a.nA;
-            const int32_t *lst = side ? a.colsB : a.colsA;
-            const int32_t col = ci < lim ? (lst ? lst[ci] : (int32_t)ci) : -1;
-            if (side) colB[cc] = col; else colA[cc] = col;
-        }
-        lds_barrier();
-        const int32_t mycol = side ? colB[cc] : colA[cc];
-        const bool live = mycol >= 0;               // padding columns read column 0 and use zeros
-        const uint4 *src = XC4 + (int64_t)(live ? mycol : 0) * nq;
-        v16i acc[2][4];
+        const uint2 *pa = XA + bi * (uint64_t)nq * qstride + 2 * (wa * 64 + l32) + h;
+        const uint2 *pb = XB + bj * (uint64_t)nq * qstride + 2 * (wb * 128 + l32) + h;
+        auto load = [&](BruteFrag &f, int qi) {
+            const uint64_t o = (uint64_t)min(qi, nq - 1) * qstride;   // clamped: past the end is never used
+#pragma unroll
+            for (int u = 0; u < 2; ++u) f.a[u] = pa[o + 2 * 32 * u];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) f.b[v] = pb[o + 2 * 32 * v];
+        };
+        v16f acc[2][4];
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = v16i{};
-        uint32_t pc = 0;
-        // one step: expand two 32-row words into LDS buffer `buf`, then 16 MFMAs
-        auto step = [&](uint32_t w0, uint32_t w1, int buf) {
-            const uint32_t wd[2] = {w0, w1};
+            for (int v = 0; v < 4; ++v) acc[u][v] = v16f{};
+        auto step = [&](BruteFrag &f, int qi) {
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const uint32_t word = wd[k];
-                pc += __popc(word);
-                uint4 lo, hi;
-                lo.x = spread4(word & 15u);
-                lo.y = spread4((word >> 4) & 15u);
-                lo.z = spread4((word >> 8) & 15u);
-                lo.w = spread4((word >> 12) & 15u);
-                hi.x = spread4((word >> 16) & 15u);
-                hi.y = spread4((word >> 20) & 15u);
-                hi.z = spread4((word >> 24) & 15u);
-                hi.w = spread4(word >> 28);
-                if (side) {
-                    Bs[buf][k][0][cc] = lo;
-                    Bs[buf][k][1][cc] = hi;
-                } else {
-                    As[buf][k][0][cc] = lo;
-                    As[buf][k][1][cc] = hi;
-                }
-            }
-            lds_barrier();
+                v8i fa[2], fb[4];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                v4i fa[2], fb[4];
+                for (int u = 0; u < 2; ++u) fa[u] = expand_fp4(k ? f.a[u].y : f.a[u].x);
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const uint4 q = As[buf][k][lane >> 5][wa * 64 + u * 32 + (lane & 31)];
-                    fa[u] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const uint4 q = Bs[buf][k][lane >> 5][wb * 128 + v * 32 + (lane & 31)];
-                    fb[v] = v4i{(int)q.x, (int)q.y, (int)q.z, (int)q.w};
-                }
+                for (int v = 0; v < 4; ++v) fb[v] = expand_fp4(k ? f.b[v].y : f.b[v].x);
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        acc[u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[u], fb[v], acc[u][v], 0, 0, 0);
+                        acc[u][v] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[u], fb[v], acc[u][v], 4, 4, 0,
+                                                                                     127, 0, 127);
+            }
+            load(f, qi + 2);
+            // keep the loads where they are: each set is consumed two steps later
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        BruteFrag f0, f1;
+        load(f0, 0);
+        load(f1, 1);
+        int qi = 0;
+        for (; qi + 1 < nq; qi += 2) {      // no branches inside: each wait is for the oldest loads only
+            step(f0, qi);
+            step(f1, qi + 1);
+        }
+        if (qi < nq) step(f0, qi);
+
+        // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
+        // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b|, exact in FP32
+        // (|values| < 2^26).  A cheap test of the row maximum (and minimum, two-sided) runs on every
+        // fragment; the rare fragments that hit are checked pair by pair.
+        const bool diag = a.tri && bi == bj;
+        // 2|z_a| of the lane's 16 rows of A fragment u
+        auto rows_pop2 = [&](int u, float *tA) {
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint4 v4 = *reinterpret_cast<const uint4 *>(
+                    &a.popA[bi * BF_TILE + wa * 64 + u * 32 + q4 * 8 + h * 4]);
+                tA[4 * q4 + 0] = (float)(2 * (int32_t)v4.x);
+                tA[4 * q4 + 1] = (float)(2 * (int32_t)v4.y);
+                tA[4 * q4 + 2] = (float)(2 * (int32_t)v4.z);
+                tA[4 * q4 + 3] = (float)(2 * (int32_t)v4.w);
             }
         };
-        // quads of 4 words (128 rows): the next quad is loaded while this one is used;
-        // Y's words are the same for every lane (scalar loads)
-        const int nquad = (a.nw + 3) >> 2;
-        const uint4 zero4 = make_uint4(0, 0, 0, 0);
-        uint4 q = src[0];
-        if (!live) q = zero4;
-        for (int qi = 0; qi < nquad; ++qi) {
-            uint4 qn = src[min(qi + 1, nq - 1)];
-            if (!live || qi + 1 >= nq) qn = zero4;
-            if (!side && live) {
-                const uint4 yq = y4[qi];
-                q.x ^= yq.x;
-                q.y ^= yq.y;
-                q.z ^= yq.z;
-                q.w ^= yq.w;
-            }
-            const int w = qi * 4;   // words past nw are zero (padding), so they add nothing
-            step(q.x, w + 1 < a.nw ? q.y : 0u, 0);
-            if (w + 2 < a.nw) step(q.z, w + 3 < a.nw ? q.w : 0u, 1);
-            q = qn;
-        }
-        if (side) popB[cc] = pc; else popA[cc] = pc;
-        lds_barrier();
-        // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
-        // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b| (32-bit: 4n < 2^31);
-        // the cheap test runs on every pair, the validity checks only on the few that pass.
-        const bool diag = a.tri && bi == bj;
-        const int32_t n32 = (int32_t)a.n, smin32 = (int32_t)a.smin;
+        uint32_t hitmask = 0;     // bit u*4+v: this lane has a candidate in fragment (u, v)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            int32_t pa16[16];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v4 = *reinterpret_cast<const uint4 *>(&popA[wa * 64 + u * 32 + q * 8 + (lane >> 5) * 4]);
-                pa16[4 * q + 0] = 2 * (int32_t)v4.x;
-                pa16[4 * q + 1] = 2 * (int32_t)v4.y;
-                pa16[4 * q + 2] = 2 * (int32_t)v4.z;
-                pa16[4 * q + 3] = 2 * (int32_t)v4.w;
-            }
+            float tA[16];
+            rows_pop2(u, tA);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int cb = wb * 128 + v * 32 + (lane & 31);
-                const int32_t pb2 = 2 * (int32_t)popB[cb];
-                const int32_t hi = smin32 - n32 + pb2;         // s >= smin
-                const int32_t lo = -smin32 - n32 + pb2;        // s <= -smin (two-sided)
-                uint32_t passmask = 0;
+                const int32_t pb2 = 2 * (int32_t)a.popB[bj * BF_TILE + wb * 128 + v * 32 + l32];
+                float mx = -1e30f, mn = 1e30f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int32_t x = 4 * acc[u][v][r] - pa16[r];
-                    const bool pass = x >= hi || (a.two_sided && x <= lo);
-                    passmask |= (pass ? 1u : 0u) << r;
+                    const float x = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
+                    mx = fmaxf(mx, x);
+                    if (a.two_sided) mn = fminf(mn, x);
                 }
-                if (__ballot(passmask != 0) == 0) continue;
-                const int32_t gb = colB[cb];
-                uint32_t m = passmask;
-                while (m) {
-                    const int r = __ffs(m) - 1;
-                    m &= m - 1;
-                    const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                    const int32_t ga = colA[ra];
-                    if (!(ga >= 0 && gb >= 0 && ga != gb && (!diag || ra < cb))) passmask &= ~(1u << r);
+                const bool hit = mx >= (float)(smin32 - n32 + pb2) || (a.two_sided && mn <= (float)(-smin32 - n32 + pb2));
+                hitmask |= (hit ? 1u : 0u) << (u * 4 + v);
+            }
+        }
+        if (__ballot(hitmask != 0) == 0) continue;
+        // pair-by-pair pass on the fragments that hit (rare): x = 4C - 2|z_a| of the fragment goes
+        // to the wave's LDS slot, so that the pass can index its rows at run time, then validity
+        // (padding columns, j != k, a < b on a diagonal block) and the survivors' slots, with one
+        // atomic per fragment and wave.  s = n - 2|x_b| + x.
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            float tA[16];
+            rows_pop2(u, tA);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (__ballot((hitmask >> (u * 4 + v)) & 1u) == 0) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) fragbuf[wave][r][lane] = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
+                const int cb = wb * 128 + v * 32 + l32;
+                const int64_t cjb = (int64_t)bj * BF_TILE + cb;
+                const bool okb = cjb < a.nB && ((hitmask >> (u * 4 + v)) & 1u);
+                const int32_t gb = cjb < a.nB ? (a.colsB ? a.colsB[cjb] : (int32_t)cjb) : -1;
+                const int32_t pb2 = 2 * (int32_t)a.popB[bj * BF_TILE + cb];
+                const int32_t hi = smin32 - n32 + pb2, lo = -smin32 - n32 + pb2;
+                const int row0 = wa * 64 + u * 32 + h * 4;
+                uint32_t m = 0;
+                if (okb) {
+#pragma unroll 4
+                    for (int r = 0; r < 16; ++r) {
+                        const int ra = row0 + (r >> 2) * 8 + (r & 3);
+                        const int32_t x = (int32_t)fragbuf[wave][r][lane];
+                        const bool pass = x >= hi || (a.two_sided && x <= lo);
+                        const bool ok = (int64_t)bi * BF_TILE + ra < a.nA && !(diag && ra >= cb);
+                        m |= (pass && ok ? 1u : 0u) << r;
+                    }
                 }
-                const int mine = __popc(passmask);
+                // with column lists a column can meet itself (the same id on both sides); with
+                // identity lists that happens only on a diagonal block, excluded by a < b
+                if (a.colsA || a.colsB) {
+                    for (uint32_t mm = m; mm;) {
+                        const int r = __ffs(mm) - 1;
+                        mm &= mm - 1;
+                        const int64_t cja = (int64_t)bi * BF_TILE + row0 + (r >> 2) * 8 + (r & 3);
+                        if ((a.colsA ? a.colsA[cja] : (int32_t)cja) == gb) m &= ~(1u << r);
+                    }
+                }
+                const int mine = __popc(m);
                 int incl = mine;
 #pragma unroll
                 for (int d = 1; d < 64; d <<= 1) {
@@ -1274,41 +1339,47 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint4 *__restr
                 }
                 const int total = __shfl(incl, 63, 64);
                 if (total == 0) continue;
-                unsigned long long base = 0;
-                if (lane == 0) {
-                    base = atomicAdd(a.surv_count, (unsigned long long)total);
-                    atomicAdd(&a.info[0].passed, (unsigned long long)total);
-                }
+                unsigned int base = 0;
+                if (lane == 0) base = atomicAdd(&wg_n, (unsigned int)total);
                 base = __shfl(base, 0, 64);
-                unsigned long long idx = base + (unsigned long long)(incl - mine);
-                while (passmask) {
-                    const int r = __ffs(passmask) - 1;
-                    passmask &= passmask - 1;
-                    const int ra = wa * 64 + u * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                    const int32_t ga = colA[ra];
-                    if (idx < a.surv_cap) {
-                        int32_t cval = 0;
-#pragma unroll
-                        for (int q = 0; q < 16; ++q)
-                            if (q == r) cval = acc[u][v][q];
+                uint64_t idx = base + (uint64_t)(incl - mine);
+                Survivor *mysurv = a.surv + (uint64_t)blockIdx.x * a.cap_wg;
+                while (m) {
+                    const int r = __ffs(m) - 1;
+                    m &= m - 1;
+                    const int64_t cja = (int64_t)bi * BF_TILE + row0 + (r >> 2) * 8 + (r & 3);
+                    const int32_t ga = a.colsA ? a.colsA[cja] : (int32_t)cja;
+                    if (idx < a.cap_wg) {
                         Survivor sv;
                         sv.j = (uint32_t)min(ga, gb);
                         sv.k = (uint32_t)max(ga, gb);
                         sv.rep = 0;
-                        sv.s = n32 - 2 * (int32_t)(popA[ra] + popB[cb]) + 4 * cval;
+                        sv.s = n32 - pb2 + (int32_t)fragbuf[wave][r][lane];
                         sv.value = (double)sv.s;
                         sv.ysel = 0;
                         sv.pad = 0;
-                        a.surv[idx] = sv;
+                        mysurv[idx] = sv;
                     }
                     ++idx;
                 }
             }
         }
-        lds_barrier();   // colA/colB/popA/popB are rewritten by the next block pair
     }
+    __syncthreads();
+    if (tid == 0) a.wg_count[blockIdx.x] = wg_n;
 }
 
+// Dense copy of the workgroups' survivor regions: workgroup g's count[g] survivors
+// (at most cap each) go to dense[offs[g] ...].
+__global__ __launch_bounds__(256) void k_brute_compact(const Survivor *__restrict__ sparse, uint64_t cap,
+                                                       const unsigned int *__restrict__ count,
+                                                       const unsigned long long *__restrict__ offs,
+                                                       Survivor *__restrict__ dense)
+{
+    const int g = blockIdx.x;
+    const unsigned int c = count[g];
+    for (unsigned int i = threadIdx.x; i < c; i += 256) dense[offs[g] + i] = sparse[(uint64_t)g * cap + i];
+}
 
 // ---------------------------------------------------------------- planner --
 
@@ -1674,13 +1745,40 @@ hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStre
     return hipGetLastError();
 }
 
+hipError_t launch_brute_stage(const uint32_t *XC, int W32p, int nw, const int32_t *cols, int64_t ncols,
+                              const uint32_t *yb, uint4 *XB, uint32_t *pop, hipStream_t st)
+{
+    const int nq = W32p >> 2;
+    const int64_t nblk = (ncols + BF_TILE - 1) / BF_TILE;
+    if (nblk == 0) return hipSuccess;
+    const uint64_t total = (uint64_t)nblk * nq * BF_TILE;
+    hipLaunchKernelGGL(k_brute_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<const uint4 *>(XC), nq, nw, cols, ncols, reinterpret_cast<const uint4 *>(yb),
+                       nblk, XB);
+    hipLaunchKernelGGL(k_brute_pop, dim3((unsigned)((nblk * BF_TILE + 255) / 256)), dim3(256), 0, st, XB, nq, nblk,
+                       pop);
+    return hipGetLastError();
+}
+
+int brute_grid(const BruteArgs &a)
+{
+    const uint64_t G = (a.ntiles + 7) / 8 * 8;
+    return (int)std::min<uint64_t>(G, (uint64_t)a.grid_blocks);
+}
+
+hipError_t launch_brute_compact(const Survivor *sparse, uint64_t cap, const unsigned int *count,
+                                const unsigned long long *offs, int grid, Survivor *dense, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_brute_compact, dim3(grid), dim3(256), 0, st, sparse, cap, count, offs, dense);
+    return hipGetLastError();
+}
+
 hipError_t launch_brute(const BruteArgs &a, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
-    const uint64_t G = (a.ntiles + 7) / 8 * 8;
-    const uint64_t grid = std::min<uint64_t>(G, (uint64_t)a.grid_blocks);
-    hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a, reinterpret_cast<const uint4 *>(a.XC),
-                       reinterpret_cast<const uint4 *>(a.yb));
+    const uint64_t grid = (uint64_t)brute_grid(a);
+    hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a, reinterpret_cast<const uint2 *>(a.XBA),
+                       reinterpret_cast<const uint2 *>(a.XBB));
     return hipGetLastError();
 }
 

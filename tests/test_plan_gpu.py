@@ -66,9 +66,10 @@ def test_sampled_strengths_predict_candidates(ctx):
 
 
 def test_plan_strong_pair_uses_xyz_and_finds_it(ctx):
-    XT = synthgen.rademacher(1000, 20000, seed=7)
+    # large p: the exact search grows as p^2, xyz about as p for a strong pair
+    XT = synthgen.rademacher(1000, 200_000, seed=7)
     r = np.random.default_rng(1)
-    Y = (XT[10].astype(np.int16) * XT[12000]).astype(np.int8)
+    Y = (XT[10].astype(np.int16) * XT[120_000]).astype(np.int8)
     flip = r.random(1000) < 0.05          # strength about 0.95
     Y[flip] = -Y[flip]
     x = ctx.x_create(XT)
@@ -77,7 +78,7 @@ def test_plan_strong_pair_uses_xyz_and_finds_it(ctx):
     assert plan["predicted_recall"] >= 0.99 and plan["predicted_ms"] < plan["brute_ms"]
     assert plan["L"] == theory.L_for(0.99, 0.9 ** plan["m"])
     res = ctx.search(x, Y, m=plan["m"], L=plan["L"], kappa=0.5, seed=3)
-    assert (10, 12000) in set(zip(res["pairs"]["j"].tolist(), res["pairs"]["k"].tolist()))
+    assert (10, 120_000) in set(zip(res["pairs"]["j"].tolist(), res["pairs"]["k"].tolist()))
 
 
 def test_plan_weak_target_prefers_brute_force(ctx):
