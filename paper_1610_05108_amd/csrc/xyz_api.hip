@@ -777,6 +777,9 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     ba.nbA = (nA + BF_TILE - 1) / BF_TILE;
     ba.nbB = (nB + BF_TILE - 1) / BF_TILE;
     ba.ntiles = ba.tri ? (uint64_t)ba.nbA * (ba.nbA + 1) / 2 : (uint64_t)ba.nbA * ba.nbB;
+    ba.nsbA = (ba.nbA + 7) / 8;
+    ba.nsbB = (ba.nbB + 7) / 8;
+    ba.nslots = 64 * (ba.tri ? (uint64_t)ba.nsbA * (ba.nsbA + 1) / 2 : (uint64_t)ba.nsbA * ba.nsbB);
     {
         // blocked copies of both sides (z = y ^ x on the A side) and their popcounts
         uint4 *xa = nullptr, *xb = nullptr;
@@ -797,7 +800,7 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     ba.smin = xyz_smin(n, kappa, two);
     ba.two_sided = two;
     ba.grid_blocks = std::max(8, c->cu_count / 8 * 8);
-    if (ba.ntiles > 0x7fffffffull) return fail(XYZ_EUNSUPPORTED, "too many column blocks for one launch");
+    if (ba.nslots > 0x7fffffffull) return fail(XYZ_EUNSUPPORTED, "too many column blocks for one launch");
     // each workgroup of the persistent launch owns cap_wg survivor slots; a workgroup that
     // finds more reports its count, and the launch is redone with room for the largest
     const int grid = ba.ntiles ? brute_grid(ba) : 1;

@@ -137,7 +137,7 @@ hipError_t launch_dedup(const Survivor *surv, uint64_t S, int64_t p, int64_t n, 
 // Exact search of eq. (1) over column blocks on FP4 matrix cores.
 struct BruteArgs {
     const uint4 *XBA;        // A side staged: [nbA][nq][BF_TILE] quads of z = y ^ x (zero padded, words 0,2,1,3)
-    const uint4 *XBB;        // B side staged: [nbB][nq][BF_TILE] quads of x
+    const uint4 *XBB;        // B side staged: [nbB][nq][BF_TILE] quads of x (nibble bits 0, 2 swapped)
     const uint32_t *popA;    // [nbA * BF_TILE] popcounts of the staged A columns
     const uint32_t *popB;    // [nbB * BF_TILE]
     int nq;                  // quads (4 words, 128 rows) per column
@@ -148,6 +148,8 @@ struct BruteArgs {
     int tri;                 // A and B are the same list: only block pairs bi <= bj, and a < b on the diagonal
     int64_t nbA, nbB;        // number of 256-column blocks per side
     uint64_t ntiles;         // block pairs
+    int64_t nsbA, nsbB;      // super-blocks of 8 x 8 block pairs per side (ceil(nb / 8))
+    uint64_t nslots;         // work slots: 64 per super-block (upper triangle of super-blocks when tri)
     int64_t n;
     int64_t smin;
     int two_sided;
@@ -158,8 +160,8 @@ struct BruteArgs {
 };
 constexpr int BF_TILE = 256;
 // Stage ncols columns (cols: device ids, or null for 0..ncols-1) into XB [nblk][W32p/4][BF_TILE]
-// quads (words in the order 0, 2, 1, 3), XORed with yb when yb is not null, words >= nw and
-// padding columns zero, and their
+// quads (words in the order 0, 2, 1, 3): with yb, the A side z = y ^ x; without, the B side x
+// with bits 0 and 2 of every nibble swapped; words >= nw and padding columns zero; and their
 // popcounts into pop [nblk * BF_TILE].
 hipError_t launch_brute_stage(const uint32_t *XC, int W32p, int nw, const int32_t *cols, int64_t ncols,
                               const uint32_t *yb, uint4 *XB, uint32_t *pop, hipStream_t st);

@@ -1108,7 +1108,13 @@ __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// One thread per (block, quad, column): XB[(blk * nq + qi) * 256 + c].
+XYZ_DEV uint32_t swap02(uint32_t w)
+{
+    return (w & 0xAAAAAAAAu) | ((w & 0x11111111u) << 2) | ((w >> 2) & 0x11111111u);
+}
+
+// One thread per (block, quad, column): XB[(blk * nq + qi) * 256 + c].  The A side
+// (y given) holds z = y ^ x; the B side holds x with bits 0 and 2 of every nibble swapped.
 __global__ __launch_bounds__(256) void k_brute_stage(const uint4 *__restrict__ XC4, int nq, int nw,
                                                      const int32_t *__restrict__ cols, int64_t ncols,
                                                      const uint4 *__restrict__ y4, int64_t nblk,
@@ -1137,6 +1143,13 @@ __global__ __launch_bounds__(256) void k_brute_stage(const uint4 *__restrict__ X
         if (w + 2 >= nw) v.z = 0;
         if (w + 3 >= nw) v.w = 0;
     }
+    if (!y4) {
+        // B side: swap bits 0 and 2 of every nibble (see expand_a / expand_b)
+        v.x = swap02(v.x);
+        v.y = swap02(v.y);
+        v.z = swap02(v.z);
+        v.w = swap02(v.w);
+    }
     XB[i] = make_uint4(v.x, v.z, v.y, v.w);
 }
 
@@ -1157,13 +1170,23 @@ __global__ __launch_bounds__(256) void k_brute_pop(const uint4 *__restrict__ XB,
 }
 
 // 32 bits of one column word -> 32 e2m1 nibbles (the low half of an FP4
-// operand), 1.0 (0b0010) for a set bit and 0 otherwise.  Dword d holds bits d,
-// d + 4, ..., d + 28 (nibble q <- bit 4q + d): any fixed assignment of rows to
-// nibbles works, because A and B fragments are expanded the same way and the
-// product sums over all of them.
-XYZ_DEV v8i expand_fp4(uint32_t w)
+// operand), nonzero for a set bit.  Row r = 4q + e of the word (nibble q, e in
+// 0..3) goes to nibble q of dword e.  On the A side a set bit keeps its place
+// in the nibble, so dwords 0, 1, 2 hold the values 0.5, 1, 2 (e2m1 0b0001,
+// 0b0010, 0b0100) with one AND each, and dword 3 moves bit 3 to bit 1 (1.0).
+// The B side was staged with bits 0 and 2 of each nibble swapped, so the same
+// masks give it the values 2, 1, 0.5, 1: every product of two set bits is
+// exactly 1.  Which rows share a nibble does not matter, because A and B
+// assign rows to (dword, nibble) the same way and the product sums over all.
+XYZ_DEV v8i expand_a(uint32_t w)
 {
-    return v8i{(int)((w << 1) & 0x22222222u), (int)(w & 0x22222222u), (int)((w >> 1) & 0x22222222u),
+    return v8i{(int)(w & 0x11111111u), (int)(w & 0x22222222u), (int)(w & 0x44444444u),
+               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+
+XYZ_DEV v8i expand_b(uint32_t w)
+{
+    return v8i{(int)(w & 0x44444444u), (int)(w & 0x22222222u), (int)(w & 0x11111111u),
                (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
 }
 
@@ -1172,12 +1195,13 @@ XYZ_DEV v8i expand_fp4(uint32_t w)
 // as 2 x 4 fragments of 32 x 32.  Each lane loads its fragments' words straight
 // from the staged layout (the waves of a workgroup share them through the L1
 // cache), expands them in registers and feeds the matrix cores: no barriers,
-// and quads are loaded two steps ahead.  XA and XB are kernel
+// and quads are loaded three steps ahead.  XA and XB are kernel
 // arguments of their own so that the compiler sees global, read-only pointers.
 struct BruteFrag {
     uint2 a[2], b[4];        // words (h, h + 2) of quad qi for the lane's 2 A and 4 B columns
 };
 
+template <bool TWO>
 __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restrict__ XA,
                                                const uint2 *__restrict__ XB)
 {
@@ -1192,23 +1216,27 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
     const int nq = a.nq;
     const uint64_t qstride = 2 * BF_TILE;            // uint2 per quad of a block
     const int32_t n32 = (int32_t)a.n, smin32 = (int32_t)a.smin;
-    // blocks g = x mod 8 run on XCD x; G and the grid are multiples of 8, so
-    // t(g) is a bijection onto [0, G) and each XCD gets a contiguous range
-    const uint64_t G = (a.ntiles + 7) / 8 * 8;
+    // Work slots: block pairs grouped in super-blocks of 8 x 8 (slot t: super-block t / 64,
+    // then row-major inside it), so that the 32 workgroups an XCD runs at a time share 12
+    // blocks in its L2.  Workgroups g = x mod 8 run on XCD x; the slot count and the grid
+    // are multiples of 8, so t(g) is a bijection and each XCD gets a contiguous range.
+    const uint64_t G = a.nslots;
     const uint64_t per = G / 8;
     for (uint64_t g = blockIdx.x; g < G; g += gridDim.x) {
         const uint64_t t = (g % 8) * per + g / 8;
-        if (t >= a.ntiles) continue;
-        uint64_t bi, bj;
+        const uint64_t sb = t / 64, w = t % 64;
+        uint64_t I, J;
         if (a.tri) {
             uint32_t i0, j0;
-            tri_index(t, (uint64_t)a.nbA, i0, j0);
-            bi = i0;
-            bj = j0;
+            tri_index(sb, (uint64_t)a.nsbA, i0, j0);
+            I = i0;
+            J = j0;
         } else {
-            bi = t / (uint64_t)a.nbB;
-            bj = t % (uint64_t)a.nbB;
+            I = sb / (uint64_t)a.nsbB;
+            J = sb % (uint64_t)a.nsbB;
         }
+        const uint64_t bi = I * 8 + w / 8, bj = J * 8 + w % 8;
+        if (bi >= (uint64_t)a.nbA || bj >= (uint64_t)a.nbB || (a.tri && bi > bj)) continue;
         const uint2 *pa = XA + bi * (uint64_t)nq * qstride + 2 * (wa * 64 + l32) + h;
         const uint2 *pb = XB + bj * (uint64_t)nq * qstride + 2 * (wb * 128 + l32) + h;
         auto load = [&](BruteFrag &f, int qi) {
@@ -1228,9 +1256,9 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
             for (int k = 0; k < 2; ++k) {
                 v8i fa[2], fb[4];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) fa[u] = expand_fp4(k ? f.a[u].y : f.a[u].x);
+                for (int u = 0; u < 2; ++u) fa[u] = expand_a(k ? f.a[u].y : f.a[u].x);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) fb[v] = expand_fp4(k ? f.b[v].y : f.b[v].x);
+                for (int v = 0; v < 4; ++v) fb[v] = expand_b(k ? f.b[v].y : f.b[v].x);
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -1238,20 +1266,27 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
                         acc[u][v] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[u], fb[v], acc[u][v], 4, 4, 0,
                                                                                      127, 0, 127);
             }
-            load(f, qi + 2);
-            // keep the loads where they are: each set is consumed two steps later
+            load(f, qi + 3);
+            // keep the loads where they are: each set is consumed three steps later
             __builtin_amdgcn_sched_barrier(0);
         };
-        BruteFrag f0, f1;
+        BruteFrag f0, f1, f2;
         load(f0, 0);
         load(f1, 1);
+        load(f2, 2);
         int qi = 0;
-        for (; qi + 1 < nq; qi += 2) {      // no branches inside: each wait is for the oldest loads only
+        for (; qi + 2 < nq; qi += 3) {      // no branches inside: each wait is for the oldest loads only
             step(f0, qi);
             step(f1, qi + 1);
+            step(f2, qi + 2);
         }
         if (qi < nq) step(f0, qi);
+        if (qi + 1 < nq) step(f1, qi + 1);
 
+        // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
+        // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b|, exact in FP32
+        // (|values| < 2^26).  A cheap test of the row maximum (and minimum, two-sided) runs on every
+        // fragment; the rare fragments that hit are checked pair by pair.
         // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
         // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b|, exact in FP32
         // (|values| < 2^26).  A cheap test of the row maximum (and minimum, two-sided) runs on every
@@ -1282,9 +1317,9 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
                 for (int r = 0; r < 16; ++r) {
                     const float x = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
                     mx = fmaxf(mx, x);
-                    if (a.two_sided) mn = fminf(mn, x);
+                    if (TWO) mn = fminf(mn, x);
                 }
-                const bool hit = mx >= (float)(smin32 - n32 + pb2) || (a.two_sided && mn <= (float)(-smin32 - n32 + pb2));
+                const bool hit = mx >= (float)(smin32 - n32 + pb2) || (TWO && mn <= (float)(-smin32 - n32 + pb2));
                 hitmask |= (hit ? 1u : 0u) << (u * 4 + v);
             }
         }
@@ -1315,7 +1350,7 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
                     for (int r = 0; r < 16; ++r) {
                         const int ra = row0 + (r >> 2) * 8 + (r & 3);
                         const int32_t x = (int32_t)fragbuf[wave][r][lane];
-                        const bool pass = x >= hi || (a.two_sided && x <= lo);
+                        const bool pass = x >= hi || (TWO && x <= lo);
                         const bool ok = (int64_t)bi * BF_TILE + ra < a.nA && !(diag && ra >= cb);
                         m |= (pass && ok ? 1u : 0u) << r;
                     }
@@ -1762,8 +1797,7 @@ hipError_t launch_brute_stage(const uint32_t *XC, int W32p, int nw, const int32_
 
 int brute_grid(const BruteArgs &a)
 {
-    const uint64_t G = (a.ntiles + 7) / 8 * 8;
-    return (int)std::min<uint64_t>(G, (uint64_t)a.grid_blocks);
+    return (int)std::min<uint64_t>(a.nslots, (uint64_t)a.grid_blocks);
 }
 
 hipError_t launch_brute_compact(const Survivor *sparse, uint64_t cap, const unsigned int *count,
@@ -1777,8 +1811,11 @@ hipError_t launch_brute(const BruteArgs &a, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
     const uint64_t grid = (uint64_t)brute_grid(a);
-    hipLaunchKernelGGL(k_brute, dim3((unsigned)grid), dim3(512), 0, st, a, reinterpret_cast<const uint2 *>(a.XBA),
-                       reinterpret_cast<const uint2 *>(a.XBB));
+    const uint2 *XA = reinterpret_cast<const uint2 *>(a.XBA), *XB = reinterpret_cast<const uint2 *>(a.XBB);
+    if (a.two_sided)
+        hipLaunchKernelGGL(k_brute<true>, dim3((unsigned)grid), dim3(512), 0, st, a, XA, XB);
+    else
+        hipLaunchKernelGGL(k_brute<false>, dim3((unsigned)grid), dim3(512), 0, st, a, XA, XB);
     return hipGetLastError();
 }
 
