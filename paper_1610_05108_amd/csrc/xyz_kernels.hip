@@ -1287,10 +1287,6 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
         // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b|, exact in FP32
         // (|values| < 2^26).  A cheap test of the row maximum (and minimum, two-sided) runs on every
         // fragment; the rare fragments that hit are checked pair by pair.
-        // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
-        // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b|, exact in FP32
-        // (|values| < 2^26).  A cheap test of the row maximum (and minimum, two-sided) runs on every
-        // fragment; the rare fragments that hit are checked pair by pair.
         const bool diag = a.tri && bi == bj;
         // 2|z_a| of the lane's 16 rows of A fragment u
         auto rows_pop2 = [&](int u, float *tA) {
