@@ -1,0 +1,195 @@
+"""Parity at the workloads' full sizes, in the configuration the benchmark runs.
+
+The oracle cannot search these sizes whole, so the checks are of three kinds:
+bit-exact agreement with the oracle on a few repetitions (genotype workload),
+per-pair values recomputed by the oracle one by one, and exact integer
+properties that hold at any size: the candidate count |E_l| of a repetition
+is a function of the row draw alone (the sum over buckets b of a_b a_{b^c},
+Section 2.2), recomputed here from the oracle's row generator and the
+definition of the projection (Section 2.1, tau = 0).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import theory
+import synthgen
+import paper_1610_05108_amd as xyz
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = xyz.Context(0)
+    yield c
+    c.close()
+
+
+def _candidates(neg, cbits, m):
+    """|E_l| (one-sided, unordered pairs) from the (p, m) sampled-row bits of X
+    (1 = negative entry) and the m bits of Y on the same rows."""
+    key = (neg.astype(np.int64) << np.arange(m, dtype=np.int64)).sum(axis=1)
+    c = int((np.asarray(cbits, dtype=np.int64) << np.arange(m, dtype=np.int64)).sum())
+    cnt = np.bincount(key, minlength=1 << m).astype(np.int64)
+    if c == 0:
+        return int((cnt * (cnt - 1) // 2).sum())
+    b = np.arange(1 << m)
+    sel = b < (b ^ c)
+    return int((cnt[b[sel]] * cnt[(b ^ c)[sel]]).sum())
+
+
+def _pairs_set(res):
+    return set(zip(res["pairs"]["j"].tolist(), res["pairs"]["k"].tolist()))
+
+
+# ------------------------------------------------ genotype workload, n=2000 p=1e5
+
+@pytest.fixture(scope="module")
+def genotype(ctx):
+    d = synthgen.config2(seed=0)
+    return d, ctx.x_create(d.XT)
+
+
+def test_genotype_repetitions_bit_exact(ctx, genotype):
+    """Two repetitions of the bench's xyz plan shape (m=12) against the oracle:
+    identical pair sets, values, first repetitions, hits and per-repetition counts."""
+    d, x = genotype
+    kappa, m = 0.11, 12
+    got = ctx.search(x, d.Y, m=m, L=2, kappa=kappa, seed=1000, rep_offset=37)
+    want, wreps = oracle.search(d.XT, d.Y, m, 2, kappa, seed=1000, rep_offset=37)
+    assert len(want) > 0
+    for f in ("j", "k", "s", "first_rep", "hits"):
+        assert np.array_equal(got["pairs"][f], want[f]), f
+    for f in ("candidates", "passed", "fresh"):
+        assert np.array_equal(got["reps"][f], wreps[f]), f
+
+
+def test_genotype_candidate_counts_full_run(ctx, genotype):
+    """The bench's xyz plan (m=12, L=200): |E_l| of sampled repetitions equals the
+    count recomputed from the oracle's row draws."""
+    d, x = genotype
+    m, L, seed = 12, 200, 1000
+    r = ctx.search(x, d.Y, m=m, L=L, kappa=0.13, seed=seed)
+    neg = d.XT < 0
+    for l in (0, 1, 99, 199):
+        rows = oracle.draw_rows(d.n, seed, l, m)
+        want = _candidates(neg[:, rows], d.Y[rows] < 0, m)
+        assert int(r["reps"]["candidates"][l]) == want, l
+    # every reported pair's value, recomputed by the oracle
+    pr = r["pairs"]
+    assert len(pr) > 0
+    for q in np.random.default_rng(0).choice(len(pr), size=min(300, len(pr)), replace=False):
+        assert int(pr["s"][q]) == oracle.pair_value(d.XT, d.Y, int(pr["j"][q]), int(pr["k"][q]))
+
+
+def test_genotype_exact_search_sampled(ctx, genotype):
+    """The exact search as the bench runs it: reported values match the oracle, random
+    pairs are reported exactly when they pass eq. (1), and xyz's pairs are a subset."""
+    d, x = genotype
+    kappa = 0.12
+    b = ctx.bruteforce(x, d.Y, kappa)
+    got = {(int(j), int(k)): int(s) for j, k, s in zip(b["pairs"]["j"], b["pairs"]["k"], b["pairs"]["s"])}
+    assert len(got) > 1000
+    rng = np.random.default_rng(1)
+    keys = list(got)
+    for q in rng.choice(len(keys), size=300, replace=False):
+        j, k = keys[q]
+        assert got[(j, k)] == oracle.pair_value(d.XT, d.Y, j, k)
+    for _ in range(3000):
+        j, k = sorted(rng.choice(d.p, size=2, replace=False).tolist())
+        s = oracle.pair_value(d.XT, d.Y, j, k)
+        assert ((j, k) in got) == (s / d.n > kappa), (j, k, s)
+    xr = ctx.search(x, d.Y, m=12, L=50, kappa=kappa, seed=5)
+    for j, k, s in zip(xr["pairs"]["j"], xr["pairs"]["k"], xr["pairs"]["s"]):
+        assert got[(int(j), int(k))] == int(s)
+
+
+# ------------------------------------------ large Rademacher workload, n=5000 p=1e6
+
+@pytest.fixture(scope="module")
+def rademacher_large(ctx):
+    d = synthgen.config3(seed=0)
+    return d, ctx.x_create(d.bits, n=d.n)
+
+
+def _unpack_cols(d, cols):
+    return np.stack([synthgen.unpack_column(d.bits[c], d.n) for c in cols])
+
+
+def test_large_binary_full_search(ctx, rademacher_large):
+    """m=14, L=500, kappa=0.12 as configured: candidate counts of sampled repetitions
+    exact, every reported value exact, planted pairs found where eq. (9) says so."""
+    d, x = rademacher_large
+    m, L, kappa, seed = 14, 500, 0.12, 0
+    r = ctx.search(x, d.Y, m=m, L=L, kappa=kappa, seed=seed)
+    for l in (0, 250, 499):
+        rows = oracle.draw_rows(d.n, seed, l, m)
+        neg = ((d.bits[:, rows >> 6] >> (rows & 63).astype(np.uint64)) & np.uint64(1)).astype(bool)
+        assert int(r["reps"]["candidates"][l]) == _candidates(neg, d.Y[rows] < 0, m), l
+    found = _pairs_set(r)
+    for (j, k), s in zip(zip(r["pairs"]["j"].tolist(), r["pairs"]["k"].tolist()), r["pairs"]["s"].tolist()):
+        X2 = _unpack_cols(d, (j, k))
+        assert s == oracle.pair_value(X2, d.Y, 0, 1)
+    for (j, k) in d.planted:
+        s = oracle.pair_value(_unpack_cols(d, (j, k)), d.Y, 0, 1)
+        eta = theory.eta(theory.gamma_from_stat(s / d.n), m, L)
+        if eta > 0.999:
+            assert (j, k) in found, (j, k, s, eta)
+        if (j, k) in found:
+            assert s / d.n > kappa
+
+
+def test_large_binary_exact_blocks(ctx, rademacher_large):
+    """The exact search on 20 random 50k x 50k column blocks: the pairs it reports are
+    exactly the planted pairs inside the block (a random pair at s/n > 0.12 with
+    n = 5000 lies 8.5 standard deviations out), with the oracle's values."""
+    d, x = rademacher_large
+    kappa = 0.12
+    rng = np.random.default_rng(3)
+    truth = {}
+    for j, k in d.planted:
+        truth[(j, k)] = oracle.pair_value(_unpack_cols(d, (j, k)), d.Y, 0, 1)
+    for _ in range(20):
+        A = rng.choice(d.p, size=50_000, replace=False).astype(np.int32)
+        B = rng.choice(d.p, size=50_000, replace=False).astype(np.int32)
+        b = ctx.bruteforce(x, d.Y, kappa, colsA=A, colsB=B)
+        got = {(int(j), int(k)): int(s) for j, k, s in zip(b["pairs"]["j"], b["pairs"]["k"], b["pairs"]["s"])}
+        sa, sb = set(A.tolist()), set(B.tolist())
+        want = {pq: s for pq, s in truth.items() if s / d.n > kappa and
+                ((pq[0] in sa and pq[1] in sb) or (pq[1] in sa and pq[0] in sb))}
+        assert got == want
+
+
+# ------------------------------------------------- continuous workload, n=1000 p=2e5
+
+@pytest.fixture(scope="module")
+def continuous(ctx):
+    d = synthgen.config4(seed=0)
+    return d, ctx.x_create(d.XT)
+
+
+def test_continuous_full_search(ctx, continuous):
+    """m=12, L=300, kappa=0.5 with |Y|-weighted rows on the signs of X: candidate
+    counts exact, reported values within 1e-12 relative of the oracle's binary64
+    sums, planted pairs found where eq. (9) with the weighted strength says so."""
+    d, x = continuous
+    m, L, kappa, seed = 12, 300, 0.5, 0
+    r = ctx.search(x, d.Y, m=m, L=L, kappa=kappa, seed=seed)
+    neg = d.XT < 0
+    for l in (0, 150, 299):
+        rows = oracle.draw_rows(d.n, seed, l, m, Y=d.Y)
+        assert int(r["reps"]["candidates"][l]) == _candidates(neg[:, rows], d.Y[rows] < 0, m), l
+    pr = r["pairs"]
+    found = _pairs_set(r)
+    for q in range(len(pr)):
+        j, k = int(pr["j"][q]), int(pr["k"][q])
+        want = oracle.pair_value(d.XT[[j, k]], d.Y, 0, 1)
+        assert abs(pr["value"][q] - want) <= 1e-12 * max(1.0, abs(want)), (j, k)
+        assert want / d.n > kappa - 1e-12
+    for (j, k) in d.planted:
+        v = oracle.pair_value(d.XT[[j, k]], d.Y, 0, 1)
+        Xs = np.where(d.XT[[j, k]] < 0, -1, 1).astype(np.int8)
+        eta = theory.eta(theory.gamma_tilde(Xs, d.Y, 0, 1), m, L)
+        if eta > 0.999 and v / d.n > kappa + 1e-9:
+            assert (j, k) in found, (j, k, v, eta)
