@@ -414,6 +414,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     const bool real_y = yfmt != XYZ_Y_I8_PM1;
     const bool real_x = x->fmt == XYZ_X_F32;
     const bool real = real_x || real_y;
+    // +-1 data with exact FP32 counts: large bucket products go to the matrix cores
+    const int mfma = (!real && n < (1 << 24)) ? 1 : 0;
     Timer tm;
     tm.on = (P.flags & XYZ_PROFILE) != 0;
     tm.st = st;
@@ -460,7 +462,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     XYZ_TRY(ws(c, WS_KEYS, (size_t)chunk * p, &keys));
     XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
     XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
-    XYZ_TRY(ws(c, WS_BASE, 2 * ((size_t)chunk * nys + 1), &base));
+    XYZ_TRY(ws(c, WS_BASE, 3 * ((size_t)chunk * nys + 1), &base));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
     HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
     uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
@@ -490,23 +492,26 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
         while (redo) {
             redo = false;
             tm.begin(3);
-            HIP_TRY(launch_bucket(keys, p, m, R, nys, cinfo, two, offs, perm, st));
+            HIP_TRY(launch_bucket(keys, p, m, R, nys, cinfo, two, mfma, offs, perm, st));
             tm.end();
             tm.begin(4);
             HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
-            // large-tile total at base[R nys], small-tile total at base[2 R nys + 1]
-            unsigned long long ntiles = 0, nsmall = 0;
-            HIP_TRY(hipMemcpyAsync(&ntiles, base + (size_t)R * nys, sizeof ntiles, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * (size_t)R * nys + 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
+            // list totals at base[K (R nys + 1) + R nys]: popcount, small, matrix-core tiles
+            const size_t cnt1 = (size_t)R * nys + 1;
+            unsigned long long ntiles = 0, nsmall = 0, nmfma = 0;
+            HIP_TRY(hipMemcpyAsync(&ntiles, base + cnt1 - 1, sizeof ntiles, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * cnt1 - 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&nmfma, base + 3 * cnt1 - 1, sizeof nmfma, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             Tile *tiles = nullptr;
-            XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall), &tiles));
-            HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, base, tiles, st));
+            XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
+            HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, mfma, base, tiles, st));
             tm.end();
             VerifyArgs va{};
             va.tiles = tiles;
             va.ntiles = ntiles;
             va.nsmall = nsmall;
+            va.nmfma = nmfma;
             va.perm = perm;
             va.XC = x->XC;
             va.W32p = x->W32p;
@@ -524,13 +529,14 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             va.surv_count = scnt;
             va.surv_cap = surv_cap;
             va.info = cinfo;
-            const int g = (int)std::min<unsigned long long>(std::max(ntiles + nsmall, 1ull), (unsigned long long)grid);
+            const int g = (int)std::min<unsigned long long>(std::max(ntiles + nsmall + nmfma, 1ull),
+                                                            (unsigned long long)grid);
             tm.begin(5);
             if (real) HIP_TRY(launch_verify_real(va, real_x ? 1 : 0, g, st));
             else HIP_TRY(launch_verify_bin(va, g, st));
             tm.end();
-            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0);
-            timing.tiles += (int64_t)(ntiles + nsmall);
+            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0) + (nmfma ? 1 : 0);
+            timing.tiles += (int64_t)(ntiles + nsmall + nmfma);
             unsigned long long cnt = 0;
             HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));

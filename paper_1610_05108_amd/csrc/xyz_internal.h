@@ -15,12 +15,18 @@ constexpr int MAX_M_LDS = 15;
 // A bucket product that fits one tile and has at most this many candidate
 // pairs goes to the small-tile list (verified many tiles per wave).
 constexpr uint32_t SMALL_TILE_PAIRS = 96;
+// Bucket products whose sides both have at least MTILE_MIN columns (MTILE_MIN_DIAG
+// for a bucket's own pairs) are verified on the matrix cores in MTILE x MTILE tiles
+// (+-1 data, n < 2^24).
+constexpr int MTILE = 64;
+constexpr uint32_t MTILE_MIN = 16;
+constexpr uint32_t MTILE_MIN_DIAG = 24;
 
 struct Tile {            // 16 bytes
     uint32_t rep;        // repetition index relative to the launch's first repetition
     uint32_t a0;         // first position of the A block in perm (absolute)
     uint32_t b0;         // first position of the B block in perm (absolute)
-    uint8_t na, nb;      // block sizes (1..TILE)
+    uint8_t na, nb;      // block sizes (1..TILE, or 1..MTILE for matrix-core tiles)
     uint8_t diag;        // 1: A and B are the same block of one bucket; keep positions a < b only
     uint8_t ysel;        // response index within a batch
 };
@@ -50,6 +56,7 @@ struct RepInfo {         // per repetition and response, filled on the device
     unsigned long long cmask;
     unsigned int max_bucket;
     unsigned int small_tiles; // one-tile bucket products with at most SMALL_TILE_PAIRS pairs
+    unsigned long long mfma_tiles; // MTILE x MTILE tiles of products verified on the matrix cores
 };
 
 // ------------------------------------------------------------ launchers --
@@ -84,23 +91,25 @@ hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uin
 hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nrep, const int32_t *rows,
                        uint32_t *keys, hipStream_t st);
 // Bucket sort of each repetition's keys (one workgroup per repetition) plus the histogram-only
-// statistics of nys responses (info[r * nys + y]): candidates, tiles, max bucket.
-// offs [nrep][2^m + 1], perm [nrep][p].
+// statistics of nys responses (info[r * nys + y]): candidates, tile counts of the three lists
+// (matrix-core tiles only when mfma != 0), max bucket.  offs [nrep][2^m + 1], perm [nrep][p].
 hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info,
-                         int two_sided, uint32_t *offs, uint32_t *perm, hipStream_t st);
-// Exclusive scans over count = nrep*nys entries into base [2 count + 2] (u64): base[0..count]
-// of info[].tiles (large tiles), base[count+1 .. 2 count+1] of info[].small_tiles.
+                         int two_sided, int mfma, uint32_t *offs, uint32_t *perm, hipStream_t st);
+// Exclusive scans over count = nrep*nys entries into base [3 (count + 1)] (u64): list K
+// (0: popcount tiles, 1: small tiles, 2: matrix-core tiles) at base + K (count + 1), its total
+// at base[K (count + 1) + count].
 hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st);
-// Emit the tiles of every (repetition, response): large tiles at base[r * nys + y], small
-// ones after all large tiles, at base[count] + base[count + 1 + r * nys + y].
+// Emit the tiles of every (repetition, response): popcount tiles first, then small tiles,
+// then matrix-core tiles (MTILE x MTILE), each list ordered by (repetition, response).
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
-                        int two_sided, const unsigned long long *base, Tile *tiles, hipStream_t st);
+                        int two_sided, int mfma, const unsigned long long *base, Tile *tiles, hipStream_t st);
 
 // Shared arguments of the verification kernels.
 struct VerifyArgs {
     const Tile *tiles;
     uint64_t ntiles;         // large tiles: tiles[0, ntiles)
     uint64_t nsmall;         // small tiles: tiles[ntiles, ntiles + nsmall)
+    uint64_t nmfma;          // matrix-core tiles: tiles[ntiles + nsmall, ... + nmfma)
     const uint32_t *perm;
     const uint32_t *XC;      // [p][W32p] bits
     int W32p;

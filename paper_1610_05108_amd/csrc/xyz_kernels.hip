@@ -347,25 +347,42 @@ __global__ __launch_bounds__(256) void k_hash(const uint64_t *__restrict__ XR, i
 
 // Bucket pair (b, b2) of a repetition: b < b2 -> all pairs of the two buckets;
 // b == b2 (partner mask 0) -> pairs inside the bucket.  Returns the candidate
-// count; T is the number of TILE x TILE tiles, or 0 when the product is empty
-// or small (one tile with at most SMALL_TILE_PAIRS pairs: small = 1).
-XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, unsigned long long &T,
-                                         uint32_t &small)
+// count and sorts the product into one of three tile lists:
+//   kind 1: one TILE x TILE tile with at most SMALL_TILE_PAIRS pairs (small list),
+//   kind 2: T tiles of TILE x TILE (popcount list),
+//   kind 3: T tiles of MTILE x MTILE for the matrix cores (both sides at least
+//           MTILE_MIN columns, +-1 data with n < 2^24 only: mfma != 0).
+XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, int mfma, int &kind,
+                                         unsigned long long &T)
 {
+    kind = 0;
     T = 0;
-    small = 0;
     if (b < b2) {
         const unsigned long long c = (unsigned long long)a * a2;
         if (c == 0) return 0;
-        if (a <= (uint32_t)TILE && a2 <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) small = 1;
-        else T = cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
+        if (mfma && a >= MTILE_MIN && a2 >= MTILE_MIN) {
+            kind = 3;
+            T = cdiv_u64(a, MTILE) * cdiv_u64(a2, MTILE);
+        } else if (a <= (uint32_t)TILE && a2 <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
+            kind = 1;
+            T = 1;
+        } else {
+            kind = 2;
+            T = cdiv_u64(a, TILE) * cdiv_u64(a2, TILE);
+        }
         return c;
     }
     if (b == b2 && a >= 2) {
         const unsigned long long c = (unsigned long long)a * (a - 1) / 2;
-        if (a <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
-            small = 1;
+        if (mfma && a >= MTILE_MIN_DIAG) {
+            kind = 3;
+            const unsigned long long n = cdiv_u64(a, MTILE);
+            T = n * (n + 1) / 2;
+        } else if (a <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
+            kind = 1;
+            T = 1;
         } else {
+            kind = 2;
             const unsigned long long n = cdiv_u64(a, TILE);
             T = n * (n + 1) / 2;
         }
@@ -375,7 +392,7 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
 }
 
 __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ keys, int64_t p, int m, int nys,
-                                                 RepInfo *__restrict__ info, int two_sided,
+                                                 RepInfo *__restrict__ info, int two_sided, int mfma,
                                                  uint32_t *__restrict__ offs, uint32_t *__restrict__ perm)
 {
     extern __shared__ uint32_t cnt[];
@@ -393,30 +410,29 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
         RepInfo *inf = info + (int64_t)r * nys + y;
         const uint32_t c = (uint32_t)inf->cmask & mask;
         const uint32_t cn = (~c) & mask;
-        unsigned long long cand = 0, tiles = 0, small = 0;
+        unsigned long long cand = 0, cnts[4] = {0, 0, 0, 0};
         unsigned mx = 0;
         for (int b = threadIdx.x; b < nb; b += 1024) {
             const uint32_t a = cnt[b];
             mx = max(mx, a);
-            unsigned long long T;
-            uint32_t sm;
-            cand += product_tiles((uint32_t)b, (uint32_t)b ^ c, a, cnt[b ^ c], T, sm);
-            tiles += T;
-            small += sm;
-            if (two_sided && cn != c) {
-                cand += product_tiles((uint32_t)b, (uint32_t)b ^ cn, a, cnt[b ^ cn], T, sm);
-                tiles += T;
-                small += sm;
+            for (int side = 0; side < ((two_sided && cn != c) ? 2 : 1); ++side) {
+                const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
+                unsigned long long T;
+                int kind;
+                cand += product_tiles((uint32_t)b, b2, a, cnt[b2], mfma, kind, T);
+                cnts[kind] += T;
             }
         }
         cand = block_sum<1024>(cand, shm);
-        tiles = block_sum<1024>(tiles, shm);
-        small = block_sum<1024>(small, shm);
+        const unsigned long long tiles = block_sum<1024>(cnts[2], shm);
+        const unsigned long long small = block_sum<1024>(cnts[1], shm);
+        const unsigned long long mtiles = block_sum<1024>(cnts[3], shm);
         mx = block_max<1024>(mx, shmax);
         if (threadIdx.x == 0) {
             inf->candidates = cand;
             inf->tiles = tiles;
             inf->small_tiles = (unsigned)small;
+            inf->mfma_tiles = mtiles;
             inf->max_bucket = mx;
             inf->passed = 0;
             inf->fresh = 0;
@@ -451,15 +467,18 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const RepInfo *__restrict__ 
     __shared__ unsigned long long shm[17];
     const int seg = (count + 1023) / 1024;
     const int i0 = min(count, (int)threadIdx.x * seg), i1 = min(count, i0 + seg);
-    for (int list = 0; list < 2; ++list) {
+    auto tiles_of = [&](int list, int i) -> unsigned long long {
+        return list == 0 ? info[i].tiles : (list == 1 ? (unsigned long long)info[i].small_tiles : info[i].mfma_tiles);
+    };
+    for (int list = 0; list < 3; ++list) {
         unsigned long long *bs = base + list * (count + 1);
         unsigned long long loc = 0;
-        for (int i = i0; i < i1; ++i) loc += list ? info[i].small_tiles : info[i].tiles;
+        for (int i = i0; i < i1; ++i) loc += tiles_of(list, i);
         unsigned long long tot;
         unsigned long long pre = block_scan_excl<1024>(loc, shm, &tot);
         for (int i = i0; i < i1; ++i) {
             bs[i] = pre;
-            pre += list ? info[i].small_tiles : info[i].tiles;
+            pre += tiles_of(list, i);
         }
         if (threadIdx.x == 0) bs[count] = tot;
         __syncthreads();
@@ -482,49 +501,54 @@ XYZ_DEV void tri_index(uint64_t t, uint64_t T, uint32_t &ia, uint32_t &ib)
     ib = (uint32_t)(i + (int64_t)(t - S(i)));
 }
 
-XYZ_DEV Tile make_tile(uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1, uint32_t a, uint32_t o2, uint32_t a2,
-                       uint32_t ia, uint32_t ib, uint8_t diag)
+XYZ_DEV Tile make_tile(uint32_t ts, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1, uint32_t a, uint32_t o2,
+                       uint32_t a2, uint32_t ia, uint32_t ib, uint8_t diag)
 {
     Tile t;
     t.rep = r;
-    t.a0 = pbase + o1 + ia * TILE;
-    t.b0 = pbase + o2 + ib * TILE;
-    t.na = (uint8_t)min((uint32_t)TILE, a - ia * TILE);
-    t.nb = (uint8_t)min((uint32_t)TILE, a2 - ib * TILE);
+    t.a0 = pbase + o1 + ia * ts;
+    t.b0 = pbase + o2 + ib * ts;
+    t.na = (uint8_t)min(ts, a - ia * ts);
+    t.nb = (uint8_t)min(ts, a2 - ib * ts);
     t.diag = diag;
     t.ysel = (uint8_t)ysel;
     return t;
 }
 
-// Tile number t of the product of bucket b and its partner b2.
-XYZ_DEV Tile pair_tile(uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t b, uint32_t b2,
+// Tile number t (tiles of ts x ts) of the product of bucket b and its partner b2.
+XYZ_DEV Tile pair_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t b, uint32_t b2,
                        const uint32_t *of)
 {
     const uint32_t o1 = of[b], a = of[b + 1] - o1;
     const uint32_t o2 = of[b2], a2 = of[b2 + 1] - o2;
     if (b != b2) {
-        const uint32_t nB = (a2 + TILE - 1) / TILE;
-        return make_tile(r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
+        const uint32_t nB = (a2 + ts - 1) / ts;
+        return make_tile(ts, r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
     }
-    const uint32_t T = (a + TILE - 1) / TILE;
+    const uint32_t T = (a + ts - 1) / ts;
     uint32_t ia, ib;
     tri_index(t, T, ia, ib);
-    return make_tile(r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
+    return make_tile(ts, r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
 }
 
 // Bucket products with more tiles than this are emitted by the whole block.
 constexpr unsigned HEAVY_TILES = 64;
 constexpr int HEAVY_CAP = 512;
 
+// Tiles of every (repetition, response) into three regions of one array: the
+// popcount tiles (TILE) at base0[ry], the small tiles after all popcount tiles
+// at base0[count] + base1[ry], the matrix-core tiles (MTILE) after those at
+// base0[count] + base1[count] + base2[ry] (baseK = base + K (count + 1)).
 __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs, int64_t p, int m, int nys,
-                                               const RepInfo *__restrict__ info, int two_sided,
+                                               const RepInfo *__restrict__ info, int two_sided, int mfma,
                                                const unsigned long long *__restrict__ base, Tile *__restrict__ tiles)
 {
     __shared__ unsigned long long shm[5];
-    __shared__ uint32_t hb[HEAVY_CAP], hb2[HEAVY_CAP];
+    __shared__ uint32_t hb[HEAVY_CAP], hb2[HEAVY_CAP], hts[HEAVY_CAP];
     __shared__ unsigned long long hpos[HEAVY_CAP], hcnt_t[HEAVY_CAP];
     __shared__ int hcnt;
     const int ry = blockIdx.x, count = gridDim.x;
+    const unsigned long long *base0 = base, *base1 = base + (count + 1), *base2 = base + 2 * (count + 1);
     const int r = ry / nys, y = ry % nys;
     const int nb = 1 << m;
     const uint32_t mask = (uint32_t)(nb - 1);
@@ -535,46 +559,44 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     if (threadIdx.x == 0) hcnt = 0;
     const int seg = (nb + 255) / 256;
     const int b0 = min(nb, (int)threadIdx.x * seg), b1 = min(nb, b0 + seg);
-    unsigned long long loc = 0, sloc = 0;
+    unsigned long long loc[4] = {0, 0, 0, 0};
     for (int b = b0; b < b1; ++b) {
         const uint32_t a = of[b + 1] - of[b];
         for (int side = 0; side < (second ? 2 : 1); ++side) {
             const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
             unsigned long long T;
-            uint32_t sm;
-            product_tiles(b, b2, a, of[b2 + 1] - of[b2], T, sm);
-            loc += T;
-            sloc += sm;
+            int kind;
+            product_tiles(b, b2, a, of[b2 + 1] - of[b2], mfma, kind, T);
+            loc[kind] += T;
         }
     }
-    unsigned long long tot;
-    unsigned long long pos = base[ry] + block_scan_excl<256>(loc, shm, &tot);
-    unsigned long long spos = base[count] + base[count + 1 + ry] + block_scan_excl<256>(sloc, shm, &tot);
+    unsigned long long tot, pos[4];
+    pos[2] = base0[ry] + block_scan_excl<256>(loc[2], shm, &tot);
+    pos[1] = base0[count] + base1[ry] + block_scan_excl<256>(loc[1], shm, &tot);
+    pos[3] = base0[count] + base1[count] + base2[ry] + block_scan_excl<256>(loc[3], shm, &tot);
     const uint32_t pbase = (uint32_t)((int64_t)r * p);
     for (int b = b0; b < b1; ++b) {
         for (int side = 0; side < (second ? 2 : 1); ++side) {
             const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
             unsigned long long T;
-            uint32_t sm;
-            product_tiles(b, b2, of[b + 1] - of[b], of[b2 + 1] - of[b2], T, sm);
-            if (sm) {
-                tiles[spos++] = pair_tile(0, r, y, pbase, b, b2, of);
-                continue;
-            }
-            if (T == 0) continue;
+            int kind;
+            product_tiles(b, b2, of[b + 1] - of[b], of[b2 + 1] - of[b2], mfma, kind, T);
+            if (kind == 0) continue;
+            const uint32_t ts = kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE;
             int h = -1;
             if (T > HEAVY_TILES) {
                 h = atomicAdd(&hcnt, 1);
                 if (h < HEAVY_CAP) {
                     hb[h] = b;
                     hb2[h] = b2;
-                    hpos[h] = pos;
+                    hts[h] = ts;
+                    hpos[h] = pos[kind];
                     hcnt_t[h] = T;
                 }
             }
             if (h < 0 || h >= HEAVY_CAP)
-                for (unsigned long long t = 0; t < T; ++t) tiles[pos + t] = pair_tile(t, r, y, pbase, b, b2, of);
-            pos += T;
+                for (unsigned long long t = 0; t < T; ++t) tiles[pos[kind] + t] = pair_tile(ts, t, r, y, pbase, b, b2, of);
+            pos[kind] += T;
         }
     }
     __syncthreads();
@@ -582,8 +604,56 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     for (int h = 0; h < nh; ++h) {
         const unsigned long long T = hcnt_t[h], p0 = hpos[h];
         for (unsigned long long t = threadIdx.x; t < T; t += 256)
-            tiles[p0 + t] = pair_tile(t, r, y, pbase, hb[h], hb2[h], of);
+            tiles[p0 + t] = pair_tile(hts[h], t, r, y, pbase, hb[h], hb2[h], of);
     }
+}
+
+// ----------------------------------------------------------- FP4 operands --
+//
+// The 0/1 dot products of the exact search and of large verification tiles run
+// on v_mfma_scale_f32_32x32x64_f8f6f4 with e2m1 operands: lanes 0-31 feed 32
+// rows of their column, lanes 32-63 the next 32 rows, 16 bytes (32 nibbles)
+// each; FP32 accumulation of the integer counts is exact below 2^24.
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+XYZ_DEV uint32_t swap02(uint32_t w)
+{
+    return (w & 0xAAAAAAAAu) | ((w & 0x11111111u) << 2) | ((w >> 2) & 0x11111111u);
+}
+
+// 32 bits of one column word -> 32 e2m1 nibbles (the low half of an FP4
+// operand), nonzero for a set bit.  Row r = 4q + e of the word (nibble q, e in
+// 0..3) goes to nibble q of dword e.  On the A side a set bit keeps its place
+// in the nibble, so dwords 0, 1, 2 hold the values 0.5, 1, 2 (e2m1 0b0001,
+// 0b0010, 0b0100) with one AND each, and dword 3 moves bit 3 to bit 1 (1.0).
+// The exact search stages its B side with bits 0 and 2 of each nibble swapped,
+// so the same masks give it the values 2, 1, 0.5, 1 (expand_b); an unstaged B
+// word takes two more shifts (expand_b_plain).  Every product of two set bits
+// is exactly 1.  Which rows share a nibble does not matter, because A and B
+// assign rows to (dword, nibble) the same way and the product sums over all.
+XYZ_DEV v8i expand_a(uint32_t w)
+{
+    return v8i{(int)(w & 0x11111111u), (int)(w & 0x22222222u), (int)(w & 0x44444444u),
+               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+
+XYZ_DEV v8i expand_b(uint32_t w)
+{
+    return v8i{(int)(w & 0x44444444u), (int)(w & 0x22222222u), (int)(w & 0x11111111u),
+               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+
+XYZ_DEV v8i expand_b_plain(uint32_t w)
+{
+    return v8i{(int)((w << 2) & 0x44444444u), (int)(w & 0x22222222u), (int)((w >> 2) & 0x11111111u),
+               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+
+XYZ_DEV v16f mfma_fp4(v8i a, v8i b, v16f c)
+{
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
 }
 
 // ------------------------------------------------------------ verification --
@@ -766,6 +836,164 @@ __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
         default: break;
         }
         __syncthreads();
+    }
+}
+
+// Matrix-core tiles (products of two buckets with at least MTILE_MIN columns
+// each; +-1 data, n < 2^24).  One wave per MTILE x MTILE tile, as 2 x 2
+// fragments of 32 x 32: the counts C = #{i : z_ia = x_ib = 1}, z = y ^ x,
+// accumulate on v_mfma_scale_f32_32x32x64_f8f6f4 over 64-row steps, lane half h
+// feeding words h and h + 2 of each quad of its columns (A columns u*32 + lane%32,
+// B columns v*32 + lane%32), so every column of the tile is read once; the
+// popcounts |z_a|, |x_b| are taken on the way and s = n - 2|z_a| - 2|x_b| + 4C.
+// Three quads are in flight per lane.  Accumulator register r of lane l holds A row
+// u*32 + (r/4)*8 + (l/32)*4 + r%4 and B column v*32 + l%32.
+struct MQuad {
+    uint4 a[2], b[2], y;
+};
+
+__global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
+{
+    __shared__ uint32_t zpop[4][MTILE];
+    const unsigned lane = lane_id();
+    const int h = (int)(lane >> 5), c = (int)(lane & 31);
+    const int W4 = a.W32p >> 2;
+    const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
+    const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall);
+    const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nwave = (uint64_t)gridDim.x * 4;
+    const int32_t n32 = (int32_t)a.n;
+    for (uint64_t ti = wid; ti < a.nmfma; ti += nwave) {
+        const Tile t = tile_from(T4[ti]);
+        const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
+        const uint4 *pa[2], *pb[2];
+        uint32_t ma[2], mb[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ca = u * 32 + c, cb = u * 32 + c;
+            ma[u] = ca < t.na ? ~0u : 0u;
+            mb[u] = cb < t.nb ? ~0u : 0u;
+            pa[u] = XC4 + (int64_t)a.perm[t.a0 + (ca < t.na ? ca : 0)] * W4;
+            pb[u] = XC4 + (int64_t)a.perm[t.b0 + (cb < t.nb ? cb : 0)] * W4;
+        }
+        v16f acc[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) acc[u][v] = v16f{};
+        uint32_t popa[2] = {0, 0}, popb[2] = {0, 0};
+        auto load = [&](MQuad &q, int qi) {
+            const int o = min(qi, W4 - 1);          // clamped: a quad past the end is never used
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                q.a[u] = pa[u][o];
+                q.b[u] = pb[u][o];
+            }
+            q.y = y4[o];
+        };
+        auto step = [&](MQuad &q, int qi) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                v8i fa[2], fb[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const uint32_t wa = k ? (h ? q.a[u].w : q.a[u].z) : (h ? q.a[u].y : q.a[u].x);
+                    const uint32_t wy = k ? (h ? q.y.w : q.y.z) : (h ? q.y.y : q.y.x);
+                    const uint32_t wb = k ? (h ? q.b[u].w : q.b[u].z) : (h ? q.b[u].y : q.b[u].x);
+                    const uint32_t za = (wa ^ wy) & ma[u], xb = wb & mb[u];
+                    popa[u] = bcnt_acc(za, popa[u]);
+                    popb[u] = bcnt_acc(xb, popb[u]);
+                    fa[u] = expand_a(za);
+                    fb[u] = expand_b_plain(xb);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) acc[u][v] = mfma_fp4(fa[u], fb[v], acc[u][v]);
+            }
+            load(q, qi + 3);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        MQuad q0, q1, q2;
+        load(q0, 0);
+        load(q1, 1);
+        load(q2, 2);
+        int qi = 0;
+        for (; qi + 2 < W4; qi += 3) {      // no branches inside: each wait is for the oldest loads only
+            step(q0, qi);
+            step(q1, qi + 1);
+            step(q2, qi + 2);
+        }
+        if (qi < W4) step(q0, qi);
+        if (qi + 1 < W4) step(q1, qi + 1);
+        // whole-column popcounts: the two lane halves of a column hold half of the words each
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            popa[u] += __shfl_xor(popa[u], 32, 64);
+            popb[u] += __shfl_xor(popb[u], 32, 64);
+        }
+        const int32_t smin = (int32_t)a.smin[t.ysel];
+        uint32_t pm[2][2];
+        int mine = 0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int cb = v * 32 + c;
+                uint32_t m = 0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int rl = (r >> 2) * 8 + h * 4 + (r & 3), ra = u * 32 + rl;
+                    const int32_t pz = (int32_t)__shfl(popa[u], rl, 64);   // |z| of A column ra
+                    const int32_t sv = n32 - 2 * pz - 2 * (int32_t)popb[v] + 4 * (int32_t)acc[u][v][r];
+                    const bool pass = a.two_sided ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin);
+                    const bool ok = ra < t.na && cb < t.nb && (!t.diag || ra < cb);
+                    m |= (pass && ok ? 1u : 0u) << r;
+                }
+                pm[u][v] = m;
+                mine += __popc(m);
+            }
+        }
+        unsigned long long idx = reserve_survivors(a, t, mine);
+        if (idx == ~0ull) continue;
+        // rare: the A columns' popcounts go to the wave's LDS slot, read back per survivor
+        const int wv = (int)(threadIdx.x >> 6);
+        if (h == 0) {
+            zpop[wv][c] = popa[0];
+            zpop[wv][32 + c] = popa[1];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int cb = v * 32 + c;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if (!((pm[u][v] >> r) & 1u)) continue;
+                    const int ra = u * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+                    const uint32_t j = a.perm[t.a0 + ra], k = a.perm[t.b0 + cb];
+                    const int32_t sv = n32 - 2 * (int32_t)zpop[wv][ra] - 2 * (int32_t)popb[v] +
+                                       4 * (int32_t)acc[u][v][r];
+                    if (idx < a.surv_cap) {
+                        Survivor sr;
+                        sr.j = min(j, k);
+                        sr.k = max(j, k);
+                        sr.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                        sr.s = sv;
+                        sr.value = (double)sv;
+                        sr.ysel = t.ysel;
+                        sr.pad = 0;
+                        a.surv[idx] = sr;
+                    }
+                    ++idx;
+                }
+            }
+        // the slot is rewritten by this wave's next tile only after every lane has read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -1105,14 +1333,6 @@ __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
 // h + 2 of the quad: 8 contiguous bytes, and a wave's fragment load is 512
 // contiguous bytes.
 
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-
-XYZ_DEV uint32_t swap02(uint32_t w)
-{
-    return (w & 0xAAAAAAAAu) | ((w & 0x11111111u) << 2) | ((w >> 2) & 0x11111111u);
-}
-
 // One thread per (block, quad, column): XB[(blk * nq + qi) * 256 + c].  The A side
 // (y given) holds z = y ^ x; the B side holds x with bits 0 and 2 of every nibble swapped.
 __global__ __launch_bounds__(256) void k_brute_stage(const uint4 *__restrict__ XC4, int nq, int nw,
@@ -1167,27 +1387,6 @@ __global__ __launch_bounds__(256) void k_brute_pop(const uint4 *__restrict__ XB,
         pc += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
     }
     pop[i] = pc;
-}
-
-// 32 bits of one column word -> 32 e2m1 nibbles (the low half of an FP4
-// operand), nonzero for a set bit.  Row r = 4q + e of the word (nibble q, e in
-// 0..3) goes to nibble q of dword e.  On the A side a set bit keeps its place
-// in the nibble, so dwords 0, 1, 2 hold the values 0.5, 1, 2 (e2m1 0b0001,
-// 0b0010, 0b0100) with one AND each, and dword 3 moves bit 3 to bit 1 (1.0).
-// The B side was staged with bits 0 and 2 of each nibble swapped, so the same
-// masks give it the values 2, 1, 0.5, 1: every product of two set bits is
-// exactly 1.  Which rows share a nibble does not matter, because A and B
-// assign rows to (dword, nibble) the same way and the product sums over all.
-XYZ_DEV v8i expand_a(uint32_t w)
-{
-    return v8i{(int)(w & 0x11111111u), (int)(w & 0x22222222u), (int)(w & 0x44444444u),
-               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
-}
-
-XYZ_DEV v8i expand_b(uint32_t w)
-{
-    return v8i{(int)(w & 0x44444444u), (int)(w & 0x22222222u), (int)(w & 0x11111111u),
-               (int)((w >> 2) & 0x22222222u), 0, 0, 0, 0};
 }
 
 // A workgroup of 8 waves owns a 256 x 256 block of column pairs; wave (wa, wb)
@@ -1736,10 +1935,11 @@ hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nr
 }
 
 hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info, int two_sided,
-                         uint32_t *offs, uint32_t *perm, hipStream_t st)
+                         int mfma, uint32_t *offs, uint32_t *perm, hipStream_t st)
 {
     const size_t lds = (size_t)4 << m;
-    hipLaunchKernelGGL(k_bucket, dim3(nrep), dim3(1024), lds, st, keys, p, m, nys, info, two_sided, offs, perm);
+    hipLaunchKernelGGL(k_bucket, dim3(nrep), dim3(1024), lds, st, keys, p, m, nys, info, two_sided, mfma, offs,
+                       perm);
     return hipGetLastError();
 }
 
@@ -1750,9 +1950,10 @@ hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *
 }
 
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
-                        int two_sided, const unsigned long long *base, Tile *tiles, hipStream_t st)
+                        int two_sided, int mfma, const unsigned long long *base, Tile *tiles, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tiles, dim3(nrep * nys), dim3(256), 0, st, offs, p, m, nys, info, two_sided, base, tiles);
+    hipLaunchKernelGGL(k_tiles, dim3(nrep * nys), dim3(256), 0, st, offs, p, m, nys, info, two_sided, mfma, base,
+                       tiles);
     return hipGetLastError();
 }
 
@@ -1761,6 +1962,9 @@ hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
     if (a.ntiles)
         hipLaunchKernelGGL(k_verify_bin, dim3((unsigned)std::min<uint64_t>(a.ntiles, (uint64_t)grid)), dim3(64), 0, st,
                            a);
+    if (a.nmfma)
+        hipLaunchKernelGGL(k_verify_mfma, dim3((unsigned)std::min<uint64_t>((a.nmfma + 3) / 4, (uint64_t)grid)),
+                           dim3(256), 0, st, a);
     if (a.nsmall) {
         const uint64_t groups = (a.nsmall + 63) / 64;                  // 64 small tiles per wave step
         hipLaunchKernelGGL(k_verify_small, dim3((unsigned)std::min<uint64_t>(groups, (uint64_t)grid)), dim3(64), 0, st,
