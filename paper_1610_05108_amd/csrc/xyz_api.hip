@@ -326,10 +326,12 @@ extern "C" int64_t xyz_x_p(const xyz_x *x) { return x ? x->p : 0; }
 
 int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m)
 {
-    const int64_t nb = 1ll << m;
     int64_t chunk = std::min<int64_t>(L, 4096);
     chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((1ll << 32) - 1) / p));   // u32 positions in perm
-    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / (8 * p + 4 * (nb + 1))));
+    // bytes per repetition: keys and permutation, plus the LDS path's bucket offsets or the sort
+    // path's scratch (two key/value buffers, heads, runs and per-run tile counts)
+    const int64_t per_rep = m <= MAX_M_LDS ? 8 * p + 4 * ((1ll << m) + 1) : 64 * p;
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / per_rep));
     chunk = std::min<int64_t>(chunk, 65535);                                           // grid y of k_hash
     if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
     return std::max<int64_t>(chunk, 1);
@@ -348,8 +350,6 @@ xyz_status xyz_rt::validate_params(const xyz_x *x, const xyz_params *P, int yfmt
 {
     if (!P) return fail(XYZ_EINVAL, "params is NULL");
     if (P->m < 0 || P->m > XYZ_MAX_M) return fail(XYZ_EINVAL, "m=%d out of range [0, %d]", P->m, XYZ_MAX_M);
-    if (P->m > MAX_M_LDS)
-        return fail(XYZ_EUNSUPPORTED, "m=%d: this build sorts keys of at most %d bits", P->m, MAX_M_LDS);
     if (P->L < 1) return fail(XYZ_EINVAL, "L=%d < 1", P->L);
     if (!std::isfinite(P->kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
     if (P->rep_offset < 0) return fail(XYZ_EINVAL, "rep_offset < 0");
@@ -460,7 +460,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     unsigned long long *base = nullptr, *scnt = nullptr;
     XYZ_TRY(ws(c, WS_ROWS, (size_t)chunk * std::max(m, 1), &rows));
     XYZ_TRY(ws(c, WS_KEYS, (size_t)chunk * p, &keys));
-    XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
+    if (m <= MAX_M_LDS) XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
     XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
     XYZ_TRY(ws(c, WS_BASE, 3 * ((size_t)chunk * nys + 1), &base));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
@@ -491,22 +491,66 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
         bool redo = true;
         while (redo) {
             redo = false;
-            tm.begin(3);
-            HIP_TRY(launch_bucket(keys, p, m, R, nys, cinfo, two, mfma, offs, perm, st));
-            tm.end();
-            tm.begin(4);
-            HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
-            // list totals at base[K (R nys + 1) + R nys]: popcount, small, matrix-core tiles
-            const size_t cnt1 = (size_t)R * nys + 1;
             unsigned long long ntiles = 0, nsmall = 0, nmfma = 0;
-            HIP_TRY(hipMemcpyAsync(&ntiles, base + cnt1 - 1, sizeof ntiles, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * cnt1 - 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipMemcpyAsync(&nmfma, base + 3 * cnt1 - 1, sizeof nmfma, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
             Tile *tiles = nullptr;
-            XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
-            HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, mfma, base, tiles, st));
-            tm.end();
+            if (m <= MAX_M_LDS) {
+                tm.begin(3);
+                HIP_TRY(launch_bucket(keys, p, m, R, nys, cinfo, two, mfma, offs, perm, st));
+                tm.end();
+                tm.begin(4);
+                HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
+                // list totals at base[K (R nys + 1) + R nys]: popcount, small, matrix-core tiles
+                const size_t cnt1 = (size_t)R * nys + 1;
+                HIP_TRY(hipMemcpyAsync(&ntiles, base + cnt1 - 1, sizeof ntiles, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * cnt1 - 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&nmfma, base + 3 * cnt1 - 1, sizeof nmfma, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
+                HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, mfma, base, tiles, st));
+                tm.end();
+            } else {
+                // m > MAX_M_LDS: sort the keys, take runs of equal keys as buckets
+                const uint64_t S = (uint64_t)R * (uint64_t)p;
+                uint64_t *K = nullptr, *K2 = nullptr, *Ks = nullptr, *rkey = nullptr;
+                uint32_t *V = nullptr, *V2 = nullptr, *hist = nullptr, *heads = nullptr, *rstart = nullptr;
+                uint32_t *dnr = nullptr, *cnt = nullptr;
+                XYZ_TRY(ws(c, WS_SKK, S, &K));
+                XYZ_TRY(ws(c, WS_SKK2, S, &K2));
+                XYZ_TRY(ws(c, WS_SKV, S, &V));
+                XYZ_TRY(ws(c, WS_SKV2, S, &V2));
+                XYZ_TRY(ws(c, WS_SKHIST, radix_hist_entries(S), &hist));
+                XYZ_TRY(ws(c, WS_SKHEADS, S, &heads));
+                XYZ_TRY(ws(c, WS_SKRK, S, &rkey));
+                XYZ_TRY(ws(c, WS_SKRS, S, &rstart));
+                XYZ_TRY(ws(c, WS_SKN, 1, &dnr));
+                tm.begin(3);
+                HIP_TRY(launch_sk_sort(keys, p, m, R, K, V, K2, V2, hist, perm, &Ks, st));
+                HIP_TRY(launch_sk_runs(Ks, S, heads, hist, rkey, rstart, dnr, st));
+                uint32_t nr = 0;
+                HIP_TRY(hipMemcpyAsync(&nr, dnr, sizeof nr, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                const uint64_t ncnt = 3ull * nys * nr;
+                XYZ_TRY(ws(c, WS_SKCNT, ncnt + 1, &cnt));
+                HIP_TRY(hipMemsetAsync(cnt + ncnt, 0, sizeof(uint32_t), st));
+                HIP_TRY(launch_sk_products(rkey, rstart, dnr, nr, S, m, nys, cinfo, R * nys, two, mfma, cnt, st));
+                tm.end();
+                tm.begin(4);
+                // positions of every (list, response, run) in the tile array; list starts and total
+                XYZ_TRY(ws(c, WS_SKHIST, std::max<size_t>(radix_hist_entries(S), (size_t)((ncnt + 1) / 2048 + 16)), &hist));
+                HIP_TRY(launch_scan_u32(cnt, ncnt + 1, hist, st));
+                uint32_t bnd[3] = {0, 0, 0};
+                const uint64_t stride = (uint64_t)nys * nr;
+                HIP_TRY(hipMemcpyAsync(&bnd[0], cnt + stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&bnd[1], cnt + 2 * stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&bnd[2], cnt + ncnt, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                ntiles = bnd[0];
+                nsmall = bnd[1] - bnd[0];
+                nmfma = bnd[2] - bnd[1];
+                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
+                HIP_TRY(launch_sk_tiles(rkey, rstart, dnr, nr, S, p, m, nys, cinfo, two, mfma, cnt, tiles, st));
+                tm.end();
+            }
             VerifyArgs va{};
             va.tiles = tiles;
             va.ntiles = ntiles;
@@ -969,6 +1013,9 @@ extern "C" xyz_status xyz_sample_strengths(xyz_ctx *c, const xyz_x *x, const voi
     return XYZ_OK;
 }
 
+// Largest m the planner considers (the sort path serves m > 15).
+constexpr int PLAN_MAX_M = 24;
+
 extern "C" xyz_status xyz_plan(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
                                double gamma_target, double eta_target, uint32_t flags, void *stream,
                                xyz_plan_info *out)
@@ -986,8 +1033,8 @@ extern "C" xyz_status xyz_plan(xyz_ctx *c, const xyz_x *x, const void *Y, int yf
     const int64_t ns = std::min<int64_t>(1 << 16, (int64_t)std::max(2.0, P));
     std::vector<double> g(ns);
     XYZ_TRY(xyz_sample_strengths(c, x, Y, yfmt, mem, ns, 0x5eed5eedull, stream, g.data()));
-    std::vector<double> cand(MAX_M_LDS + 1, 0.0);
-    for (int m = 0; m <= MAX_M_LDS; ++m) {
+    std::vector<double> cand(PLAN_MAX_M + 1, 0.0);
+    for (int m = 0; m <= PLAN_MAX_M; ++m) {
         double acc = 0.0;
         for (double gq : g) acc += std::pow(gq, (double)m) + (two && m > 0 ? std::pow(1.0 - gq, (double)m) : 0.0);
         cand[m] = m == 0 ? P : P * acc / (double)ns;
@@ -1038,7 +1085,7 @@ extern "C" xyz_status xyz_plan(xyz_ctx *c, const xyz_x *x, const void *Y, int yf
         double work;
     };
     std::vector<Cand> cs;
-    for (int m = 1; m <= MAX_M_LDS; ++m) {
+    for (int m = 1; m <= PLAN_MAX_M; ++m) {
         const int64_t L = xyz_L_for(eta_target, std::pow(gamma_target, (double)m));
         if (L < 1 || L > 2000000) continue;
         const double work = (double)L * (cand[m] * std::ceil(n / 32.0) * 2.0 / 1.5e13 + (double)p * 2e-10);

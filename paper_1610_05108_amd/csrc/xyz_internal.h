@@ -104,6 +104,29 @@ hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
                         int two_sided, int mfma, const unsigned long long *base, Tile *tiles, hipStream_t st);
 
+// Bucketing for m > MAX_M_LDS (keys sorted instead of counted in LDS):
+// sort the nrep * p keys by (repetition, key) with the radix sort (K, V, K2, V2: scratch of
+// nrep * p entries; hist: radix_hist_entries(nrep * p) u32), write the sorted column ids to perm
+// [nrep][p] and return the sorted composite keys in *Ksorted (K or K2).
+hipError_t launch_sk_sort(const uint32_t *keys, int64_t p, int m, int nrep, uint64_t *K, uint32_t *V, uint64_t *K2,
+                          uint32_t *V2, uint32_t *hist, uint32_t *perm, uint64_t **Ksorted, hipStream_t st);
+// Runs of equal keys (the non-empty buckets): run_key, run_start (position in perm); nruns[0] on
+// the device.  heads: S u32 scratch; partial: scan scratch (radix_hist_entries(S) is enough).
+hipError_t launch_sk_runs(const uint64_t *K, uint64_t S, uint32_t *heads, uint32_t *partial, uint64_t *run_key,
+                          uint32_t *run_start, uint32_t *nruns, hipStream_t st);
+// Clears the statistics of info[0..count) (keeping cmask), then per (response, run) counts the
+// tiles of its bucket products in cnt[list][y][rid] (lists: popcount, small, matrix-core;
+// 3 * nys * nr entries) and adds the statistics to info.
+hipError_t launch_sk_products(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
+                              uint64_t S, int m, int nys, RepInfo *info, int count, int two_sided, int mfma,
+                              uint32_t *cnt, hipStream_t st);
+// Emits the tiles at pos[list][y][rid] (the exclusive scan of cnt laid end to end).
+hipError_t launch_sk_tiles(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
+                           uint64_t S, int64_t p, int m, int nys, const RepInfo *info, int two_sided, int mfma,
+                           const uint32_t *pos, Tile *tiles, hipStream_t st);
+// Exclusive scan in place of v[0..cnt) (partial: cdiv(cnt, 2048) + 16 u32 of scratch).
+hipError_t launch_scan_u32(uint32_t *v, uint64_t cnt, uint32_t *partial, hipStream_t st);
+
 // Shared arguments of the verification kernels.
 struct VerifyArgs {
     const Tile *tiles;

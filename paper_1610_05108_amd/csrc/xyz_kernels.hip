@@ -608,6 +608,207 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     }
 }
 
+// ------------------------------------------------ bucket sort for m > 15 --
+//
+// With more than MAX_M_LDS key bits the 2^m counters do not fit in LDS.  The
+// keys of every repetition of a chunk are then sorted by (repetition, key)
+// with the LSD radix sort below, equal keys form runs (the non-empty buckets),
+// and the partner of run b, the bucket b ^ c of the same repetition (Section
+// 2.2), is found by binary search among the sorted run keys.  The tile lists
+// are the same as on the LDS path.
+
+__global__ __launch_bounds__(256) void k_sk_init(const uint32_t *__restrict__ keys, uint64_t S, int64_t p, int m,
+                                                 uint64_t *__restrict__ K, uint32_t *__restrict__ V)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= S) return;
+    const uint64_t r = i / (uint64_t)p;
+    K[i] = (r << m) | keys[i];
+    V[i] = (uint32_t)(i - r * (uint64_t)p);
+}
+
+__global__ __launch_bounds__(256) void k_sk_heads(const uint64_t *__restrict__ K, uint64_t S,
+                                                  uint32_t *__restrict__ heads)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= S) return;
+    heads[i] = (i == 0 || K[i] != K[i - 1]) ? 1u : 0u;
+}
+
+// run rid (exclusive scan of the heads) starts at i; nruns[0] = number of runs
+__global__ __launch_bounds__(256) void k_sk_runs(const uint64_t *__restrict__ K, const uint32_t *__restrict__ hscan,
+                                                 uint64_t S, uint64_t *__restrict__ run_key,
+                                                 uint32_t *__restrict__ run_start, uint32_t *__restrict__ nruns)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= S) return;
+    const bool head = i == 0 || K[i] != K[i - 1];
+    if (head) {
+        run_key[hscan[i]] = K[i];
+        run_start[hscan[i]] = (uint32_t)i;
+    }
+    if (i == S - 1) nruns[0] = hscan[i] + (head ? 1u : 0u);
+}
+
+XYZ_DEV int64_t find_run(const uint64_t *run_key, uint32_t nr, uint64_t target)
+{
+    uint32_t lo = 0, hi = nr;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (run_key[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < nr && run_key[lo] == target) ? (int64_t)lo : -1;
+}
+
+XYZ_DEV uint32_t run_len(const uint32_t *run_start, uint32_t nr, uint64_t S, uint32_t rid)
+{
+    return (rid + 1 < nr ? run_start[rid + 1] : (uint32_t)S) - run_start[rid];
+}
+
+// The bucket products of run rid for response y, in the order of k_tiles: partner c,
+// then (two-sided) ~c; a product is taken from its smaller key.  f(b2, rid2, a2, kind, T).
+template <class F>
+XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t *run_start, uint32_t nr, uint64_t S,
+                                        int m, uint32_t rid, uint32_t c, int two_sided, int mfma, F f)
+{
+    const uint32_t mask = (uint32_t)((1ull << m) - 1);
+    const uint64_t rk = run_key[rid];
+    const uint64_t rhi = rk >> m;
+    const uint32_t b = (uint32_t)(rk & mask), a = run_len(run_start, nr, S, rid);
+    const uint32_t cn = (~c) & mask;
+    unsigned long long cand = 0;
+    for (int side = 0; side < ((two_sided && cn != c) ? 2 : 1); ++side) {
+        const uint32_t b2 = b ^ (side ? cn : c);
+        if (b2 < b) continue;
+        int64_t rid2 = rid;
+        if (b2 != b) rid2 = find_run(run_key, nr, (rhi << m) | b2);
+        if (rid2 < 0) continue;
+        const uint32_t a2 = b2 == b ? a : run_len(run_start, nr, S, (uint32_t)rid2);
+        unsigned long long T;
+        int kind;
+        cand += product_tiles(b, b2, a, a2, mfma, kind, T);
+        if (kind) f((uint32_t)rid2, a2, kind, T);
+    }
+    return cand;
+}
+
+// Per (response y, run): tile counts of the three lists into cnt[list][y][rid], and the
+// repetition's statistics (one set of atomics per wave when its lanes share a repetition).
+__global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict__ run_key,
+                                                     const uint32_t *__restrict__ run_start,
+                                                     const uint32_t *__restrict__ nruns, uint64_t S, int m, int nys,
+                                                     RepInfo *__restrict__ info, int two_sided, int mfma,
+                                                     uint32_t *__restrict__ cnt, uint64_t cnt_stride)
+{
+    const uint32_t nr = nruns[0];
+    const uint64_t tid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool on = tid < (uint64_t)nr * nys;
+    uint32_t y = 0, rid = 0;
+    unsigned long long cand = 0, tl[4] = {0, 0, 0, 0};
+    uint32_t a = 0;
+    int64_t key = -1;
+    if (on) {
+        y = (uint32_t)(tid / nr);
+        rid = (uint32_t)(tid % nr);
+        const uint64_t r = run_key[rid] >> m;
+        RepInfo *inf = info + (int64_t)r * nys + y;
+        const uint32_t c = (uint32_t)inf->cmask & (uint32_t)((1ull << m) - 1);
+        a = run_len(run_start, nr, S, rid);
+        cand = run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma,
+                            [&](uint32_t, uint32_t, int kind, unsigned long long T) { tl[kind] += T; });
+        cnt[0 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[2];
+        cnt[1 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[1];
+        cnt[2 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[3];
+        key = (int64_t)(r * nys + y);
+    }
+    // wave aggregation: lanes with the same repetition and response as lane 0
+    const int64_t k0 = __shfl(key, 0, 64);
+    const bool same = key == k0;
+    const unsigned long long all = __ballot(same || !on);
+    if (all == ~0ull && k0 >= 0) {
+        unsigned long long v[4] = {cand, tl[2], tl[1], tl[3]};
+        uint32_t mx = a;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], d, 64);
+            mx = max(mx, (uint32_t)__shfl_xor(mx, d, 64));
+        }
+        if (lane_id() == 0) {
+            RepInfo *inf = info + k0;
+            atomicAdd(&inf->candidates, v[0]);
+            atomicAdd(&inf->tiles, v[1]);
+            atomicAdd(&inf->small_tiles, (unsigned)v[2]);
+            atomicAdd(&inf->mfma_tiles, v[3]);
+            atomicMax(&inf->max_bucket, mx);
+        }
+    } else if (on) {
+        RepInfo *inf = info + key;
+        atomicAdd(&inf->candidates, cand);
+        atomicAdd(&inf->tiles, tl[2]);
+        atomicAdd(&inf->small_tiles, (unsigned)tl[1]);
+        atomicAdd(&inf->mfma_tiles, tl[3]);
+        atomicMax(&inf->max_bucket, a);
+    }
+}
+
+// Tiles of every (response, run) at pos[list][y][rid] (exclusive scan over the three lists
+// laid end to end, so the popcount, small and matrix-core lists follow each other).
+__global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ run_key,
+                                                  const uint32_t *__restrict__ run_start,
+                                                  const uint32_t *__restrict__ nruns, uint64_t S, int64_t p, int m,
+                                                  int nys, const RepInfo *__restrict__ info, int two_sided, int mfma,
+                                                  const uint32_t *__restrict__ pos, uint64_t cnt_stride,
+                                                  Tile *__restrict__ tiles)
+{
+    const uint32_t nr = nruns[0];
+    const uint64_t tid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (tid >= (uint64_t)nr * nys) return;
+    const uint32_t y = (uint32_t)(tid / nr), rid = (uint32_t)(tid % nr);
+    const uint64_t r = run_key[rid] >> m;
+    const uint32_t c = (uint32_t)info[r * nys + y].cmask & (uint32_t)((1ull << m) - 1);
+    const uint32_t pbase = (uint32_t)(r * (uint64_t)p);
+    const uint32_t o1 = run_start[rid] - pbase, a = run_len(run_start, nr, S, rid);
+    uint64_t at[4];
+    at[2] = pos[0 * cnt_stride + (uint64_t)y * nr + rid];
+    at[1] = pos[1 * cnt_stride + (uint64_t)y * nr + rid];
+    at[3] = pos[2 * cnt_stride + (uint64_t)y * nr + rid];
+    run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma,
+                 [&](uint32_t rid2, uint32_t a2, int kind, unsigned long long T) {
+                     const uint32_t ts = kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE;
+                     const uint32_t o2 = run_start[rid2] - pbase;
+                     const bool own = rid2 == rid;
+                     const uint32_t nB = (a2 + ts - 1) / ts, nA = (a + ts - 1) / ts;
+                     for (unsigned long long t = 0; t < T; ++t) {
+                         uint32_t ia, ib;
+                         if (own) {
+                             tri_index(t, nA, ia, ib);
+                         } else {
+                             ia = (uint32_t)(t / nB);
+                             ib = (uint32_t)(t % nB);
+                         }
+                         tiles[at[kind] + t] =
+                             make_tile(ts, (uint32_t)r, y, pbase, o1, a, own ? o1 : o2, own ? a : a2, ia, ib,
+                                       (uint8_t)(own && ia == ib));
+                     }
+                     at[kind] += T;
+                 });
+}
+
+__global__ __launch_bounds__(256) void k_sk_clear_info(RepInfo *__restrict__ info, int count)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    info[i].candidates = 0;
+    info[i].tiles = 0;
+    info[i].passed = 0;
+    info[i].fresh = 0;
+    info[i].max_bucket = 0;
+    info[i].small_tiles = 0;
+    info[i].mfma_tiles = 0;
+}
+
 // ----------------------------------------------------------- FP4 operands --
 //
 // The 0/1 dot products of the exact search and of large verification tiles run
@@ -2044,6 +2245,71 @@ static hipError_t scan_u32(uint32_t *v, uint64_t cnt, uint32_t *partial, hipStre
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(RS_NT), 0, st, v, cnt, partial);
     hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, partial, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(RS_NT), 0, st, v, cnt, partial, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(uint32_t *v, uint64_t cnt, uint32_t *partial, hipStream_t st)
+{
+    return scan_u32(v, cnt, partial, st);
+}
+
+hipError_t launch_sk_sort(const uint32_t *keys, int64_t p, int m, int nrep, uint64_t *K, uint32_t *V, uint64_t *K2,
+                          uint32_t *V2, uint32_t *hist, uint32_t *perm, uint64_t **Ksorted, hipStream_t st)
+{
+    const uint64_t S = (uint64_t)nrep * (uint64_t)p;
+    if (S == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sk_init, dim3(grid1(S, 256)), dim3(256), 0, st, keys, S, p, m, K, V);
+    int rbits = 0;
+    while ((1ll << rbits) < nrep) ++rbits;
+    const int bits = m + rbits;
+    const uint32_t nb = (uint32_t)((S + RS_TILE - 1) / RS_TILE);
+    const uint64_t hent = 256ull * nb;
+    uint32_t *partial = hist + hent;
+    uint64_t *ka = K, *kb = K2;
+    uint32_t *va = V, *vb = V2;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_NT), 0, st, ka, S, shift, hist, nb);
+        hipError_t e = scan_u32(hist, hent, partial, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_NT), 0, st, ka, va, kb, vb, S, shift, hist, nb);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    *Ksorted = ka;
+    return hipMemcpyAsync(perm, va, sizeof(uint32_t) * S, hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t launch_sk_runs(const uint64_t *K, uint64_t S, uint32_t *heads, uint32_t *partial, uint64_t *run_key,
+                          uint32_t *run_start, uint32_t *nruns, hipStream_t st)
+{
+    if (S == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sk_heads, dim3(grid1(S, 256)), dim3(256), 0, st, K, S, heads);
+    hipError_t e = scan_u32(heads, S, partial, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sk_runs, dim3(grid1(S, 256)), dim3(256), 0, st, K, heads, S, run_key, run_start, nruns);
+    return hipGetLastError();
+}
+
+hipError_t launch_sk_products(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
+                              uint64_t S, int m, int nys, RepInfo *info, int count, int two_sided, int mfma,
+                              uint32_t *cnt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sk_clear_info, dim3((count + 255) / 256), dim3(256), 0, st, info, count);
+    const uint64_t work = (uint64_t)nr * nys;
+    if (work == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_sk_products, dim3(grid1(work, 256)), dim3(256), 0, st, run_key, run_start, nruns, S, m, nys,
+                       info, two_sided, mfma, cnt, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_sk_tiles(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
+                           uint64_t S, int64_t p, int m, int nys, const RepInfo *info, int two_sided, int mfma,
+                           const uint32_t *pos, Tile *tiles, hipStream_t st)
+{
+    const uint64_t work = (uint64_t)nr * nys;
+    if (work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sk_tiles, dim3(grid1(work, 256)), dim3(256), 0, st, run_key, run_start, nruns, S, p, m, nys,
+                       info, two_sided, mfma, pos, work, tiles);
     return hipGetLastError();
 }
 

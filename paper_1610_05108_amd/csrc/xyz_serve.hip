@@ -60,7 +60,8 @@ uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk)
     const double p = (double)x->p, nb = std::ldexp(1.0, P.m);
     const double cand = p * (p - 1) / 2 / nb;
     const double tiles = std::max(p / 24.0, cand / 576.0);
-    const double per_rep = 8 * p + 4 * (nb + 1) + 16 * tiles + 80;
+    // the sort path (m > 15) replaces the 2^m bucket offsets by about 56 bytes of scratch per column
+    const double per_rep = 8 * p + (P.m <= 15 ? 4 * (nb + 1) : 56 * p) + 16 * tiles + 80;
     const double fixed = (double)(1 << 16) * 32 * 2 + (double)x->W32p * 4 + (double)x->nF * 8 + (double)P.L * 48;
     return (uint64_t)(per_rep * (double)chunk + fixed);
 }
