@@ -330,7 +330,8 @@ int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m)
     chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((1ll << 32) - 1) / p));   // u32 positions in perm
     // bytes per repetition: keys and permutation, plus the LDS path's bucket offsets or the sort
     // path's scratch (two key/value buffers, heads, runs and per-run tile counts)
-    const int64_t per_rep = m <= MAX_M_LDS ? 8 * p + 4 * ((1ll << m) + 1) : 64 * p;
+    const int64_t per_rep = m <= MAX_M_LDS ? 8 * p + 4 * ((1ll << m) + 1)
+                                           : 64 * p + (m <= SK_TABLE_MAX_M ? 4 * (1ll << m) : 0);
     chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / per_rep));
     chunk = std::min<int64_t>(chunk, 65535);                                           // grid y of k_hash
     if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
@@ -529,10 +530,16 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 uint32_t nr = 0;
                 HIP_TRY(hipMemcpyAsync(&nr, dnr, sizeof nr, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
+                uint32_t *table = nullptr;
+                if (m <= SK_TABLE_MAX_M) {
+                    XYZ_TRY(ws(c, WS_SKTAB, (size_t)R << m, &table));
+                    HIP_TRY(launch_sk_table(rkey, dnr, nr, (uint64_t)R << m, table, st));
+                }
                 const uint64_t ncnt = 3ull * nys * nr;
                 XYZ_TRY(ws(c, WS_SKCNT, ncnt + 1, &cnt));
                 HIP_TRY(hipMemsetAsync(cnt + ncnt, 0, sizeof(uint32_t), st));
-                HIP_TRY(launch_sk_products(rkey, rstart, dnr, nr, S, m, nys, cinfo, R * nys, two, mfma, cnt, st));
+                HIP_TRY(launch_sk_products(rkey, rstart, dnr, nr, S, m, nys, cinfo, R * nys, two, mfma, table, cnt,
+                                           st));
                 tm.end();
                 tm.begin(4);
                 // positions of every (list, response, run) in the tile array; list starts and total
@@ -548,7 +555,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 nsmall = bnd[1] - bnd[0];
                 nmfma = bnd[2] - bnd[1];
                 XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
-                HIP_TRY(launch_sk_tiles(rkey, rstart, dnr, nr, S, p, m, nys, cinfo, two, mfma, cnt, tiles, st));
+                HIP_TRY(launch_sk_tiles(rkey, rstart, dnr, nr, S, p, m, nys, cinfo, two, mfma, table, cnt, tiles, st));
                 tm.end();
             }
             VerifyArgs va{};

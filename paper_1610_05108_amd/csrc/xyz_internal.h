@@ -114,16 +114,21 @@ hipError_t launch_sk_sort(const uint32_t *keys, int64_t p, int m, int nrep, uint
 // the device.  heads: S u32 scratch; partial: scan scratch (radix_hist_entries(S) is enough).
 hipError_t launch_sk_runs(const uint64_t *K, uint64_t S, uint32_t *heads, uint32_t *partial, uint64_t *run_key,
                           uint32_t *run_start, uint32_t *nruns, hipStream_t st);
+// Largest m with a direct bucket -> run table (nrep 2^m u32) instead of binary search.
+constexpr int SK_TABLE_MAX_M = 22;
+// table[(r << m) | b] = run id + 1 for every run, 0 for empty buckets (entries = nrep 2^m).
+hipError_t launch_sk_table(const uint64_t *run_key, const uint32_t *nruns, uint32_t nr, uint64_t entries,
+                           uint32_t *table, hipStream_t st);
 // Clears the statistics of info[0..count) (keeping cmask), then per (response, run) counts the
 // tiles of its bucket products in cnt[list][y][rid] (lists: popcount, small, matrix-core;
-// 3 * nys * nr entries) and adds the statistics to info.
+// 3 * nys * nr entries) and adds the statistics to info.  table: as above, or null (binary search).
 hipError_t launch_sk_products(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
                               uint64_t S, int m, int nys, RepInfo *info, int count, int two_sided, int mfma,
-                              uint32_t *cnt, hipStream_t st);
+                              const uint32_t *table, uint32_t *cnt, hipStream_t st);
 // Emits the tiles at pos[list][y][rid] (the exclusive scan of cnt laid end to end).
 hipError_t launch_sk_tiles(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
                            uint64_t S, int64_t p, int m, int nys, const RepInfo *info, int two_sided, int mfma,
-                           const uint32_t *pos, Tile *tiles, hipStream_t st);
+                           const uint32_t *table, const uint32_t *pos, Tile *tiles, hipStream_t st);
 // Exclusive scan in place of v[0..cnt) (partial: cdiv(cnt, 2048) + 16 u32 of scratch).
 hipError_t launch_scan_u32(uint32_t *v, uint64_t cnt, uint32_t *partial, hipStream_t st);
 

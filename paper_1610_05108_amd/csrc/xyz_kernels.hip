@@ -650,8 +650,11 @@ __global__ __launch_bounds__(256) void k_sk_runs(const uint64_t *__restrict__ K,
     if (i == S - 1) nruns[0] = hscan[i] + (head ? 1u : 0u);
 }
 
-XYZ_DEV int64_t find_run(const uint64_t *run_key, uint32_t nr, uint64_t target)
+// Run of composite key (r << m) | b: from the direct table (m <= SK_TABLE_MAX_M: entry r 2^m + b
+// holds run id + 1, 0 when the bucket is empty) or by binary search over the sorted run keys.
+XYZ_DEV int64_t find_run(const uint64_t *run_key, uint32_t nr, uint64_t target, const uint32_t *table)
 {
+    if (table) return (int64_t)table[target] - 1;
     uint32_t lo = 0, hi = nr;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -670,7 +673,8 @@ XYZ_DEV uint32_t run_len(const uint32_t *run_start, uint32_t nr, uint64_t S, uin
 // then (two-sided) ~c; a product is taken from its smaller key.  f(b2, rid2, a2, kind, T).
 template <class F>
 XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t *run_start, uint32_t nr, uint64_t S,
-                                        int m, uint32_t rid, uint32_t c, int two_sided, int mfma, F f)
+                                        int m, uint32_t rid, uint32_t c, int two_sided, int mfma,
+                                        const uint32_t *table, F f)
 {
     const uint32_t mask = (uint32_t)((1ull << m) - 1);
     const uint64_t rk = run_key[rid];
@@ -682,7 +686,7 @@ XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t 
         const uint32_t b2 = b ^ (side ? cn : c);
         if (b2 < b) continue;
         int64_t rid2 = rid;
-        if (b2 != b) rid2 = find_run(run_key, nr, (rhi << m) | b2);
+        if (b2 != b) rid2 = find_run(run_key, nr, (rhi << m) | b2, table);
         if (rid2 < 0) continue;
         const uint32_t a2 = b2 == b ? a : run_len(run_start, nr, S, (uint32_t)rid2);
         unsigned long long T;
@@ -694,62 +698,71 @@ XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t 
 }
 
 // Per (response y, run): tile counts of the three lists into cnt[list][y][rid], and the
-// repetition's statistics (one set of atomics per wave when its lanes share a repetition).
+// repetition's statistics.  A block takes SK_ITEMS * 256 consecutive items; each thread sums its
+// items per (repetition, response), flushing with atomics only when that changes, and the
+// waves whose lanes end on one (repetition, response) add their sums once.
+constexpr int SK_ITEMS = 16;
+
+XYZ_DEV void sk_flush(RepInfo *info, int64_t key, const unsigned long long v[4], uint32_t mx)
+{
+    RepInfo *inf = info + key;
+    if (v[0]) atomicAdd(&inf->candidates, v[0]);
+    if (v[1]) atomicAdd(&inf->tiles, v[1]);
+    if (v[2]) atomicAdd(&inf->small_tiles, (unsigned)v[2]);
+    if (v[3]) atomicAdd(&inf->mfma_tiles, v[3]);
+    atomicMax(&inf->max_bucket, mx);
+}
+
 __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict__ run_key,
                                                      const uint32_t *__restrict__ run_start,
                                                      const uint32_t *__restrict__ nruns, uint64_t S, int m, int nys,
                                                      RepInfo *__restrict__ info, int two_sided, int mfma,
+                                                     const uint32_t *__restrict__ table,
                                                      uint32_t *__restrict__ cnt, uint64_t cnt_stride)
 {
     const uint32_t nr = nruns[0];
-    const uint64_t tid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool on = tid < (uint64_t)nr * nys;
-    uint32_t y = 0, rid = 0;
-    unsigned long long cand = 0, tl[4] = {0, 0, 0, 0};
-    uint32_t a = 0;
+    const uint64_t total = (uint64_t)nr * nys;
+    const uint64_t base = (uint64_t)blockIdx.x * SK_ITEMS * 256;
     int64_t key = -1;
-    if (on) {
-        y = (uint32_t)(tid / nr);
-        rid = (uint32_t)(tid % nr);
+    unsigned long long v[4] = {0, 0, 0, 0};
+    uint32_t mx = 0;
+    for (int it = 0; it < SK_ITEMS; ++it) {
+        const uint64_t tid = base + (uint64_t)it * 256 + threadIdx.x;
+        if (tid >= total) break;
+        const uint32_t y = (uint32_t)(tid / nr), rid = (uint32_t)(tid % nr);
         const uint64_t r = run_key[rid] >> m;
-        RepInfo *inf = info + (int64_t)r * nys + y;
-        const uint32_t c = (uint32_t)inf->cmask & (uint32_t)((1ull << m) - 1);
-        a = run_len(run_start, nr, S, rid);
-        cand = run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma,
-                            [&](uint32_t, uint32_t, int kind, unsigned long long T) { tl[kind] += T; });
+        const int64_t k = (int64_t)(r * nys + y);
+        if (k != key) {
+            if (key >= 0) sk_flush(info, key, v, mx);
+            key = k;
+            v[0] = v[1] = v[2] = v[3] = 0;
+            mx = 0;
+        }
+        const uint32_t c = (uint32_t)info[k].cmask & (uint32_t)((1ull << m) - 1);
+        unsigned long long tl[4] = {0, 0, 0, 0};
+        v[0] += run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
+                             [&](uint32_t, uint32_t, int kind, unsigned long long T) { tl[kind] += T; });
         cnt[0 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[2];
         cnt[1 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[1];
         cnt[2 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[3];
-        key = (int64_t)(r * nys + y);
+        v[1] += tl[2];
+        v[2] += tl[1];
+        v[3] += tl[3];
+        mx = max(mx, run_len(run_start, nr, S, rid));
     }
-    // wave aggregation: lanes with the same repetition and response as lane 0
+    // lanes that end on lane 0's (repetition, response) add their sums once per wave
     const int64_t k0 = __shfl(key, 0, 64);
-    const bool same = key == k0;
-    const unsigned long long all = __ballot(same || !on);
-    if (all == ~0ull && k0 >= 0) {
-        unsigned long long v[4] = {cand, tl[2], tl[1], tl[3]};
-        uint32_t mx = a;
+    const unsigned long long same = __ballot(key == k0 || key < 0);
+    if (same == ~0ull && k0 >= 0) {
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], d, 64);
             mx = max(mx, (uint32_t)__shfl_xor(mx, d, 64));
         }
-        if (lane_id() == 0) {
-            RepInfo *inf = info + k0;
-            atomicAdd(&inf->candidates, v[0]);
-            atomicAdd(&inf->tiles, v[1]);
-            atomicAdd(&inf->small_tiles, (unsigned)v[2]);
-            atomicAdd(&inf->mfma_tiles, v[3]);
-            atomicMax(&inf->max_bucket, mx);
-        }
-    } else if (on) {
-        RepInfo *inf = info + key;
-        atomicAdd(&inf->candidates, cand);
-        atomicAdd(&inf->tiles, tl[2]);
-        atomicAdd(&inf->small_tiles, (unsigned)tl[1]);
-        atomicAdd(&inf->mfma_tiles, tl[3]);
-        atomicMax(&inf->max_bucket, a);
+        if (lane_id() == 0) sk_flush(info, k0, v, mx);
+    } else if (key >= 0) {
+        sk_flush(info, key, v, mx);
     }
 }
 
@@ -759,6 +772,7 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
                                                   const uint32_t *__restrict__ run_start,
                                                   const uint32_t *__restrict__ nruns, uint64_t S, int64_t p, int m,
                                                   int nys, const RepInfo *__restrict__ info, int two_sided, int mfma,
+                                                  const uint32_t *__restrict__ table,
                                                   const uint32_t *__restrict__ pos, uint64_t cnt_stride,
                                                   Tile *__restrict__ tiles)
 {
@@ -774,7 +788,7 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
     at[2] = pos[0 * cnt_stride + (uint64_t)y * nr + rid];
     at[1] = pos[1 * cnt_stride + (uint64_t)y * nr + rid];
     at[3] = pos[2 * cnt_stride + (uint64_t)y * nr + rid];
-    run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma,
+    run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
                  [&](uint32_t rid2, uint32_t a2, int kind, unsigned long long T) {
                      const uint32_t ts = kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE;
                      const uint32_t o2 = run_start[rid2] - pbase;
@@ -794,6 +808,14 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
                      }
                      at[kind] += T;
                  });
+}
+
+__global__ __launch_bounds__(256) void k_sk_table(const uint64_t *__restrict__ run_key,
+                                                  const uint32_t *__restrict__ nruns, uint32_t *__restrict__ table)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nruns[0]) return;
+    table[run_key[i]] = (uint32_t)i + 1;
 }
 
 __global__ __launch_bounds__(256) void k_sk_clear_info(RepInfo *__restrict__ info, int count)
@@ -2290,26 +2312,35 @@ hipError_t launch_sk_runs(const uint64_t *K, uint64_t S, uint32_t *heads, uint32
     return hipGetLastError();
 }
 
+hipError_t launch_sk_table(const uint64_t *run_key, const uint32_t *nruns, uint32_t nr, uint64_t entries,
+                           uint32_t *table, hipStream_t st)
+{
+    hipError_t e = hipMemsetAsync(table, 0, sizeof(uint32_t) * entries, st);
+    if (e != hipSuccess || nr == 0) return e;
+    hipLaunchKernelGGL(k_sk_table, dim3(grid1(nr, 256)), dim3(256), 0, st, run_key, nruns, table);
+    return hipGetLastError();
+}
+
 hipError_t launch_sk_products(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
                               uint64_t S, int m, int nys, RepInfo *info, int count, int two_sided, int mfma,
-                              uint32_t *cnt, hipStream_t st)
+                              const uint32_t *table, uint32_t *cnt, hipStream_t st)
 {
     hipLaunchKernelGGL(k_sk_clear_info, dim3((count + 255) / 256), dim3(256), 0, st, info, count);
     const uint64_t work = (uint64_t)nr * nys;
     if (work == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_sk_products, dim3(grid1(work, 256)), dim3(256), 0, st, run_key, run_start, nruns, S, m, nys,
-                       info, two_sided, mfma, cnt, work);
+    hipLaunchKernelGGL(k_sk_products, dim3(grid1(work, 256 * SK_ITEMS)), dim3(256), 0, st, run_key, run_start, nruns,
+                       S, m, nys, info, two_sided, mfma, table, cnt, work);
     return hipGetLastError();
 }
 
 hipError_t launch_sk_tiles(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
                            uint64_t S, int64_t p, int m, int nys, const RepInfo *info, int two_sided, int mfma,
-                           const uint32_t *pos, Tile *tiles, hipStream_t st)
+                           const uint32_t *table, const uint32_t *pos, Tile *tiles, hipStream_t st)
 {
     const uint64_t work = (uint64_t)nr * nys;
     if (work == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sk_tiles, dim3(grid1(work, 256)), dim3(256), 0, st, run_key, run_start, nruns, S, p, m, nys,
-                       info, two_sided, mfma, pos, work, tiles);
+                       info, two_sided, mfma, table, pos, work, tiles);
     return hipGetLastError();
 }
 
