@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=None)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-large", action="store_true", help="skip the large Rademacher comparison")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-fresh", type=int, default=32)
     ap.add_argument("--serve-workers", type=int, default=2)
@@ -223,6 +224,11 @@ def main():
     pairs_per_search = p * (p - 1) / 2
     value = len(data) * pairs_per_search / (ms_per_step * 1e-3)
 
+    large = None
+    if not args.no_large:
+        large = large_binary_leg(ctx)
+        log(f"large binary: {large}")
+
     serving = None
     if not args.no_serve:
         serving = serve_leg(ctx, args.serve_requests, args.serve_fresh, args.serve_workers, seq_sample=32)
@@ -256,6 +262,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "large_binary": large,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -409,6 +416,45 @@ def serve_leg(ctx, count, fresh_count, workers, seq_sample):
         "model": {"exact_pair_rows_per_s": rate_exact, "verify_candidate_words_per_s": rate_verify,
                   "s_per_rep_column": rep_cost},
     }
+
+
+def large_binary_leg(ctx):
+    """The large Rademacher workload (n=5000, p=10^6, 20 planted pairs of strength
+    U[0.15, 0.5], bit-packed) with its configured xyz parameters (m=14, L=500,
+    kappa=0.12) against the exact matrix-core search, each timed on its second run.
+    Recall: planted pairs above kappa reported; predicted: eq. (9) at each planted
+    pair's measured strength."""
+    import torch
+    import synthgen
+    import paper_1610_05108_amd as xyz
+    d = synthgen.config3(seed=0)
+    x = xyz.xyz_x_create(ctx.h, d.bits, n=d.n)
+    Y = torch.from_numpy(d.Y).cuda()
+    m, L, kappa = 14, 500, 0.12
+    out = {"workload": f"Rademacher bits n={d.n} p={d.p}, {len(d.planted)} planted pairs, kappa={kappa}"}
+    ex = None
+    for name in ("exact", "xyz"):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "exact":
+                r = ctx.bruteforce(x, Y, kappa)
+            else:
+                r = ctx.search(x, Y, m=m, L=L, kappa=kappa, seed=rep)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        got = {(int(a), int(b)): int(s) for a, b, s in zip(r["pairs"]["j"], r["pairs"]["k"], r["pairs"]["s"])}
+        if name == "exact":
+            ex = got
+        above = [pq for pq in d.planted if pq in ex]
+        out[name] = {"ms": dt * 1e3, "planted_found": sum(1 for pq in above if pq in got),
+                     "planted_above_kappa": len(above)}
+    g = [0.5 * (1 + ex[pq] / d.n) for pq in d.planted if pq in ex]
+    eta = [1 - (1 - gg ** m) ** L for gg in g]
+    out["xyz"].update(m=m, L=L, predicted_recall_min=min(eta), predicted_recall_mean=sum(eta) / len(eta))
+    out["speedup_xyz_over_exact"] = out["exact"]["ms"] / out["xyz"]["ms"]
+    xyz.xyz_x_destroy(x)
+    return out
 
 
 def cpu_baseline(dd, m, L, n, p, reps=None):
