@@ -20,6 +20,7 @@
 #include "xyz_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace xyz {
 
@@ -1616,35 +1617,25 @@ __global__ __launch_bounds__(256) void k_brute_pop(const uint4 *__restrict__ XB,
 // computes the 64 x 128 sub-block of A columns wa*64.. and B columns wb*128..
 // as 2 x 4 fragments of 32 x 32.  Each lane loads its fragments' words straight
 // from the staged layout (the waves of a workgroup share them through the L1
-// cache), expands them in registers and feeds the matrix cores: no barriers,
-// and quads are loaded three steps ahead.  XA and XB are kernel
-// arguments of their own so that the compiler sees global, read-only pointers.
+// cache), expands them in registers and feeds the matrix cores, with no barrier
+// in the product loop.  Quads are loaded three steps ahead through a ring of
+// three register sets, across tiles: the last three steps of a tile load the
+// first three quads of the workgroup's next tile, so a tile starts with its data
+// in flight.  XA and XB are kernel arguments of their own so that the compiler
+// sees global, read-only pointers.
 struct BruteFrag {
     uint2 a[2], b[4];        // words (h, h + 2) of quad qi for the lane's 2 A and 4 B columns
 };
 
-template <bool TWO>
-__global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restrict__ XA,
-                                               const uint2 *__restrict__ XB)
+// Work slots: block pairs grouped in super-blocks of 8 x 8 (slot t: super-block t / 64,
+// then row-major inside it), so that the 32 workgroups an XCD runs at a time share 12
+// blocks in its L2.  Workgroups g = x mod 8 run on XCD x; the slot count and the grid
+// are multiples of 8, so t(g) is a bijection and each XCD gets a contiguous range.
+// Advances g (step gridDim.x) to the first slot at or after g that holds a block pair.
+XYZ_DEV bool brute_next_tile(const BruteArgs &a, uint64_t &g, uint64_t &bi, uint64_t &bj)
 {
-    __shared__ float fragbuf[8][16][64];             // per wave: one fragment of the rare pass
-    __shared__ unsigned int wg_n;                    // survivors of this workgroup so far
-    const int tid = threadIdx.x;
-    if (tid == 0) wg_n = 0;
-    __syncthreads();
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wa = wave >> 1, wb = wave & 1;
-    const int h = lane >> 5, l32 = lane & 31;
-    const int nq = a.nq;
-    const uint64_t qstride = 2 * BF_TILE;            // uint2 per quad of a block
-    const int32_t n32 = (int32_t)a.n, smin32 = (int32_t)a.smin;
-    // Work slots: block pairs grouped in super-blocks of 8 x 8 (slot t: super-block t / 64,
-    // then row-major inside it), so that the 32 workgroups an XCD runs at a time share 12
-    // blocks in its L2.  Workgroups g = x mod 8 run on XCD x; the slot count and the grid
-    // are multiples of 8, so t(g) is a bijection and each XCD gets a contiguous range.
-    const uint64_t G = a.nslots;
-    const uint64_t per = G / 8;
-    for (uint64_t g = blockIdx.x; g < G; g += gridDim.x) {
+    const uint64_t G = a.nslots, per = G / 8;
+    for (; g < G; g += gridDim.x) {
         const uint64_t t = (g % 8) * per + g / 8;
         const uint64_t sb = t / 64, w = t % 64;
         uint64_t I, J;
@@ -1657,23 +1648,65 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
             I = sb / (uint64_t)a.nsbB;
             J = sb % (uint64_t)a.nsbB;
         }
-        const uint64_t bi = I * 8 + w / 8, bj = J * 8 + w % 8;
-        if (bi >= (uint64_t)a.nbA || bj >= (uint64_t)a.nbB || (a.tri && bi > bj)) continue;
-        const uint2 *pa = XA + bi * (uint64_t)nq * qstride + 2 * (wa * 64 + l32) + h;
-        const uint2 *pb = XB + bj * (uint64_t)nq * qstride + 2 * (wb * 128 + l32) + h;
-        auto load = [&](BruteFrag &f, int qi) {
-            const uint64_t o = (uint64_t)min(qi, nq - 1) * qstride;   // clamped: past the end is never used
+        bi = I * 8 + w / 8;
+        bj = J * 8 + w % 8;
+        if (bi < (uint64_t)a.nbA && bj < (uint64_t)a.nbB && !(a.tri && bi > bj)) return true;
+    }
+    return false;
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restrict__ XA,
+                                               const uint2 *__restrict__ XB)
+{
+    __shared__ float fragbuf[8][16][64];             // per wave: one fragment of the rare pass
+    __shared__ __align__(16) uint32_t popbuf[2][2 * BF_TILE];   // the tile's A, B popcounts (by tile parity)
+    __shared__ unsigned int wg_n;                    // survivors of this workgroup so far
+    const int tid = threadIdx.x;
+    if (tid == 0) wg_n = 0;
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wa = wave >> 1, wb = wave & 1;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int nq = a.nq;
+    const uint64_t qstride = 2 * BF_TILE;            // uint2 per quad of a block
+    const int32_t n32 = (int32_t)a.n, smin32 = (int32_t)a.smin;
+    const int la = 2 * (wa * 64 + l32) + h, lb = 2 * (wb * 128 + l32) + h;   // lane offsets in a quad
+    // quad q of block b on either side (wave-uniform base; q clamped to the block)
+    auto quad = [&](const uint2 *X, uint64_t blk, int q) {
+        return X + (blk * (uint64_t)nq + (uint64_t)min(q, nq - 1)) * qstride;
+    };
+    auto load = [&](BruteFrag &f, const uint2 *qa, const uint2 *qb) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) f.a[u] = pa[o + 2 * 32 * u];
+        for (int u = 0; u < 2; ++u) f.a[u] = qa[la + 2 * 32 * u];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) f.b[v] = pb[o + 2 * 32 * v];
-        };
+        for (int v = 0; v < 4; ++v) f.b[v] = qb[lb + 2 * 32 * v];
+    };
+    uint64_t g = blockIdx.x, bi = 0, bj = 0;
+    bool have = brute_next_tile(a, g, bi, bj);
+    BruteFrag f0, f1, f2;
+    if (have) {
+        load(f0, quad(XA, bi, 0), quad(XB, bj, 0));
+        load(f1, quad(XA, bi, 1), quad(XB, bj, 1));
+        load(f2, quad(XA, bi, 2), quad(XB, bj, 2));
+    }
+    int par = 0;
+    while (have) {
+        // the next tile (or this one again when there is none: its loads are then unused)
+        uint64_t g2 = g + gridDim.x, bi2 = bi, bj2 = bj;
+        const bool have2 = brute_next_tile(a, g2, bi2, bj2);
+        if (!have2) {
+            bi2 = bi;
+            bj2 = bj;
+        }
+        // this tile's popcounts, for the epilogue: one value per thread, stored to LDS after the products
+        const uint32_t popv = tid < BF_TILE ? a.popA[bi * BF_TILE + tid] : a.popB[bj * BF_TILE + tid - BF_TILE];
+
         v16f acc[2][4];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = v16f{};
-        auto step = [&](BruteFrag &f, int qi) {
+        // one quad: the products of its two words, then the load of quad qi + 3 into the freed
+        // registers (slot s of the ring: the next tile's quad s once qi + 3 is past the end);
+        // the first quad's first product starts the accumulators (a zero operand)
+        auto step = [&](BruteFrag &f, int qi, int slot, auto first) {
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 v8i fa[2], fb[4];
@@ -1685,25 +1718,30 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        acc[u][v] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[u], fb[v], acc[u][v], 4, 4, 0,
-                                                                                     127, 0, 127);
+                        acc[u][v] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            fa[u], fb[v], (decltype(first)::value && k == 0) ? v16f{} : acc[u][v], 4, 4, 0, 127, 0,
+                            127);
             }
-            load(f, qi + 3);
+            const bool cur = qi + 3 < nq;
+            load(f, cur ? quad(XA, bi, qi + 3) : quad(XA, bi2, slot), cur ? quad(XB, bj, qi + 3) : quad(XB, bj2, slot));
             // keep the loads where they are: each set is consumed three steps later
             __builtin_amdgcn_sched_barrier(0);
         };
-        BruteFrag f0, f1, f2;
-        load(f0, 0);
-        load(f1, 1);
-        load(f2, 2);
-        int qi = 0;
+        step(f0, 0, 0, std::true_type{});
+        int qi = 1;
         for (; qi + 2 < nq; qi += 3) {      // no branches inside: each wait is for the oldest loads only
-            step(f0, qi);
-            step(f1, qi + 1);
-            step(f2, qi + 2);
+            step(f1, qi, 1, std::false_type{});
+            step(f2, qi + 1, 2, std::false_type{});
+            step(f0, qi + 2, 0, std::false_type{});
         }
-        if (qi < nq) step(f0, qi);
-        if (qi + 1 < nq) step(f1, qi + 1);
+        if (qi < nq) step(f1, qi, 1, std::false_type{});
+        if (qi + 1 < nq) step(f2, qi + 1, 2, std::false_type{});
+        // each stepped slot now holds the next tile's quad of the same number (all three when
+        // nq >= 3; with fewer quads, the slots that were not stepped are not used either)
+
+        popbuf[par][tid] = popv;
+        __syncthreads();
+        const uint32_t *popAt = popbuf[par], *popBt = popbuf[par] + BF_TILE;
 
         // epilogue: accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4, column l%32.
         // s = n - 2|z_a| - 2|x_b| + 4C >= smin  <=>  4C - 2|z_a| >= smin - n + 2|x_b|, exact in FP32
@@ -1714,8 +1752,7 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
         auto rows_pop2 = [&](int u, float *tA) {
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) {
-                const uint4 v4 = *reinterpret_cast<const uint4 *>(
-                    &a.popA[bi * BF_TILE + wa * 64 + u * 32 + q4 * 8 + h * 4]);
+                const uint4 v4 = *reinterpret_cast<const uint4 *>(&popAt[wa * 64 + u * 32 + q4 * 8 + h * 4]);
                 tA[4 * q4 + 0] = (float)(2 * (int32_t)v4.x);
                 tA[4 * q4 + 1] = (float)(2 * (int32_t)v4.y);
                 tA[4 * q4 + 2] = (float)(2 * (int32_t)v4.z);
@@ -1729,7 +1766,7 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
             rows_pop2(u, tA);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int32_t pb2 = 2 * (int32_t)a.popB[bj * BF_TILE + wb * 128 + v * 32 + l32];
+                const int32_t pb2 = 2 * (int32_t)popBt[wb * 128 + v * 32 + l32];
                 float mx = -1e30f, mn = 1e30f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
@@ -1741,82 +1778,88 @@ __global__ __launch_bounds__(512) void k_brute(BruteArgs a, const uint2 *__restr
                 hitmask |= (hit ? 1u : 0u) << (u * 4 + v);
             }
         }
-        if (__ballot(hitmask != 0) == 0) continue;
-        // pair-by-pair pass on the fragments that hit (rare): x = 4C - 2|z_a| of the fragment goes
-        // to the wave's LDS slot, so that the pass can index its rows at run time, then validity
-        // (padding columns, j != k, a < b on a diagonal block) and the survivors' slots, with one
-        // atomic per fragment and wave.  s = n - 2|x_b| + x.
+        if (__ballot(hitmask != 0) != 0) {
+            // pair-by-pair pass on the fragments that hit (rare): x = 4C - 2|z_a| of the fragment goes
+            // to the wave's LDS slot, so that the pass can index its rows at run time, then validity
+            // (padding columns, j != k, a < b on a diagonal block) and the survivors' slots, with one
+            // atomic per fragment and wave.  s = n - 2|x_b| + x.
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            float tA[16];
-            rows_pop2(u, tA);
+            for (int u = 0; u < 2; ++u) {
+                float tA[16];
+                rows_pop2(u, tA);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                if (__ballot((hitmask >> (u * 4 + v)) & 1u) == 0) continue;
+                for (int v = 0; v < 4; ++v) {
+                    if (__ballot((hitmask >> (u * 4 + v)) & 1u) == 0) continue;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) fragbuf[wave][r][lane] = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
-                const int cb = wb * 128 + v * 32 + l32;
-                const int64_t cjb = (int64_t)bj * BF_TILE + cb;
-                const bool okb = cjb < a.nB && ((hitmask >> (u * 4 + v)) & 1u);
-                const int32_t gb = cjb < a.nB ? (a.colsB ? a.colsB[cjb] : (int32_t)cjb) : -1;
-                const int32_t pb2 = 2 * (int32_t)a.popB[bj * BF_TILE + cb];
-                const int32_t hi = smin32 - n32 + pb2, lo = -smin32 - n32 + pb2;
-                const int row0 = wa * 64 + u * 32 + h * 4;
-                uint32_t m = 0;
-                if (okb) {
+                    for (int r = 0; r < 16; ++r) fragbuf[wave][r][lane] = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
+                    const int cb = wb * 128 + v * 32 + l32;
+                    const int64_t cjb = (int64_t)bj * BF_TILE + cb;
+                    const bool okb = cjb < a.nB && ((hitmask >> (u * 4 + v)) & 1u);
+                    const int32_t gb = cjb < a.nB ? (a.colsB ? a.colsB[cjb] : (int32_t)cjb) : -1;
+                    const int32_t pb2 = 2 * (int32_t)popBt[cb];
+                    const int32_t hi = smin32 - n32 + pb2, lo = -smin32 - n32 + pb2;
+                    const int row0 = wa * 64 + u * 32 + h * 4;
+                    uint32_t m = 0;
+                    if (okb) {
 #pragma unroll 4
-                    for (int r = 0; r < 16; ++r) {
-                        const int ra = row0 + (r >> 2) * 8 + (r & 3);
-                        const int32_t x = (int32_t)fragbuf[wave][r][lane];
-                        const bool pass = x >= hi || (TWO && x <= lo);
-                        const bool ok = (int64_t)bi * BF_TILE + ra < a.nA && !(diag && ra >= cb);
-                        m |= (pass && ok ? 1u : 0u) << r;
+                        for (int r = 0; r < 16; ++r) {
+                            const int ra = row0 + (r >> 2) * 8 + (r & 3);
+                            const int32_t x = (int32_t)fragbuf[wave][r][lane];
+                            const bool pass = x >= hi || (TWO && x <= lo);
+                            const bool ok = (int64_t)bi * BF_TILE + ra < a.nA && !(diag && ra >= cb);
+                            m |= (pass && ok ? 1u : 0u) << r;
+                        }
                     }
-                }
-                // with column lists a column can meet itself (the same id on both sides); with
-                // identity lists that happens only on a diagonal block, excluded by a < b
-                if (a.colsA || a.colsB) {
-                    for (uint32_t mm = m; mm;) {
-                        const int r = __ffs(mm) - 1;
-                        mm &= mm - 1;
-                        const int64_t cja = (int64_t)bi * BF_TILE + row0 + (r >> 2) * 8 + (r & 3);
-                        if ((a.colsA ? a.colsA[cja] : (int32_t)cja) == gb) m &= ~(1u << r);
+                    // with column lists a column can meet itself (the same id on both sides); with
+                    // identity lists that happens only on a diagonal block, excluded by a < b
+                    if (a.colsA || a.colsB) {
+                        for (uint32_t mm = m; mm;) {
+                            const int r = __ffs(mm) - 1;
+                            mm &= mm - 1;
+                            const int64_t cja = (int64_t)bi * BF_TILE + row0 + (r >> 2) * 8 + (r & 3);
+                            if ((a.colsA ? a.colsA[cja] : (int32_t)cja) == gb) m &= ~(1u << r);
+                        }
                     }
-                }
-                const int mine = __popc(m);
-                int incl = mine;
+                    const int mine = __popc(m);
+                    int incl = mine;
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int yv = __shfl_up(incl, d, 64);
-                    if (lane >= d) incl += yv;
-                }
-                const int total = __shfl(incl, 63, 64);
-                if (total == 0) continue;
-                unsigned int base = 0;
-                if (lane == 0) base = atomicAdd(&wg_n, (unsigned int)total);
-                base = __shfl(base, 0, 64);
-                uint64_t idx = base + (uint64_t)(incl - mine);
-                Survivor *mysurv = a.surv + (uint64_t)blockIdx.x * a.cap_wg;
-                while (m) {
-                    const int r = __ffs(m) - 1;
-                    m &= m - 1;
-                    const int64_t cja = (int64_t)bi * BF_TILE + row0 + (r >> 2) * 8 + (r & 3);
-                    const int32_t ga = a.colsA ? a.colsA[cja] : (int32_t)cja;
-                    if (idx < a.cap_wg) {
-                        Survivor sv;
-                        sv.j = (uint32_t)min(ga, gb);
-                        sv.k = (uint32_t)max(ga, gb);
-                        sv.rep = 0;
-                        sv.s = n32 - pb2 + (int32_t)fragbuf[wave][r][lane];
-                        sv.value = (double)sv.s;
-                        sv.ysel = 0;
-                        sv.pad = 0;
-                        mysurv[idx] = sv;
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const int yv = __shfl_up(incl, d, 64);
+                        if (lane >= d) incl += yv;
                     }
-                    ++idx;
+                    const int total = __shfl(incl, 63, 64);
+                    if (total == 0) continue;
+                    unsigned int base = 0;
+                    if (lane == 0) base = atomicAdd(&wg_n, (unsigned int)total);
+                    base = __shfl(base, 0, 64);
+                    uint64_t idx = base + (uint64_t)(incl - mine);
+                    Survivor *mysurv = a.surv + (uint64_t)blockIdx.x * a.cap_wg;
+                    while (m) {
+                        const int r = __ffs(m) - 1;
+                        m &= m - 1;
+                        const int64_t cja = (int64_t)bi * BF_TILE + row0 + (r >> 2) * 8 + (r & 3);
+                        const int32_t ga = a.colsA ? a.colsA[cja] : (int32_t)cja;
+                        if (idx < a.cap_wg) {
+                            Survivor sv;
+                            sv.j = (uint32_t)min(ga, gb);
+                            sv.k = (uint32_t)max(ga, gb);
+                            sv.rep = 0;
+                            sv.s = n32 - pb2 + (int32_t)fragbuf[wave][r][lane];
+                            sv.value = (double)sv.s;
+                            sv.ysel = 0;
+                            sv.pad = 0;
+                            mysurv[idx] = sv;
+                        }
+                        ++idx;
+                    }
                 }
             }
         }
+        g = g2;
+        bi = bi2;
+        bj = bj2;
+        have = have2;
+        par ^= 1;
     }
     __syncthreads();
     if (tid == 0) a.wg_count[blockIdx.x] = wg_n;
