@@ -1066,22 +1066,28 @@ __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
 // Matrix-core tiles (products of two buckets with at least MTILE_MIN columns
 // each; +-1 data, n < 2^24).  One wave per MTILE x MTILE tile, as 2 x 2
 // fragments of 32 x 32: the counts C = #{i : z_ia = x_ib = 1}, z = y ^ x,
-// accumulate on v_mfma_scale_f32_32x32x64_f8f6f4 over 64-row steps, lane half h
-// feeding words h and h + 2 of each quad of its columns (A columns u*32 + lane%32,
-// B columns v*32 + lane%32), so every column of the tile is read once; the
-// popcounts |z_a|, |x_b| are taken on the way and s = n - 2|z_a| - 2|x_b| + 4C.
-// Three quads are in flight per lane.  Accumulator register r of lane l holds A row
+// accumulate on v_mfma_scale_f32_32x32x64_f8f6f4 over 64-row steps.  A column's
+// quads are taken in pairs: lane half h loads quad 2s + h of step s, so that one
+// load instruction covers 32 contiguous bytes of each of 32 columns and no two
+// lanes load the same bytes, and the two lane halves feed the two 32-row
+// halves of each product from their own words (any pairing of the words with
+// the K dimension gives the same C, as long as both sides use it).  Lanes past
+// the end of a bucket (na, nb < 64) repeat its last column, so their products
+// duplicate real ones; the popcounts |z_a|, |x_b| are taken on the way.  Three
+// steps are in flight per lane.  Accumulator register r of lane l holds A row
 // u*32 + (r/4)*8 + (l/32)*4 + r%4 and B column v*32 + l%32.
-struct MQuad {
-    uint4 a[2], b[2], y;
+struct MStage {
+    uint4 a[2], b[2], y;     // quad 2s + h of the lane's A columns u, B columns v and of y
 };
 
-__global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
+__global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
 {
-    __shared__ uint32_t zpop[4][MTILE];
+    __shared__ __align__(16) float zpop2[4][MTILE];  // per wave: 2|z_a| of the tile's A columns
     const unsigned lane = lane_id();
     const int h = (int)(lane >> 5), c = (int)(lane & 31);
+    const int wv = (int)(threadIdx.x >> 6);
     const int W4 = a.W32p >> 2;
+    const int NF = W4 >> 1, NS = (W4 + 1) >> 1;      // full steps (two quads), all steps
     const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
     const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall);
     const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nwave = (uint64_t)gridDim.x * 4;
@@ -1090,40 +1096,36 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
         const Tile t = tile_from(T4[ti]);
         const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
         const uint4 *pa[2], *pb[2];
-        uint32_t ma[2], mb[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int ca = u * 32 + c, cb = u * 32 + c;
-            ma[u] = ca < t.na ? ~0u : 0u;
-            mb[u] = cb < t.nb ? ~0u : 0u;
-            pa[u] = XC4 + (int64_t)a.perm[t.a0 + (ca < t.na ? ca : 0)] * W4;
-            pb[u] = XC4 + (int64_t)a.perm[t.b0 + (cb < t.nb ? cb : 0)] * W4;
+            pa[u] = XC4 + (int64_t)a.perm[t.a0 + min(u * 32 + c, (int)t.na - 1)] * W4;
+            pb[u] = XC4 + (int64_t)a.perm[t.b0 + min(u * 32 + c, (int)t.nb - 1)] * W4;
         }
         v16f acc[2][2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int v = 0; v < 2; ++v) acc[u][v] = v16f{};
         uint32_t popa[2] = {0, 0}, popb[2] = {0, 0};
-        auto load = [&](MQuad &q, int qi) {
-            const int o = min(qi, W4 - 1);          // clamped: a quad past the end is never used
+        auto load = [&](MStage &st, int stg) {
+            const int q = min(2 * stg + h, W4 - 1);   // clamped: a quad past the column is masked
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                q.a[u] = pa[u][o];
-                q.b[u] = pb[u][o];
+                st.a[u] = pa[u][q];
+                st.b[u] = pb[u][q];
             }
-            q.y = y4[o];
+            st.y = y4[q];
         };
-        auto step = [&](MQuad &q, int qi) {
+        // the step's 4 products per fragment; PART: the last step of an odd quad count, whose
+        // upper lane half holds no quad; FIRST: the first product starts the accumulators
+        auto step = [&](MStage &st, int stg, auto part, auto first) {
+            const uint32_t keep = (decltype(part)::value && h) ? 0u : ~0u;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int e = 0; e < 4; ++e) {
                 v8i fa[2], fb[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const uint32_t wa = k ? (h ? q.a[u].w : q.a[u].z) : (h ? q.a[u].y : q.a[u].x);
-                    const uint32_t wy = k ? (h ? q.y.w : q.y.z) : (h ? q.y.y : q.y.x);
-                    const uint32_t wb = k ? (h ? q.b[u].w : q.b[u].z) : (h ? q.b[u].y : q.b[u].x);
-                    const uint32_t za = (wa ^ wy) & ma[u], xb = wb & mb[u];
+                    uint32_t za = st.a[u][e] ^ st.y[e], xb = st.b[u][e];
+                    if (decltype(part)::value) {
+                        za &= keep;
+                        xb &= keep;
+                    }
                     popa[u] = bcnt_acc(za, popa[u]);
                     popb[u] = bcnt_acc(xb, popb[u]);
                     fa[u] = expand_a(za);
@@ -1132,88 +1134,140 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) acc[u][v] = mfma_fp4(fa[u], fb[v], acc[u][v]);
+                    for (int v = 0; v < 2; ++v)
+                        acc[u][v] = mfma_fp4(fa[u], fb[v],
+                                             (decltype(first)::value && e == 0) ? v16f{} : acc[u][v]);
             }
-            load(q, qi + 3);
+            load(st, stg + 3);
             __builtin_amdgcn_sched_barrier(0);
         };
-        MQuad q0, q1, q2;
-        load(q0, 0);
-        load(q1, 1);
-        load(q2, 2);
-        int qi = 0;
-        for (; qi + 2 < W4; qi += 3) {      // no branches inside: each wait is for the oldest loads only
-            step(q0, qi);
-            step(q1, qi + 1);
-            step(q2, qi + 2);
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        MStage s0, s1, s2;
+        load(s0, 0);
+        load(s1, 1);
+        load(s2, 2);
+        // step s sits in s0, s1 or s2 by s mod 3; full steps first, then the partial one
+        if (NF == 0) {
+            step(s0, 0, T_{}, T_{});
+        } else {
+            step(s0, 0, F_{}, T_{});
+            int stg = 1;
+            for (; stg + 2 < NF; stg += 3) {     // no branches inside: each wait is for the oldest loads only
+                step(s1, stg, F_{}, F_{});
+                step(s2, stg + 1, F_{}, F_{});
+                step(s0, stg + 2, F_{}, F_{});
+            }
+            // stg = 1 mod 3; up to two full steps and the partial one remain
+            if (stg < NF) {
+                step(s1, stg, F_{}, F_{});
+                if (stg + 1 < NF) {
+                    step(s2, stg + 1, F_{}, F_{});
+                    if (NS > NF) step(s0, stg + 2, T_{}, F_{});
+                } else if (NS > NF) {
+                    step(s2, stg + 1, T_{}, F_{});
+                }
+            } else if (NS > NF) {
+                step(s1, stg, T_{}, F_{});
+            }
         }
-        if (qi < W4) step(q0, qi);
-        if (qi + 1 < W4) step(q1, qi + 1);
-        // whole-column popcounts: the two lane halves of a column hold half of the words each
+        // whole-column popcounts: the two lane halves of a column hold disjoint words
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             popa[u] += __shfl_xor(popa[u], 32, 64);
             popb[u] += __shfl_xor(popb[u], 32, 64);
         }
-        const int32_t smin = (int32_t)a.smin[t.ysel];
-        uint32_t pm[2][2];
-        int mine = 0;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                const int cb = v * 32 + c;
-                uint32_t m = 0;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int rl = (r >> 2) * 8 + h * 4 + (r & 3), ra = u * 32 + rl;
-                    const int32_t pz = (int32_t)__shfl(popa[u], rl, 64);   // |z| of A column ra
-                    const int32_t sv = n32 - 2 * pz - 2 * (int32_t)popb[v] + 4 * (int32_t)acc[u][v][r];
-                    const bool pass = a.two_sided ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin);
-                    const bool ok = ra < t.na && cb < t.nb && (!t.diag || ra < cb);
-                    m |= (pass && ok ? 1u : 0u) << r;
-                }
-                pm[u][v] = m;
-                mine += __popc(m);
-            }
-        }
-        unsigned long long idx = reserve_survivors(a, t, mine);
-        if (idx == ~0ull) continue;
-        // rare: the A columns' popcounts go to the wave's LDS slot, read back per survivor
-        const int wv = (int)(threadIdx.x >> 6);
+        // cheap test per fragment: x = 4C - 2|z_a| over the lane's 16 rows against
+        // smin - n + 2|x_b| (and -smin - n + 2|x_b| two-sided), exact in FP32
         if (h == 0) {
-            zpop[wv][c] = popa[0];
-            zpop[wv][32 + c] = popa[1];
+            zpop2[wv][c] = (float)(2 * popa[0]);
+            zpop2[wv][32 + c] = (float)(2 * popa[1]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int32_t smin = (int32_t)a.smin[t.ysel];
+        uint32_t hitmask = 0;
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 2; ++u) {
+            float tA[16];
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const float4 v4 = *reinterpret_cast<const float4 *>(&zpop2[wv][u * 32 + q4 * 8 + h * 4]);
+                tA[4 * q4 + 0] = v4.x;
+                tA[4 * q4 + 1] = v4.y;
+                tA[4 * q4 + 2] = v4.z;
+                tA[4 * q4 + 3] = v4.w;
+            }
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
-                const int cb = v * 32 + c;
+                const int32_t pb2 = 2 * (int32_t)popb[v];
+                float mx = -1e30f, mn = 1e30f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    if (!((pm[u][v] >> r) & 1u)) continue;
-                    const int ra = u * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-                    const uint32_t j = a.perm[t.a0 + ra], k = a.perm[t.b0 + cb];
-                    const int32_t sv = n32 - 2 * (int32_t)zpop[wv][ra] - 2 * (int32_t)popb[v] +
-                                       4 * (int32_t)acc[u][v][r];
-                    if (idx < a.surv_cap) {
-                        Survivor sr;
-                        sr.j = min(j, k);
-                        sr.k = max(j, k);
-                        sr.rep = (uint32_t)(a.rep_abs0 + t.rep);
-                        sr.s = sv;
-                        sr.value = (double)sv;
-                        sr.ysel = t.ysel;
-                        sr.pad = 0;
-                        a.surv[idx] = sr;
+                    const float x = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
+                    mx = fmaxf(mx, x);
+                    mn = fminf(mn, x);
+                }
+                const bool hit = mx >= (float)(smin - n32 + pb2) || (a.two_sided && mn <= (float)(-smin - n32 + pb2));
+                hitmask |= (hit ? 1u : 0u) << (u * 2 + v);
+            }
+        }
+        if (__ballot(hitmask != 0) != 0) {
+            // rare: exact values and validity (padding rows and columns, a < b on a diagonal tile)
+            uint32_t pm[2][2];
+            int mine = 0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    const int cb = v * 32 + c;
+                    uint32_t m = 0;
+                    if ((hitmask >> (u * 2 + v)) & 1u) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int ra = u * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+                            const int32_t sv = n32 - (int32_t)zpop2[wv][ra] - 2 * (int32_t)popb[v] +
+                                               4 * (int32_t)acc[u][v][r];
+                            const bool pass = a.two_sided ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin);
+                            const bool ok = ra < t.na && cb < t.nb && (!t.diag || ra < cb);
+                            m |= (pass && ok ? 1u : 0u) << r;
+                        }
                     }
-                    ++idx;
+                    pm[u][v] = m;
+                    mine += __popc(m);
                 }
             }
+            unsigned long long idx = reserve_survivors(a, t, mine);
+            if (idx != ~0ull) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        const int cb = v * 32 + c;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            if (!((pm[u][v] >> r) & 1u)) continue;
+                            const int ra = u * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+                            const uint32_t j = a.perm[t.a0 + ra], k = a.perm[t.b0 + cb];
+                            const int32_t sv = n32 - (int32_t)zpop2[wv][ra] - 2 * (int32_t)popb[v] +
+                                               4 * (int32_t)acc[u][v][r];
+                            if (idx < a.surv_cap) {
+                                Survivor sr;
+                                sr.j = min(j, k);
+                                sr.k = max(j, k);
+                                sr.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                                sr.s = sv;
+                                sr.value = (double)sv;
+                                sr.ysel = t.ysel;
+                                sr.pad = 0;
+                                a.surv[idx] = sr;
+                            }
+                            ++idx;
+                        }
+                    }
+            }
+        }
         // the slot is rewritten by this wave's next tile only after every lane has read it
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
