@@ -1066,28 +1066,45 @@ __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
 // Matrix-core tiles (products of two buckets with at least MTILE_MIN columns
 // each; +-1 data, n < 2^24).  One wave per MTILE x MTILE tile, as 2 x 2
 // fragments of 32 x 32: the counts C = #{i : z_ia = x_ib = 1}, z = y ^ x,
-// accumulate on v_mfma_scale_f32_32x32x64_f8f6f4 over 64-row steps.  A column's
-// quads are taken in pairs: lane half h loads quad 2s + h of step s, so that one
-// load instruction covers 32 contiguous bytes of each of 32 columns and no two
-// lanes load the same bytes, and the two lane halves feed the two 32-row
-// halves of each product from their own words (any pairing of the words with
-// the K dimension gives the same C, as long as both sides use it).  Lanes past
-// the end of a bucket (na, nb < 64) repeat its last column, so their products
-// duplicate real ones; the popcounts |z_a|, |x_b| are taken on the way.  Three
-// steps are in flight per lane.  Accumulator register r of lane l holds A row
-// u*32 + (r/4)*8 + (l/32)*4 + r%4 and B column v*32 + l%32.
+// accumulate on v_mfma_scale_f32_32x32x64_f8f6f4 over 64-row steps.  A column is
+// read in stages of four quads (64 bytes): one load instruction covers a stage
+// of 16 columns, lane l taking quad l/16 of column l%16 (random column gathers
+// run at full HBM speed only with 64 contiguous bytes or more per column and
+// instruction), and v_permlane16_swap between the loads of columns 0-15 and
+// 16-31 of a fragment brings them into the matrix layout: lane half h then
+// holds quads 2h and 2h + 1 of column lane%32 and feeds the products' 32-row
+// halves from them (any pairing of the words with the K dimension gives the
+// same C, as long as both sides use it).  Lanes past the end of a bucket
+// (na, nb < 64) repeat its last column, so their products duplicate real
+// ones; the popcounts |z_a|, |x_b| are taken on the way.  Two stages are in
+// flight per lane.  Accumulator register r of lane l holds A row u*32 + (r/4)*8
+// + (l/32)*4 + r%4 and B column v*32 + l%32.
 struct MStage {
-    uint4 a[2], b[2], y;     // quad 2s + h of the lane's A columns u, B columns v and of y
+    uint4 a[4], b[4];        // quad 4s + l/16 of A (B) column 16g + l%16 of the tile
+    uint4 y[2];              // quads 4s + 2h and 4s + 2h + 1 of y
 };
 
-__global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
+// v_permlane16_swap on each word: lanes 16-31 and 48-63 of lo trade places with
+// lanes 0-15 and 32-47 of hi.
+XYZ_DEV void swap16(uint4 &lo, uint4 &hi)
+{
+    auto x = __builtin_amdgcn_permlane16_swap(lo.x, hi.x, false, false);
+    auto y = __builtin_amdgcn_permlane16_swap(lo.y, hi.y, false, false);
+    auto z = __builtin_amdgcn_permlane16_swap(lo.z, hi.z, false, false);
+    auto w = __builtin_amdgcn_permlane16_swap(lo.w, hi.w, false, false);
+    lo = make_uint4(x[0], y[0], z[0], w[0]);
+    hi = make_uint4(x[1], y[1], z[1], w[1]);
+}
+
+__global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
 {
     __shared__ __align__(16) float zpop2[4][MTILE];  // per wave: 2|z_a| of the tile's A columns
     const unsigned lane = lane_id();
     const int h = (int)(lane >> 5), c = (int)(lane & 31);
+    const int lc = (int)(lane & 15), lq = (int)(lane >> 4);
     const int wv = (int)(threadIdx.x >> 6);
     const int W4 = a.W32p >> 2;
-    const int NF = W4 >> 1, NS = (W4 + 1) >> 1;      // full steps (two quads), all steps
+    const int NF = W4 >> 2, NS = (W4 + 3) >> 2;      // full stages, all stages
     const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
     const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall);
     const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nwave = (uint64_t)gridDim.x * 4;
@@ -1095,78 +1112,86 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
     for (uint64_t ti = wid; ti < a.nmfma; ti += nwave) {
         const Tile t = tile_from(T4[ti]);
         const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
-        const uint4 *pa[2], *pb[2];
+        const uint4 *pa[4], *pb[4];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            pa[u] = XC4 + (int64_t)a.perm[t.a0 + min(u * 32 + c, (int)t.na - 1)] * W4;
-            pb[u] = XC4 + (int64_t)a.perm[t.b0 + min(u * 32 + c, (int)t.nb - 1)] * W4;
+        for (int g = 0; g < 4; ++g) {
+            pa[g] = XC4 + (int64_t)a.perm[t.a0 + min(g * 16 + lc, (int)t.na - 1)] * W4;
+            pb[g] = XC4 + (int64_t)a.perm[t.b0 + min(g * 16 + lc, (int)t.nb - 1)] * W4;
         }
         v16f acc[2][2];
         uint32_t popa[2] = {0, 0}, popb[2] = {0, 0};
         auto load = [&](MStage &st, int stg) {
-            const int q = min(2 * stg + h, W4 - 1);   // clamped: a quad past the column is masked
+            const int q0 = 4 * min(stg, NS - 1);
+            const int q = min(q0 + lq, W4 - 1);     // clamped: quads past the column are masked
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                st.a[g] = pa[g][q];
+                st.b[g] = pb[g][q];
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) st.y[j] = y4[min(q0 + 2 * h + j, W4 - 1)];
+        };
+        // the stage's 8 products per fragment; PART: the last stage, whose quads past W4 count as zero;
+        // FIRST: the first product starts the accumulators
+        auto step = [&](MStage &st, int stg, auto part, auto first) {
+            // matrix layout: A[u][j] = quad 4s + 2h + j of A column u*32 + c (B likewise)
+            uint4 A[2][2], B[2][2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                st.a[u] = pa[u][q];
-                st.b[u] = pb[u][q];
+                A[u][0] = st.a[2 * u];
+                A[u][1] = st.a[2 * u + 1];
+                swap16(A[u][0], A[u][1]);
+                B[u][0] = st.b[2 * u];
+                B[u][1] = st.b[2 * u + 1];
+                swap16(B[u][0], B[u][1]);
             }
-            st.y = y4[q];
-        };
-        // the step's 4 products per fragment; PART: the last step of an odd quad count, whose
-        // upper lane half holds no quad; FIRST: the first product starts the accumulators
-        auto step = [&](MStage &st, int stg, auto part, auto first) {
-            const uint32_t keep = (decltype(part)::value && h) ? 0u : ~0u;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v8i fa[2], fb[2];
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t keep = (decltype(part)::value && 4 * stg + 2 * h + j >= W4) ? 0u : ~0u;
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    uint32_t za = st.a[u][e] ^ st.y[e], xb = st.b[u][e];
-                    if (decltype(part)::value) {
-                        za &= keep;
-                        xb &= keep;
+                for (int e = 0; e < 4; ++e) {
+                    v8i fa[2], fb[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        uint32_t za = A[u][j][e] ^ st.y[j][e], xb = B[u][j][e];
+                        if (decltype(part)::value) {
+                            za &= keep;
+                            xb &= keep;
+                        }
+                        popa[u] = bcnt_acc(za, popa[u]);
+                        popb[u] = bcnt_acc(xb, popb[u]);
+                        fa[u] = expand_a(za);
+                        fb[u] = expand_b_plain(xb);
                     }
-                    popa[u] = bcnt_acc(za, popa[u]);
-                    popb[u] = bcnt_acc(xb, popb[u]);
-                    fa[u] = expand_a(za);
-                    fb[u] = expand_b_plain(xb);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 2; ++v)
+                            acc[u][v] = mfma_fp4(fa[u], fb[v],
+                                                 (decltype(first)::value && j == 0 && e == 0) ? v16f{} : acc[u][v]);
                 }
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v)
-                        acc[u][v] = mfma_fp4(fa[u], fb[v],
-                                             (decltype(first)::value && e == 0) ? v16f{} : acc[u][v]);
             }
-            load(st, stg + 3);
+            load(st, stg + 2);
             __builtin_amdgcn_sched_barrier(0);
         };
         using T_ = std::true_type;
         using F_ = std::false_type;
-        MStage s0, s1, s2;
+        MStage s0, s1;
         load(s0, 0);
         load(s1, 1);
-        load(s2, 2);
-        // step s sits in s0, s1 or s2 by s mod 3; full steps first, then the partial one
+        // stage s sits in s0 (even) or s1 (odd); full stages first, then the partial one
         if (NF == 0) {
             step(s0, 0, T_{}, T_{});
         } else {
             step(s0, 0, F_{}, T_{});
             int stg = 1;
-            for (; stg + 2 < NF; stg += 3) {     // no branches inside: each wait is for the oldest loads only
+            for (; stg + 1 < NF; stg += 2) {     // no branches inside: each wait is for the oldest loads only
                 step(s1, stg, F_{}, F_{});
-                step(s2, stg + 1, F_{}, F_{});
-                step(s0, stg + 2, F_{}, F_{});
+                step(s0, stg + 1, F_{}, F_{});
             }
-            // stg = 1 mod 3; up to two full steps and the partial one remain
             if (stg < NF) {
                 step(s1, stg, F_{}, F_{});
-                if (stg + 1 < NF) {
-                    step(s2, stg + 1, F_{}, F_{});
-                    if (NS > NF) step(s0, stg + 2, T_{}, F_{});
-                } else if (NS > NF) {
-                    step(s2, stg + 1, T_{}, F_{});
-                }
+                if (NS > NF) step(s0, stg + 1, T_{}, F_{});
             } else if (NS > NF) {
                 step(s1, stg, T_{}, F_{});
             }
