@@ -880,6 +880,30 @@ XYZ_DEV v16f mfma_fp4(v8i a, v8i b, v16f c)
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
 }
 
+// Bit plane pl of four words as one FP4 operand (word d in dword d): planes 0, 1, 2
+// keep bit pl of every nibble (e2m1 values 0.5, 1, 2), plane 3 moves bit 3 to bit 1
+// (value 1).  With the same plane on both sides, a product of two set bits is
+// 0.25, 1, 4 or 1, and the per-block scales 2^1, 2^0, 2^-1, 2^0 on each side
+// (mfma_fp4_plane) make it exactly 1: no bit swap on either side.
+XYZ_DEV v8i plane_fp4(uint4 w, int pl)
+{
+    if (pl == 3)
+        return v8i{(int)((w.x >> 2) & 0x22222222u), (int)((w.y >> 2) & 0x22222222u),
+                   (int)((w.z >> 2) & 0x22222222u), (int)((w.w >> 2) & 0x22222222u), 0, 0, 0, 0};
+    const uint32_t m = 0x11111111u << pl;
+    return v8i{(int)(w.x & m), (int)(w.y & m), (int)(w.z & m), (int)(w.w & m), 0, 0, 0, 0};
+}
+
+XYZ_DEV v16f mfma_fp4_plane(v8i a, v8i b, v16f c, int pl)
+{
+    // E8M0 block scales: 128 = 2^1, 127 = 2^0, 126 = 2^-1
+    switch (pl) {
+    case 0: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 128, 0, 128);
+    case 2: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 126, 0, 126);
+    default: return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+    }
+}
+
 // ------------------------------------------------------------ verification --
 //
 // One wave per tile (<= 32 x 32 column pairs).  Lane (ia, ib) = (lane & 7,
@@ -1148,27 +1172,36 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const uint32_t keep = (decltype(part)::value && 4 * stg + 2 * h + j >= W4) ? 0u : ~0u;
+                uint4 za[2], xb[2];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                for (int u = 0; u < 2; ++u) {
+                    za[u] = make_uint4(A[u][j].x ^ st.y[j].x, A[u][j].y ^ st.y[j].y, A[u][j].z ^ st.y[j].z,
+                                       A[u][j].w ^ st.y[j].w);
+                    xb[u] = B[u][j];
+                    if (decltype(part)::value) {
+                        za[u] = make_uint4(za[u].x & keep, za[u].y & keep, za[u].z & keep, za[u].w & keep);
+                        xb[u] = make_uint4(xb[u].x & keep, xb[u].y & keep, xb[u].z & keep, xb[u].w & keep);
+                    }
+                    popa[u] = bcnt_acc(za[u].w, bcnt_acc(za[u].z, bcnt_acc(za[u].y, bcnt_acc(za[u].x, popa[u]))));
+                    popb[u] = bcnt_acc(xb[u].w, bcnt_acc(xb[u].z, bcnt_acc(xb[u].y, bcnt_acc(xb[u].x, popb[u]))));
+                }
+                // one product per bit plane of the quad's four words
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) {
                     v8i fa[2], fb[2];
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
-                        uint32_t za = A[u][j][e] ^ st.y[j][e], xb = B[u][j][e];
-                        if (decltype(part)::value) {
-                            za &= keep;
-                            xb &= keep;
-                        }
-                        popa[u] = bcnt_acc(za, popa[u]);
-                        popb[u] = bcnt_acc(xb, popb[u]);
-                        fa[u] = expand_a(za);
-                        fb[u] = expand_b_plain(xb);
+                        fa[u] = plane_fp4(za[u], pl);
+                        fb[u] = plane_fp4(xb[u], pl);
                     }
 #pragma unroll
                     for (int u = 0; u < 2; ++u)
 #pragma unroll
                         for (int v = 0; v < 2; ++v)
-                            acc[u][v] = mfma_fp4(fa[u], fb[v],
-                                                 (decltype(first)::value && j == 0 && e == 0) ? v16f{} : acc[u][v]);
+                            acc[u][v] = mfma_fp4_plane(fa[u], fb[v],
+                                                       (decltype(first)::value && j == 0 && pl == 0) ? v16f{}
+                                                                                                    : acc[u][v],
+                                                       pl);
                 }
             }
             load(st, stg + 2);
