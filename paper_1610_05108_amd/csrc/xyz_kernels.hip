@@ -392,6 +392,8 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
     return 0;
 }
 
+constexpr int BKU = 8;       // keys per thread and round in k_bucket
+
 __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ keys, int64_t p, int m, int nys,
                                                  RepInfo *__restrict__ info, int two_sided, int mfma,
                                                  uint32_t *__restrict__ offs, uint32_t *__restrict__ perm)
@@ -405,7 +407,15 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
     const uint32_t *kr = keys + (int64_t)r * p;
     for (int b = threadIdx.x; b < nb; b += 1024) cnt[b] = 0;
     __syncthreads();
-    for (int64_t j = threadIdx.x; j < p; j += 1024) atomicAdd(&cnt[kr[j]], 1u);
+    // the key loads of BKU iterations go out together (the loop is latency-bound otherwise)
+    for (int64_t j0 = threadIdx.x; j0 < p; j0 += 1024 * BKU) {
+        uint32_t kv[BKU];
+#pragma unroll
+        for (int u = 0; u < BKU; ++u) kv[u] = j0 + u * 1024 < p ? kr[j0 + u * 1024] : ~0u;
+#pragma unroll
+        for (int u = 0; u < BKU; ++u)
+            if (kv[u] != ~0u) atomicAdd(&cnt[kv[u]], 1u);
+    }
     __syncthreads();
     for (int y = 0; y < nys; ++y) {
         RepInfo *inf = info + (int64_t)r * nys + y;
@@ -456,9 +466,13 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
     if (threadIdx.x == 0) of[nb] = (uint32_t)p;
     __syncthreads();
     uint32_t *pr = perm + (int64_t)r * p;
-    for (int64_t j = threadIdx.x; j < p; j += 1024) {
-        const uint32_t pos = atomicAdd(&cnt[kr[j]], 1u);
-        pr[pos] = (uint32_t)j;
+    for (int64_t j0 = threadIdx.x; j0 < p; j0 += 1024 * BKU) {
+        uint32_t kv[BKU];
+#pragma unroll
+        for (int u = 0; u < BKU; ++u) kv[u] = j0 + u * 1024 < p ? kr[j0 + u * 1024] : ~0u;
+#pragma unroll
+        for (int u = 0; u < BKU; ++u)
+            if (kv[u] != ~0u) pr[atomicAdd(&cnt[kv[u]], 1u)] = (uint32_t)(j0 + u * 1024);
     }
 }
 
