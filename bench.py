@@ -97,6 +97,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-fresh", type=int, default=32)
     ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--scaling-law", action="store_true",
+                    help="only run the scaling experiment of Section 5.2 (time to discovery against p)")
+    ap.add_argument("--scaling-p", type=str, default="10000,30000,100000,300000,1000000")
+    ap.add_argument("--scaling-gamma", type=str, default="0.7,0.8,0.9")
+    ap.add_argument("--scaling-n", type=int, default=4000)
+    ap.add_argument("--scaling-sims", type=int, default=40)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -109,6 +115,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30, "copies": 3}), flush=True)
+        return
+    if args.scaling_law:
+        import paper_1610_05108_amd as xyz
+        ctx = xyz.Context(0)
+        out = scaling_law_leg(ctx, args.scaling_n, [int(v) for v in args.scaling_p.split(",")],
+                              [float(v) for v in args.scaling_gamma.split(",")], args.scaling_sims)
+        print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards over repetitions "
@@ -455,6 +468,90 @@ def large_binary_leg(ctx):
     out["speedup_xyz_over_exact"] = out["exact"]["ms"] / out["xyz"]["ms"]
     xyz.xyz_x_destroy(x)
     return out
+
+
+def scaling_law_leg(ctx, n, ps, gammas, sims, gamma0=0.55):
+    """Section 5.2: Rademacher X (n x p), one strong pair (columns 0 and 1) of
+    strength gamma, M chosen so that p^(-1/M) is close to gamma0 (0.55: above the
+    bulk of the strengths, which sit near 1/2), and the time until the pair is
+    found, averaged over `sims` row-sampling seeds.  Repetitions run in chunks
+    until the pair appears; its first repetition l* gives (l* + 1) repetitions
+    to discovery, whose time is (l* + 1) x the measured GPU time per repetition
+    and whose work is the operation count of the complexity bound (terms (ii)
+    to (iv): M p + p log2 p + n |E_l| per repetition, |E_l| measured).  Theorem 2
+    predicts both to grow as p^(1 + log gamma / log gamma0); the fitted slopes of
+    log time and log work against log p are reported beside that exponent, over
+    all p and over p >= 1e5 (where fixed per-call costs no longer dominate the
+    time).  The bound counts a repetition's candidate set as if the bulk of the
+    strengths sat at gamma0, i.e. of order p pairs; with the bulk at 1/2 it holds
+    about p^2 2^-M pairs, which gives the sharper exponent
+    2 - log 2 / log(1/gamma0) + log gamma / log gamma0 ("predicted_bulk_half").
+    Expected repetitions to discovery: 1 / gamma^M (eq. (9) with L = 1).  Every
+    (p, gamma, simulation) draws its rows with a seed of its own."""
+    import torch
+    import synthgen
+    import paper_1610_05108_amd as xyz
+    pts = []
+    for p in ps:
+        t0 = time.time()
+        bits = synthgen.scaling_x(n, p, seed=p)
+        x = xyz.xyz_x_create(ctx.h, bits, n=n)
+        M = max(1, int(round(math.log(p) / math.log(1.0 / gamma0))))
+        log(f"scaling: p={p} n={n} M={M} data {time.time() - t0:.1f}s")
+        for g in gammas:
+            agree = int(round(g * n))
+            gg = agree / n
+            Y = torch.from_numpy(synthgen.scaling_y(bits, n, agree, seed=1)).cuda()
+            q = gg ** M
+            chunk = int(min(4096, max(4, math.ceil(0.5 / q))))
+            kappa = (2 * gg - 1) / 2           # half the pair's s/n: far above the null pairs
+            reps, ms, work, cands = [], [], [], []
+            t1 = time.time()
+            for sim in range(sims):
+                off, tot_ms, tot_reps, cand_before, found = 0, 0.0, 0, 0, None
+                while found is None and off < 200 * math.ceil(1 / q):
+                    seed = (p * 7919 + agree * 104729 + sim * 15485863) % (1 << 31)
+                    r = ctx.search(x, Y, m=M, L=chunk, kappa=kappa, seed=seed, rep_offset=off, profile=True)
+                    tot_ms += r["timing"]["total_ms"]
+                    tot_reps += chunk
+                    pr = r["pairs"]
+                    hit = (pr["j"] == 0) & (pr["k"] == 1)
+                    cand = r["reps"]["candidates"].astype(np.int64)
+                    if hit.any():
+                        found = int(pr["first_rep"][hit][0])
+                        cand_before += int(cand[:found - off + 1].sum())
+                    else:
+                        cand_before += int(cand.sum())
+                        off += chunk
+                if found is None:
+                    continue
+                nrep = found + 1
+                reps.append(nrep)
+                ms.append(nrep * tot_ms / tot_reps)
+                cands.append(cand_before / nrep)
+                work.append(nrep * (M * p + p * math.log2(p)) + n * cand_before)
+            pt = {"p": p, "gamma": gg, "M": M, "gamma0": p ** (-1.0 / M), "sims": len(reps),
+                  "mean_reps": float(np.mean(reps)), "expected_reps": 1.0 / q,
+                  "mean_ms": float(np.mean(ms)), "mean_work": float(np.mean(work)),
+                  "candidates_per_rep": float(np.mean(cands))}
+            log(f"  gamma={gg:.3f}: {pt['mean_reps']:.1f} reps (expected {pt['expected_reps']:.1f}), "
+                f"{pt['mean_ms']:.2f} ms, work {pt['mean_work']:.3g}, {time.time() - t1:.1f}s")
+            pts.append(pt)
+        xyz.xyz_x_destroy(x)
+    fits = {}
+    for g in sorted({pt["gamma"] for pt in pts}):
+        f = {"predicted_bound": 1.0 + math.log(g) / math.log(gamma0),
+             "predicted_bulk_half": 2.0 - math.log(2) / math.log(1 / gamma0) + math.log(g) / math.log(gamma0)}
+        for tag, lo in (("", 0), ("_large_p", 100_000)):
+            sel = [pt for pt in pts if pt["gamma"] == g and pt["p"] >= lo]
+            if len(sel) < 2:
+                continue
+            lp = np.log([pt["p"] for pt in sel])
+            f["time_slope" + tag] = float(np.polyfit(lp, np.log([pt["mean_ms"] for pt in sel]), 1)[0])
+            f["work_slope" + tag] = float(np.polyfit(lp, np.log([pt["mean_work"] for pt in sel]), 1)[0])
+        fits[f"{g:.3f}"] = f
+    return {"experiment": "time to discovery against p (Section 5.2, Theorem 2)", "n": n, "gamma0": gamma0,
+            "data": "synthetic Rademacher, one pair of strength gamma", "points": pts, "fits": fits}
 
 
 def cpu_baseline(dd, m, L, n, p, reps=None):

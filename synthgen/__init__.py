@@ -29,6 +29,7 @@ __all__ = [
     "Dataset", "rademacher", "genotype", "gaussian",
     "config1", "config2", "config3", "config4", "config5_shared", "config5_requests",
     "config5_fresh", "small_binary", "small_continuous", "rows_table", "pack_bits_colmajor",
+    "scaling_x", "scaling_y",
 ]
 
 
@@ -200,6 +201,29 @@ def config3(seed: int = 0, n: int = 5000, p: int = 1_000_000, npairs: int = 20,
         signs.append(sg)
     return Dataset(n, p, None, Y, pairs, dict(L=500, m=14, kappa=0.12, seed=seed, two_sided=signed),
                    bits=bits, meta=dict(target_s=targets, signs=signs))
+
+
+def scaling_x(n: int, p: int, seed: int) -> np.ndarray:
+    """Rademacher X of the scaling experiment (Section 5.2), bit-packed as
+    ``(p, ceil(n/64))`` uint64 (same layout as ``Dataset.bits``)."""
+    r = _rng(seed, 17)
+    w = (n + 63) // 64
+    bits = r.integers(0, np.iinfo(np.uint64).max, size=(p, w), dtype=np.uint64, endpoint=True)
+    tail = n - (w - 1) * 64
+    if tail < 64:
+        bits[:, w - 1] &= np.uint64((1 << tail) - 1)
+    return bits
+
+
+def scaling_y(bits: np.ndarray, n: int, agree: int, seed: int) -> np.ndarray:
+    """Response of the scaling experiment: Y_i = X_i0 X_i1 on ``agree`` rows chosen
+    at random and -X_i0 X_i1 on the others, so that columns 0 and 1 form the one
+    strong pair, with Y_i X_i0 X_i1 = +1 on exactly ``agree`` rows.  int8 +-1."""
+    r = _rng(seed, 19)
+    x0, x1 = unpack_column(bits[0], n), unpack_column(bits[1], n)
+    sign = np.full(n, -1, dtype=np.int8)
+    sign[r.choice(n, size=agree, replace=False)] = 1
+    return (x0 * x1 * sign).astype(np.int8)
 
 
 def config4(seed: int = 0, n: int = 1000, p: int = 200_000) -> Dataset:
