@@ -51,6 +51,12 @@ def lib():
                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.xo_search_ex.restype = ctypes.c_int
+        L.xo_search_ex.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.c_void_p]
         L.xo_brute.restype = ctypes.c_int
         L.xo_brute.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
@@ -125,11 +131,13 @@ def _take_pairs(ptr, npairs):
 
 
 def search(XT, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
-           rep_offset: int = 0, rows=None):
+           rep_offset: int = 0, rows=None, unbiased: bool = False):
     """Algorithm 2 run by the oracle.  Returns (pairs, reps) structured arrays.
 
     XT: (p, n) int8 +-1 or real; Y: (n,) int8 +-1 or real.  rows: optional
-    (L, m) int32 table of row indices replacing the sampler.
+    (L, m) int32 table of row indices replacing the sampler.  unbiased (real X
+    only): the unbiased transform of Section 3.2 with row scaling instead of
+    the sign transform.
     """
     XT_, xk = _x_arg(XT)
     Y_, yk = _y_arg(Y)
@@ -141,9 +149,9 @@ def search(XT, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool =
         rp = rows_.ctypes.data
     out = ctypes.c_void_p()
     cnt = ctypes.c_int64()
-    rc = lib().xo_search(XT_.ctypes.data, xk, Y_.ctypes.data, yk, n, p, m, L, float(kappa),
-                         seed & (2**64 - 1), int(bool(two_sided)), rep_offset, rp,
-                         ctypes.byref(out), ctypes.byref(cnt), reps.ctypes.data)
+    rc = lib().xo_search_ex(XT_.ctypes.data, xk, Y_.ctypes.data, yk, n, p, m, L, float(kappa),
+                            seed & (2**64 - 1), int(bool(two_sided)), rep_offset, rp, int(bool(unbiased)),
+                            ctypes.byref(out), ctypes.byref(cnt), reps.ctypes.data)
     if rc != 0:
         raise OracleError(f"xo_search failed ({rc})")
     return _take_pairs(out.value, cnt.value), reps[:L]

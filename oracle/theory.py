@@ -93,3 +93,18 @@ def gamma_example_unweighted(sigma2: float) -> float:
     """Section 3.1 example, Y = X_1 X_2 + eps with eps ~ N(0, sigma^2):
     1/2 (1 + P(|eps| < 1)), the quantity the paper's sigma^2 table lists."""
     return 0.5 * (1.0 + math.erf(1.0 / math.sqrt(2.0 * sigma2)))
+
+
+def gamma_unbiased(XT: np.ndarray, Y: np.ndarray, j: int, k: int, scale: bool = True) -> float:
+    """Proposition 4 (Section 3.2): strength under the unbiased transform,
+    1/2 + sum_i Y_i X_ij X_ik / (2 ||Y||_1).  With ``scale`` the rows are first
+    divided by nu_i = max_j |X_ij| and Y_i multiplied by nu_i^2 (the remark after
+    Proposition 4), which leaves the numerator unchanged and turns the
+    denominator into 2 sum_i |Y_i| nu_i^2."""
+    X = np.asarray(XT, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    num = float(np.sum(Y * X[j] * X[k]))
+    w = np.abs(Y)
+    if scale:
+        w = w * np.max(np.abs(X), axis=0) ** 2
+    return 0.5 + num / (2.0 * float(w.sum()))

@@ -22,7 +22,13 @@
  *    Figure 2).
  *  - Continuous Y (Section 3.1): Z = sgn(Y) o X, rows drawn with probability
  *    |Y_i| / ||Y||_1.  Continuous X (Section 3.2): X is first mapped to its
- *    signs (the "sign transform").
+ *    signs (the "sign transform"), or, on request, by the unbiased transform
+ *    of Section 3.2 (Proposition 4): each row is divided by its largest
+ *    absolute entry nu_i and Y_i is multiplied by nu_i^2 (the paper's remark
+ *    after Proposition 4), so rows are drawn with probability proportional to
+ *    |Y_i| nu_i^2, and every sampled entry becomes +1 with probability
+ *    (1 + X_ij / nu_i) / 2, drawn afresh for each repetition, draw and column;
+ *    the Z side uses the same draw, Z~_ij = sgn(Y_i) X~_ij.
  *
  * Readings where the paper leaves a choice (each is also listed in the
  * design notes of the repository):
@@ -42,7 +48,15 @@
  *    a uniform row is floor(u * n / 2^64); a |Y|-weighted row is the first i
  *    whose running sum |Y_0| + ... + |Y_i| exceeds (u >> 11) * 2^-53 * ||Y||_1;
  *  - two-sided search (Section 4 runs xyz on +r and -r in turn) adds the
- *    equal pairs of X against -Z and keeps |s|/n > kappa.
+ *    equal pairs of X against -Z and keeps |s|/n > kappa;
+ *  - the unbiased transform's draws are counter based: draw t of repetition
+ *    l seeds a stream, output number 1 + l*2^16 + t of SplitMix64 seeded with
+ *    seed ^ 0x2545F4914F6CDD1D, and column j takes the top 24 bits u of that
+ *    stream's output number 1 + j; X~_ij = +1 exactly when, in binary64,
+ *    (u * 2) * nu_i < (nu_i + X_ij) * 2^24 (u / 2^24 < (1 + X_ij / nu_i) / 2
+ *    without a division), and with probability 1/2 (u < 2^23) on a row whose
+ *    entries are all zero (nu_i = 0; such a row is drawn only from a row table);
+ *    the row weights are |Y_i| * (nu_i * nu_i), summed left to right.
  */
 #define _GNU_SOURCE
 #include <stdint.h>
@@ -104,6 +118,38 @@ static int64_t weighted_row(uint64_t u, const double *cdf, const double *Y, int6
     for (int64_t i = n - 1; i >= 0; i--)
         if (Y[i] != 0.0) return i;
     return -1;
+}
+
+/* Row draws of repetition l with probability proportional to w_i >= 0 (a
+ * row of weight 0 is never drawn; the last row of positive weight catches a
+ * draw at the very top of the running sum). */
+static int draw_rows_w(const double *w, int64_t n, uint64_t seed, int64_t l, int m, int32_t *out)
+{
+    double *cdf = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!cdf) return XO_ENOMEM;
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; i++) { acc = acc + w[i]; cdf[i] = acc; }
+    if (!(acc > 0.0)) { free(cdf); return XO_EINVAL; }
+    for (int t = 0; t < m; t++) {
+        uint64_t u = draw_u64(seed, l, t);
+        out[t] = (int32_t)weighted_row(u, cdf, w, n);
+    }
+    free(cdf);
+    return XO_OK;
+}
+
+/* Unbiased transform (Section 3.2, Proposition 4) of entry x of a row with
+ * largest absolute entry nu, for draw t of repetition l and column j:
+ * +1 with probability (1 + x / nu) / 2. */
+#define XO_UNBIASED_STREAM 0x2545F4914F6CDD1Dull
+static int8_t unbiased_sign(uint64_t seed, int64_t l, int t, int64_t j, double x, double nu)
+{
+    uint64_t stream = xo_splitmix64(seed ^ XO_UNBIASED_STREAM, 1ull + (uint64_t)l * 65536ull + (uint64_t)t);
+    uint64_t u = xo_splitmix64(stream, 1ull + (uint64_t)j) >> 40;
+    int plus;
+    if (nu > 0.0) plus = ((double)u * 2.0) * nu < (nu + x) * 16777216.0;
+    else plus = u < 8388608ull;
+    return plus ? 1 : -1;
 }
 
 /* Row draws of repetition l.  Y == NULL selects the uniform sampler. */
@@ -250,12 +296,15 @@ static int cmp_record(const void *pa, const void *pb)
  * the sampler.  Outputs malloc'ed arrays (free with xo_free); reps must hold
  * L entries.
  */
-int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, int64_t p,
-              int m, int L, double kappa, uint64_t seed, int two_sided, int rep_offset,
-              const int32_t *rows_in, xo_pair **out_pairs, int64_t *out_npairs, xo_rep *reps)
+/* transform: 0 = sign transform of real X (or +-1 X as is), 1 = unbiased
+ * transform of real X (Section 3.2). */
+int xo_search_ex(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, int64_t p,
+                 int m, int L, double kappa, uint64_t seed, int two_sided, int rep_offset,
+                 const int32_t *rows_in, int transform, xo_pair **out_pairs, int64_t *out_npairs, xo_rep *reps)
 {
     if (n <= 0 || p <= 0 || m < 0 || m > 64 || L < 0 || !(kappa == kappa) || isinf(kappa))
         return XO_EINVAL;
+    if (transform != 0 && (transform != 1 || xkind != 1)) return XO_EINVAL;
     const int8_t *Xb = (const int8_t *)Xv; const double *Xd = (const double *)Xv;
     const int8_t *Yb = (const int8_t *)Yv; const double *Yd = (const double *)Yv;
     int binary = (xkind == 0 && ykind == 0);
@@ -305,6 +354,20 @@ int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, i
         if (!(acc > 0.0)) { free(Xs); free(Z); free(Ys); free(Ydw); free(Xdw); return XO_EINVAL; }
     }
 
+    /* unbiased transform: row maxima nu_i and row weights |Y_i| nu_i^2 */
+    double *nu = NULL, *wrow = NULL;
+    if (transform == 1) {
+        nu = (double *)malloc(sizeof(double) * (size_t)n);
+        wrow = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!nu || !wrow) { free(Xs); free(Z); free(Ys); free(Ydw); free(Xdw); free(nu); free(wrow); return XO_ENOMEM; }
+        for (int64_t i = 0; i < n; i++) {
+            double v = 0.0;
+            for (int64_t j = 0; j < p; j++) if (fabs(Xd[j * n + i]) > v) v = fabs(Xd[j * n + i]);
+            nu[i] = v;
+            wrow[i] = fabs(ykind == 0 ? (double)Yb[i] : Yd[i]) * (v * v);
+        }
+    }
+
     int mm = m > 0 ? m : 1;
     int8_t *tx = (int8_t *)malloc((size_t)(p * mm));
     int8_t *tz = (int8_t *)malloc((size_t)(p * mm));
@@ -322,6 +385,9 @@ int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, i
                 if (rows[t] < 0 || rows[t] >= n) { rc = XO_EINVAL; break; }
             }
             if (rc != XO_OK) break;
+        } else if (transform == 1) {
+            rc = draw_rows_w(wrow, n, seed, l, m, rows);
+            if (rc != XO_OK) break;
         } else {
             rc = xo_draw_rows(ykind == 1 ? Yd : NULL, n, seed, l, m, rows);
             if (rc != XO_OK) break;
@@ -332,8 +398,15 @@ int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, i
         /* projections x = X^T R, z = Z^T R, represented by the sampled tuples */
         for (int64_t j = 0; j < p; j++)
             for (int t = 0; t < m; t++) {
-                tx[j * m + t] = Xs[j * n + rows[t]];
-                tz[j * m + t] = Z[j * n + rows[t]];
+                if (transform == 1) {
+                    int64_t i = rows[t];
+                    int8_t xt = unbiased_sign(seed, l, t, j, Xd[j * n + i], nu[i]);
+                    tx[j * m + t] = xt;
+                    tz[j * m + t] = (int8_t)(Ys[i] * xt);
+                } else {
+                    tx[j * m + t] = Xs[j * n + rows[t]];
+                    tz[j * m + t] = Z[j * n + rows[t]];
+                }
             }
         cand.n = 0;
         int32_t maxb = 0;
@@ -395,10 +468,18 @@ int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, i
         }
     }
     free(Xs); free(Z); free(Ys); free(Ydw); free(Xdw); free(tx); free(tz); free(rows);
-    free(cand.v); free(rec);
+    free(cand.v); free(rec); free(nu); free(wrow);
     if (rc != XO_OK) { free(pairs); return rc; }
     *out_pairs = pairs; *out_npairs = np_;
     return XO_OK;
+}
+
+int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, int64_t p,
+              int m, int L, double kappa, uint64_t seed, int two_sided, int rep_offset,
+              const int32_t *rows_in, xo_pair **out_pairs, int64_t *out_npairs, xo_rep *reps)
+{
+    return xo_search_ex(Xv, xkind, Yv, ykind, n, p, m, L, kappa, seed, two_sided, rep_offset, rows_in, 0,
+                        out_pairs, out_npairs, reps);
 }
 
 /* The plain definition T(kappa) = {j < k : Y^T(X_j o X_k)/n > kappa} (eq. (1)),

@@ -363,3 +363,55 @@ def test_M_star_is_pareto_optimal():
                     L2 += 1
                 c2 = theory.cost(M2, L2, n, p, theory.sum_gamma_pow(sample, total, M2))
                 assert c2 >= c_star * (1 - 1e-9) or M2 == Ms
+
+
+# ------------------------------------------------- unbiased transform (Section 3.2)
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_unbiased_transform_collision_rate_is_proposition_4(m):
+    """Two continuous columns plus one column that only sets the row maxima: the
+    oracle's collision frequency of the pair over many repetitions equals
+    Proposition 4's strength (with row scaling) to the power m.  A transform
+    drawn as (1 - x)/2 or row weights without nu_i^2 move the rate by more than
+    ten times the tolerance."""
+    r = np.random.default_rng(11)
+    n = 40
+    XT = r.uniform(-1, 1, size=(3, n)).astype(np.float32)
+    XT[2] *= 2.5                                     # the row maxima come from column 2 on most rows
+    XT[1] = (0.8 * XT[0] + 0.2 * r.uniform(-1, 1, size=n)).astype(np.float32)
+    Y = (XT[0].astype(np.float64) * XT[1] + 0.1 * r.standard_normal(n)).astype(np.float32)
+    L = 40_000
+    _, reps = oracle.search(XT, Y, m, L, 10.0, seed=5, unbiased=True)
+    # unordered candidates: (0,1) collides with prob g01^m, (0,2), (1,2) with theirs
+    want = sum(theory.gamma_unbiased(XT, Y, a, b) ** m for a, b in ((0, 1), (0, 2), (1, 2)))
+    got = float(reps["candidates"].mean())
+    se = math.sqrt(3 * 0.25 / L)
+    assert abs(got - want) < 5 * se, (got, want)
+    # the scaled strength differs clearly from the unscaled one on this data
+    assert abs(theory.gamma_unbiased(XT, Y, 0, 1) - theory.gamma_unbiased(XT, Y, 0, 1, scale=False)) > 0.05
+
+
+def test_unbiased_strength_uniform_example_is_13_18():
+    """Section 3.2 prints 13/18 as the limit of the true pair's strength under the
+    unbiased transform for X ~ Uniform(-1, 1) and Y = X_j X_k without noise."""
+    r = np.random.default_rng(12)
+    n = 400_000
+    XT = r.uniform(-1, 1, size=(2, n))
+    Y = XT[0] * XT[1]
+    g = theory.gamma_unbiased(XT, Y, 0, 1, scale=False)
+    assert abs(g - 13 / 18) < 3e-3, g
+
+
+def test_unbiased_search_deterministic_and_rows_table():
+    """The transform's draws are counter based: the same seed gives the same
+    candidates, and a row table with an all-zero row (nu = 0, drawn only
+    through the table) is accepted."""
+    d = synthgen.small_continuous(50, 30, seed=13, planted=[(1, 4)])
+    XT = d.XT.copy()
+    XT[:, 7] = 0.0                                  # row 7 all zero
+    a = oracle.search(XT, d.Y, 5, 6, 0.2, seed=3, unbiased=True)
+    b = oracle.search(XT, d.Y, 5, 6, 0.2, seed=3, unbiased=True)
+    assert np.array_equal(a[1]["candidates"], b[1]["candidates"]) and np.array_equal(a[0], b[0])
+    rows = np.full((4, 5), 7, dtype=np.int32)
+    rows[:, 0] = [0, 1, 2, 3]
+    oracle.search(XT, d.Y, 5, 4, 0.2, rows=rows, unbiased=True)
