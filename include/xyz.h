@@ -66,6 +66,17 @@ typedef int32_t xyz_status;
 #define XYZ_PROFILE   2u  /* time the GPU stages with HIP events and report them in xyz_timing */
 #define XYZ_EXACT     4u  /* xyz_serve_submit only: answer with the exact search of eq. (1), as xyz_bruteforce
                              over all columns; m, L, seed, rep_offset and rows are ignored */
+#define XYZ_UNBIASED  8u  /* float32 X only: hash with the unbiased transform of Section 3.2 (Proposition 4)
+                             instead of the sign transform.  Each row is divided by its largest absolute
+                             entry nu_i and Y_i multiplied by nu_i^2, so rows are drawn with probability
+                             proportional to |Y_i| nu_i^2 (+-1 Y: nu_i^2), and every sampled entry becomes +1
+                             with probability (1 + X_ij / nu_i) / 2, drawn afresh for each repetition, draw
+                             and column from a counter-based SplitMix64 stream (draw t of repetition l: stream
+                             seed = output 1 + l*2^16 + t of SplitMix64 seeded with seed ^ 0x2545F4914F6CDD1D;
+                             column j: top 24 bits u of that stream's output 1 + j; +1 exactly when, in
+                             binary64, (u * 2) * nu_i < (nu_i + X_ij) * 2^24; on an all-zero row, when
+                             u < 2^23).  The strength check stays eq. (1) on the original X and Y.
+                             XYZ_EUNSUPPORTED for int8 or bit-packed X. */
 
 #define XYZ_MAX_M 30      /* largest supported number of sampled rows per repetition */
 
@@ -82,7 +93,7 @@ typedef struct {
     int32_t L;            /* repetitions, >= 1 */
     double kappa;         /* keep Y^T(X_j o X_k)/n > kappa (strict), finite */
     uint64_t seed;        /* row sampler seed */
-    uint32_t flags;       /* XYZ_TWO_SIDED | XYZ_PROFILE */
+    uint32_t flags;       /* XYZ_TWO_SIDED | XYZ_PROFILE | XYZ_UNBIASED */
     int32_t rep_offset;   /* index of the first repetition (split or resumed runs); >= 0 */
     const int32_t *rows;  /* optional host table of L*m row indices in [0, n) replacing the sampler;
                              repetition l uses rows[l*m .. l*m+m-1] */

@@ -24,7 +24,7 @@ XYZ_OK, XYZ_EINVAL, XYZ_ENOMEM, XYZ_EDEVICE, XYZ_EAGAIN, XYZ_ECANCELED, XYZ_EUNS
 XYZ_MEM_HOST, XYZ_MEM_DEVICE = 0, 1
 XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32 = 0, 1, 2
 XYZ_Y_I8_PM1, XYZ_Y_F32, XYZ_Y_F64 = 0, 1, 2
-XYZ_TWO_SIDED, XYZ_PROFILE, XYZ_EXACT = 1, 2, 4
+XYZ_TWO_SIDED, XYZ_PROFILE, XYZ_EXACT, XYZ_UNBIASED = 1, 2, 4, 8
 XYZ_MAX_M = 30
 
 PAIR_DTYPE = np.dtype([("j", np.int32), ("k", np.int32), ("s", np.int64), ("value", np.float64),
@@ -233,10 +233,11 @@ def xyz_x_destroy(x) -> None:
     lib().xyz_x_destroy(x)
 
 
-def _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile):
+def _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased=False):
     prm = xyz_params()
     prm.m, prm.L, prm.kappa, prm.seed = int(m), int(L), float(kappa), int(seed) & (2 ** 64 - 1)
-    prm.flags = (XYZ_TWO_SIDED if two_sided else 0) | (XYZ_PROFILE if profile else 0)
+    prm.flags = ((XYZ_TWO_SIDED if two_sided else 0) | (XYZ_PROFILE if profile else 0) |
+                 (XYZ_UNBIASED if unbiased else 0))
     prm.rep_offset = int(rep_offset)
     keep = None
     if rows is not None:
@@ -264,9 +265,10 @@ def _take_result(h):
 
 
 def xyz_search(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
-               rep_offset: int = 0, rows=None, profile: bool = False, stream=None):
-    """Algorithm 2 on resident X.  Returns {'pairs', 'reps', 'timing'}."""
-    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile)
+               rep_offset: int = 0, rows=None, profile: bool = False, stream=None, unbiased: bool = False):
+    """Algorithm 2 on resident X.  Returns {'pairs', 'reps', 'timing'}.  unbiased:
+    hash float32 X with the unbiased transform of Section 3.2 (XYZ_UNBIASED)."""
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased)
     ptr, mem, keep = _ptr(Y)
     h = ctypes.c_void_p()
     _check(lib().xyz_search(ctx, x, ptr, _y_format(Y), mem, ctypes.byref(prm), _stream(stream, Y), ctypes.byref(h)))
@@ -294,7 +296,8 @@ def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
     keep_rows = []
     for q, kw in enumerate(params):
         prm, kr = _params(kw["m"], kw["L"], kw["kappa"], kw.get("seed", 0), kw.get("two_sided", False),
-                          kw.get("rep_offset", 0), kw.get("rows"), kw.get("profile", False))
+                          kw.get("rep_offset", 0), kw.get("rows"), kw.get("profile", False),
+                          kw.get("unbiased", False))
         arr[q] = prm
         keep_rows.append(kr)
     yp = (ctypes.c_void_p * nY)(*ptrs)

@@ -355,7 +355,10 @@ xyz_status xyz_rt::validate_params(const xyz_x *x, const xyz_params *P, int yfmt
     if (!std::isfinite(P->kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
     if (P->rep_offset < 0) return fail(XYZ_EINVAL, "rep_offset < 0");
     if ((int64_t)P->rep_offset + P->L > (1ll << 31)) return fail(XYZ_EINVAL, "repetition index overflow");
-    if (P->flags & ~(uint32_t)(XYZ_TWO_SIDED | XYZ_PROFILE)) return fail(XYZ_EINVAL, "unknown flags 0x%x", P->flags);
+    if (P->flags & ~(uint32_t)(XYZ_TWO_SIDED | XYZ_PROFILE | XYZ_UNBIASED))
+        return fail(XYZ_EINVAL, "unknown flags 0x%x", P->flags);
+    if ((P->flags & XYZ_UNBIASED) && x->fmt != XYZ_X_F32)
+        return fail(XYZ_EUNSUPPORTED, "the unbiased transform needs float32 X");
     if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
     if (P->rows) {
         const int64_t cnt = (int64_t)P->L * P->m;
@@ -415,6 +418,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     const bool real_y = yfmt != XYZ_Y_I8_PM1;
     const bool real_x = x->fmt == XYZ_X_F32;
     const bool real = real_x || real_y;
+    const bool unbiased = (P.flags & XYZ_UNBIASED) != 0 && real_x;
     // +-1 data with exact FP32 counts: large bucket products go to the matrix cores
     const int mfma = (!real && n < (1 << 24)) ? 1 : 0;
     Timer tm;
@@ -430,7 +434,15 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     XYZ_TRY(pack_ys(c, x, nys, Ys, yfmt, mem, st, &yb, &yd, &err));
     double *cdf = nullptr;
     int64_t *last = nullptr;
-    if (real_y && m > 0) {
+    uint32_t *nu = nullptr;
+    if (unbiased && m > 0) {
+        // Section 3.2: rows scaled by their largest absolute entry, weights |Y_i| nu_i^2
+        XYZ_TRY(ws(c, WS_NU, (size_t)n, &nu));
+        XYZ_TRY(ws(c, WS_CDF, (size_t)n, &cdf));
+        XYZ_TRY(ws(c, WS_LAST, 1, &last));
+        HIP_TRY(launch_row_absmax(x->XF, x->nF, n, p, nu, st));
+        HIP_TRY(launch_cdf_unbiased(yd, nu, n, cdf, last, err, st));
+    } else if (real_y && m > 0) {
         XYZ_TRY(ws(c, WS_CDF, (size_t)n, &cdf));
         XYZ_TRY(ws(c, WS_LAST, 1, &last));
         HIP_TRY(launch_cdf(yd, n, cdf, last, err, st));
@@ -481,13 +493,16 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             if (P.rows) {
                 HIP_TRY(hipMemcpyAsync(rows, P.rows + (size_t)r0 * m, sizeof(int32_t) * R * m, hipMemcpyHostToDevice, st));
             } else {
-                HIP_TRY(launch_sample(P.seed, rep_abs0, R, m, n, real_y ? 1 : 0, cdf, last, rows, st));
+                HIP_TRY(launch_sample(P.seed, rep_abs0, R, m, n, (real_y || unbiased) ? 1 : 0, cdf, last, rows, st));
             }
         }
         HIP_TRY(launch_cmask(rows, R, m, nys, yb, x->W32p, cinfo, st));
         tm.end();
         tm.begin(2);
-        HIP_TRY(launch_hash(x->XR, x->P64, p, m, R, rows, keys, st));
+        if (unbiased && m > 0)
+            HIP_TRY(launch_hash_unbiased(x->XF, x->nF, p, m, R, rows, nu, P.seed, rep_abs0, keys, st));
+        else
+            HIP_TRY(launch_hash(x->XR, x->P64, p, m, R, rows, keys, st));
         tm.end();
         bool redo = true;
         while (redo) {

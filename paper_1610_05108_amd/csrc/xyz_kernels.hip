@@ -266,6 +266,43 @@ __global__ void k_cdf(const double *__restrict__ yd, int64_t n, double *__restri
     if (!(acc > 0.0)) atomicOr(err, 8);
 }
 
+// ------------------------------------------------------ unbiased transform --
+//
+// Section 3.2, Proposition 4: with rows scaled by nu_i = max_j |X_ij| (and Y_i by
+// nu_i^2), a sampled entry becomes +1 with probability (1 + X_ij / nu_i) / 2,
+// independently for every repetition, draw and column.
+
+// nu_i as float bits: non-negative floats order like their bit patterns, so an
+// integer atomic max over |x| bits is the float max.  Thread (i, column slice).
+__global__ __launch_bounds__(256) void k_row_absmax(const float *__restrict__ XF, int64_t nF, int64_t n, int64_t p,
+                                                    int64_t cols_per, uint32_t *__restrict__ nu)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j0 = (int64_t)blockIdx.y * cols_per, j1 = min(p, j0 + cols_per);
+    uint32_t mb = 0;
+    for (int64_t j = j0; j < j1; ++j) mb = max(mb, __float_as_uint(XF[j * nF + i]) & 0x7FFFFFFFu);
+    if (mb) atomicMax(&nu[i], mb);
+}
+
+// Running sum of the row weights |Y_i| * (nu_i * nu_i), binary64, i = 0, 1, ..., n-1.
+__global__ void k_cdf_unbiased(const double *__restrict__ yd, const uint32_t *__restrict__ nu, int64_t n,
+                               double *__restrict__ cdf, int64_t *__restrict__ last, int *__restrict__ err)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    int64_t lst = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = (double)__uint_as_float(nu[i]);
+        const double w = __dmul_rn(fabs(yd[i]), __dmul_rn(v, v));
+        acc = __dadd_rn(acc, w);
+        cdf[i] = acc;
+        if (w != 0.0) lst = i;
+    }
+    *last = lst;
+    if (!(acc > 0.0)) atomicOr(err, 8);
+}
+
 // ----------------------------------------------------------------- sampler --
 
 // SplitMix64 (Steele, Lea & Flood 2014): output number k of the generator seeded with `seed`.
@@ -340,6 +377,45 @@ __global__ __launch_bounds__(256) void k_hash(const uint64_t *__restrict__ XR, i
     for (int t = 0; t < m; ++t) {
         const uint64_t word = XR[(int64_t)rr[t] * P64 + w];
         key |= (uint32_t)((word >> sh) & 1ull) << t;
+    }
+    keys[(int64_t)r * p + j] = key;
+}
+
+// Keys under the unbiased transform: thread (column j, repetition r); bit t is
+// [X~ = -1] for sampled row r_t.  Draw t of repetition l seeds a SplitMix64
+// stream (output 1 + l*2^16 + t of the generator seeded with seed ^ UNB_STREAM);
+// column j takes the top 24 bits u of the stream's output 1 + j, and X~ = +1
+// exactly when (u * 2) * nu < (nu + x) * 2^24 in binary64 (u / 2^24 < (1 + x/nu) / 2
+// without a division; every product is exact), or u < 2^23 on an all-zero row.
+constexpr uint64_t UNB_STREAM = 0x2545F4914F6CDD1Dull;
+
+__global__ __launch_bounds__(256) void k_hash_unbiased(const float *__restrict__ XF, int64_t nF, int64_t p, int m,
+                                                       const int32_t *__restrict__ rows,
+                                                       const uint32_t *__restrict__ nu, uint64_t seed, int64_t rep0,
+                                                       uint32_t *__restrict__ keys)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    __shared__ int32_t rr[32];
+    __shared__ float nus[32];
+    __shared__ uint64_t ss[32];
+    if (threadIdx.x < (unsigned)m) {
+        const int t = (int)threadIdx.x;
+        const int32_t row = rows[(int64_t)r * m + t];
+        rr[t] = row;
+        nus[t] = __uint_as_float(nu[row]);
+        ss[t] = splitmix64_at(seed ^ UNB_STREAM, 1ull + (uint64_t)(rep0 + r) * 65536ull + (uint64_t)t);
+    }
+    __syncthreads();
+    if (j >= p) return;
+    uint32_t key = 0;
+    for (int t = 0; t < m; ++t) {
+        const double x = (double)XF[j * nF + rr[t]];
+        const double v = (double)nus[t];
+        const uint64_t u = splitmix64_at(ss[t], 1ull + (uint64_t)j) >> 40;
+        const bool plus = v > 0.0 ? __dmul_rn(__dmul_rn((double)u, 2.0), v) < __dmul_rn(__dadd_rn(v, x), 16777216.0)
+                                  : u < 8388608ull;
+        key |= (plus ? 0u : 1u) << t;
     }
     keys[(int64_t)r * p + j] = key;
 }
@@ -2316,6 +2392,31 @@ hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uin
 {
     hipLaunchKernelGGL(k_cmask, dim3(grid1((uint64_t)nrep * nys, 256)), dim3(256), 0, st, rows, nrep, m, nys, yb,
                        yb_stride, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_absmax(const float *XF, int64_t nF, int64_t n, int64_t p, uint32_t *nu, hipStream_t st)
+{
+    const hipError_t e = hipMemsetAsync(nu, 0, sizeof(uint32_t) * (size_t)n, st);
+    if (e != hipSuccess) return e;
+    const int64_t slices = std::min<int64_t>(std::max<int64_t>(p / 64, 1), 4096);
+    const int64_t per = (p + slices - 1) / slices;
+    hipLaunchKernelGGL(k_row_absmax, dim3(grid1(n, 256), (unsigned)slices), dim3(256), 0, st, XF, nF, n, p, per, nu);
+    return hipGetLastError();
+}
+
+hipError_t launch_cdf_unbiased(const double *yd, const uint32_t *nu, int64_t n, double *cdf, int64_t *last, int *err,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cdf_unbiased, dim3(1), dim3(64), 0, st, yd, nu, n, cdf, last, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_unbiased(const float *XF, int64_t nF, int64_t p, int m, int nrep, const int32_t *rows,
+                                const uint32_t *nu, uint64_t seed, int64_t rep0, uint32_t *keys, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hash_unbiased, dim3(grid1(p, 256), nrep), dim3(256), 0, st, XF, nF, p, m, rows, nu, seed,
+                       rep0, keys);
     return hipGetLastError();
 }
 
