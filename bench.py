@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s (256 CUs x 64 lanes x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP4_TFLOPS = 10100.0                  # dense FP4 matrix-core peak (the exact search runs in e2m1)
+PEAK_FP64_TFLOPS = 78.6                    # FP64 vector peak (continuous verification: binary64 FMAs)
 
 
 def log(*a):
@@ -94,6 +95,7 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=None)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-large", action="store_true", help="skip the large Rademacher comparison")
+    ap.add_argument("--no-continuous", action="store_true", help="skip the continuous workload")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-fresh", type=int, default=32)
     ap.add_argument("--serve-workers", type=int, default=2)
@@ -242,6 +244,11 @@ def main():
         large = large_binary_leg(ctx)
         log(f"large binary: {large}")
 
+    continuous = None
+    if not args.no_continuous:
+        continuous = continuous_leg(ctx)
+        log(f"continuous: {continuous}")
+
     serving = None
     if not args.no_serve:
         serving = serve_leg(ctx, args.serve_requests, args.serve_fresh, args.serve_workers, seq_sample=32)
@@ -276,6 +283,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "large_binary": large,
+        "continuous": continuous,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -552,6 +560,49 @@ def scaling_law_leg(ctx, n, ps, gammas, sims, gamma0=0.55):
         fits[f"{g:.3f}"] = f
     return {"experiment": "time to discovery against p (Section 5.2, Theorem 2)", "n": n, "gamma0": gamma0,
             "data": "synthetic Rademacher, one pair of strength gamma", "points": pts, "fits": fits}
+
+
+def continuous_leg(ctx):
+    """The continuous workload (X ~ N(0,1) float32, n=1000, p=200,000, real Y with
+    five planted pairs and ten main effects) at its configured parameters (m=12,
+    L=300, kappa=0.5; signs of X hashed, |Y|-weighted rows), each search timed on
+    its second run, and the same search with the unbiased transform of Section
+    3.2 (XYZ_UNBIASED).  Recall: planted pairs reported among those whose value
+    exceeds kappa (values from a plain float64 product on the device).  Roofline
+    of the verification (k_verify_real): candidate pairs x n multiply-adds in
+    binary64 over the verification time, against the FP64 vector peak."""
+    import torch
+    import synthgen
+    d = synthgen.config4(seed=0)
+    XT = torch.from_numpy(d.XT).cuda()
+    x = ctx.x_create(XT)
+    Y = torch.from_numpy(d.Y).cuda()
+    m, L, kappa = 12, 300, 0.5
+    Yd = Y.double()
+    vals = {pq: float((Yd * XT[pq[0]].double() * XT[pq[1]].double()).sum()) for pq in d.planted}
+    above = [pq for pq in d.planted if vals[pq] / d.n > kappa]
+    out = {"workload": f"continuous X n={d.n} p={d.p}, real Y, {len(d.planted)} planted pairs, m={m} L={L} "
+                       f"kappa={kappa}", "planted_above_kappa": len(above)}
+    for name, unb in (("sign", False), ("unbiased", True)):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.search(x, Y, m=m, L=L, kappa=kappa, seed=rep, unbiased=unb, profile=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        pr = r["pairs"]
+        got = set(zip(pr["j"].tolist(), pr["k"].tolist()))
+        tm = r["timing"]
+        flops = 2.0 * tm["candidates"] * d.n
+        out[name] = {"ms": dt * 1e3, "verify_ms": tm["verify_ms"], "hash_ms": tm["hash_ms"],
+                     "candidates": tm["candidates"], "planted_found": sum(1 for pq in above if pq in got),
+                     "verify_roofline": {"kernel": "k_verify_real", "bound": "fp64", "unit": "TFLOP/s",
+                                         "achieved": flops / (tm["verify_ms"] * 1e-3) / 1e12,
+                                         "peak": PEAK_FP64_TFLOPS,
+                                         "frac": flops / (tm["verify_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}}
+    import paper_1610_05108_amd as xyz
+    xyz.xyz_x_destroy(x)
+    return out
 
 
 def cpu_baseline(dd, m, L, n, p, reps=None):

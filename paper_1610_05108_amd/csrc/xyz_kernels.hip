@@ -1617,6 +1617,10 @@ __global__ __launch_bounds__(64) void k_verify_small(VerifyArgs a)
 // Real-valued verification: v = sum_i (Y_i X_ij) X_ik in binary64.  Rows are
 // staged in chunks of 32: A holds Y_i X_ia (exact in binary64 for float
 // inputs), B holds X_ib; each lane accumulates its RA x RB block with FMAs.
+// Staging: load q covers 8 columns, lane l taking rows 4(l%8) .. 4(l%8) + 3 of
+// column 8q + l/8 (16 contiguous bytes of float X, or one word of bits), and
+// the next chunk's loads are issued before the current chunk's products.
+// Rows past n are zero in Y (and in float X), so no row needs a mask.
 constexpr int CR = 32;
 
 template <int RA, int RB>
@@ -1625,38 +1629,56 @@ XYZ_DEV void verify_real_tile(const Tile &t, const uint32_t *colA, const uint32_
 {
     const unsigned lane = lane_id();
     const int ia = lane & 7, ib = lane >> 3;
+    const int sr = (int)(lane & 7) * 4, sc = (int)(lane >> 3);
     const double *yd = a.yd + (int64_t)t.ysel * a.nF;
     double acc[RA][RB];
 #pragma unroll
     for (int u = 0; u < RA; ++u)
 #pragma unroll
         for (int v = 0; v < RB; ++v) acc[u][v] = 0.0;
-    const int64_t nchunk = (a.n + CR - 1) / CR;
-    const int row = lane & 31, half = lane >> 5;
+    // the lane's staged columns (past the end of a bucket: its last column, never reported)
+    int64_t ca[RA], cb[RB];
+#pragma unroll
+    for (int q = 0; q < RA; ++q) ca[q] = colA[min(8 * q + sc, (int)t.na - 1)];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) cb[q] = colB[min(8 * q + sc, (int)t.nb - 1)];
+    float4 xa[RA], xb[RB];
+    uint32_t wa[RA], wb[RB];
+    double2 y01, y23;
+    auto load = [&](int64_t c) {
+        const int64_t i0 = c * CR + sr;
+        if (x_real) {
+#pragma unroll
+            for (int q = 0; q < RA; ++q) xa[q] = *reinterpret_cast<const float4 *>(a.XF + ca[q] * a.nF + i0);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) xb[q] = *reinterpret_cast<const float4 *>(a.XF + cb[q] * a.nF + i0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < RA; ++q) wa[q] = a.XC[ca[q] * a.W32p + c];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) wb[q] = a.XC[cb[q] * a.W32p + c];
+        }
+        y01 = *reinterpret_cast<const double2 *>(yd + i0);
+        y23 = *reinterpret_cast<const double2 *>(yd + i0 + 2);
+    };
+    auto xval = [&](const float4 &f, uint32_t w, int e) -> double {
+        if (x_real) return (double)(e == 0 ? f.x : e == 1 ? f.y : e == 2 ? f.z : f.w);
+        return ((w >> (sr + e)) & 1u) ? -1.0 : 1.0;
+    };
+    const int64_t nchunk = a.nF / CR;
+    load(0);
     for (int64_t c = 0; c < nchunk; ++c) {
-        const int64_t i = c * CR + row;
-        const bool inr = i < a.n;
-        const double yv = inr ? yd[i] : 0.0;
-        // each lane stages row `row` of columns half, half + 2, ...
-        for (int ci = half; ci < 8 * RA; ci += 2) {
-            double v = 0.0;
-            if (ci < t.na && inr) {
-                double x;
-                if (x_real) x = (double)a.XF[(int64_t)colA[ci] * a.nF + i];
-                else x = ((a.XC[(int64_t)colA[ci] * a.W32p + (i >> 5)] >> (i & 31)) & 1u) ? -1.0 : 1.0;
-                v = yv * x;
-            }
-            As[ci][row] = v;
-        }
-        for (int ci = half; ci < 8 * RB; ci += 2) {
-            double v = 0.0;
-            if (ci < t.nb && inr) {
-                if (x_real) v = (double)a.XF[(int64_t)colB[ci] * a.nF + i];
-                else v = ((a.XC[(int64_t)colB[ci] * a.W32p + (i >> 5)] >> (i & 31)) & 1u) ? -1.0 : 1.0;
-            }
-            Bs[ci][row] = v;
-        }
+        const double yv[4] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+        for (int q = 0; q < RA; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) As[8 * q + sc][sr + e] = yv[e] * xval(xa[q], wa[q], e);
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[8 * q + sc][sr + e] = xval(xb[q], wb[q], e);
         __syncthreads();
+        if (c + 1 < nchunk) load(c + 1);
 #pragma unroll 4
         for (int rr = 0; rr < CR; ++rr) {
             double av[RA], bv[RB];
