@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--scaling-gamma", type=str, default="0.7,0.8,0.9")
     ap.add_argument("--scaling-n", type=int, default=4000)
     ap.add_argument("--scaling-sims", type=int, default=40)
+    ap.add_argument("--lasso", action="store_true",
+                    help="only run the regression experiment of Section 5.4 (Lasso with all interactions)")
+    ap.add_argument("--lasso-p", type=str, default="250,500,1000")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -124,6 +127,11 @@ def main():
         out = scaling_law_leg(ctx, args.scaling_n, [int(v) for v in args.scaling_p.split(",")],
                               [float(v) for v in args.scaling_gamma.split(",")], args.scaling_sims)
         print(json.dumps(out), flush=True)
+        return
+    if args.lasso:
+        import paper_1610_05108_amd as xyz
+        ctx = xyz.Context(0)
+        print(json.dumps(lasso_leg(ctx, [int(v) for v in args.lasso_p.split(",")])), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards over repetitions "
@@ -603,6 +611,45 @@ def continuous_leg(ctx):
     import paper_1610_05108_amd as xyz
     xyz.xyz_x_destroy(x)
     return out
+
+
+def lasso_leg(ctx, ps, n=1000, settings=(1, 2), nlam=12):
+    """Section 5.4 (settings 1 and 2): the Lasso path over all main effects and
+    interactions (Algorithm 3) on a grid of `nlam` lambdas from lambda_max (the
+    largest main-effect gradient) down to lambda_max / 50, with the interaction
+    KKT check done by (a) the xyz search, L = sqrt(p) as in Section 5.4 and
+    m = ceil(log2 p), and (b) the exhaustive check of all pairs on the GPU (m = 0:
+    every pair is a candidate).  Reports the wall time of each path and how many
+    of the 10 true interactions and 20 main effects the final model holds."""
+    import torch
+    import synthgen
+    import paper_1610_05108_amd as xyz
+    from paper_1610_05108_amd.lasso import lasso_interactions, xyz_screen
+    out = []
+    for setting in settings:
+        for p in ps:
+            X, Y, mains, inters = synthgen.lasso_setting(n, p, setting, seed=p)
+            x = ctx.x_create(np.ascontiguousarray(X.T))
+            Xc = X.astype(np.float64) - X.mean(0)
+            lam_max = float(np.abs(Xc.T @ (Y - Y.mean())).max() / n)
+            lambdas = lam_max * np.logspace(0, -math.log10(50), nlam)
+            row = {"setting": setting, "p": p, "n": n}
+            for name, screen in (("xyz", xyz_screen(ctx, x, m=int(math.ceil(math.log2(p))),
+                                                    L=int(math.ceil(math.sqrt(p))), seed=1)),
+                                 ("exhaustive", xyz_screen(ctx, x, m=0, L=1))):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                path = lasso_interactions(X, Y, lambdas, screen)
+                dt = time.perf_counter() - t0
+                row[name] = {"s": dt, "inter_found": sum(1 for pq in inters if pq in path.inter[-1]),
+                             "main_found": sum(1 for j in mains if j in path.main[-1]),
+                             "model_size": len(path.main[-1]) + len(path.inter[-1]),
+                             "kkt_rounds": int(sum(path.rounds))}
+            log(f"lasso: {row}")
+            out.append(row)
+            xyz.xyz_x_destroy(x)
+    return {"experiment": "Lasso with all interactions, KKT screening by xyz (Section 5.4, Algorithm 3)",
+            "data": "synthetic, settings 1-2 of Section 5.4", "points": out}
 
 
 def cpu_baseline(dd, m, L, n, p, reps=None):

@@ -29,7 +29,7 @@ __all__ = [
     "Dataset", "rademacher", "genotype", "gaussian",
     "config1", "config2", "config3", "config4", "config5_shared", "config5_requests",
     "config5_fresh", "small_binary", "small_continuous", "rows_table", "pack_bits_colmajor",
-    "scaling_x", "scaling_y",
+    "scaling_x", "scaling_y", "lasso_setting",
 ]
 
 
@@ -224,6 +224,33 @@ def scaling_y(bits: np.ndarray, n: int, agree: int, seed: int) -> np.ndarray:
     sign = np.full(n, -1, dtype=np.int8)
     sign[r.choice(n, size=agree, replace=False)] = 1
     return (x0 * x1 * sign).astype(np.int8)
+
+
+def lasso_setting(n: int, p: int, setting: int, seed: int = 0):
+    """Regression data of Section 5.4, settings 1 and 2 (Sigma = I): X ~ N(0, I)
+    float32 (n, p); 20 main effects and 10 interactions with magnitudes
+    U[2, 6] and random signs, mu = 0, eps ~ N(0, 1).  Setting 1 is
+    hierarchical (interactions drawn among pairs of main effects), setting 2
+    strictly non-hierarchical (interactions among the other columns).
+    Returns (X, Y, mains {j: beta}, inters {(j, k): theta})."""
+    r = _rng(seed, 23 + setting)
+    X = r.standard_normal((n, p)).astype(np.float32)
+    cols = r.permutation(p)
+    main = [int(j) for j in cols[:20]]
+    pool = main if setting == 1 else [int(j) for j in cols[20:]]
+    pairs = set()
+    while len(pairs) < 10:
+        j, k = r.choice(len(pool), size=2, replace=False)
+        pairs.add((min(pool[j], pool[k]), max(pool[j], pool[k])))
+    mains = {j: float(r.uniform(2, 6) * r.choice([-1, 1])) for j in main}
+    inters = {pq: float(r.uniform(2, 6) * r.choice([-1, 1])) for pq in sorted(pairs)}
+    Xd = X.astype(np.float64)
+    y = r.standard_normal(n)
+    for j, b in mains.items():
+        y += b * Xd[:, j]
+    for (j, k), t in inters.items():
+        y += t * Xd[:, j] * Xd[:, k]
+    return X, y, mains, inters
 
 
 def config4(seed: int = 0, n: int = 1000, p: int = 200_000) -> Dataset:
