@@ -10,14 +10,19 @@ on the GPU before timing).
 A step answers all five searches at >= 95 % predicted recall of the planted
 pairs above kappa.  The candidate plans are xyz with m in {8, 10, 12} rows
 and L from eq. (15) for the weakest planted pair above kappa, and the exact
-search of eq. (1) on the int8 matrix cores (recall 1); each is timed once on
+search of eq. (1) on the FP4 (e2m1) matrix cores (recall 1); each is timed once on
 the first data set and the fastest is used for every step.  Inputs are
 resident in HBM before timing; an xyz search includes packing Y, row
 sampling, projection, bucket sort, candidate expansion, verification,
 merging and the copy of the result to the host.
 
 Prints one JSON line.  Pairs screened per search = p (p - 1) / 2 (the whole
-search space, as in the paper's "interactions screened").
+search space, as in the paper's "interactions screened").  Beside the timed
+steps it reports the large Rademacher workload (xyz against the exact
+search), the continuous workload (sign and unbiased transforms), the serving
+stream and the CPU oracle's rate on a bounded sample.  Separate modes:
+--scaling-law (Section 5.2), --lasso (Section 5.4), --calibrate-copy (the
+reference for the HBM byte counters).
 """
 from __future__ import annotations
 

@@ -173,7 +173,7 @@ xyz_status xyz_search_batch(xyz_ctx *ctx, const xyz_x *x, int32_t nY, const void
                             int mem, const xyz_params *params, void *stream, xyz_result **outs);
 
 /* Exact search of eq. (1) over the pairs (a, b), a in colsA, b in colsB,
- * a != b, reported once as (min, max) (brute force, int8 matrix cores for
+ * a != b, reported once as (min, max) (brute force, FP4 e2m1 matrix cores for
  * +-1 data).  colsA / colsB: host arrays of column indices, or NULL for all
  * columns.  flags: XYZ_TWO_SIDED | XYZ_PROFILE. */
 xyz_status xyz_bruteforce(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
