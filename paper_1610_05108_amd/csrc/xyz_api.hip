@@ -419,8 +419,9 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     const bool real_x = x->fmt == XYZ_X_F32;
     const bool real = real_x || real_y;
     const bool unbiased = (P.flags & XYZ_UNBIASED) != 0 && real_x;
-    // +-1 data with exact FP32 counts: large bucket products go to the matrix cores
-    const int mfma = (!real && n < (1 << 24)) ? 1 : 0;
+    // large bucket products go to the matrix cores in 64 x 64 tiles: FP4 with exact FP32
+    // counts for +-1 data (n < 2^24, mfma = 1), FP64 for real data (mfma = 2)
+    const int mfma = real ? 2 : (n < (1 << 24) ? 1 : 0);
     Timer tm;
     tm.on = (P.flags & XYZ_PROFILE) != 0;
     tm.st = st;

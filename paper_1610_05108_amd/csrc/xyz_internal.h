@@ -17,10 +17,13 @@ constexpr int MAX_M_LDS = 15;
 constexpr uint32_t SMALL_TILE_PAIRS = 96;
 // Bucket products whose sides both have at least MTILE_MIN columns (MTILE_MIN_DIAG
 // for a bucket's own pairs) are verified on the matrix cores in MTILE x MTILE tiles
-// (+-1 data, n < 2^24).
+// (+-1 data, n < 2^24; FP4).
 constexpr int MTILE = 64;
 constexpr uint32_t MTILE_MIN = 16;
 constexpr uint32_t MTILE_MIN_DIAG = 24;
+// Real data: only products too large for one 32 x 32 tile on both sides go to the
+// 64 x 64 FP64 matrix-core tiles (smaller ones pack better into the 32 x 32 tiles).
+constexpr uint32_t MTILE_MIN_REAL = 33;
 
 struct Tile {            // 16 bytes
     uint32_t rep;        // repetition index relative to the launch's first repetition

@@ -427,8 +427,9 @@ __global__ __launch_bounds__(256) void k_hash_unbiased(const float *__restrict__
 // count and sorts the product into one of three tile lists:
 //   kind 1: one TILE x TILE tile with at most SMALL_TILE_PAIRS pairs (small list),
 //   kind 2: T tiles of TILE x TILE (popcount list),
-//   kind 3: T tiles of MTILE x MTILE for the matrix cores (both sides at least
-//           MTILE_MIN columns, +-1 data with n < 2^24 only: mfma != 0).
+//   kind 3: T tiles of MTILE x MTILE for the matrix cores (mfma = 1, +-1 data with
+//           n < 2^24: both sides at least MTILE_MIN columns; mfma = 2, real data:
+//           both sides at least MTILE_MIN_REAL).
 XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, int mfma, int &kind,
                                          unsigned long long &T)
 {
@@ -437,7 +438,8 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
     if (b < b2) {
         const unsigned long long c = (unsigned long long)a * a2;
         if (c == 0) return 0;
-        if (mfma && a >= MTILE_MIN && a2 >= MTILE_MIN) {
+        const uint32_t mmin = mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN;
+        if (mfma && a >= mmin && a2 >= mmin) {
             kind = 3;
             T = cdiv_u64(a, MTILE) * cdiv_u64(a2, MTILE);
         } else if (a <= (uint32_t)TILE && a2 <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
@@ -451,7 +453,7 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
     }
     if (b == b2 && a >= 2) {
         const unsigned long long c = (unsigned long long)a * (a - 1) / 2;
-        if (mfma && a >= MTILE_MIN_DIAG) {
+        if (mfma && a >= (mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN_DIAG)) {
             kind = 3;
             const unsigned long long n = cdiv_u64(a, MTILE);
             T = n * (n + 1) / 2;
@@ -1728,6 +1730,166 @@ XYZ_DEV void verify_real_tile(const Tile &t, const uint32_t *colA, const uint32_
             }
 }
 
+// The same products on the FP64 matrix cores (v_mfma_f64_16x16x4_f64) for the
+// 64 x 64 tiles of large bucket products (each column of a product staged
+// once, against twice or more in 32 x 32 tiles): FA x FB fragments of 16 x 16,
+// one product per 4 staged rows.  Lane l feeds A column u*16 + l%16 and B column
+// v*16 + l%16 at row l/16 of the 4; accumulator element e of lane l is the pair
+// (u*16 + l/16 + 4e, v*16 + l%16).  Staging as in verify_real_tile.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int FA, int FB>
+XYZ_DEV void verify_real_mfma_tile(const Tile &t, const uint32_t *colA, const uint32_t *colB,
+                                   double (*As)[CR + 1], double (*Bs)[CR + 1], const VerifyArgs &a, int x_real)
+{
+    constexpr int RA = 2 * FA, RB = 2 * FB;
+    const unsigned lane = lane_id();
+    const int sr = (int)(lane & 7) * 4, sc = (int)(lane >> 3);
+    const int li = (int)(lane & 15), lk = (int)(lane >> 4);
+    const double *yd = a.yd + (int64_t)t.ysel * a.nF;
+    v4d acc[FA][FB];
+#pragma unroll
+    for (int u = 0; u < FA; ++u)
+#pragma unroll
+        for (int v = 0; v < FB; ++v) acc[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
+    int64_t ca[RA], cb[RB];
+#pragma unroll
+    for (int q = 0; q < RA; ++q) ca[q] = colA[min(8 * q + sc, (int)t.na - 1)];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) cb[q] = colB[min(8 * q + sc, (int)t.nb - 1)];
+    float4 xa[RA], xb[RB];
+    uint32_t wa[RA], wb[RB];
+    double2 y01, y23;
+    auto load = [&](int64_t c) {
+        const int64_t i0 = c * CR + sr;
+        if (x_real) {
+#pragma unroll
+            for (int q = 0; q < RA; ++q) xa[q] = *reinterpret_cast<const float4 *>(a.XF + ca[q] * a.nF + i0);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) xb[q] = *reinterpret_cast<const float4 *>(a.XF + cb[q] * a.nF + i0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < RA; ++q) wa[q] = a.XC[ca[q] * a.W32p + c];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) wb[q] = a.XC[cb[q] * a.W32p + c];
+        }
+        y01 = *reinterpret_cast<const double2 *>(yd + i0);
+        y23 = *reinterpret_cast<const double2 *>(yd + i0 + 2);
+    };
+    auto xval = [&](const float4 &f, uint32_t w, int e) -> double {
+        if (x_real) return (double)(e == 0 ? f.x : e == 1 ? f.y : e == 2 ? f.z : f.w);
+        return ((w >> (sr + e)) & 1u) ? -1.0 : 1.0;
+    };
+    const int64_t nchunk = a.nF / CR;
+    load(0);
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const double yv[4] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+        for (int q = 0; q < RA; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) As[8 * q + sc][sr + e] = yv[e] * xval(xa[q], wa[q], e);
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[8 * q + sc][sr + e] = xval(xb[q], wb[q], e);
+        __syncthreads();
+        if (c + 1 < nchunk) load(c + 1);
+#pragma unroll
+        for (int ks = 0; ks < CR / 4; ++ks) {
+            const int k = ks * 4 + lk;
+            double av[FA], bv[FB];
+#pragma unroll
+            for (int u = 0; u < FA; ++u) av[u] = As[u * 16 + li][k];
+#pragma unroll
+            for (int v = 0; v < FB; ++v) bv[v] = Bs[v * 16 + li][k];
+#pragma unroll
+            for (int u = 0; u < FA; ++u)
+#pragma unroll
+                for (int v = 0; v < FB; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const double kappa = a.kappa[t.ysel];
+    const double dn = (double)a.n;
+    uint64_t passmask = 0;   // bit (u*FB + v)*4 + e: up to 64 pairs per lane
+#pragma unroll
+    for (int u = 0; u < FA; ++u)
+#pragma unroll
+        for (int v = 0; v < FB; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int pa = u * 16 + lk + 4 * e, pb = v * 16 + li;
+                const double st = __ddiv_rn(acc[u][v][e], dn);
+                const bool pass = a.two_sided ? (fabs(st) > kappa) : (st > kappa);
+                if (pa < t.na && pb < t.nb && (!t.diag || pa < pb) && pass) passmask |= 1ull << ((u * FB + v) * 4 + e);
+            }
+    unsigned long long idx = reserve_survivors(a, t, __popcll(passmask));
+    if (idx == ~0ull) return;
+#pragma unroll
+    for (int u = 0; u < FA; ++u)
+#pragma unroll
+        for (int v = 0; v < FB; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if ((passmask >> ((u * FB + v) * 4 + e)) & 1ull) {
+                    const uint32_t j = colA[u * 16 + lk + 4 * e], k = colB[v * 16 + li];
+                    if (idx < a.surv_cap) {
+                        Survivor sv;
+                        sv.j = min(j, k);
+                        sv.k = max(j, k);
+                        sv.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                        sv.s = 0;
+                        sv.value = acc[u][v][e];
+                        sv.ysel = t.ysel;
+                        sv.pad = 0;
+                        a.surv[idx] = sv;
+                    }
+                    ++idx;
+                }
+}
+
+// 64 x 64 tiles of large products of real data, on the FP64 matrix cores (a kernel
+// of its own: its accumulators and 64-row LDS tiles would cut the occupancy of
+// the 32 x 32 kernel).
+__global__ __launch_bounds__(64) void k_verify_real_mfma(VerifyArgs a, int x_real)
+{
+    __shared__ double As[MTILE][CR + 1];
+    __shared__ double Bs[MTILE][CR + 1];
+    __shared__ uint32_t colA[MTILE], colB[MTILE];
+    const unsigned lane = lane_id();
+    const Tile *T = a.tiles + a.ntiles + a.nsmall;
+    for (uint64_t ti = blockIdx.x; ti < a.nmfma; ti += gridDim.x) {
+        const Tile t = T[ti];
+        {
+            if (lane < t.na) colA[lane] = a.perm[t.a0 + lane];
+            if (lane < t.nb) colB[lane] = a.perm[t.b0 + lane];
+            __syncthreads();
+            const int fa = (t.na + 15) >> 4, fb = (t.nb + 15) >> 4;
+            switch (fa * 5 + fb) {
+            case 6: verify_real_mfma_tile<1, 1>(t, colA, colB, As, Bs, a, x_real); break;
+            case 7: verify_real_mfma_tile<1, 2>(t, colA, colB, As, Bs, a, x_real); break;
+            case 8: verify_real_mfma_tile<1, 3>(t, colA, colB, As, Bs, a, x_real); break;
+            case 9: verify_real_mfma_tile<1, 4>(t, colA, colB, As, Bs, a, x_real); break;
+            case 11: verify_real_mfma_tile<2, 1>(t, colA, colB, As, Bs, a, x_real); break;
+            case 12: verify_real_mfma_tile<2, 2>(t, colA, colB, As, Bs, a, x_real); break;
+            case 13: verify_real_mfma_tile<2, 3>(t, colA, colB, As, Bs, a, x_real); break;
+            case 14: verify_real_mfma_tile<2, 4>(t, colA, colB, As, Bs, a, x_real); break;
+            case 16: verify_real_mfma_tile<3, 1>(t, colA, colB, As, Bs, a, x_real); break;
+            case 17: verify_real_mfma_tile<3, 2>(t, colA, colB, As, Bs, a, x_real); break;
+            case 18: verify_real_mfma_tile<3, 3>(t, colA, colB, As, Bs, a, x_real); break;
+            case 19: verify_real_mfma_tile<3, 4>(t, colA, colB, As, Bs, a, x_real); break;
+            case 21: verify_real_mfma_tile<4, 1>(t, colA, colB, As, Bs, a, x_real); break;
+            case 22: verify_real_mfma_tile<4, 2>(t, colA, colB, As, Bs, a, x_real); break;
+            case 23: verify_real_mfma_tile<4, 3>(t, colA, colB, As, Bs, a, x_real); break;
+            case 24: verify_real_mfma_tile<4, 4>(t, colA, colB, As, Bs, a, x_real); break;
+            default: break;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
 {
     __shared__ double As[TILE][CR + 1];
@@ -2490,8 +2652,11 @@ hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
 
 hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStream_t st)
 {
-    if (a.ntiles + a.nsmall == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_verify_real, dim3(grid), dim3(64), 0, st, a, x_real);
+    if (a.ntiles + a.nsmall > 0)
+        hipLaunchKernelGGL(k_verify_real, dim3(grid), dim3(64), 0, st, a, x_real);
+    if (a.nmfma > 0)
+        hipLaunchKernelGGL(k_verify_real_mfma, dim3((unsigned)std::min<uint64_t>(a.nmfma, (uint64_t)grid)), dim3(64), 0,
+                           st, a, x_real);
     return hipGetLastError();
 }
 

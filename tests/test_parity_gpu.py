@@ -325,3 +325,24 @@ def test_bruteforce_real_data(ctx):
     ref = oracle.brute(d.XT, d.Y, 0.2)
     assert np.array_equal(res["pairs"][["j", "k"]], ref[["j", "k"]])
     assert np.allclose(res["pairs"]["value"], ref["value"], rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("n,p,m,two,xbin", [
+    (200, 300, 2, False, False),
+    (100, 200, 1, False, False),
+    (150, 400, 3, True, False),
+    (190, 350, 2, False, True),
+])
+def test_real_large_buckets_matrix_tiles(ctx, n, p, m, two, xbin):
+    """Buckets of 40-150 columns: products larger than one 32 x 32 tile on both
+    sides are verified in 64 x 64 tiles on the FP64 matrix cores (every fragment
+    count 1-4 per side, diagonal tiles of a bucket's own pairs, ragged edges)."""
+    d = synthgen.small_continuous(n, p, seed=5, planted=[(0, 1)], noise=0.8)
+    XT = d.XT
+    if xbin:
+        XT = np.where(d.XT < 0, -1, 1).astype(np.int8)
+    x = ctx.x_create(XT)
+    res = ctx.search(x, d.Y, m=m, L=2, kappa=0.05, seed=1, two_sided=two)
+    rp, rr = oracle.search(XT, d.Y, m, 2, 0.05, seed=1, two_sided=two)
+    assert_same_real(res, rp, rr, 0.05, n)
+    assert len(rp) > 1000
