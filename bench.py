@@ -613,8 +613,7 @@ def continuous_leg(ctx):
                                          "achieved": flops / (tm["verify_ms"] * 1e-3) / 1e12,
                                          "peak": PEAK_FP64_TFLOPS,
                                          "frac": flops / (tm["verify_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}}
-    import paper_1610_05108_amd as xyz
-    xyz.xyz_x_destroy(x)
+    ctx.x_destroy(x)
     return out
 
 
@@ -628,7 +627,6 @@ def lasso_leg(ctx, ps, n=1000, settings=(1, 2), nlam=12):
     of the 10 true interactions and 20 main effects the final model holds."""
     import torch
     import synthgen
-    import paper_1610_05108_amd as xyz
     from paper_1610_05108_amd.lasso import lasso_interactions, xyz_screen
     out = []
     for setting in settings:
@@ -652,7 +650,7 @@ def lasso_leg(ctx, ps, n=1000, settings=(1, 2), nlam=12):
                              "kkt_rounds": int(sum(path.rounds))}
             log(f"lasso: {row}")
             out.append(row)
-            xyz.xyz_x_destroy(x)
+            ctx.x_destroy(x)
     return {"experiment": "Lasso with all interactions, KKT screening by xyz (Section 5.4, Algorithm 3)",
             "data": "synthetic, settings 1-2 of Section 5.4", "points": out}
 

@@ -428,6 +428,15 @@ class Context:
         self._xs.append(x)
         return x
 
+    def x_destroy(self, x):
+        """Free a matrix made by x_create (once: close() no longer frees it)."""
+        for q, h in enumerate(self._xs):
+            if h == x:
+                del self._xs[q]
+                xyz_x_destroy(x)
+                return
+        raise XyzError(XYZ_EINVAL, "matrix not owned by this context")
+
     def search(self, x, Y, **kw):
         return xyz_search(self.h, x, Y, **kw)
 
