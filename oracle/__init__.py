@@ -169,3 +169,6 @@ def brute(XT, Y, kappa: float, two_sided: bool = False):
     if rc != 0:
         raise OracleError(f"xo_brute failed ({rc})")
     return _take_pairs(out.value, cnt.value)
+
+
+from . import dense  # noqa: E402,F401  (Algorithm 1 with dense projections)

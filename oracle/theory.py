@@ -108,3 +108,40 @@ def gamma_unbiased(XT: np.ndarray, Y: np.ndarray, j: int, k: int, scale: bool = 
     if scale:
         w = w * np.max(np.abs(X), axis=0) ** 2
     return 0.5 + num / (2.0 * float(w.sum()))
+
+
+# ------------------------------------------------------------------
+# Section 5.1: dense Gaussian projections against minimal subsampling at an
+# equal budget (the mean size of E_1 is p when every pair has strength 1/2),
+# one repetition.
+
+def M_minimal(p: int) -> int:
+    """Section 5.1: subsample size M = ceil(log(1/p) / log(1/2)) of minimal subsampling."""
+    return int(math.ceil(math.log(1.0 / p) / math.log(0.5) - 1e-12))
+
+
+def eta_minimal(gamma: float, p: int) -> float:
+    """Section 5.1 with eq. (9), L = 1: minimal subsampling finds a pair of strength gamma with
+    probability gamma^M, M = M_minimal(p)."""
+    return gamma ** M_minimal(p)
+
+
+def tau_gauss(p: int, n: int, sd: float = 1.0) -> float:
+    """Section 5.1: the close-pairs threshold of dense Gaussian projections, the (1/p)-quantile of
+    |W| for the projected distance W = x_j - z_k of a pair of strength 1/2.  For +-1 data
+    X_j - Z_k is 0 on agreeing rows and +-2 elsewhere, so with R ~ N(0, sd^2 I) the distance is
+    exactly N(0, 4 n (1 - gamma) sd^2); the paper writes the variance as n (1 - gamma), a
+    different unit that cancels from eta_gauss.  P(|W| <= tau) = erf(tau / (sigma sqrt 2))."""
+    from scipy.special import erfinv
+    sigma = math.sqrt(4.0 * n * 0.5) * sd
+    return sigma * math.sqrt(2.0) * float(erfinv(1.0 / p))
+
+
+def eta_gauss(gamma: float, p: int) -> float:
+    """Section 5.1: probability that dense Gaussian projections with tau = tau_gauss(p, n) put a
+    pair of strength gamma into E_1, P(|W| <= tau) for W ~ N(0, 4 n (1 - gamma)); the sd ratio
+    sqrt((1 - gamma) / (1/2)) leaves erf(erfinv(1/p) sqrt(0.5 / (1 - gamma))), free of n."""
+    from scipy.special import erfinv
+    if gamma >= 1.0:
+        return 1.0
+    return math.erf(float(erfinv(1.0 / p)) * math.sqrt(0.5 / (1.0 - gamma)))

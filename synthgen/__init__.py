@@ -29,7 +29,7 @@ __all__ = [
     "Dataset", "rademacher", "genotype", "gaussian",
     "config1", "config2", "config3", "config4", "config5_shared", "config5_requests",
     "config5_fresh", "small_binary", "small_continuous", "rows_table", "pack_bits_colmajor",
-    "scaling_x", "scaling_y", "lasso_setting",
+    "scaling_x", "scaling_y", "lasso_setting", "gaussian_projections", "subsample_projections",
 ]
 
 
@@ -424,3 +424,38 @@ def rows_table(n: int, L: int, m: int, seed: int) -> np.ndarray:
     """
     r = _rng(seed, 31)
     return r.integers(0, n, size=(L, m), dtype=np.int32)
+
+
+def gaussian_projections(n: int, L: int, seed: int, frac_bits: int | None = None):
+    """L dense Gaussian projection vectors on a fixed-point grid: R[l, i] =
+    round(2^frac_bits G), G ~ N(0, 1) clipped to [-8, 8], as int32 (L, n).
+
+    The default grid 2^frac_bits <= 2^30 / n keeps sum_i |R[l, i]| below 2^31
+    (the bound under which integer projections of +-1 data cannot overflow
+    32 bits).  Returns (R, sd) with sd = 2^frac_bits, the scale of one unit
+    normal on the grid.
+    """
+    if frac_bits is None:
+        frac_bits = max(0, int(np.floor(np.log2((1 << 30) / max(n, 1)))))
+    r = _rng(seed, 41)
+    g = np.clip(r.standard_normal(size=(L, n)), -8.0, 8.0)
+    R = np.rint(g * float(1 << frac_bits)).astype(np.int32)
+    return R, float(1 << frac_bits)
+
+
+def subsample_projections(n: int, L: int, M: int, seed: int, bits: int = 20):
+    """L sparse projection vectors built from subsampled rows: M row indices per
+    vector drawn uniformly with replacement, each given a weight D of random
+    sign and magnitude uniform in [2^bits, 2^(bits+1)); weights of a repeated
+    row add up.  Returns (R (L, n), rows int32 (L, M), D (L, M)), int32 for
+    bits <= 20 (then M <= 512 keeps sum_i |R[l, i]| below 2^31), else int64."""
+    if bits <= 20 and M > 512:
+        raise ValueError("M <= 512")
+    r = _rng(seed, 42)
+    rows = r.integers(0, n, size=(L, M), dtype=np.int32)
+    D = r.integers(1 << bits, 1 << (bits + 1), size=(L, M), dtype=np.int64) * np.where(r.random((L, M)) < 0.5, -1, 1)
+    R = np.zeros((L, n), dtype=np.int64)
+    for l in range(L):
+        np.add.at(R[l], rows[l], D[l])
+    dt = np.int32 if bits <= 20 else np.int64
+    return R.astype(dt), rows, D.astype(dt)
