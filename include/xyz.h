@@ -180,6 +180,33 @@ xyz_status xyz_bruteforce(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt,
                           uint32_t flags, const int32_t *colsA, int64_t nA, const int32_t *colsB,
                           int64_t nB, void *stream, xyz_result **out);
 
+/* --------------------------------------------------- dense projections --
+ * Algorithm 1 (Section 2.1) with a dense projection vector per repetition
+ * (class (a) of Section 2.1), the scheme that Section 5.1 and Theorem 1
+ * compare with minimal subsampling.  Repetition l projects the columns of X
+ * and of Z = Y o X onto R_l, x = X^T R_l and z = Z^T R_l; E_l holds the ordered
+ * pairs (j, k), j != k, with |x_j - z_k| <= tau; every unordered pair {j, k}
+ * with (j, k) or (k, j) in E_l is checked once against eq. (1) (strict
+ * Y^T(X_j o X_k)/n > kappa) and kept pairs are reported as (min, max).
+ *
+ * X: resident, +-1 (XYZ_X_I8_PM1 or XYZ_X_BITS; float X is XYZ_EUNSUPPORTED).
+ * Y: n entries, XYZ_Y_I8_PM1 only, host or device memory per mem.
+ * R: host array of L * n int32 weights, repetition l uses R[l*n .. l*n+n-1]:
+ *    the projection vector on a fixed-point grid chosen by the caller (for a
+ *    Gaussian F, round(2^b N(0, 1))).  sum_i |R[l*n+i]| must not exceed
+ *    2^31 - 1 (XYZ_EINVAL otherwise): projections are then exact int32 sums, so
+ *    E_l does not depend on summation order.  Copied before the call returns.
+ * tau: close-pairs threshold on the same grid, >= 0.  L >= 1; rep_offset >= 0
+ *    numbers the repetitions (first_rep) as in xyz_search.
+ * flags: XYZ_PROFILE only (others: XYZ_EUNSUPPORTED).
+ * Result: pairs as from xyz_search (s exact); per repetition, candidates =
+ * unordered pairs checked, passed, fresh, cmask = 0 and max_bucket = the
+ * largest window max_j |{k : |x_j - z_k| <= tau}| (k = j included).  The
+ * caller frees it with xyz_result_free. */
+xyz_status xyz_dense_search(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem, const int32_t *R,
+                            int32_t L, int64_t tau, double kappa, int32_t rep_offset, uint32_t flags, void *stream,
+                            xyz_result **out);
+
 /* ---------------------------------------------------- parameter choice --
  * Section 2.3: a pair of strength gamma (eq. (3); gamma = (1 + s/n)/2 by
  * eq. (4)) lands in E_l with probability gamma^m, so it is found within L

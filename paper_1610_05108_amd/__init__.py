@@ -34,7 +34,7 @@ REP_DTYPE = np.dtype([("candidates", np.int64), ("passed", np.int64), ("fresh", 
 
 EXPORTS = [
     "xyz_version", "xyz_last_error", "xyz_init", "xyz_fini", "xyz_ctx_bytes", "xyz_x_create", "xyz_x_destroy",
-    "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_bruteforce", "xyz_result_npairs",
+    "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_bruteforce", "xyz_dense_search", "xyz_result_npairs",
     "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_free", "xyz_smin",
     "xyz_eta", "xyz_L_for", "xyz_m_for_L", "xyz_mstar", "xyz_sample_strengths", "xyz_plan",
     "xyz_serve_start", "xyz_serve_submit", "xyz_serve_poll", "xyz_serve_wait", "xyz_serve_cancel",
@@ -106,6 +106,8 @@ def lib():
         "xyz_search_batch": (I32, [P, P, I32, ctypes.POINTER(P), ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(xyz_params), P, ctypes.POINTER(P)]),
         "xyz_bruteforce": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, D, U32, P, I64, P, I64, P, ctypes.POINTER(P)]),
+        "xyz_dense_search": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, P, I32, I64, D, I32, U32, P,
+                                   ctypes.POINTER(P)]),
         "xyz_result_npairs": (I64, [P]),
         "xyz_result_pairs": (P, [P]),
         "xyz_result_nreps": (I32, [P]),
@@ -307,6 +309,23 @@ def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
     return [_take_result(outs[q]) for q in range(nY)]
 
 
+def xyz_dense_search(ctx, x, Y, R, tau: int, kappa: float, rep_offset: int = 0, profile: bool = False,
+                     stream=None):
+    """Algorithm 1 with dense projections: R is (L, n) int32 (one projection vector
+    per repetition, sum |R_l| < 2^31), tau the close-pairs threshold on R's grid.
+    Returns {'pairs', 'reps', 'timing'} as xyz_search."""
+    Rv = np.ascontiguousarray(R, dtype=np.int32)
+    if Rv.ndim != 2:
+        raise ValueError("R must be (L, n)")
+    ptr, mem, keep = _ptr(Y)
+    h = ctypes.c_void_p()
+    _check(lib().xyz_dense_search(ctx, x, ptr, _y_format(Y), mem, Rv.ctypes.data, Rv.shape[0], int(tau),
+                                  float(kappa), int(rep_offset), XYZ_PROFILE if profile else 0,
+                                  _stream(stream, Y), ctypes.byref(h)))
+    del keep
+    return _take_result(h)
+
+
 def xyz_bruteforce(ctx, x, Y, kappa: float, colsA=None, colsB=None, two_sided: bool = False,
                    profile: bool = False, stream=None):
     """Exact eq. (1) over colsA x colsB (all columns when None)."""
@@ -442,6 +461,9 @@ class Context:
 
     def search_batch(self, x, Ys, params, stream=None):
         return xyz_search_batch(self.h, x, Ys, params, stream=stream)
+
+    def dense_search(self, x, Y, R, tau, kappa, **kw):
+        return xyz_dense_search(self.h, x, Y, R, tau, kappa, **kw)
 
     def bruteforce(self, x, Y, kappa, **kw):
         return xyz_bruteforce(self.h, x, Y, kappa, **kw)

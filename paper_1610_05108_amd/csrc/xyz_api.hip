@@ -402,6 +402,30 @@ xyz_status pack_ys(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, i
     return XYZ_OK;
 }
 
+xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_offset, const Survivor *surv,
+                         uint64_t S, RepInfo *info, Timer &tm, xyz_timing &timing, double t0, hipStream_t st,
+                         xyz_result **outs);
+
+// The survivor buffer overflowed (cnt records for capacity *cap): grow it, keep the first
+// `done` records (earlier chunks), and reset the device count to `done` so that the chunk
+// can be run again.
+xyz_status grow_survivors(xyz_ctx *c, unsigned long long cnt, uint64_t done, unsigned long long *scnt,
+                          Survivor **surv, uint64_t *cap, hipStream_t st)
+{
+    const uint64_t ncap = std::max<uint64_t>(cnt + cnt / 2, *cap * 2);
+    Survivor *tmp = nullptr;
+    XYZ_TRY(ws(c, WS_SURV2, done, &tmp));
+    if (done) HIP_TRY(hipMemcpyAsync(tmp, *surv, done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(ws(c, WS_SURV, ncap, surv));
+    if (done) HIP_TRY(hipMemcpyAsync(*surv, tmp, done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
+    *cap = ncap;
+    const unsigned long long keep = done;
+    HIP_TRY(hipMemcpyAsync(scnt, &keep, sizeof keep, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return XYZ_OK;
+}
+
 // One group of searches sharing X, m, L, seed, rep_offset and flags.  With
 // nys > 1 every Y must be +-1 and no row table may be given, so the row draws,
 // projections and bucket sort are shared (Z = Y o X changes only the partner mask).
@@ -608,18 +632,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             if (cnt > surv_cap) {
-                // grow the survivor buffer, keep what earlier chunks found, and redo this chunk
-                uint64_t ncap = std::max<uint64_t>(cnt + cnt / 2, surv_cap * 2);
-                Survivor *tmp = nullptr;
-                XYZ_TRY(ws(c, WS_SURV2, surv_done, &tmp));
-                if (surv_done) HIP_TRY(hipMemcpyAsync(tmp, surv, surv_done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
-                HIP_TRY(hipStreamSynchronize(st));
-                XYZ_TRY(ws(c, WS_SURV, ncap, &surv));
-                if (surv_done) HIP_TRY(hipMemcpyAsync(surv, tmp, surv_done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
-                surv_cap = ncap;
-                const unsigned long long keep = surv_done;
-                HIP_TRY(hipMemcpyAsync(scnt, &keep, sizeof keep, hipMemcpyHostToDevice, st));
-                HIP_TRY(hipStreamSynchronize(st));
+                XYZ_TRY(grow_survivors(c, cnt, surv_done, scnt, &surv, &surv_cap, st));
                 redo = true;
             } else {
                 surv_done = cnt;
@@ -628,7 +641,19 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     }
 
     // ---- merge repetitions
-    const uint64_t S = surv_done;
+    return merge_results(c, x, nys, L, P.rep_offset, surv, surv_done, info, tm, timing, t0, st, outs);
+}
+
+namespace {
+
+// Merge the S survivors of a finished search into one result per response: unique pairs
+// sorted by (j, k) with their first repetition and hits (Algorithm 2, "add to I"), and the
+// per-repetition statistics of info [L][nys].
+xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_offset, const Survivor *surv,
+                         uint64_t S, RepInfo *info, Timer &tm, xyz_timing &timing, double t0, hipStream_t st,
+                         xyz_result **outs)
+{
+    const int64_t n = x->n, p = x->p;
     uint64_t *dk = nullptr, *dk2 = nullptr;
     uint32_t *dv = nullptr, *dv2 = nullptr, *hist = nullptr, *heads = nullptr;
     OutPair *dout = nullptr;
@@ -645,7 +670,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     HIP_TRY(hipMemsetAsync(ycnt, 0, sizeof(unsigned long long) * nys, st));
     tm.begin(6);
     HIP_TRY(launch_dedup(surv, S, p, n, nys, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info,
-                         (int64_t)P.rep_offset, st));
+                         (int64_t)rep_offset, st));
     tm.end();
     unsigned long long U = 0;
     std::vector<unsigned long long> hy(nys);
@@ -684,6 +709,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     }
     return XYZ_OK;
 }
+
+}  // namespace
 
 extern "C" xyz_status xyz_search(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem,
                                  const xyz_params *params, void *stream, xyz_result **out)
@@ -1141,4 +1168,115 @@ extern "C" xyz_status xyz_plan(xyz_ctx *c, const xyz_x *x, const void *Y, int yf
     }
     *out = best;
     return XYZ_OK;
+}
+
+extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem,
+                                       const int32_t *R, int32_t L, int64_t tau, double kappa, int32_t rep_offset,
+                                       uint32_t flags, void *stream, xyz_result **out)
+{
+    if (!c || !x || !Y || !R || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
+    if (L < 1) return fail(XYZ_EINVAL, "L=%d < 1", (int)L);
+    if (tau < 0) return fail(XYZ_EINVAL, "tau=%lld < 0", (long long)tau);
+    if (!std::isfinite(kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
+    if (rep_offset < 0) return fail(XYZ_EINVAL, "rep_offset=%d < 0", (int)rep_offset);
+    if (flags & ~XYZ_PROFILE) return fail(XYZ_EUNSUPPORTED, "the dense search takes XYZ_PROFILE only");
+    if (x->fmt == XYZ_X_F32) return fail(XYZ_EUNSUPPORTED, "the dense search takes +-1 X");
+    if (yfmt != XYZ_Y_I8_PM1) return fail(XYZ_EUNSUPPORTED, "the dense search takes +-1 Y");
+    const int64_t n = x->n, p = x->p;
+    for (int64_t l = 0; l < L; ++l) {
+        int64_t a = 0;
+        for (int64_t i = 0; i < n; ++i) a += R[l * n + i] < 0 ? -(int64_t)R[l * n + i] : (int64_t)R[l * n + i];
+        if (a > INT32_MAX)
+            return fail(XYZ_EINVAL, "sum of |R| of repetition %lld is %lld > 2^31 - 1", (long long)l, (long long)a);
+    }
+    const int64_t taub = std::min<int64_t>(tau, 1ll << 33);   // |x_j - z_k| < 2^32 always
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const double t0 = now_ms();
+    Timer tm;
+    tm.on = (flags & XYZ_PROFILE) != 0;
+    tm.st = st;
+    xyz_timing timing{};
+
+    uint32_t *yb = nullptr;
+    double *yd = nullptr;
+    int *err = nullptr;
+    tm.begin(0);
+    const void *ys[1] = {Y};
+    XYZ_TRY(pack_ys(c, x, 1, ys, yfmt, mem, st, &yb, &yd, &err));
+    tm.end();
+    XYZ_TRY(check_err_flag(err, st));
+    const int64_t smin = xyz_smin(n, kappa, 0);
+
+    // repetitions in chunks of whole projection groups: 32 bytes per (repetition, column)
+    const int G = dense_group_reps();
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(256, (1ll << 30) / (32 * p)));
+    if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
+    if (chunk >= G) chunk -= chunk % G;
+    chunk = std::min<int64_t>(chunk, L);
+    const int64_t ngrp = (chunk + G - 1) / G;
+    RepInfo *info = nullptr;
+    int32_t *dR = nullptr, *dW = nullptr, *drs = nullptr, *xs = nullptr, *zs = nullptr;
+    uint64_t *K = nullptr, *K2 = nullptr;
+    uint32_t *V = nullptr, *V2 = nullptr, *hist = nullptr;
+    unsigned long long *scnt = nullptr;
+    XYZ_TRY(ws(c, WS_INFO, (size_t)L, &info));
+    XYZ_TRY(ws(c, WS_DPR, (size_t)(chunk * n), &dR));
+    XYZ_TRY(ws(c, WS_DPW, (size_t)(ngrp * G * n * 2), &dW));
+    XYZ_TRY(ws(c, WS_DPRS, (size_t)(2 * chunk), &drs));
+    XYZ_TRY(ws(c, WS_DPX, (size_t)(chunk * p), &xs));
+    XYZ_TRY(ws(c, WS_DPZ, (size_t)(chunk * p), &zs));
+    XYZ_TRY(ws(c, WS_SKK, (size_t)(chunk * p), &K));
+    XYZ_TRY(ws(c, WS_SKK2, (size_t)(chunk * p), &K2));
+    XYZ_TRY(ws(c, WS_SKV, (size_t)(chunk * p), &V));
+    XYZ_TRY(ws(c, WS_SKV2, (size_t)(chunk * p), &V2));
+    XYZ_TRY(ws(c, WS_SKHIST, radix_hist_entries((uint64_t)(chunk * p)), &hist));
+    XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
+    HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo) * L, st));
+    HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
+    uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
+    Survivor *surv = nullptr;
+    XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
+    uint64_t surv_done = 0;
+
+    for (int64_t r0 = 0; r0 < L; r0 += chunk) {
+        const int nr = (int)std::min<int64_t>(chunk, L - r0);
+        RepInfo *cinfo = info + r0;
+        tm.begin(1);
+        HIP_TRY(hipMemcpyAsync(dR, R + r0 * n, sizeof(int32_t) * nr * n, hipMemcpyHostToDevice, st));
+        tm.end();
+        tm.begin(2);
+        HIP_TRY(launch_dense_project(x->XR, x->P64, p, n, dR, nr, yb, dW, drs, drs + chunk, xs, zs, K, V, c->cu_count,
+                                     st));
+        tm.end();
+        int rbits = 0;
+        while ((1 << rbits) < nr) ++rbits;
+        uint64_t *Ks = nullptr;
+        uint32_t *Vs = nullptr;
+        tm.begin(3);
+        HIP_TRY(launch_radix_sort(K, V, K2, V2, (uint64_t)nr * p, 32 + rbits, hist, &Ks, &Vs, st));
+        tm.end();
+        for (bool redo = true; redo;) {
+            redo = false;
+            HIP_TRY(hipMemsetAsync(cinfo, 0, sizeof(RepInfo) * nr, st));
+            tm.begin(5);
+            HIP_TRY(launch_dense_verify(xs, zs, Ks, Vs, p, nr, taub, x->XC, x->W32p, yb, n, smin,
+                                        (int64_t)rep_offset + r0, surv, scnt, surv_cap, cinfo, st));
+            tm.end();
+            timing.verify_launches += 1;
+            unsigned long long cnt = 0;
+            HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (cnt > surv_cap) {
+                XYZ_TRY(grow_survivors(c, cnt, surv_done, scnt, &surv, &surv_cap, st));
+                redo = true;
+            } else {
+                surv_done = cnt;
+            }
+        }
+    }
+    return merge_results(c, x, 1, L, rep_offset, surv, surv_done, info, tm, timing, t0, st, out);
 }

@@ -233,6 +233,29 @@ hipError_t launch_pair_strengths(const uint32_t *XC, int W32p, const uint32_t *y
 
 // Radix histogram scratch size (u32 entries) for S items.
 size_t radix_hist_entries(uint64_t S);
+// Stable LSD radix sort of S (key, value) pairs on the low `bits` bits of the keys, ping-ponging
+// between (K, V) and (K2, V2); hist holds radix_hist_entries(S) u32.  *Kout / *Vout name the
+// buffers that hold the sorted sequence.
+hipError_t launch_radix_sort(uint64_t *K, uint32_t *V, uint64_t *K2, uint32_t *V2, uint64_t S, int bits,
+                             uint32_t *hist, uint64_t **Kout, uint32_t **Vout, hipStream_t st);
+
+// ------------------------------------------- dense projections (Algorithm 1) --
+// Repetitions processed per projection pass; the weight buffer W of launch_dense_project holds
+// ceil(nrep / dense_group_reps()) * dense_group_reps() * n * 2 int32.
+int dense_group_reps();
+// x = X^T R_r and z = (Y o X)^T R_r (int32, exact when sum_i |R_r,i| < 2^31) for the nrep rows of
+// R [nrep][n] (device), into xs / zs [nrep][p]; sort keys K [nrep][p] = (r << 32) | (z + 2^31)
+// with the column id in V.  Scratch: W (see above), rs / rys [nrep].
+hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int64_t n, const int32_t *R, int nrep,
+                                const uint32_t *yb, int32_t *W, int32_t *rs, int32_t *rys, int32_t *xs, int32_t *zs,
+                                uint64_t *K, uint32_t *V, int cu_count, hipStream_t st);
+// E_r = {(j, k) : |x_j - z_k| <= tau} from the sorted keys Ks / column ids Vs of each repetition,
+// and the check s >= smin of every unordered pair of E_r u E_r^T (j != k) once.  Survivors as
+// in launch_verify_bin; info[r].candidates / passed / max_bucket (largest window) accumulate.
+hipError_t launch_dense_verify(const int32_t *xs, const int32_t *zs, const uint64_t *Ks, const uint32_t *Vs,
+                               int64_t p, int nrep, int64_t tau, const uint32_t *XC, int W32p, const uint32_t *yb,
+                               int64_t n, int64_t smin, int64_t rep_abs0, Survivor *surv,
+                               unsigned long long *surv_count, uint64_t surv_cap, RepInfo *info, hipStream_t st);
 // Set kernel attributes (large dynamic LDS); called once per device.
 hipError_t kernels_init();
 

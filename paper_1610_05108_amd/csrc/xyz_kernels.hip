@@ -2740,13 +2740,21 @@ hipError_t launch_sk_sort(const uint32_t *keys, int64_t p, int m, int nrep, uint
     hipLaunchKernelGGL(k_sk_init, dim3(grid1(S, 256)), dim3(256), 0, st, keys, S, p, m, K, V);
     int rbits = 0;
     while ((1ll << rbits) < nrep) ++rbits;
-    const int bits = m + rbits;
+    uint32_t *Vs = nullptr;
+    hipError_t e = launch_radix_sort(K, V, K2, V2, S, m + rbits, hist, Ksorted, &Vs, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(perm, Vs, sizeof(uint32_t) * S, hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t launch_radix_sort(uint64_t *K, uint32_t *V, uint64_t *K2, uint32_t *V2, uint64_t S, int bits,
+                             uint32_t *hist, uint64_t **Kout, uint32_t **Vout, hipStream_t st)
+{
     const uint32_t nb = (uint32_t)((S + RS_TILE - 1) / RS_TILE);
     const uint64_t hent = 256ull * nb;
     uint32_t *partial = hist + hent;
     uint64_t *ka = K, *kb = K2;
     uint32_t *va = V, *vb = V2;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = 0; S > 0 && shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_NT), 0, st, ka, S, shift, hist, nb);
         hipError_t e = scan_u32(hist, hent, partial, st);
         if (e != hipSuccess) return e;
@@ -2754,8 +2762,9 @@ hipError_t launch_sk_sort(const uint32_t *keys, int64_t p, int m, int nrep, uint
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
-    *Ksorted = ka;
-    return hipMemcpyAsync(perm, va, sizeof(uint32_t) * S, hipMemcpyDeviceToDevice, st);
+    *Kout = ka;
+    *Vout = va;
+    return hipGetLastError();
 }
 
 hipError_t launch_sk_runs(const uint64_t *K, uint64_t S, uint32_t *heads, uint32_t *partial, uint64_t *run_key,
