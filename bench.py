@@ -21,8 +21,9 @@ search space, as in the paper's "interactions screened").  Beside the timed
 steps it reports the large Rademacher workload (xyz against the exact
 search), the continuous workload (sign and unbiased transforms), the serving
 stream and the CPU oracle's rate on a bounded sample.  Separate modes:
---scaling-law (Section 5.2), --lasso (Section 5.4), --calibrate-copy (the
-reference for the HBM byte counters).
+--scaling-law (Section 5.2), --lasso (Section 5.4), --dense (Section 5.1:
+dense Gaussian projections against minimal subsampling), --calibrate-copy
+(the reference for the HBM byte counters).
 """
 from __future__ import annotations
 
@@ -113,6 +114,9 @@ def main():
     ap.add_argument("--lasso", action="store_true",
                     help="only run the regression experiment of Section 5.4 (Lasso with all interactions)")
     ap.add_argument("--lasso-p", type=str, default="250,500,1000")
+    ap.add_argument("--dense", action="store_true",
+                    help="only Section 5.1: dense Gaussian projections vs minimal subsampling")
+    ap.add_argument("--dense-p", type=str, default="1000,10000,100000,1000000")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -132,6 +136,11 @@ def main():
         out = scaling_law_leg(ctx, args.scaling_n, [int(v) for v in args.scaling_p.split(",")],
                               [float(v) for v in args.scaling_gamma.split(",")], args.scaling_sims)
         print(json.dumps(out), flush=True)
+        return
+    if args.dense:
+        import paper_1610_05108_amd as xyz
+        ctx = xyz.Context(0)
+        print(json.dumps(dense_leg(ctx, [int(v) for v in args.dense_p.split(",")])), flush=True)
         return
     if args.lasso:
         import paper_1610_05108_amd as xyz
@@ -615,6 +624,71 @@ def continuous_leg(ctx):
                                          "frac": flops / (tm["verify_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}}
     ctx.x_destroy(x)
     return out
+
+
+def dense_leg(ctx, ps, n=1000, gammas=(0.7, 0.8, 0.9), per=300, target_hits=40, max_reps=20000):
+    """Section 5.1 on the GPU: dense Gaussian projections (Algorithm 1,
+    xyz_dense_search, tau = xyz_tau_dense for a mean |E_1| of p ordered pairs
+    when every strength is 1/2) against minimal subsampling (Algorithm 2,
+    xyz_search, M = ceil(log2 p)), on +-1 data with `per` planted pairs of each
+    strength in `gammas` against one Y (n = 1000 as in Section 5.1).  A
+    repetition discovers a pair when its candidates hold it: for dense
+    projections either orientation, predicted 1 - (1 - eta_dense)^2; for
+    minimal subsampling E_l is symmetric and the rate is gamma^M.  Reports the
+    measured and predicted rates, candidates per repetition, GPU time per
+    repetition (warm, whole call / L) and the time to discovery, time per
+    repetition / rate."""
+    import torch
+    import synthgen
+    import paper_1610_05108_amd as xyz
+    out = []
+    for p in ps:
+        per_p = min(per, p // (4 * len(gammas)))         # planted pairs use at most half of the columns
+        XT, Y, pairs = synthgen.strength_pairs(n, p, gammas, per_p, seed=p)
+        x = ctx.x_create(XT)
+        kappa = 2.0 * min(gammas) - 1.0 - 0.05        # planted pairs pass; random pairs are 11 sd below
+        M = int(math.ceil(math.log2(p) - 1e-9))
+        g0 = min(gammas)
+        row = {"p": p, "n": n, "M": M, "pairs_per_strength": per_p}
+
+        def rates(res, L):
+            hits = {(int(a), int(b)): int(h) for a, b, h in zip(res["pairs"]["j"], res["pairs"]["k"],
+                                                                   res["pairs"]["hits"])}
+            return {str(g): sum(hits.get((j, k), 0) for j, k, gg in pairs if gg == g) / (per_p * L) for g in gammas}
+
+        # dense Gaussian projections
+        rate0 = 1.0 - (1.0 - xyz.xyz_eta_dense(g0, p)) ** 2
+        L = int(min(max_reps, max(16, math.ceil(target_hits / (per_p * rate0)))))
+        R, sd = synthgen.gaussian_projections(n, L, seed=p + 1)
+        tau = int(round(xyz.xyz_tau_dense(p, n, sd)))
+        ctx.dense_search(x, Y, R[:8], tau, kappa)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.dense_search(x, Y, R, tau, kappa)
+        dt = time.perf_counter() - t0
+        meas = rates(res, L)
+        row["dense"] = {"L": L, "tau": tau, "sd": sd, "ms_per_rep": 1e3 * dt / L,
+                        "candidates_per_rep": float(res["reps"]["candidates"].mean()),
+                        "rate": meas,
+                        "rate_predicted": {str(g): 1.0 - (1.0 - xyz.xyz_eta_dense(g, p)) ** 2 for g in gammas}}
+        # minimal subsampling
+        L = int(min(max_reps, max(16, math.ceil(target_hits / (per_p * g0 ** M)))))
+        ctx.search(x, Y, m=M, L=min(L, 8), kappa=kappa, seed=5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.search(x, Y, m=M, L=L, kappa=kappa, seed=7)
+        dt = time.perf_counter() - t0
+        row["minimal"] = {"L": L, "ms_per_rep": 1e3 * dt / L,
+                          "candidates_per_rep": float(res["reps"]["candidates"].mean()),
+                          "rate": rates(res, L), "rate_predicted": {str(g): g ** M for g in gammas}}
+        for key in ("dense", "minimal"):
+            e = row[key]
+            e["ms_to_discovery"] = {g: (e["ms_per_rep"] / r if r > 0 else None) for g, r in e["rate"].items()}
+        log(f"dense vs minimal: {row}")
+        out.append(row)
+        ctx.x_destroy(x)
+    return {"experiment": "dense Gaussian projections vs minimal subsampling at equal budget (Section 5.1)",
+            "data": "synthetic +-1, planted pairs of exact strength", "points": out}
 
 
 def lasso_leg(ctx, ps, n=1000, settings=(1, 2), nlam=12):

@@ -225,6 +225,17 @@ int32_t xyz_m_for_L(double gamma, int64_t L, double eta, int32_t m_max);
 int32_t xyz_mstar(double gamma, int64_t n, int64_t p, const double *gammas, int64_t ns, double total_pairs,
                   int32_t m_max);
 
+/* Section 5.1, dense Gaussian projections at the budget of minimal subsampling (the mean
+ * size of E_1 is p when every pair has strength 1/2), for +-1 data and R ~ N(0, sd^2 I): the
+ * projected distance x_j - z_k of a pair of strength gamma is exactly N(0, 4 n (1 - gamma) sd^2).
+ * xyz_tau_dense: the threshold tau with P(|x_j - z_k| <= tau) = 1/p at gamma = 1/2 (the
+ * (1/p)-quantile of |W|); NAN unless p >= 2, n >= 1, sd > 0.
+ * xyz_eta_dense: the probability that the ordered pair (j, k) of strength gamma lands in E_1
+ * at that tau, erf(erfinv(1/p) sqrt(1/2 / (1 - gamma))), free of n; NAN unless p >= 2 and
+ * 0 <= gamma <= 1. */
+double xyz_tau_dense(int64_t p, int64_t n, double sd);
+double xyz_eta_dense(double gamma, int64_t p);
+
 /* Strengths of npairs column pairs drawn uniformly (j != k) with SplitMix64(seed): gamma = fraction of rows
  * with sgn(Y_i) = X~_ij X~_ik, weighted by |Y_i|/||Y||_1 for real Y (the collision probability of one row
  * draw, Section 3.1).  out: host array of npairs doubles. */

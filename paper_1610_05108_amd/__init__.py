@@ -36,7 +36,8 @@ EXPORTS = [
     "xyz_version", "xyz_last_error", "xyz_init", "xyz_fini", "xyz_ctx_bytes", "xyz_x_create", "xyz_x_destroy",
     "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_bruteforce", "xyz_dense_search", "xyz_result_npairs",
     "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_free", "xyz_smin",
-    "xyz_eta", "xyz_L_for", "xyz_m_for_L", "xyz_mstar", "xyz_sample_strengths", "xyz_plan",
+    "xyz_eta", "xyz_tau_dense", "xyz_eta_dense", "xyz_L_for", "xyz_m_for_L", "xyz_mstar",
+    "xyz_sample_strengths", "xyz_plan",
     "xyz_serve_start", "xyz_serve_submit", "xyz_serve_poll", "xyz_serve_wait", "xyz_serve_cancel",
     "xyz_serve_stats_get", "xyz_serve_stop",
 ]
@@ -116,6 +117,8 @@ def lib():
         "xyz_result_free": (None, [P]),
         "xyz_smin": (I64, [I64, D, ctypes.c_int]),
         "xyz_eta": (D, [D, I32, I64]),
+        "xyz_tau_dense": (D, [I64, I64, D]),
+        "xyz_eta_dense": (D, [D, I64]),
         "xyz_L_for": (I64, [D, D]),
         "xyz_m_for_L": (I32, [D, I64, D, I32]),
         "xyz_mstar": (I32, [D, I64, I64, P, I64, D, I32]),
@@ -344,6 +347,14 @@ def xyz_bruteforce(ctx, x, Y, kappa: float, colsA=None, colsB=None, two_sided: b
 
 def xyz_eta(gamma: float, m: int, L: int) -> float:
     return float(lib().xyz_eta(float(gamma), int(m), int(L)))
+
+
+def xyz_tau_dense(p: int, n: int, sd: float = 1.0) -> float:
+    return float(lib().xyz_tau_dense(int(p), int(n), float(sd)))
+
+
+def xyz_eta_dense(gamma: float, p: int) -> float:
+    return float(lib().xyz_eta_dense(float(gamma), int(p)))
 
 
 def xyz_L_for(eta: float, beta: float) -> int:

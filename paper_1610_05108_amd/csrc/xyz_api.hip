@@ -993,6 +993,38 @@ extern "C" double xyz_eta(double gamma, int32_t m, int64_t L)
     return 1.0 - std::pow(1.0 - std::pow(gamma, (double)m), (double)L);
 }
 
+namespace {
+
+// erf^{-1}(y) for y in (0, 1/2]: Newton's method on erf(x) - y (derivative 2/sqrt(pi) exp(-x^2))
+// from the first term of the series, x = y sqrt(pi) / 2; erf is concave on x > 0, so the
+// iterates increase monotonically to the root.
+double erf_inv_small(double y)
+{
+    double x = y * 0.88622692545275801365;
+    for (int it = 0; it < 60; ++it) {
+        const double d = (std::erf(x) - y) / (1.12837916709551257390 * std::exp(-x * x));
+        x -= d;
+        if (std::fabs(d) <= 1e-17 * x) break;
+    }
+    return x;
+}
+
+}  // namespace
+
+extern "C" double xyz_tau_dense(int64_t p, int64_t n, double sd)
+{
+    if (p < 2 || n < 1 || !(sd > 0.0) || !std::isfinite(sd)) return NAN;
+    // W ~ N(0, 4 n (1 - 1/2) sd^2): P(|W| <= tau) = erf(tau / (sd sqrt(2n) sqrt 2)) = 1/p
+    return 2.0 * std::sqrt((double)n) * sd * erf_inv_small(1.0 / (double)p);
+}
+
+extern "C" double xyz_eta_dense(double gamma, int64_t p)
+{
+    if (p < 2 || !(gamma >= 0.0 && gamma <= 1.0)) return NAN;
+    if (gamma >= 1.0) return 1.0;
+    return std::erf(erf_inv_small(1.0 / (double)p) * std::sqrt(0.5 / (1.0 - gamma)));
+}
+
 extern "C" int64_t xyz_L_for(double eta, double beta)
 {
     if (!(eta > 0.0 && eta < 1.0) || !(beta > 0.0) || beta > 1.0) return -1;

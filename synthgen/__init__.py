@@ -30,6 +30,7 @@ __all__ = [
     "config1", "config2", "config3", "config4", "config5_shared", "config5_requests",
     "config5_fresh", "small_binary", "small_continuous", "rows_table", "pack_bits_colmajor",
     "scaling_x", "scaling_y", "lasso_setting", "gaussian_projections", "subsample_projections",
+    "strength_pairs",
 ]
 
 
@@ -459,3 +460,34 @@ def subsample_projections(n: int, L: int, M: int, seed: int, bits: int = 20):
         np.add.at(R[l], rows[l], D[l])
     dt = np.int32 if bits <= 20 else np.int64
     return R.astype(dt), rows, D.astype(dt)
+
+
+def strength_pairs(n: int, p: int, gammas, per: int, seed: int):
+    """+-1 data with `per` disjoint planted pairs of each strength gamma in
+    `gammas` against one Y: columns 2q and 2q + 1 form pair q; X_{2q+1} equals
+    Y o X_{2q} on round(gamma n) rows and its negation on the others (half of
+    those rows with Y = +1 and half with Y = -1, as far as possible).  The
+    remaining columns are Rademacher.  Returns (XT (p, n) int8, Y (n,) int8,
+    pairs [(j, k, gamma)])."""
+    r = _rng(seed, 43)
+    XT = rademacher(n, p, seed)
+    Y = np.where(r.random(n) < 0.5, 1, -1).astype(np.int8)
+    pos, neg = np.flatnonzero(Y == 1), np.flatnonzero(Y == -1)
+    pairs = []
+    q = 0
+    for g in gammas:
+        dis_n = n - int(round(g * n))
+        for _ in range(per):
+            j, k = 2 * q, 2 * q + 1
+            if k >= p:
+                raise ValueError("p too small for the planted pairs")
+            a = min(dis_n // 2, len(pos))
+            b = min(dis_n - a, len(neg))
+            dis = np.zeros(n, dtype=bool)
+            dis[r.choice(pos, a, replace=False)] = True
+            dis[r.choice(neg, b, replace=False)] = True
+            dis[r.choice(np.flatnonzero(~dis), dis_n - a - b, replace=False)] = True
+            XT[k] = np.where(dis, -Y * XT[j], Y * XT[j]).astype(np.int8)
+            pairs.append((j, k, float(g)))
+            q += 1
+    return XT, Y, pairs

@@ -1,6 +1,7 @@
 """Host-side checks of libxyz that need no GPU: the shared library loads,
 exports every function include/xyz.h declares, and its host logic (the
 integer threshold of eq. (1)) agrees with the definition."""
+import math
 import os
 import re
 
@@ -91,3 +92,14 @@ def test_mstar_matches_oracle():
         for gamma in (0.6, 0.75, 0.85, 0.95):
             total = float(p) * p
             assert xyz.xyz_mstar(gamma, n, p, g, total) == theory.M_star(gamma, n, p, g, total, M_max=64)
+
+
+@pytest.mark.parametrize("p", [2, 10, 1000, 10**6, 10**9])
+def test_dense_tau_eta_match_closed_forms(p):
+    """Section 5.1 parameter choice of the library against the oracle's closed forms (scipy's erfinv)."""
+    for n, sd in ((1000, 1.0), (77, 65536.0)):
+        assert xyz.xyz_tau_dense(p, n, sd) == pytest.approx(theory.tau_gauss(p, n, sd), rel=1e-12)
+    for g in (0.0, 0.3, 0.5, 0.7, 0.9, 0.999):
+        assert xyz.xyz_eta_dense(g, p) == pytest.approx(theory.eta_gauss(g, p), rel=1e-12, abs=1e-300)
+    assert xyz.xyz_eta_dense(1.0, p) == 1.0
+    assert math.isnan(xyz.xyz_tau_dense(1, 10, 1.0)) and math.isnan(xyz.xyz_eta_dense(1.5, p))
