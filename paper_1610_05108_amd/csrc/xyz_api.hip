@@ -1266,6 +1266,8 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
     XYZ_TRY(ws(c, WS_SKV, (size_t)(chunk * p), &V));
     XYZ_TRY(ws(c, WS_SKV2, (size_t)(chunk * p), &V2));
     XYZ_TRY(ws(c, WS_SKHIST, radix_hist_entries((uint64_t)(chunk * p)), &hist));
+    uint32_t *didx = nullptr;
+    XYZ_TRY(ws(c, WS_DPI, (size_t)chunk * (dense_index_buckets(p) + 1), &didx));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
     HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo) * L, st));
     HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
@@ -1295,7 +1297,7 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
             redo = false;
             HIP_TRY(hipMemsetAsync(cinfo, 0, sizeof(RepInfo) * nr, st));
             tm.begin(5);
-            HIP_TRY(launch_dense_verify(xs, zs, Ks, Vs, p, nr, taub, x->XC, x->W32p, yb, n, smin,
+            HIP_TRY(launch_dense_verify(xs, zs, Ks, Vs, didx, p, nr, taub, x->XC, x->W32p, yb, n, smin,
                                         (int64_t)rep_offset + r0, surv, scnt, surv_cap, cinfo, st));
             tm.end();
             timing.verify_launches += 1;

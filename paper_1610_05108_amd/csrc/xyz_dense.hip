@@ -7,7 +7,7 @@
 //     z_j = sum_i Y_i R_i - 2 sum_{i : X_ij = -1} Y_i R_i,
 // exact in int32 because the caller bounds sum_i |R_i| below 2^31.  The z of a
 // repetition are sorted (with the column ids), and column j walks the window of
-// sorted z with |x_j - z_k| <= tau, found by two binary searches: that is E_l.
+// sorted z with |x_j - z_k| <= tau, starting from an index of the sorted z: that is E_l.
 // Each unordered pair {j, k} of E_l u E_l^T is checked once, from the side that
 // owns it (j when (j, k) is in E_l and, if k < j, (k, j) is not), by
 // s = n - 2 popcount(y ^ x_j ^ x_k) against the integer threshold of eq. (1).
@@ -143,13 +143,49 @@ namespace {
 
 __device__ __forceinline__ int32_t dp_zval(uint64_t key) { return (int32_t)((uint32_t)key ^ 0x80000000u); }
 
-// First position t in [0, p) of the sorted keys Ks with z >= v (p if none).
-__device__ __forceinline__ uint32_t dp_first_ge(const uint64_t *Ks, uint32_t p, int64_t v)
+// Buckets of the index: nb equal slices of [zmin, zmax]; bucket(v) is non-decreasing in v.
+__device__ __forceinline__ uint32_t dp_bucket(int64_t v, int64_t zmin, uint64_t range, uint32_t nb)
 {
-    uint32_t lo = 0, hi = p;
+    return (uint32_t)((uint64_t)(v - zmin) * nb / range);
+}
+
+}  // namespace
+
+// Index of each repetition's sorted z: idx[rep][b] = first position t with bucket(z_t) >= b
+// (b = 0 .. nb; idx[rep][nb] = p).  Thread t writes the entries of the buckets in
+// (bucket(z_{t-1}), bucket(z_t)], so that every entry is written once.
+__global__ __launch_bounds__(256) void k_dense_index(const uint64_t *__restrict__ Ks, int64_t p, uint32_t nb,
+                                                     uint32_t *__restrict__ idx)
+{
+    const int rep = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= p) return;
+    const uint64_t *K = Ks + (int64_t)rep * p;
+    uint32_t *ix = idx + (int64_t)rep * (nb + 1);
+    const int64_t zmin = dp_zval(K[0]), zmax = dp_zval(K[p - 1]);
+    const uint64_t range = (uint64_t)(zmax - zmin) + 1;
+    const uint32_t b = dp_bucket(dp_zval(K[t]), zmin, range, nb);
+    const int64_t b0 = t == 0 ? -1 : (int64_t)dp_bucket(dp_zval(K[t - 1]), zmin, range, nb);
+    for (int64_t q = b0 + 1; q <= (int64_t)b; ++q) ix[q] = (uint32_t)t;
+    if (t == p - 1)
+        for (int64_t q = (int64_t)b + 1; q <= (int64_t)nb; ++q) ix[q] = (uint32_t)p;
+}
+
+namespace {
+
+// First position t in [0, p) of a repetition's sorted keys K with z >= v (p if none), via the
+// index: the position lies in [ix[bucket(v)], ix[bucket(v) + 1]].
+__device__ __forceinline__ uint32_t dp_first_ge(const uint64_t *K, const uint32_t *ix, uint32_t p, uint32_t nb,
+                                                int64_t zmin, int64_t zmax, int64_t v)
+{
+    if (v <= zmin) return 0;
+    if (v > zmax) return p;
+    const uint64_t range = (uint64_t)(zmax - zmin) + 1;
+    const uint32_t b = dp_bucket(v, zmin, range, nb);
+    uint32_t lo = ix[b], hi = ix[b + 1];
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if ((int64_t)dp_zval(Ks[mid]) < v) lo = mid + 1;
+        if ((int64_t)dp_zval(K[mid]) < v) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -158,10 +194,13 @@ __device__ __forceinline__ uint32_t dp_first_ge(const uint64_t *Ks, uint32_t p, 
 }  // namespace
 
 // E_l and its check.  Grid (ceil(p / 256), nrep): thread (rep, j) walks the window of the
-// repetition's sorted z with |x_j - z_k| <= tau.
+// repetition's sorted z with |x_j - z_k| <= tau: its start from the index and a binary
+// search inside one bucket, its end by walking while z_k <= x_j + tau.
 __global__ __launch_bounds__(256) void k_dense_verify(const int32_t *__restrict__ xs, const int32_t *__restrict__ zs,
                                                       const uint64_t *__restrict__ Ks,
-                                                      const uint32_t *__restrict__ Vs, int64_t p, int64_t tau,
+                                                      const uint32_t *__restrict__ Vs,
+                                                      const uint32_t *__restrict__ idx, uint32_t nb, int64_t p,
+                                                      int64_t tau,
                                                       const uint32_t *__restrict__ XC, int W32p,
                                                       const uint32_t *__restrict__ yb, int64_t n, int64_t smin,
                                                       int64_t rep_abs0, Survivor *__restrict__ surv,
@@ -176,13 +215,15 @@ __global__ __launch_bounds__(256) void k_dense_verify(const int32_t *__restrict_
     if (j < p) {
         const int32_t xj = xs[base + j], zj = zs[base + j];
         const uint64_t *K = Ks + base;
-        const uint32_t lo = dp_first_ge(K, (uint32_t)p, (int64_t)xj - tau);
-        const uint32_t hi = dp_first_ge(K, (uint32_t)p, (int64_t)xj + tau + 1);
-        window = hi > lo ? hi - lo : 0;
+        const int64_t zmin = dp_zval(K[0]), zmax = dp_zval(K[p - 1]);
+        const int64_t zhi = (int64_t)xj + tau;
+        const uint32_t lo = dp_first_ge(K, idx + (int64_t)rep * (nb + 1), (uint32_t)p, nb, zmin, zmax,
+                                        (int64_t)xj - tau);
         const uint4 *xj4 = reinterpret_cast<const uint4 *>(XC + j * (int64_t)W32p);
         const uint4 *y4 = reinterpret_cast<const uint4 *>(yb);
         const int W4 = W32p >> 2;
-        for (uint32_t t = lo; t < hi; ++t) {
+        uint32_t t = lo;
+        for (; t < (uint32_t)p && (int64_t)dp_zval(K[t]) <= zhi; ++t) {
             const uint32_t k = Vs[base + t];
             if ((int64_t)k == j) continue;
             if ((int64_t)k < j) {                  // (k, j) in E_l as well: the pair is k's
@@ -214,6 +255,7 @@ __global__ __launch_bounds__(256) void k_dense_verify(const int32_t *__restrict_
                 }
             }
         }
+        window = t - lo;
     }
     for (int d = 32; d >= 1; d >>= 1) {
         cand += __shfl_xor(cand, d, 64);
@@ -255,14 +297,19 @@ hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int6
     return hipGetLastError();
 }
 
+uint32_t dense_index_buckets(int64_t p) { return (uint32_t)std::max<int64_t>(1, p / 4); }
+
 hipError_t launch_dense_verify(const int32_t *xs, const int32_t *zs, const uint64_t *Ks, const uint32_t *Vs,
-                               int64_t p, int nrep, int64_t tau, const uint32_t *XC, int W32p, const uint32_t *yb,
-                               int64_t n, int64_t smin, int64_t rep_abs0, Survivor *surv,
+                               uint32_t *idx, int64_t p, int nrep, int64_t tau, const uint32_t *XC, int W32p,
+                               const uint32_t *yb, int64_t n, int64_t smin, int64_t rep_abs0, Survivor *surv,
                                unsigned long long *surv_count, uint64_t surv_cap, RepInfo *info, hipStream_t st)
 {
     if (nrep <= 0 || p <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dense_verify, dim3((unsigned)((p + 255) / 256), (unsigned)nrep), dim3(256), 0, st, xs, zs,
-                       Ks, Vs, p, tau, XC, W32p, yb, n, smin, rep_abs0, surv, surv_count, surv_cap, info);
+    const uint32_t nb = dense_index_buckets(p);
+    const dim3 grid((unsigned)((p + 255) / 256), (unsigned)nrep);
+    hipLaunchKernelGGL(k_dense_index, grid, dim3(256), 0, st, Ks, p, nb, idx);
+    hipLaunchKernelGGL(k_dense_verify, grid, dim3(256), 0, st, xs, zs, Ks, Vs, idx, nb, p, tau, XC, W32p, yb, n, smin,
+                       rep_abs0, surv, surv_count, surv_cap, info);
     return hipGetLastError();
 }
 

@@ -249,12 +249,14 @@ int dense_group_reps();
 hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int64_t n, const int32_t *R, int nrep,
                                 const uint32_t *yb, int32_t *W, int32_t *rs, int32_t *rys, int32_t *xs, int32_t *zs,
                                 uint64_t *K, uint32_t *V, int cu_count, hipStream_t st);
+// Buckets of the per-repetition index of the sorted z (idx holds nrep * (buckets + 1) u32).
+uint32_t dense_index_buckets(int64_t p);
 // E_r = {(j, k) : |x_j - z_k| <= tau} from the sorted keys Ks / column ids Vs of each repetition,
 // and the check s >= smin of every unordered pair of E_r u E_r^T (j != k) once.  Survivors as
 // in launch_verify_bin; info[r].candidates / passed / max_bucket (largest window) accumulate.
 hipError_t launch_dense_verify(const int32_t *xs, const int32_t *zs, const uint64_t *Ks, const uint32_t *Vs,
-                               int64_t p, int nrep, int64_t tau, const uint32_t *XC, int W32p, const uint32_t *yb,
-                               int64_t n, int64_t smin, int64_t rep_abs0, Survivor *surv,
+                               uint32_t *idx, int64_t p, int nrep, int64_t tau, const uint32_t *XC, int W32p,
+                               const uint32_t *yb, int64_t n, int64_t smin, int64_t rep_abs0, Survivor *surv,
                                unsigned long long *surv_count, uint64_t surv_cap, RepInfo *info, hipStream_t st);
 // Set kernel attributes (large dynamic LDS); called once per device.
 hipError_t kernels_init();
