@@ -143,10 +143,13 @@ namespace {
 
 __device__ __forceinline__ int32_t dp_zval(uint64_t key) { return (int32_t)((uint32_t)key ^ 0x80000000u); }
 
-// Buckets of the index: nb equal slices of [zmin, zmax]; bucket(v) is non-decreasing in v.
-__device__ __forceinline__ uint32_t dp_bucket(int64_t v, int64_t zmin, uint64_t range, uint32_t nb)
+// Buckets of the index: nb equal slices of [zmin, zmax], bucket(v) = floor((v - zmin) scale)
+// with scale = nb / (zmax - zmin + 1) in binary64 (v - zmin < 2^33 is exact; rounding keeps the
+// map non-decreasing in v, and both the index and the search use this one function).
+__device__ __forceinline__ uint32_t dp_bucket(int64_t v, int64_t zmin, double scale, uint32_t nb)
 {
-    return (uint32_t)((uint64_t)(v - zmin) * nb / range);
+    const uint32_t b = (uint32_t)((double)(v - zmin) * scale);
+    return b < nb ? b : nb - 1;
 }
 
 }  // namespace
@@ -163,9 +166,9 @@ __global__ __launch_bounds__(256) void k_dense_index(const uint64_t *__restrict_
     const uint64_t *K = Ks + (int64_t)rep * p;
     uint32_t *ix = idx + (int64_t)rep * (nb + 1);
     const int64_t zmin = dp_zval(K[0]), zmax = dp_zval(K[p - 1]);
-    const uint64_t range = (uint64_t)(zmax - zmin) + 1;
-    const uint32_t b = dp_bucket(dp_zval(K[t]), zmin, range, nb);
-    const int64_t b0 = t == 0 ? -1 : (int64_t)dp_bucket(dp_zval(K[t - 1]), zmin, range, nb);
+    const double scale = (double)nb / ((double)(zmax - zmin) + 1.0);
+    const uint32_t b = dp_bucket(dp_zval(K[t]), zmin, scale, nb);
+    const int64_t b0 = t == 0 ? -1 : (int64_t)dp_bucket(dp_zval(K[t - 1]), zmin, scale, nb);
     for (int64_t q = b0 + 1; q <= (int64_t)b; ++q) ix[q] = (uint32_t)t;
     if (t == p - 1)
         for (int64_t q = (int64_t)b + 1; q <= (int64_t)nb; ++q) ix[q] = (uint32_t)p;
@@ -180,8 +183,7 @@ __device__ __forceinline__ uint32_t dp_first_ge(const uint64_t *K, const uint32_
 {
     if (v <= zmin) return 0;
     if (v > zmax) return p;
-    const uint64_t range = (uint64_t)(zmax - zmin) + 1;
-    const uint32_t b = dp_bucket(v, zmin, range, nb);
+    const uint32_t b = dp_bucket(v, zmin, (double)nb / ((double)(zmax - zmin) + 1.0), nb);
     uint32_t lo = ix[b], hi = ix[b + 1];
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
