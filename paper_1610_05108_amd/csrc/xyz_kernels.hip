@@ -2306,6 +2306,7 @@ __global__ __launch_bounds__(256) void k_pair_strengths(const uint32_t *__restri
 // ------------------------------------------------------- scan, radix sort --
 
 constexpr int RS_NT = 256, RS_IPT = 8, RS_TILE = RS_NT * RS_IPT;
+constexpr uint64_t RS_SMALL = 32768;   // survivor counts merged by one workgroup
 
 __global__ __launch_bounds__(RS_NT) void k_scan_reduce(const uint32_t *__restrict__ in, uint64_t cnt,
                                                        uint32_t *__restrict__ partial)
@@ -2443,16 +2444,14 @@ __global__ __launch_bounds__(256) void k_dedup_heads(const uint64_t *__restrict_
     heads[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_dedup_emit(const uint64_t *__restrict__ keys,
-                                                    const uint32_t *__restrict__ vals,
-                                                    const Survivor *__restrict__ surv, uint64_t S,
-                                                    const uint32_t *__restrict__ heads_scan, int64_t n, int nys,
-                                                    OutPair *__restrict__ out, unsigned long long *__restrict__ ycount,
-                                                    RepInfo *__restrict__ info, int64_t rep_abs0)
+// The unique pair whose first sorted record is at position i goes to out[u]: first repetition,
+// hits, and the per-response and per-repetition counters (lanes with equal targets add once).
+// Called by the lanes that hold a head only.
+XYZ_DEV void dedup_emit_head(uint64_t i, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                             const Survivor *__restrict__ surv, uint64_t S, uint64_t u, int64_t n, int nys,
+                             OutPair *__restrict__ out, unsigned long long *__restrict__ ycount,
+                             RepInfo *__restrict__ info, int64_t rep_abs0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S) return;
-    if (i != 0 && keys[i] == keys[i - 1]) return;
     const Survivor s0 = surv[vals[i]];
     uint32_t first = s0.rep;
     int32_t hits = 0;
@@ -2468,7 +2467,6 @@ __global__ __launch_bounds__(256) void k_dedup_emit(const uint64_t *__restrict__
     o.stat = __ddiv_rn(s0.value, (double)n);
     o.first_rep = (int32_t)first;
     o.hits = hits;
-    const uint32_t u = heads_scan[i];
     out[u] = o;
     // per-response and per-repetition counters: lanes with equal targets add once
     unsigned long long todo = __ballot(1);
@@ -2492,6 +2490,133 @@ __global__ __launch_bounds__(256) void k_dedup_emit(const uint64_t *__restrict__
             atomicAdd(&info[(int64_t)(v >> 8) * nys + (int64_t)(v & 255)].fresh, (unsigned long long)__popcll(same));
         left &= ~same;
     }
+}
+
+__global__ __launch_bounds__(256) void k_dedup_emit(const uint64_t *__restrict__ keys,
+                                                    const uint32_t *__restrict__ vals,
+                                                    const Survivor *__restrict__ surv, uint64_t S,
+                                                    const uint32_t *__restrict__ heads_scan, int64_t n, int nys,
+                                                    OutPair *__restrict__ out, unsigned long long *__restrict__ ycount,
+                                                    RepInfo *__restrict__ info, int64_t rep_abs0)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    if (i != 0 && keys[i] == keys[i - 1]) return;
+    dedup_emit_head(i, keys, vals, surv, S, heads_scan[i], n, nys, out, ycount, info, rep_abs0);
+}
+
+// Merges of at most RS_SMALL survivors run in one workgroup each: the sort's passes and the
+// heads' prefix sum stay inside one launch instead of a few launches per pass.
+constexpr int RSS_NT = 1024;
+
+// Stable LSD radix sort of S (key, value) pairs on the low `bits` bits, 8 bits per pass, by one
+// workgroup: items are taken in index order, RSS_NT per step, each ranked among equal digits
+// by (count in earlier waves of the step) + (rank among its wave's peers, 8 ballots).
+// Ping-pongs between (k0, v0) and (k1, v1): the result is in (k0, v0) after an even number of
+// passes, else in (k1, v1).
+__global__ __launch_bounds__(RSS_NT) void k_rs_sort_small(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                                                          uint32_t S, int bits)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[RSS_NT / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        if (tid < 256) run[tid] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < S; i += RSS_NT) atomicAdd(&run[(uint32_t)(ka[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (tid < 64) {                              // exclusive scan of the 256 counts by one wave
+            const uint32_t c0 = run[4 * tid], c1 = run[4 * tid + 1], c2 = run[4 * tid + 2], c3 = run[4 * tid + 3];
+            const uint32_t sum = c0 + c1 + c2 + c3;
+            uint32_t inc = sum;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = __shfl_up(inc, d, 64);
+                if (tid >= d) inc += t;
+            }
+            const uint32_t ex = inc - sum;
+            run[4 * tid] = ex;
+            run[4 * tid + 1] = ex + c0;
+            run[4 * tid + 2] = ex + c0 + c1;
+            run[4 * tid + 3] = ex + c0 + c1 + c2;
+        }
+        __syncthreads();
+        for (uint32_t base = 0; base < S; base += RSS_NT) {
+#pragma unroll
+            for (int q = 0; q < RSS_NT / 64 / 4; ++q) wcnt[(tid >> 8) + 4 * q][tid & 255] = 0;
+            __syncthreads();
+            const uint32_t i = base + tid;
+            const bool valid = i < S;
+            uint64_t k = 0;
+            uint32_t v = 0, d = 0;
+            if (valid) {
+                k = ka[i];
+                v = va[i];
+                d = (uint32_t)(k >> shift) & 255u;
+            }
+            unsigned long long peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const unsigned long long bal = __ballot(valid && bit);
+                peers &= bit ? bal : ~bal;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+            if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = run[d] + rank;
+                for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+                kb[pos] = k;
+                vb[pos] = v;
+            }
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t add = 0;
+#pragma unroll
+                for (int q = 0; q < RSS_NT / 64; ++q) add += wcnt[q][tid];
+                run[tid] += add;
+            }
+            __syncthreads();
+        }
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+}
+
+// Heads of the sorted keys, their prefix sum and the unique pairs, by one workgroup.
+__global__ __launch_bounds__(RSS_NT) void k_dedup_small(const uint64_t *__restrict__ keys,
+                                                        const uint32_t *__restrict__ vals,
+                                                        const Survivor *__restrict__ surv, uint32_t S, int64_t n,
+                                                        int nys, OutPair *__restrict__ out,
+                                                        unsigned long long *__restrict__ nout,
+                                                        unsigned long long *__restrict__ ycount,
+                                                        RepInfo *__restrict__ info, int64_t rep_abs0)
+{
+    __shared__ uint32_t wsum[RSS_NT / 64];
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint32_t u0 = 0;
+    for (uint32_t base = 0; base < S; base += RSS_NT) {
+        const uint32_t i = base + tid;
+        const bool head = i < S && (i == 0 || keys[i] != keys[i - 1]);
+        const unsigned long long hb = __ballot(head);
+        if ((tid & 63) == 0) wsum[w] = (uint32_t)__popcll(hb);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int q = 0; q < RSS_NT / 64; ++q) {
+            const uint32_t c = wsum[q];
+            before += q < w ? c : 0u;
+            total += c;
+        }
+        if (head)
+            dedup_emit_head(i, keys, vals, surv, S, u0 + before + (uint32_t)__popcll(hb & lanemask_lt()), n, nys, out,
+                            ycount, info, rep_abs0);
+        u0 += total;
+        __syncthreads();
+    }
+    if (tid == 0) *nout = u0;
 }
 
 __global__ void k_dedup_count(const uint32_t *__restrict__ heads_scan, const uint64_t *__restrict__ keys, uint64_t S,
@@ -2825,6 +2950,13 @@ hipError_t launch_dedup(const Survivor *surv, uint64_t S, int64_t p, int64_t n, 
     const double span = (double)nys * (double)p * (double)p;
     int bits = 1;
     while (bits < 64 && (double)(1ull << bits) < span) ++bits;
+    if (S <= RS_SMALL) {
+        hipLaunchKernelGGL(k_rs_sort_small, dim3(1), dim3(RSS_NT), 0, st, keys, vals, keys2, vals2, (uint32_t)S, bits);
+        const bool odd = ((bits + 7) / 8) & 1;
+        hipLaunchKernelGGL(k_dedup_small, dim3(1), dim3(RSS_NT), 0, st, odd ? keys2 : keys, odd ? vals2 : vals, surv,
+                           (uint32_t)S, n, nys, out, nout, ycount, info, rep_abs0);
+        return hipGetLastError();
+    }
     const uint32_t nb = (uint32_t)((S + RS_TILE - 1) / RS_TILE);
     const uint64_t hent = 256ull * nb;
     uint32_t *partial = hist + hent;
