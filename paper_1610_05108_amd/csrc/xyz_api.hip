@@ -169,16 +169,21 @@ xyz_status ws(xyz_ctx *c, int slot, size_t count, T **out)
     return XYZ_OK;
 }
 
-xyz_status check_err_flag(int *d_err, hipStream_t st)
+xyz_status err_flag_status(int h)
 {
-    int h = 0;
-    HIP_TRY(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
     if (h & 1) return fail(XYZ_EINVAL, "X holds a value other than -1 or +1");
     if (h & 2) return fail(XYZ_EINVAL, "X holds NaN or Inf");
     if (h & 4) return fail(XYZ_EINVAL, "Y holds an invalid value (not +-1 for the +-1 format, or NaN/Inf)");
     if (h & 8) return fail(XYZ_EINVAL, "Y is zero everywhere: the |Y|-weighted sampler has no row to draw");
     return XYZ_OK;
+}
+
+xyz_status check_err_flag(int *d_err, hipStream_t st)
+{
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return err_flag_status(h);
 }
 
 double now_ms()
@@ -848,7 +853,8 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     tm.begin(0);
     XYZ_TRY(pack_ys(c, x, 1, ys, yfmt, mem, st, &yb, &yd, &err));
     tm.end();
-    XYZ_TRY(check_err_flag(err, st));
+    // the packing's error flag is read back with the survivor counts below (no wait here)
+    int herr = 0;
     int32_t *dA = nullptr, *dB = nullptr;
     if (colsA) {
         XYZ_TRY(ws(c, WS_ROWS, (size_t)nA + (colsB ? nB : 0), &dA));
@@ -921,7 +927,9 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
         tm.end();
         timing.verify_launches += 1;
         HIP_TRY(hipMemcpyAsync(hcnt.data(), wcnt, sizeof(unsigned int) * grid, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        XYZ_TRY(err_flag_status(herr));
         uint64_t mx = 0;
         S = 0;
         for (unsigned int v : hcnt) {

@@ -89,3 +89,23 @@ def test_empty_inputs_rejected(ctx):
         ctx.x_create(np.zeros((0, 10), dtype=np.int8))
     with pytest.raises(xyz.XyzError):
         ctx.x_create(np.zeros((10, 0), dtype=np.int8))
+
+
+def test_bruteforce_rejects_bad_y_then_recovers(ctx):
+    """An invalid response (0 in +-1 data, NaN in float data) is an error of the exact
+    search, reported after its kernels ran; the next call on the same context is exact."""
+    d = synthgen.small_binary(90, 70, seed=31, planted=[(2, 3)])
+    x = ctx.x_create(d.XT)
+    bad = d.Y.copy()
+    bad[5] = 0
+    with pytest.raises(xyz.XyzError):
+        ctx.bruteforce(x, bad, 0.1)
+    yf = d.Y.astype(np.float32)
+    yf[3] = np.nan
+    with pytest.raises(xyz.XyzError):
+        ctx.bruteforce(x, yf, 0.1)
+    got = ctx.bruteforce(x, d.Y, 0.1)
+    want = oracle.brute(d.XT, d.Y, 0.1)
+    assert len(want) > 0
+    for f in ("j", "k", "s"):
+        assert np.array_equal(got["pairs"][f], want[f]), f
