@@ -1193,13 +1193,10 @@ __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
 // same C, as long as both sides use it).  Lanes past the end of a bucket
 // (na, nb < 64) repeat its last column, so their products duplicate real
 // ones; the popcounts |z_a|, |x_b| are taken on the way.  Two stages are in
-// flight per lane.  Accumulator register r of lane l holds A row u*32 + (r/4)*8
-// + (l/32)*4 + r%4 and B column v*32 + l%32.
-struct MStage {
-    uint4 a[4], b[4];        // quad 4s + l/16 of A (B) column 16g + l%16 of the tile
-    uint4 y[2];              // quads 4s + 2h and 4s + 2h + 1 of y
-};
-
+// flight per lane, two waves per SIMD.  A side with at most 32 columns (the
+// remainder of a bucket just over 64 columns, or a bucket of at most 32) takes
+// one fragment row or column only.  Accumulator register r of lane l holds A
+// row u*32 + (r/4)*8 + (l/32)*4 + r%4 and B column v*32 + l%32.
 // v_permlane16_swap on each word: lanes 16-31 and 48-63 of lo trade places with
 // lanes 0-15 and 32-47 of hi.
 XYZ_DEV void swap16(uint4 &lo, uint4 &hi)
@@ -1212,7 +1209,7 @@ XYZ_DEV void swap16(uint4 &lo, uint4 &hi)
     hi = make_uint4(x[1], y[1], z[1], w[1]);
 }
 
-__global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
+__global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
 {
     __shared__ __align__(16) float zpop2[4][MTILE];  // per wave: 2|z_a| of the tile's A columns
     const unsigned lane = lane_id();
@@ -1220,76 +1217,89 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
     const int lc = (int)(lane & 15), lq = (int)(lane >> 4);
     const int wv = (int)(threadIdx.x >> 6);
     const int W4 = a.W32p >> 2;
-    const int NF = W4 >> 2, NS = (W4 + 3) >> 2;      // full stages, all stages
+    const int NS = (W4 + 3) >> 2;                   // stages of four quads
     const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
     const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall);
     const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nwave = (uint64_t)gridDim.x * 4;
     const int32_t n32 = (int32_t)a.n;
-    for (uint64_t ti = wid; ti < a.nmfma; ti += nwave) {
-        const Tile t = tile_from(T4[ti]);
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    // One tile as NU x NV fragments: a side of at most 32 columns takes one fragment row
+    // (column), so that neither its products nor its loads are spent on empty fragments.
+    auto tile_body = [&](const Tile &t, auto nu_c, auto nv_c) {
+        constexpr int NU = decltype(nu_c)::value, NV = decltype(nv_c)::value;
         const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
-        const uint4 *pa[4], *pb[4];
+        const uint4 *pa[2 * NU], *pb[2 * NV];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < 2 * NU; ++g)
             pa[g] = XC4 + (int64_t)a.perm[t.a0 + min(g * 16 + lc, (int)t.na - 1)] * W4;
+#pragma unroll
+        for (int g = 0; g < 2 * NV; ++g)
             pb[g] = XC4 + (int64_t)a.perm[t.b0 + min(g * 16 + lc, (int)t.nb - 1)] * W4;
-        }
-        v16f acc[2][2];
-        uint32_t popa[2] = {0, 0}, popb[2] = {0, 0};
-        auto load = [&](MStage &st, int stg) {
+        v16f acc[NU][NV];
+        uint32_t popa[NU], popb[NV];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) popa[u] = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) popb[v] = 0;
+        struct Stage {
+            uint4 a[2 * NU], b[2 * NV];  // quad 4s + l/16 of A (B) column 16g + l%16 of the tile
+            uint4 y[2];                  // quads 4s + 2h and 4s + 2h + 1 of y
+        };
+        auto load = [&](Stage &st, int stg) {
             const int q0 = 4 * min(stg, NS - 1);
             const int q = min(q0 + lq, W4 - 1);     // clamped: quads past the column are masked
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                st.a[g] = pa[g][q];
-                st.b[g] = pb[g][q];
-            }
+            for (int g = 0; g < 2 * NU; ++g) st.a[g] = pa[g][q];
+#pragma unroll
+            for (int g = 0; g < 2 * NV; ++g) st.b[g] = pb[g][q];
 #pragma unroll
             for (int j = 0; j < 2; ++j) st.y[j] = y4[min(q0 + 2 * h + j, W4 - 1)];
         };
-        // the stage's 8 products per fragment; PART: the last stage, whose quads past W4 count as zero;
-        // FIRST: the first product starts the accumulators
-        auto step = [&](MStage &st, int stg, auto part, auto first) {
+        // the stage's 8 products per fragment (quads past W4 count as zero); FIRST: the first
+        // product starts the accumulators
+        auto step = [&](Stage &st, int stg, auto first) {
             // matrix layout: A[u][j] = quad 4s + 2h + j of A column u*32 + c (B likewise)
-            uint4 A[2][2], B[2][2];
+            uint4 A[NU][2], B[NV][2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < NU; ++u) {
                 A[u][0] = st.a[2 * u];
                 A[u][1] = st.a[2 * u + 1];
                 swap16(A[u][0], A[u][1]);
-                B[u][0] = st.b[2 * u];
-                B[u][1] = st.b[2 * u + 1];
-                swap16(B[u][0], B[u][1]);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                B[v][0] = st.b[2 * v];
+                B[v][1] = st.b[2 * v + 1];
+                swap16(B[v][0], B[v][1]);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const uint32_t keep = (decltype(part)::value && 4 * stg + 2 * h + j >= W4) ? 0u : ~0u;
-                uint4 za[2], xb[2];
+                const uint32_t keep = 4 * stg + 2 * h + j < W4 ? ~0u : 0u;
+                uint4 za[NU], xb[NV];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    za[u] = make_uint4(A[u][j].x ^ st.y[j].x, A[u][j].y ^ st.y[j].y, A[u][j].z ^ st.y[j].z,
-                                       A[u][j].w ^ st.y[j].w);
-                    xb[u] = B[u][j];
-                    if (decltype(part)::value) {
-                        za[u] = make_uint4(za[u].x & keep, za[u].y & keep, za[u].z & keep, za[u].w & keep);
-                        xb[u] = make_uint4(xb[u].x & keep, xb[u].y & keep, xb[u].z & keep, xb[u].w & keep);
-                    }
+                for (int u = 0; u < NU; ++u) {
+                    za[u] = make_uint4((A[u][j].x ^ st.y[j].x) & keep, (A[u][j].y ^ st.y[j].y) & keep,
+                                       (A[u][j].z ^ st.y[j].z) & keep, (A[u][j].w ^ st.y[j].w) & keep);
                     popa[u] = bcnt_acc(za[u].w, bcnt_acc(za[u].z, bcnt_acc(za[u].y, bcnt_acc(za[u].x, popa[u]))));
-                    popb[u] = bcnt_acc(xb[u].w, bcnt_acc(xb[u].z, bcnt_acc(xb[u].y, bcnt_acc(xb[u].x, popb[u]))));
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    xb[v] = make_uint4(B[v][j].x & keep, B[v][j].y & keep, B[v][j].z & keep, B[v][j].w & keep);
+                    popb[v] = bcnt_acc(xb[v].w, bcnt_acc(xb[v].z, bcnt_acc(xb[v].y, bcnt_acc(xb[v].x, popb[v]))));
                 }
                 // one product per bit plane of the quad's four words
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl) {
-                    v8i fa[2], fb[2];
+                    v8i fa[NU], fb[NV];
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        fa[u] = plane_fp4(za[u], pl);
-                        fb[u] = plane_fp4(xb[u], pl);
-                    }
+                    for (int u = 0; u < NU; ++u) fa[u] = plane_fp4(za[u], pl);
 #pragma unroll
-                    for (int u = 0; u < 2; ++u)
+                    for (int v = 0; v < NV; ++v) fb[v] = plane_fp4(xb[v], pl);
 #pragma unroll
-                        for (int v = 0; v < 2; ++v)
+                    for (int u = 0; u < NU; ++u)
+#pragma unroll
+                        for (int v = 0; v < NV; ++v)
                             acc[u][v] = mfma_fp4_plane(fa[u], fb[v],
                                                        (decltype(first)::value && j == 0 && pl == 0) ? v16f{}
                                                                                                     : acc[u][v],
@@ -1299,39 +1309,27 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
             load(st, stg + 2);
             __builtin_amdgcn_sched_barrier(0);
         };
-        using T_ = std::true_type;
-        using F_ = std::false_type;
-        MStage s0, s1;
+        // stage s sits in s0 (even) or s1 (odd)
+        Stage s0, s1;
         load(s0, 0);
         load(s1, 1);
-        // stage s sits in s0 (even) or s1 (odd); full stages first, then the partial one
-        if (NF == 0) {
-            step(s0, 0, T_{}, T_{});
-        } else {
-            step(s0, 0, F_{}, T_{});
-            int stg = 1;
-            for (; stg + 1 < NF; stg += 2) {     // no branches inside: each wait is for the oldest loads only
-                step(s1, stg, F_{}, F_{});
-                step(s0, stg + 1, F_{}, F_{});
-            }
-            if (stg < NF) {
-                step(s1, stg, F_{}, F_{});
-                if (NS > NF) step(s0, stg + 1, T_{}, F_{});
-            } else if (NS > NF) {
-                step(s1, stg, T_{}, F_{});
-            }
+        step(s0, 0, T_{});
+        int stg = 1;
+        for (; stg + 1 < NS; stg += 2) {     // no branches inside: each wait is for the oldest loads only
+            step(s1, stg, F_{});
+            step(s0, stg + 1, F_{});
         }
+        if (stg < NS) step(s1, stg, F_{});
         // whole-column popcounts: the two lane halves of a column hold disjoint words
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            popa[u] += __shfl_xor(popa[u], 32, 64);
-            popb[u] += __shfl_xor(popb[u], 32, 64);
-        }
+        for (int u = 0; u < NU; ++u) popa[u] += __shfl_xor(popa[u], 32, 64);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) popb[v] += __shfl_xor(popb[v], 32, 64);
         // cheap test per fragment: x = 4C - 2|z_a| over the lane's 16 rows against
         // smin - n + 2|x_b| (and -smin - n + 2|x_b| two-sided), exact in FP32
         if (h == 0) {
-            zpop2[wv][c] = (float)(2 * popa[0]);
-            zpop2[wv][32 + c] = (float)(2 * popa[1]);
+#pragma unroll
+            for (int u = 0; u < NU; ++u) zpop2[wv][u * 32 + c] = (float)(2 * popa[u]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1339,7 +1337,7 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
         const int32_t smin = (int32_t)a.smin[t.ysel];
         uint32_t hitmask = 0;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < NU; ++u) {
             float tA[16];
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) {
@@ -1350,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
                 tA[4 * q4 + 3] = v4.w;
             }
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
+            for (int v = 0; v < NV; ++v) {
                 const int32_t pb2 = 2 * (int32_t)popb[v];
                 float mx = -1e30f, mn = 1e30f;
 #pragma unroll
@@ -1365,12 +1363,12 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
         }
         if (__ballot(hitmask != 0) != 0) {
             // rare: exact values and validity (padding rows and columns, a < b on a diagonal tile)
-            uint32_t pm[2][2];
+            uint32_t pm[NU][NV];
             int mine = 0;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < NU; ++u) {
 #pragma unroll
-                for (int v = 0; v < 2; ++v) {
+                for (int v = 0; v < NV; ++v) {
                     const int cb = v * 32 + c;
                     uint32_t m = 0;
                     if ((hitmask >> (u * 2 + v)) & 1u) {
@@ -1391,9 +1389,9 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
             unsigned long long idx = reserve_survivors(a, t, mine);
             if (idx != ~0ull) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < NU; ++u)
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) {
+                    for (int v = 0; v < NV; ++v) {
                         const int cb = v * 32 + c;
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
@@ -1422,6 +1420,16 @@ __global__ __launch_bounds__(256) void k_verify_mfma(VerifyArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    for (uint64_t ti = wid; ti < a.nmfma; ti += nwave) {
+        const Tile t = tile_from(T4[ti]);
+        const bool wa = t.na > 32, wb = t.nb > 32;     // wave-uniform
+        if (wa && wb) tile_body(t, I2{}, I2{});
+        else if (wa) tile_body(t, I2{}, I1{});
+        else if (wb) tile_body(t, I1{}, I2{});
+        else tile_body(t, I1{}, I1{});
     }
 }
 

@@ -346,3 +346,22 @@ def test_real_large_buckets_matrix_tiles(ctx, n, p, m, two, xbin):
     rp, rr = oracle.search(XT, d.Y, m, 2, 0.05, seed=1, two_sided=two)
     assert_same_real(res, rp, rr, 0.05, n)
     assert len(rp) > 1000
+
+
+@pytest.mark.parametrize("n,p,m,L,kappa,two,ybias,seed", [
+    (1000, 2600, 5, 4, 0.12, False, 0.5, 41),   # ~81 columns per bucket: 64 + remainder tiles, all four fragment shapes
+    (300, 3000, 6, 6, 0.2, True, 0.45, 42),     # ~47 per bucket: sides on both sides of 32, two-sided
+    (129, 2900, 5, 3, 0.25, False, 1.0, 43),    # Y = +1: partner mask 0, diagonal tiles; one partial stage
+    (5000, 2100, 5, 2, 0.05, False, 0.5, 44),   # 40 quads per column: many stages
+])
+def test_matrix_tile_fragment_shapes(ctx, n, p, m, L, kappa, two, ybias, seed):
+    """Matrix-core tiles whose sides hold more or fewer than 32 columns (one or two
+    fragment rows / columns per side), remainder tiles of buckets past 64 columns,
+    and diagonal tiles of a bucket's own pairs, bit-exact against the oracle."""
+    planted = [(0, 1), (5, 9)] if ybias < 1.0 else []      # planted pairs would drive Y
+    d = synthgen.small_binary(n, p, seed=seed, planted=planted, flip=0.1, y_bias=ybias)
+    res, rp, rr = run_both(ctx, d.XT, d.Y, m, L, kappa, seed=seed, two_sided=two)
+    assert rr["max_bucket"].max() > 64
+    if ybias == 1.0:
+        assert (rr["cmask"] == 0).all()
+    assert_same_binary(res, rp, rr)
