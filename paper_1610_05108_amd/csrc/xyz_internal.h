@@ -24,12 +24,16 @@ constexpr uint32_t MTILE_MIN_DIAG = 24;
 // Real data: only products too large for one 32 x 32 tile on both sides go to the
 // 64 x 64 FP64 matrix-core tiles (smaller ones pack better into the 32 x 32 tiles).
 constexpr uint32_t MTILE_MIN_REAL = 33;
+// +-1 data: a product with one side of at most MTILE columns and the other of at most
+// MTILE_WIDE is verified as one tile (up to 3 x 2 fragments of 32 x 32), so that neither
+// side is read twice; larger products are cut into MTILE x MTILE tiles.
+constexpr uint32_t MTILE_WIDE = 96;
 
 struct Tile {            // 16 bytes
     uint32_t rep;        // repetition index relative to the launch's first repetition
     uint32_t a0;         // first position of the A block in perm (absolute)
     uint32_t b0;         // first position of the B block in perm (absolute)
-    uint8_t na, nb;      // block sizes (1..TILE, or 1..MTILE for matrix-core tiles)
+    uint8_t na, nb;      // block sizes (1..TILE, or 1..MTILE_WIDE for matrix-core tiles)
     uint8_t diag;        // 1: A and B are the same block of one bucket; keep positions a < b only
     uint8_t ysel;        // response index within a batch
 };

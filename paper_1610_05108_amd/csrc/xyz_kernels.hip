@@ -428,8 +428,16 @@ __global__ __launch_bounds__(256) void k_hash_unbiased(const float *__restrict__
 //   kind 1: one TILE x TILE tile with at most SMALL_TILE_PAIRS pairs (small list),
 //   kind 2: T tiles of TILE x TILE (popcount list),
 //   kind 3: T tiles of MTILE x MTILE for the matrix cores (mfma = 1, +-1 data with
-//           n < 2^24: both sides at least MTILE_MIN columns; mfma = 2, real data:
-//           both sides at least MTILE_MIN_REAL).
+//           n < 2^24: both sides at least MTILE_MIN columns, and a product within
+//           MTILE x MTILE_WIDE is one tile; mfma = 2, real data: both sides at least
+//           MTILE_MIN_REAL).
+// A product of two different buckets that is one matrix-core tile (+-1 data): one side of
+// at most MTILE columns, the other of at most MTILE_WIDE.
+XYZ_DEV bool mfma_single(uint32_t a, uint32_t a2, int mfma)
+{
+    return mfma == 1 && ((a <= (uint32_t)MTILE && a2 <= MTILE_WIDE) || (a <= MTILE_WIDE && a2 <= (uint32_t)MTILE));
+}
+
 XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, int mfma, int &kind,
                                          unsigned long long &T)
 {
@@ -441,7 +449,7 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
         const uint32_t mmin = mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN;
         if (mfma && a >= mmin && a2 >= mmin) {
             kind = 3;
-            T = cdiv_u64(a, MTILE) * cdiv_u64(a2, MTILE);
+            T = mfma_single(a, a2, mfma) ? 1 : cdiv_u64(a, MTILE) * cdiv_u64(a2, MTILE);
         } else if (a <= (uint32_t)TILE && a2 <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
             kind = 1;
             T = 1;
@@ -608,13 +616,29 @@ XYZ_DEV Tile make_tile(uint32_t ts, uint32_t r, uint32_t ysel, uint32_t pbase, u
     return t;
 }
 
-// Tile number t (tiles of ts x ts) of the product of bucket b and its partner b2.
+// The product of two different buckets as one matrix-core tile (mfma_single).
+XYZ_DEV Tile single_tile(uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1, uint32_t a, uint32_t o2, uint32_t a2)
+{
+    Tile t;
+    t.rep = r;
+    t.a0 = pbase + o1;
+    t.b0 = pbase + o2;
+    t.na = (uint8_t)a;
+    t.nb = (uint8_t)a2;
+    t.diag = 0;
+    t.ysel = (uint8_t)ysel;
+    return t;
+}
+
+// Tile number t (tiles of ts x ts, or the one tile of mfma_single) of the product of bucket b
+// and its partner b2.
 XYZ_DEV Tile pair_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t b, uint32_t b2,
-                       const uint32_t *of)
+                       const uint32_t *of, int mfma)
 {
     const uint32_t o1 = of[b], a = of[b + 1] - o1;
     const uint32_t o2 = of[b2], a2 = of[b2 + 1] - o2;
     if (b != b2) {
+        if (ts == (uint32_t)MTILE && mfma_single(a, a2, mfma)) return single_tile(r, ysel, pbase, o1, a, o2, a2);
         const uint32_t nB = (a2 + ts - 1) / ts;
         return make_tile(ts, r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
     }
@@ -688,7 +712,8 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
                 }
             }
             if (h < 0 || h >= HEAVY_CAP)
-                for (unsigned long long t = 0; t < T; ++t) tiles[pos[kind] + t] = pair_tile(ts, t, r, y, pbase, b, b2, of);
+                for (unsigned long long t = 0; t < T; ++t)
+                    tiles[pos[kind] + t] = pair_tile(ts, t, r, y, pbase, b, b2, of, mfma);
             pos[kind] += T;
         }
     }
@@ -697,7 +722,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     for (int h = 0; h < nh; ++h) {
         const unsigned long long T = hcnt_t[h], p0 = hpos[h];
         for (unsigned long long t = threadIdx.x; t < T; t += 256)
-            tiles[p0 + t] = pair_tile(hts[h], t, r, y, pbase, hb[h], hb2[h], of);
+            tiles[p0 + t] = pair_tile(hts[h], t, r, y, pbase, hb[h], hb2[h], of, mfma);
     }
 }
 
@@ -886,6 +911,11 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
                      const uint32_t ts = kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE;
                      const uint32_t o2 = run_start[rid2] - pbase;
                      const bool own = rid2 == rid;
+                     if (kind == 3 && !own && mfma_single(a, a2, mfma)) {
+                         tiles[at[kind]] = single_tile((uint32_t)r, y, pbase, o1, a, o2, a2);
+                         at[kind] += T;
+                         return;
+                     }
                      const uint32_t nB = (a2 + ts - 1) / ts, nA = (a + ts - 1) / ts;
                      for (unsigned long long t = 0; t < T; ++t) {
                          uint32_t ia, ib;
@@ -1193,9 +1223,11 @@ __global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
 // same C, as long as both sides use it).  Lanes past the end of a bucket
 // (na, nb < 64) repeat its last column, so their products duplicate real
 // ones; the popcounts |z_a|, |x_b| are taken on the way.  Two stages are in
-// flight per lane, two waves per SIMD.  A side with at most 32 columns (the
-// remainder of a bucket just over 64 columns, or a bucket of at most 32) takes
-// one fragment row or column only.  Accumulator register r of lane l holds A
+// flight per lane.  A tile side of w columns takes ceil(w / 32) fragments: a
+// product with one side of at most 64 columns and the other of at most 96 is
+// one tile of up to 3 x 2 fragments (neither side is read twice), and the
+// remainder of a larger bucket cut into 64-column blocks takes only the
+// fragments it fills.  Accumulator register r of lane l holds A
 // row u*32 + (r/4)*8 + (l/32)*4 + r%4 and B column v*32 + l%32.
 // v_permlane16_swap on each word: lanes 16-31 and 48-63 of lo trade places with
 // lanes 0-15 and 32-47 of hi.
@@ -1211,7 +1243,7 @@ XYZ_DEV void swap16(uint4 &lo, uint4 &hi)
 
 __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
 {
-    __shared__ __align__(16) float zpop2[4][MTILE];  // per wave: 2|z_a| of the tile's A columns
+    __shared__ __align__(16) float zpop2[4][MTILE_WIDE];  // per wave: 2|z_a| of the tile's A columns
     const unsigned lane = lane_id();
     const int h = (int)(lane >> 5), c = (int)(lane & 31);
     const int lc = (int)(lane & 15), lq = (int)(lane >> 4);
@@ -1224,8 +1256,8 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
     const int32_t n32 = (int32_t)a.n;
     using T_ = std::true_type;
     using F_ = std::false_type;
-    // One tile as NU x NV fragments: a side of at most 32 columns takes one fragment row
-    // (column), so that neither its products nor its loads are spent on empty fragments.
+    // One tile as NU x NV fragments of 32 x 32, NU = ceil(na / 32) (at most 3 x 2 or 2 x 3),
+    // so that no products or loads are spent on empty fragments.
     auto tile_body = [&](const Tile &t, auto nu_c, auto nv_c) {
         constexpr int NU = decltype(nu_c)::value, NV = decltype(nv_c)::value;
         const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
@@ -1358,7 +1390,7 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
                     mn = fminf(mn, x);
                 }
                 const bool hit = mx >= (float)(smin - n32 + pb2) || (a.two_sided && mn <= (float)(-smin - n32 + pb2));
-                hitmask |= (hit ? 1u : 0u) << (u * 2 + v);
+                hitmask |= (hit ? 1u : 0u) << (u * 3 + v);
             }
         }
         if (__ballot(hitmask != 0) != 0) {
@@ -1371,7 +1403,7 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
                 for (int v = 0; v < NV; ++v) {
                     const int cb = v * 32 + c;
                     uint32_t m = 0;
-                    if ((hitmask >> (u * 2 + v)) & 1u) {
+                    if ((hitmask >> (u * 3 + v)) & 1u) {
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
                             const int ra = u * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
@@ -1423,13 +1455,23 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
     };
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
     for (uint64_t ti = wid; ti < a.nmfma; ti += nwave) {
         const Tile t = tile_from(T4[ti]);
-        const bool wa = t.na > 32, wb = t.nb > 32;     // wave-uniform
-        if (wa && wb) tile_body(t, I2{}, I2{});
-        else if (wa) tile_body(t, I2{}, I1{});
-        else if (wb) tile_body(t, I1{}, I2{});
-        else tile_body(t, I1{}, I1{});
+        // fragments per side (wave-uniform); tiles are at most MTILE x MTILE_WIDE, so 3 x 3
+        // does not occur
+        const int fu = (t.na + 31) >> 5, fv = (t.nb + 31) >> 5;
+        switch (fu * 4 + fv) {
+        case 5: tile_body(t, I1{}, I1{}); break;
+        case 6: tile_body(t, I1{}, I2{}); break;
+        case 7: tile_body(t, I1{}, I3{}); break;
+        case 9: tile_body(t, I2{}, I1{}); break;
+        case 10: tile_body(t, I2{}, I2{}); break;
+        case 11: tile_body(t, I2{}, I3{}); break;
+        case 13: tile_body(t, I3{}, I1{}); break;
+        case 14: tile_body(t, I3{}, I2{}); break;
+        default: break;
+        }
     }
 }
 
