@@ -1222,6 +1222,7 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
     if (tau < 0) return fail(XYZ_EINVAL, "tau=%lld < 0", (long long)tau);
     if (!std::isfinite(kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
     if (rep_offset < 0) return fail(XYZ_EINVAL, "rep_offset=%d < 0", (int)rep_offset);
+    if ((int64_t)rep_offset + L > (1ll << 31)) return fail(XYZ_EINVAL, "repetition index overflow");
     if (flags & ~XYZ_PROFILE) return fail(XYZ_EUNSUPPORTED, "the dense search takes XYZ_PROFILE only");
     if (x->fmt == XYZ_X_F32) return fail(XYZ_EUNSUPPORTED, "the dense search takes +-1 X");
     if (yfmt != XYZ_Y_I8_PM1) return fail(XYZ_EUNSUPPORTED, "the dense search takes +-1 Y");
@@ -1291,8 +1292,7 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
         HIP_TRY(hipMemcpyAsync(dR, R + r0 * n, sizeof(int32_t) * nr * n, hipMemcpyHostToDevice, st));
         tm.end();
         tm.begin(2);
-        HIP_TRY(launch_dense_project(x->XR, x->P64, p, n, dR, nr, yb, dW, drs, drs + chunk, xs, zs, K, V, c->cu_count,
-                                     st));
+        HIP_TRY(launch_dense_project(x->XR, x->P64, p, n, dR, nr, yb, dW, drs, drs + chunk, xs, zs, K, V, st));
         tm.end();
         int rbits = 0;
         while ((1 << rbits) < nr) ++rbits;

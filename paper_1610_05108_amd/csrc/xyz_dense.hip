@@ -277,7 +277,7 @@ int dense_group_reps() { return DP_R; }
 
 hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int64_t n, const int32_t *R, int nrep,
                                 const uint32_t *yb, int32_t *W, int32_t *rs, int32_t *rys, int32_t *xs, int32_t *zs,
-                                uint64_t *K, uint32_t *V, int cu_count, hipStream_t st)
+                                uint64_t *K, uint32_t *V, hipStream_t st)
 {
     if (nrep <= 0 || p <= 0) return hipSuccess;
     const int ng = (nrep + DP_R - 1) / DP_R;
@@ -295,7 +295,6 @@ hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int6
     const int64_t tot = (int64_t)nrep * p;
     hipLaunchKernelGGL(k_dense_keys, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, xs, zs, p, nrep, rs, rys,
                        K, V);
-    (void)cu_count;
     return hipGetLastError();
 }
 

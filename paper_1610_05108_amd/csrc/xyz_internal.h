@@ -252,7 +252,7 @@ int dense_group_reps();
 // with the column id in V.  Scratch: W (see above), rs / rys [nrep].
 hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int64_t n, const int32_t *R, int nrep,
                                 const uint32_t *yb, int32_t *W, int32_t *rs, int32_t *rys, int32_t *xs, int32_t *zs,
-                                uint64_t *K, uint32_t *V, int cu_count, hipStream_t st);
+                                uint64_t *K, uint32_t *V, hipStream_t st);
 // Buckets of the per-repetition index of the sorted z (idx holds nrep * (buckets + 1) u32).
 uint32_t dense_index_buckets(int64_t p);
 // E_r = {(j, k) : |x_j - z_k| <= tau} from the sorted keys Ks / column ids Vs of each repetition,
