@@ -194,8 +194,9 @@ xyz_status xyz_bruteforce(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt,
  * R: host array of L * n int32 weights, repetition l uses R[l*n .. l*n+n-1]:
  *    the projection vector on a fixed-point grid chosen by the caller (for a
  *    Gaussian F, round(2^b N(0, 1))).  sum_i |R[l*n+i]| must not exceed
- *    2^31 - 1 (XYZ_EINVAL otherwise): projections are then exact int32 sums, so
- *    E_l does not depend on summation order.  Copied before the call returns.
+ *    2^31 - 1 and no |R[l*n+i]| may exceed 2^31 - 2^24 (XYZ_EINVAL otherwise):
+ *    projections are then exact int32 sums, so E_l does not depend on
+ *    summation order.  Copied before the call returns.
  * tau: close-pairs threshold on the same grid, >= 0.  L >= 1; rep_offset >= 0
  *    numbers the repetitions (first_rep) as in xyz_search.
  * flags: XYZ_PROFILE only (others: XYZ_EUNSUPPORTED).

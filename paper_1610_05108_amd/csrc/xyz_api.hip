@@ -1227,11 +1227,19 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
     if (x->fmt == XYZ_X_F32) return fail(XYZ_EUNSUPPORTED, "the dense search takes +-1 X");
     if (yfmt != XYZ_Y_I8_PM1) return fail(XYZ_EUNSUPPORTED, "the dense search takes +-1 Y");
     const int64_t n = x->n, p = x->p;
+    // the projections are int32 sums; each weight is four balanced base-256 digits on the
+    // matrix cores, which hold |w| <= 127 (1 + 2^8 + 2^16 + 2^24) > 2^31 - 2^24
     for (int64_t l = 0; l < L; ++l) {
-        int64_t a = 0;
-        for (int64_t i = 0; i < n; ++i) a += R[l * n + i] < 0 ? -(int64_t)R[l * n + i] : (int64_t)R[l * n + i];
+        int64_t a = 0, mx = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t v = R[l * n + i] < 0 ? -(int64_t)R[l * n + i] : (int64_t)R[l * n + i];
+            a += v;
+            mx = std::max(mx, v);
+        }
         if (a > INT32_MAX)
             return fail(XYZ_EINVAL, "sum of |R| of repetition %lld is %lld > 2^31 - 1", (long long)l, (long long)a);
+        if (mx > (1ll << 31) - (1ll << 24))
+            return fail(XYZ_EINVAL, "|R| of repetition %lld reaches %lld > 2^31 - 2^24", (long long)l, (long long)mx);
     }
     const int64_t taub = std::min<int64_t>(tau, 1ll << 33);   // |x_j - z_k| < 2^32 always
     HIP_TRY(hipSetDevice(c->device));
@@ -1252,22 +1260,21 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
     XYZ_TRY(check_err_flag(err, st));
     const int64_t smin = xyz_smin(n, kappa, 0);
 
-    // repetitions in chunks of whole projection groups: 32 bytes per (repetition, column)
-    const int G = dense_group_reps();
+    // repetitions in chunks of whole projection groups of 8: 32 bytes per (repetition, column)
+    const int64_t G = 8;
     int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(256, (1ll << 30) / (32 * p)));
     if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
     if (chunk >= G) chunk -= chunk % G;
     chunk = std::min<int64_t>(chunk, L);
-    const int64_t ngrp = (chunk + G - 1) / G;
     RepInfo *info = nullptr;
-    int32_t *dR = nullptr, *dW = nullptr, *drs = nullptr, *xs = nullptr, *zs = nullptr;
+    int32_t *dR = nullptr, *xs = nullptr, *zs = nullptr;
+    void *dW = nullptr;
     uint64_t *K = nullptr, *K2 = nullptr;
     uint32_t *V = nullptr, *V2 = nullptr, *hist = nullptr;
     unsigned long long *scnt = nullptr;
     XYZ_TRY(ws(c, WS_INFO, (size_t)L, &info));
     XYZ_TRY(ws(c, WS_DPR, (size_t)(chunk * n), &dR));
-    XYZ_TRY(ws(c, WS_DPW, (size_t)(ngrp * G * n * 2), &dW));
-    XYZ_TRY(ws(c, WS_DPRS, (size_t)(2 * chunk), &drs));
+    XYZ_TRY(ws_get(c, WS_DPW, dense_weight_bytes(n, (int)chunk), &dW));
     XYZ_TRY(ws(c, WS_DPX, (size_t)(chunk * p), &xs));
     XYZ_TRY(ws(c, WS_DPZ, (size_t)(chunk * p), &zs));
     XYZ_TRY(ws(c, WS_SKK, (size_t)(chunk * p), &K));
@@ -1292,7 +1299,7 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
         HIP_TRY(hipMemcpyAsync(dR, R + r0 * n, sizeof(int32_t) * nr * n, hipMemcpyHostToDevice, st));
         tm.end();
         tm.begin(2);
-        HIP_TRY(launch_dense_project(x->XR, x->P64, p, n, dR, nr, yb, dW, drs, drs + chunk, xs, zs, K, V, st));
+        HIP_TRY(launch_dense_project(x->XR, x->P64, x->XC, x->W32p, p, n, dR, nr, yb, dW, xs, zs, K, V, st));
         tm.end();
         int rbits = 0;
         while ((1 << rbits) < nr) ++rbits;

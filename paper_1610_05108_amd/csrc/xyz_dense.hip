@@ -2,14 +2,14 @@
 // compared with minimal subsampling in Section 5.1 and Theorem 1).
 //
 // Repetition l projects every column of X and of Z = Y o X onto an integer
-// vector R_l: x = X^T R_l and z = Z^T R_l.  For +-1 data
-//     x_j = sum_i R_i - 2 sum_{i : X_ij = -1} R_i,
-//     z_j = sum_i Y_i R_i - 2 sum_{i : X_ij = -1} Y_i R_i,
-// exact in int32 because the caller bounds sum_i |R_i| below 2^31.  The z of a
+// vector R_l: x = X^T R_l and z = Z^T R_l = X^T (Y o R_l), exact in int32
+// because the caller bounds sum_i |R_i| below 2^31.  The projections of 8
+// repetitions at a time are one integer matrix product on the int8 matrix
+// cores (+-1 X against the base-256 digits of the weights).  The z of a
 // repetition are sorted (with the column ids), and column j walks the window of
-// sorted z with |x_j - z_k| <= tau, starting from an index of the sorted z: that is E_l.
-// Each unordered pair {j, k} of E_l u E_l^T is checked once, from the side that
-// owns it (j when (j, k) is in E_l and, if k < j, (k, j) is not), by
+// sorted z with |x_j - z_k| <= tau, starting from an index of the sorted z: that
+// is E_l.  Each unordered pair {j, k} of E_l u E_l^T is checked once, from the
+// side that owns it (j when (j, k) is in E_l and, if k < j, (k, j) is not), by
 // s = n - 2 popcount(y ^ x_j ^ x_k) against the integer threshold of eq. (1).
 #include "xyz_internal.h"
 
@@ -20,123 +20,113 @@ namespace xyz {
 namespace {
 
 constexpr int DP_R = 8;        // repetitions per projection pass (one group)
-constexpr int DP_ROWS = 256;   // rows per projection workgroup slice (more when n needs > DP_SLICES)
-constexpr int DP_SLICES = 32768;
 
 __device__ __forceinline__ unsigned dp_lane() { return threadIdx.x & 63u; }
 
 }  // namespace
 
-// Weights of repetition group g interleaved per row for the projection:
-// W[((g n + i) DP_R + r) 2 + 0] = R_{gDP_R+r, i}, [.. + 1] = Y_i R_{gDP_R+r, i}
-// (zero for repetitions past nrep), and the per-repetition sums rs[rep] =
-// sum_i R_i, rys[rep] = sum_i Y_i R_i (int32: bounded by sum_i |R_i| < 2^31).
+typedef int dp_v4i __attribute__((ext_vector_type(4)));
+typedef int dp_v16i __attribute__((ext_vector_type(16)));
+
+// The projection x = X^T R is a contraction over the rows; it runs on the int8 matrix cores.
+// A weight w (R_i or Y_i R_i, |w| < 2^31) is written in balanced base-256 digits,
+// w = d0 + 2^8 d1 + 2^16 d2 + 2^24 d3 with every d in [-128, 127], so that
+// x = sum_k 2^(8k) (X^T D_k) exactly; each X^T D_k is at most 128 n in magnitude (exact in
+// int32 for n < 2^24).  Output column c of a repetition group is 2r (R of repetition r) or
+// 2r + 1 (Y o R); the matrix product's 64 columns are digit k = n / 16 of output column
+// c = n % 16.
+__device__ __forceinline__ int dp_digit(int32_t w, int k)
+{
+    int32_t v = w;
+    for (int q = 0; q < k; ++q) v = (v - (int32_t)(int8_t)(v & 0xff)) >> 8;
+    return (int)(int8_t)(v & 0xff);
+}
+
+// Digits of repetition group g in the matrix cores' B layout: WL[((g nK + ks) 2 + h) 64 + n]
+// is 16 bytes, byte s = digit n / 16 of weight column n % 16 at row 32 ks + 16 h + s
+// (0 for rows past n and repetitions past nrep).
 __global__ __launch_bounds__(256) void k_dense_weights(const int32_t *__restrict__ R, int64_t n, int nrep,
-                                                       const uint32_t *__restrict__ yb, int32_t *__restrict__ W,
-                                                       int32_t *__restrict__ rs, int32_t *__restrict__ rys)
+                                                       const uint32_t *__restrict__ yb, int nK,
+                                                       uint4 *__restrict__ WL)
 {
     const int g = blockIdx.y;
-    __shared__ int32_t part[2][DP_R][4];
-    int32_t sr[DP_R], sy[DP_R];
-#pragma unroll
-    for (int r = 0; r < DP_R; ++r) sr[r] = sy[r] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int32_t ys = ((yb[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
-        int32_t *o = W + (((int64_t)g * n + i) * DP_R) * 2;
-#pragma unroll
-        for (int r = 0; r < DP_R; ++r) {
-            const int rep = g * DP_R + r;
-            const int32_t v = rep < nrep ? R[(int64_t)rep * n + i] : 0;
-            o[2 * r] = v;
-            o[2 * r + 1] = ys * v;
-            sr[r] += v;
-            sy[r] += ys * v;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (ks, h, col) of the group
+    if (e >= (int64_t)nK * 128) return;
+    const int col = (int)(e & 63), h = (int)((e >> 6) & 1);
+    const int64_t ks = e >> 7;
+    const int k = col >> 4, c = col & 15, rep = g * DP_R + (c >> 1);
+    uint32_t wd[4] = {0, 0, 0, 0};
+    if (rep < nrep) {
+        for (int sb = 0; sb < 16; ++sb) {
+            const int64_t i = ks * 32 + 16 * h + sb;
+            if (i >= n) break;
+            int32_t w = R[(int64_t)rep * n + i];
+            if ((c & 1) && ((yb[i >> 5] >> (i & 31)) & 1u)) w = -w;
+            wd[sb >> 2] |= ((uint32_t)dp_digit(w, k) & 0xffu) << (8 * (sb & 3));
         }
     }
-#pragma unroll
-    for (int r = 0; r < DP_R; ++r) {
-        for (int d = 32; d >= 1; d >>= 1) {
-            sr[r] += __shfl_xor(sr[r], d, 64);
-            sy[r] += __shfl_xor(sy[r], d, 64);
-        }
-    }
-    const int w = threadIdx.x >> 6;
-    if (dp_lane() == 0) {
-#pragma unroll
-        for (int r = 0; r < DP_R; ++r) {
-            part[0][r][w] = sr[r];
-            part[1][r][w] = sy[r];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < DP_R) {
-        const int r = threadIdx.x, rep = g * DP_R + r;
-        if (rep < nrep) {
-            atomicAdd(&rs[rep], part[0][r][0] + part[0][r][1] + part[0][r][2] + part[0][r][3]);
-            atomicAdd(&rys[rep], part[1][r][0] + part[1][r][1] + part[1][r][2] + part[1][r][3]);
-        }
-    }
+    WL[((int64_t)g * nK + ks) * 128 + h * 64 + col] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
 }
 
-// Partial sums over one slice of `rows` rows: sx[rep][j] += sum_{i : X_ij = -1} R_i and
-// sz[rep][j] += sum_{i : X_ij = -1} Y_i R_i.  One thread per column; the 64 columns of a
-// wave read one word of each row of XR (bit j % 64 of word j / 64 is 1 iff X_ij = -1).
-__global__ __launch_bounds__(256) void k_dense_project(const uint64_t *__restrict__ XR, int64_t P64, int64_t p,
-                                                       int64_t n, int64_t rows, const int32_t *__restrict__ W,
-                                                       int nrep, int32_t *__restrict__ sx, int32_t *__restrict__ sz)
+// x and z of DP_R repetitions for 32 columns per wave, over all rows: the A operand is 16
+// rows of one column as int8 +-1 (bit b of a nibble spread to byte b by one multiply), the B
+// operand the weight digits.  Lane l takes column l % 32 and row half l / 32 of every 32-row
+// step; accumulator r of lane l holds column (r/4)*8 + (l/32)*4 + r%4 of the wave's 32 and
+// product column l % 32.  Writes xs, zs [rep][p] and the sort keys (rep << 32) | (z + 2^31)
+// with the column id.
+__global__ __launch_bounds__(256) void k_dense_project(const uint32_t *__restrict__ XC, int W32p, int64_t p,
+                                                       int nK, const uint4 *__restrict__ WL, int nrep,
+                                                       int32_t *__restrict__ xs, int32_t *__restrict__ zs,
+                                                       uint64_t *__restrict__ K, uint32_t *__restrict__ V)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int q = __builtin_amdgcn_readfirstlane((int)(j >> 6));
-    if (q >= P64) return;                           // the whole wave lies past the last word
-    const int g = blockIdx.y;
-    const int64_t i0 = (int64_t)blockIdx.z * rows, i1 = i0 + rows < n ? i0 + rows : n;
     const unsigned lane = dp_lane();
-    int32_t ax[DP_R], az[DP_R];
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    if (j0 >= p) return;                            // the whole wave lies past the last column
+    const int g = blockIdx.y;
+    const int h = (int)(lane >> 5), lc = (int)(lane & 31);
+    const int64_t col = j0 + lc < p ? j0 + lc : p - 1;
+    const uint4 *xc4 = reinterpret_cast<const uint4 *>(XC + col * (int64_t)W32p);
+    const uint4 *wl = WL + (int64_t)g * nK * 128 + h * 64 + lc;
+    dp_v16i acc0 = {}, acc1 = {};
+    for (int q = 0; 4 * q < nK; ++q) {
+        const uint4 w4 = xc4[q];                    // rows 128 q .. 128 q + 127 (W32p is a multiple of 4)
+        const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
-    for (int r = 0; r < DP_R; ++r) ax[r] = az[r] = 0;
-    const uint64_t *col = XR + q;
-    const int4 *Wg = reinterpret_cast<const int4 *>(W + (int64_t)g * n * DP_R * 2);
-#pragma unroll 2
-    for (int64_t i = i0; i < i1; ++i) {
-        const uint64_t w = col[i * P64];
-        const int32_t m = -(int32_t)((w >> lane) & 1u);      // all ones iff X_ij = -1
-        const int4 *wr = Wg + i * (DP_R / 2);
+        for (int e = 0; e < 4; ++e) {
+            const int ks = 4 * q + e;
+            if (ks >= nK) break;
+            const uint32_t bits = (ws[e] >> (16 * h)) & 0xffffu;
+            dp_v4i av;
 #pragma unroll
-        for (int h = 0; h < DP_R / 2; ++h) {
-            const int4 v = wr[h];                            // R, YR of repetitions 2h, 2h + 1
-            ax[2 * h] += v.x & m;
-            az[2 * h] += v.y & m;
-            ax[2 * h + 1] += v.z & m;
-            az[2 * h + 1] += v.w & m;
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint32_t m = (((bits >> (4 * q4)) & 15u) * 0x00204081u) & 0x01010101u;
+                av[q4] = (int)(0x01010101u | (m * 0xfeu));   // byte b: -1 when bit b is set, else +1
+            }
+            const uint4 b0 = wl[(int64_t)ks * 128], b1 = wl[(int64_t)ks * 128 + 32];
+            const dp_v4i bv0 = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w};
+            const dp_v4i bv1 = {(int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+            acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv1, acc1, 0, 0, 0);
         }
     }
-    if (j >= p) return;
+    // digits 0 and 1 of output column c sit in lanes c and c + 16 of acc0, digits 2 and 3 in acc1
+    const int c = lc & 15, rep = g * DP_R + (c >> 1);
 #pragma unroll
-    for (int r = 0; r < DP_R; ++r) {
-        const int rep = g * DP_R + r;
-        if (rep < nrep) {
-            atomicAdd(&sx[(int64_t)rep * p + j], ax[r]);
-            atomicAdd(&sz[(int64_t)rep * p + j], az[r]);
+    for (int r = 0; r < 16; ++r) {
+        const int32_t d1 = __shfl_xor(acc0[r], 16, 64), d3 = __shfl_xor(acc1[r], 16, 64);
+        const int64_t v = (int64_t)acc0[r] + ((int64_t)d1 << 8) + ((int64_t)acc1[r] << 16) + ((int64_t)d3 << 24);
+        const int64_t j = j0 + (r >> 2) * 8 + h * 4 + (r & 3);
+        if (lc < 16 && j < p && rep < nrep) {
+            const int64_t t = (int64_t)rep * p + j;
+            if (c & 1) {
+                zs[t] = (int32_t)v;
+                K[t] = ((uint64_t)rep << 32) | (uint64_t)((uint32_t)(int32_t)v ^ 0x80000000u);
+                V[t] = (uint32_t)j;
+            } else {
+                xs[t] = (int32_t)v;
+            }
         }
     }
-}
-
-// x = rs - 2 sx and z = rys - 2 sz in place; sort keys (rep << 32) | (z + 2^31) with the
-// column id as value (keys of one repetition are contiguous after the sort).
-__global__ __launch_bounds__(256) void k_dense_keys(int32_t *__restrict__ xs, int32_t *__restrict__ zs, int64_t p,
-                                                    int nrep, const int32_t *__restrict__ rs,
-                                                    const int32_t *__restrict__ rys, uint64_t *__restrict__ K,
-                                                    uint32_t *__restrict__ V)
-{
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (int64_t)nrep * p) return;
-    const int rep = (int)(t / p);
-    const int32_t x = (int32_t)((uint32_t)rs[rep] - 2u * (uint32_t)xs[t]);
-    const int32_t z = (int32_t)((uint32_t)rys[rep] - 2u * (uint32_t)zs[t]);
-    xs[t] = x;
-    zs[t] = z;
-    K[t] = ((uint64_t)rep << 32) | (uint64_t)((uint32_t)z ^ 0x80000000u);
-    V[t] = (uint32_t)(t - (int64_t)rep * p);
 }
 
 namespace {
@@ -273,28 +263,26 @@ __global__ __launch_bounds__(256) void k_dense_verify(const int32_t *__restrict_
 
 // ------------------------------------------------------------ launchers --
 
-int dense_group_reps() { return DP_R; }
+size_t dense_weight_bytes(int64_t n, int nrep)
+{
+    const int64_t nK = (n + 31) / 32, ng = (nrep + DP_R - 1) / DP_R;
+    return (size_t)(ng * nK * 128) * sizeof(uint4);
+}
 
-hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int64_t n, const int32_t *R, int nrep,
-                                const uint32_t *yb, int32_t *W, int32_t *rs, int32_t *rys, int32_t *xs, int32_t *zs,
+hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, const uint32_t *XC, int W32p, int64_t p, int64_t n,
+                                const int32_t *R, int nrep, const uint32_t *yb, void *W, int32_t *xs, int32_t *zs,
                                 uint64_t *K, uint32_t *V, hipStream_t st)
 {
+    (void)XR;
+    (void)P64;
     if (nrep <= 0 || p <= 0) return hipSuccess;
     const int ng = (nrep + DP_R - 1) / DP_R;
-    hipError_t e = hipMemsetAsync(rs, 0, sizeof(int32_t) * nrep, st);
-    if (e == hipSuccess) e = hipMemsetAsync(rys, 0, sizeof(int32_t) * nrep, st);
-    if (e == hipSuccess) e = hipMemsetAsync(xs, 0, sizeof(int32_t) * nrep * p, st);
-    if (e == hipSuccess) e = hipMemsetAsync(zs, 0, sizeof(int32_t) * nrep * p, st);
-    if (e != hipSuccess) return e;
-    const unsigned wblocks = (unsigned)std::min<int64_t>((n + 255) / 256, 64);
-    hipLaunchKernelGGL(k_dense_weights, dim3(wblocks, ng), dim3(256), 0, st, R, n, nrep, yb, W, rs, rys);
-    const unsigned bx = (unsigned)((p + 255) / 256);
-    const int64_t rows = std::max<int64_t>(DP_ROWS, (n + DP_SLICES - 1) / DP_SLICES);
-    const unsigned bz = (unsigned)((n + rows - 1) / rows);
-    hipLaunchKernelGGL(k_dense_project, dim3(bx, ng, bz), dim3(256), 0, st, XR, P64, p, n, rows, W, nrep, xs, zs);
-    const int64_t tot = (int64_t)nrep * p;
-    hipLaunchKernelGGL(k_dense_keys, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, xs, zs, p, nrep, rs, rys,
-                       K, V);
+    const int nK = (int)((n + 31) / 32);
+    uint4 *WL = static_cast<uint4 *>(W);
+    hipLaunchKernelGGL(k_dense_weights, dim3((unsigned)(((int64_t)nK * 128 + 255) / 256), ng), dim3(256), 0, st, R, n,
+                       nrep, yb, nK, WL);
+    hipLaunchKernelGGL(k_dense_project, dim3((unsigned)((p + 127) / 128), ng), dim3(256), 0, st, XC, W32p, p, nK, WL,
+                       nrep, xs, zs, K, V);
     return hipGetLastError();
 }
 

@@ -244,14 +244,14 @@ hipError_t launch_radix_sort(uint64_t *K, uint32_t *V, uint64_t *K2, uint32_t *V
                              uint32_t *hist, uint64_t **Kout, uint32_t **Vout, hipStream_t st);
 
 // ------------------------------------------- dense projections (Algorithm 1) --
-// Repetitions processed per projection pass; the weight buffer W of launch_dense_project holds
-// ceil(nrep / dense_group_reps()) * dense_group_reps() * n * 2 int32.
-int dense_group_reps();
+// Repetitions are projected in groups of 8 on the int8 matrix cores; dense_weight_bytes is the
+// size of the weight-digit buffer W of launch_dense_project for n rows and nrep repetitions.
+size_t dense_weight_bytes(int64_t n, int nrep);
 // x = X^T R_r and z = (Y o X)^T R_r (int32, exact when sum_i |R_r,i| < 2^31) for the nrep rows of
-// R [nrep][n] (device), into xs / zs [nrep][p]; sort keys K [nrep][p] = (r << 32) | (z + 2^31)
-// with the column id in V.  Scratch: W (see above), rs / rys [nrep].
-hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, int64_t p, int64_t n, const int32_t *R, int nrep,
-                                const uint32_t *yb, int32_t *W, int32_t *rs, int32_t *rys, int32_t *xs, int32_t *zs,
+// R [nrep][n] (device), from the column bits XC [p][W32p], into xs / zs [nrep][p]; sort keys
+// K [nrep][p] = (r << 32) | (z + 2^31) with the column id in V.
+hipError_t launch_dense_project(const uint64_t *XR, int64_t P64, const uint32_t *XC, int W32p, int64_t p, int64_t n,
+                                const int32_t *R, int nrep, const uint32_t *yb, void *W, int32_t *xs, int32_t *zs,
                                 uint64_t *K, uint32_t *V, hipStream_t st);
 // Buckets of the per-repetition index of the sorted z (idx holds nrep * (buckets + 1) u32).
 uint32_t dense_index_buckets(int64_t p);

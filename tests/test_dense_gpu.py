@@ -117,6 +117,14 @@ def test_dense_rejects(ctx):
     big = np.full((1, 60), 1 << 26, dtype=np.int32)           # sum |R| = 60 * 2^26 > 2^31
     with pytest.raises(xyz.XyzError):
         ctx.dense_search(x, d.Y, big, 10, 0.1)
+    one = np.zeros((1, 60), dtype=np.int32)
+    one[0, 7] = (1 << 31) - (1 << 24) + 1                     # one weight past the digits' range
+    with pytest.raises(xyz.XyzError):
+        ctx.dense_search(x, d.Y, one, 10, 0.1)
+    one[0, 7] = -((1 << 31) - (1 << 24))                      # the largest accepted weight is exact
+    res = ctx.dense_search(x, d.Y, one, 0, -1.0)
+    rp, rr = dense_search(d.XT, d.Y, one, 0, -1.0)
+    assert_same(res, rp, rr)
     with pytest.raises(xyz.XyzError):
         ctx.dense_search(x, d.Y.astype(np.float32), R, 10, 0.1)
     c = synthgen.small_continuous(60, 40, seed=1)
