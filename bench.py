@@ -149,7 +149,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards over repetitions "
-              "and responses, but this build measures the single-GPU share.", file=sys.stderr)
+              "and responses; this benchmark measures one GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ typedef int32_t xyz_status;
 #define XYZ_EDEVICE      (-3)  /* a HIP call failed; the context should be destroyed */
 #define XYZ_EAGAIN       (-4)  /* serving: the request is not finished yet */
 #define XYZ_ECANCELED    (-5)  /* serving: the request was cancelled or the server stopped */
-#define XYZ_EUNSUPPORTED (-6)  /* valid request outside what this build implements */
+#define XYZ_EUNSUPPORTED (-6)  /* valid request outside what the library implements */
 
 #define XYZ_MEM_HOST   0
 #define XYZ_MEM_DEVICE 1
