@@ -167,3 +167,19 @@ def test_dense_large_p_chunks(ctx):
         assert s == pr["s"] and s / n > kappa
         l = int(pr["first_rep"])
         assert abs(xs[l, a] - zs[l, b]) <= tau or abs(xs[l, b] - zs[l, a]) <= tau
+
+
+def test_dense_device_y_and_growing_workspaces(ctx):
+    """Y handed over in device memory, and calls of growing size on one context (the
+    workspaces grow between calls) give the oracle's results."""
+    import torch
+    for n, p, L, seed in ((90, 300, 3, 21), (400, 2500, 17, 22), (150, 700, 9, 23)):
+        d = synthgen.small_binary(n, p, seed=seed, planted=[(4, 8)], flip=0.1)
+        R, sd = synthgen.gaussian_projections(n, L, seed=seed)
+        tau = int(round(theory.tau_gauss(50, n, sd)))
+        x = ctx.x_create(d.XT)
+        yd = torch.from_numpy(d.Y).cuda()
+        res = ctx.dense_search(x, yd, R, tau, 0.1, rep_offset=3)
+        rp, rr = dense_search(d.XT, d.Y, R, tau, 0.1, rep_offset=3)
+        assert_same(res, rp, rr)
+        ctx.x_destroy(x)
