@@ -99,3 +99,17 @@ def test_gaussian_rate_matches_eta_gauss():
     q = 1.0 - (1.0 - eta) ** 2
     mu, sdev = L * q, math.sqrt(L * q * (1.0 - q))
     assert abs(hits - mu) < 4.5 * sdev, (hits, mu, sdev)
+
+
+def test_gaussian_budget_is_p_candidates():
+    """Section 5.1's budget: with tau = tau_gauss(p, n) and random +-1 data (strengths
+    near 1/2), a repetition holds about p candidate pairs (each orientation about 1/p
+    per ordered pair; p(p-1) ordered pairs, overlaps of order 1)."""
+    p, n, L = 300, 200, 40
+    XT = synthgen.rademacher(n, p, seed=31)
+    Y = np.where(np.random.default_rng(32).random(n) < 0.5, 1, -1).astype(np.int8)
+    R, sd = synthgen.gaussian_projections(n, L, seed=33, frac_bits=16)
+    tau = int(round(theory.tau_gauss(p, n, sd)))
+    _, reps = dense_search(XT, Y, R, tau, 2.0)
+    mean = float(reps["candidates"].mean())
+    assert abs(mean - p) < 0.08 * p, mean
