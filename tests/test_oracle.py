@@ -415,3 +415,116 @@ def test_unbiased_search_deterministic_and_rows_table():
     rows = np.full((4, 5), 7, dtype=np.int32)
     rows[:, 0] = [0, 1, 2, 3]
     oracle.search(XT, d.Y, 5, 4, 0.2, rows=rows, unbiased=True)
+
+
+# ------------------------------------------ bucket sizes and first repetitions
+#
+# Section 2.2 groups the columns by their projected value (Figure 2); the
+# statistic max_bucket is the size of the largest group of X columns.  Algorithm
+# 2 adds the pairs of each repetition to I; fresh_l counts the pairs of I whose
+# first repetition is l.  Both are checked against counts made here directly
+# from the data, not from the oracle's records.
+
+def _x_groups(XT, rows):
+    """Sizes of the groups of X columns with equal entries on the sampled rows."""
+    sub = np.ascontiguousarray(XT[:, rows])            # p x m
+    if sub.shape[1] == 0:
+        return np.array([XT.shape[0]])
+    _, counts = np.unique(sub, axis=0, return_counts=True)
+    return counts
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+def test_max_bucket_all_columns_equal_is_p(m):
+    """Every column the same: one group of p X columns, whatever Y is.  Counting
+    the Z side into the group as well would give 2p whenever Y is +1 on every
+    sampled row (m = 0 always)."""
+    n, p, L = 16, 9, 60
+    col = synthgen.rademacher(n, 1, seed=3)[0]
+    XT = np.repeat(col[None, :], p, axis=0)
+    Y = synthgen.small_binary(n, 2, seed=4).Y
+    assert (Y == 1).any() and (Y == -1).any()
+    _, reps = oracle.search(XT, Y, m, L, 0.0, seed=8)
+    assert np.all(reps["max_bucket"] == p)
+    if m > 0:
+        assert np.any(reps["cmask"] == 0), "some repetition samples only rows with Y = +1"
+
+
+def test_max_bucket_hand_built_groups():
+    """Columns built with chosen patterns on the sampled rows (0, 1): group sizes
+    5, 3, 2, 1.  Y = -1 on row 0 makes each X group meet the Z side of the
+    group with bit 0 flipped, so X + Z counts (5 + 3, ...) differ from 5."""
+    n = 8
+    patterns = {(1, 1): 5, (-1, 1): 3, (1, -1): 2, (-1, -1): 1}
+    cols = []
+    r = np.random.default_rng(1)
+    for (a, b), cnt in patterns.items():
+        for _ in range(cnt):
+            c = (2 * r.integers(0, 2, size=n) - 1).astype(np.int8)
+            c[0], c[1] = a, b
+            cols.append(c)
+    XT = np.stack(cols).astype(np.int8)
+    Y = np.ones(n, dtype=np.int8)
+    Y[0] = -1
+    rows = np.array([[0, 1], [1, 0], [0, 0], [1, 1]], dtype=np.int32)
+    _, reps = oracle.search(XT, Y, 2, 4, 0.0, rows=rows)
+    want = [int(_x_groups(XT, rows[l]).max()) for l in range(4)]
+    assert want == [5, 5, 7, 8]          # rows (0,0): row 0 alone -> 5+2 | 3+1; rows (1,1): 5+3 | 2+1
+    assert reps["max_bucket"].tolist() == want
+
+
+def test_max_bucket_random_matches_group_count():
+    d = synthgen.small_binary(30, 200, seed=17, planted=[(3, 9)], flip=0.2)
+    for m in (1, 3, 5):
+        rows = synthgen.rows_table(30, 6, m, seed=m)
+        for two in (False, True):
+            _, reps = oracle.search(d.XT, d.Y, m, 6, 0.1, rows=rows, two_sided=two)
+            assert reps["max_bucket"].tolist() == [int(_x_groups(d.XT, rows[l]).max()) for l in range(6)]
+
+
+def _first_reps_direct(XT, Y, rows, rep_offset, kappa, two_sided=False):
+    """first repetition of every pair of I by direct enumeration: the smallest
+    l = rep_offset + l' with (j, k) in E_l (O(p^2 m)) and s/n > kappa."""
+    X = XT.T.astype(np.int64)
+    Z = Y.astype(np.int64)[:, None] * X
+    n = X.shape[0]
+    S = X.T @ (Y.astype(np.int64)[:, None] * X)         # s_jk for every pair (textbook GEMM)
+    first = {}
+    for li, rw in enumerate(rows):
+        for (j, k) in _direct_E(X, Z, rw, two_sided):
+            st = int(S[j, k]) / n
+            if (abs(st) if two_sided else st) > kappa and (j, k) not in first:
+                first[(j, k)] = rep_offset + li
+    return first
+
+
+@pytest.mark.parametrize("rep_offset", [0, 5])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_fresh_counts_first_repetitions(rep_offset, two_sided):
+    d = synthgen.small_binary(28, 40, seed=23, planted=[(2, 7), (11, 30)], flip=0.15)
+    m, L, kappa = 2, 9, 0.1
+    rows = synthgen.rows_table(28, L, m, seed=31)
+    pairs, reps = oracle.search(d.XT, d.Y, m, L, kappa, rows=rows, rep_offset=rep_offset, two_sided=two_sided)
+    first = _first_reps_direct(d.XT, d.Y, rows, rep_offset, kappa, two_sided)
+    assert {(int(a), int(b)): int(f) for a, b, f in zip(pairs["j"], pairs["k"], pairs["first_rep"])} == first
+    want = np.bincount(np.array(list(first.values()), dtype=np.int64) - rep_offset, minlength=L)
+    assert reps["fresh"].tolist() == want.tolist()
+    assert int(reps["fresh"].sum()) == len(pairs)
+    assert int(reps["fresh"].sum()) < int(reps["passed"].sum()), "some pairs pass in several repetitions"
+
+
+def test_fresh_of_split_runs():
+    """Each part's fresh counts sum to its own unique pairs; the full run's fresh
+    is the histogram of the first repetitions merged over the parts."""
+    d = synthgen.small_binary(50, 40, seed=14, planted=[(1, 2), (5, 30)], flip=0.15)
+    full, rf = oracle.search(d.XT, d.Y, 4, 12, 0.2, seed=3)
+    a, ra = oracle.search(d.XT, d.Y, 4, 5, 0.2, seed=3, rep_offset=0)
+    b, rb = oracle.search(d.XT, d.Y, 4, 7, 0.2, seed=3, rep_offset=5)
+    assert int(ra["fresh"].sum()) == len(a) and int(rb["fresh"].sum()) == len(b)
+    assert int(rf["fresh"].sum()) == len(full)
+    first = {}
+    for arr in (a, b):
+        for r in arr:
+            key = (int(r["j"]), int(r["k"]))
+            first[key] = min(first.get(key, 10 ** 9), int(r["first_rep"]))
+    assert rf["fresh"].tolist() == np.bincount(list(first.values()), minlength=12).tolist()
