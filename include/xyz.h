@@ -172,6 +172,24 @@ xyz_status xyz_search(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int
 xyz_status xyz_search_batch(xyz_ctx *ctx, const xyz_x *x, int32_t nY, const void *const *Y, int yfmt,
                             int mem, const xyz_params *params, void *stream, xyz_result **outs);
 
+/* xyz_search for callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same search, with the same result, but no device memory is
+ * allocated or freed, and no host memory either.  Every workspace is carved from one static device
+ * array of XYZ_NOALLOC_SCRATCH_BYTES per device, held from the library's first xyz_init on that
+ * device until the process ends; calls that overlap on one device race on it (serialise them).
+ * Y: n entries per yfmt / mem; params: as xyz_search, without XYZ_PROFILE (XYZ_EUNSUPPORTED).
+ * pairs: caller-owned host array of pairs_cap entries (NULL when pairs_cap = 0); *npairs receives the
+ * number of pairs found, sorted by (j, k); when it exceeds pairs_cap nothing is written to pairs and
+ * XYZ_ENOMEM is returned (call again with room for *npairs).  reps: caller-owned host array of L
+ * entries.  A search whose workspace exceeds the scratch fails with XYZ_ENOMEM: before any launch
+ * when the statistics of L repetitions, packed Y and one repetition's keys, permutation and bucket
+ * offsets need more than half of it; during the search when tiles, survivors and merge scratch
+ * need more than the rest. */
+#define XYZ_NOALLOC_SCRATCH_BYTES (256ull << 20)
+xyz_status xyz_search_noalloc(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem,
+                              const xyz_params *params, void *stream, xyz_pair *pairs, int64_t pairs_cap,
+                              int64_t *npairs, xyz_rep_stats *reps);
+
 /* Exact search of eq. (1) over the pairs (a, b), a in colsA, b in colsB,
  * a != b, reported once as (min, max) (brute force, FP4 e2m1 matrix cores for
  * +-1 data).  colsA / colsB: host arrays of column indices, or NULL for all

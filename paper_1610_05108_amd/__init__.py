@@ -34,7 +34,7 @@ REP_DTYPE = np.dtype([("candidates", np.int64), ("passed", np.int64), ("fresh", 
 
 EXPORTS = [
     "xyz_version", "xyz_last_error", "xyz_init", "xyz_fini", "xyz_ctx_bytes", "xyz_x_create", "xyz_x_destroy",
-    "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_bruteforce", "xyz_dense_search", "xyz_result_npairs",
+    "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_search_noalloc", "xyz_bruteforce", "xyz_dense_search", "xyz_result_npairs",
     "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_free", "xyz_smin",
     "xyz_eta", "xyz_tau_dense", "xyz_eta_dense", "xyz_L_for", "xyz_m_for_L", "xyz_mstar",
     "xyz_sample_strengths", "xyz_plan",
@@ -106,6 +106,8 @@ def lib():
         "xyz_search": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(xyz_params), P, ctypes.POINTER(P)]),
         "xyz_search_batch": (I32, [P, P, I32, ctypes.POINTER(P), ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(xyz_params), P, ctypes.POINTER(P)]),
+        "xyz_search_noalloc": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(xyz_params), P, P, I64,
+                                     ctypes.POINTER(I64), P]),
         "xyz_bruteforce": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, D, U32, P, I64, P, I64, P, ctypes.POINTER(P)]),
         "xyz_dense_search": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, P, I32, I64, D, I32, U32, P,
                                    ctypes.POINTER(P)]),
@@ -312,6 +314,28 @@ def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
     return [_take_result(outs[q]) for q in range(nY)]
 
 
+def xyz_search_noalloc(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
+                       rep_offset: int = 0, rows=None, stream=None, unbiased: bool = False, pairs_cap: int = 1 << 16):
+    """xyz_search through the entry point that allocates no memory (workspaces in the library's
+    static device scratch).  Returns {'pairs', 'reps'}; raises XyzError (code XYZ_ENOMEM, with
+    'npairs' set) when more than pairs_cap pairs are found."""
+    if int(L) < 1:
+        raise ValueError("L must be >= 1")
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, False, unbiased)
+    ptr, mem, keep = _ptr(Y)
+    pairs = np.zeros(max(int(pairs_cap), 1), dtype=PAIR_DTYPE)
+    reps = np.zeros(int(L), dtype=REP_DTYPE)
+    npairs = ctypes.c_int64(0)
+    rc = lib().xyz_search_noalloc(ctx, x, ptr, _y_format(Y), mem, ctypes.byref(prm), _stream(stream, Y),
+                                  pairs.ctypes.data, int(pairs_cap), ctypes.byref(npairs), reps.ctypes.data)
+    del keep, keep_rows
+    if rc != XYZ_OK:
+        err = XyzError(rc, (lib().xyz_last_error() or b"").decode())
+        err.npairs = int(npairs.value)
+        raise err
+    return {"pairs": pairs[:int(npairs.value)].copy(), "reps": reps}
+
+
 def xyz_dense_search(ctx, x, Y, R, tau: int, kappa: float, rep_offset: int = 0, profile: bool = False,
                      stream=None):
     """Algorithm 1 with dense projections: R is (L, n) int32 (one projection vector
@@ -469,6 +493,9 @@ class Context:
 
     def search(self, x, Y, **kw):
         return xyz_search(self.h, x, Y, **kw)
+
+    def search_noalloc(self, x, Y, **kw):
+        return xyz_search_noalloc(self.h, x, Y, **kw)
 
     def search_batch(self, x, Ys, params, stream=None):
         return xyz_search_batch(self.h, x, Ys, params, stream=stream)

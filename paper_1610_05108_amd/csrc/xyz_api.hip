@@ -137,6 +137,23 @@ void dev_free(xyz_ctx *c, void *p, size_t bytes)
     c->used -= std::min<uint64_t>(c->used, bytes);
 }
 
+// Arena mode: carve the slot from the context's arena (bump pointer, 256-byte aligned); a slot
+// that is the last carved region grows in place.  Nothing is allocated or freed.
+xyz_status arena_get(xyz_ctx *c, DevBuf &b, size_t bytes, void **out)
+{
+    const size_t want = (size_t)round_up((int64_t)std::max<size_t>(bytes, 256), 256);
+    const bool top = b.p && (char *)b.p + b.bytes == c->arena + c->arena_used;
+    const size_t start = top ? (size_t)((char *)b.p - c->arena) : c->arena_used;
+    if (start + want > c->arena_size)
+        return fail(XYZ_ENOMEM, "the search needs more than the %zu bytes of static scratch (%zu in use, %zu more "
+                    "requested)", c->arena_size, c->arena_used, want);
+    b.p = c->arena + start;
+    b.bytes = want;
+    c->arena_used = start + want;
+    *out = b.p;
+    return XYZ_OK;
+}
+
 // Grow-only workspace slot.
 xyz_status ws_get(xyz_ctx *c, int slot, size_t bytes, void **out)
 {
@@ -145,6 +162,7 @@ xyz_status ws_get(xyz_ctx *c, int slot, size_t bytes, void **out)
         *out = b.p;
         return XYZ_OK;
     }
+    if (c->arena) return arena_get(c, b, bytes, out);
     size_t want = std::max(bytes, b.bytes + b.bytes / 4);
     want = (size_t)round_up((int64_t)std::max<size_t>(want, 256), 256);
     dev_free(c, b.p, b.bytes);
@@ -227,6 +245,7 @@ extern "C" xyz_status xyz_init(int device, uint64_t hbm_budget_bytes, xyz_ctx **
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(XYZ_EUNSUPPORTED, "libxyz is built for gfx950; device %d is %s", device, prop.gcnArchName);
     HIP_TRY(kernels_init());
+    XYZ_TRY(scratch_setup(device));
     xyz_ctx *c = new xyz_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
@@ -302,7 +321,7 @@ extern "C" xyz_status xyz_x_create(xyz_ctx *c, const void *X, int fmt, int mem, 
     int *err = nullptr;
     s = ws(c, WS_ERR, 4, &err);
     if (s != XYZ_OK) return cleanup(s);
-    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) return cleanup(fail(XYZ_EDEVICE, "memset failed"));
+    if (launch_zero(err, sizeof(int), st) != hipSuccess) return cleanup(fail(XYZ_EDEVICE, "zeroing the error flag failed"));
     hipError_t e;
     if (fmt == XYZ_X_I8_PM1) e = launch_pack_x_i8((const int8_t *)src, ld, n, p, x->W32p, x->XC, err, st);
     else if (fmt == XYZ_X_F32) e = launch_pack_x_f32((const float *)src, ld, n, p, x->W32p, x->XC, x->XF, x->nF, err, st);
@@ -389,7 +408,7 @@ xyz_status pack_ys(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, i
     XYZ_TRY(ws(c, WS_YB, (size_t)nys * x->W32p, &yb));
     XYZ_TRY(ws(c, WS_YD, (size_t)nys * x->nF, &yd));
     XYZ_TRY(ws(c, WS_ERR, 1, &err));
-    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
+    HIP_TRY(launch_zero(err, sizeof(int), st));
     for (int y = 0; y < nys; ++y) {
         const void *src = Ys[y];
         if (mem == XYZ_MEM_HOST) {
@@ -409,7 +428,7 @@ xyz_status pack_ys(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, i
 
 xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_offset, const Survivor *surv,
                          uint64_t S, RepInfo *info, Timer &tm, xyz_timing &timing, double t0, hipStream_t st,
-                         xyz_result **outs);
+                         xyz_result **outs, const DirectOut *direct = nullptr);
 
 // The survivor buffer overflowed (cnt records for capacity *cap): grow it, keep the first
 // `done` records (earlier chunks), and reset the device count to `done` so that the chunk
@@ -437,8 +456,9 @@ xyz_status grow_survivors(xyz_ctx *c, unsigned long long cnt, uint64_t done, uns
 }  // namespace
 
 xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
-                             const xyz_params *const *Ps, hipStream_t st, xyz_result **outs)
+                             const xyz_params *const *Ps, hipStream_t st, xyz_result **outs, const DirectOut *direct)
 {
+    if (nys < 1 || nys > 255 || (direct && nys != 1)) return fail(XYZ_EINVAL, "group of %d searches", nys);
     const double t0 = now_ms();
     const xyz_params &P = *Ps[0];
     const int64_t n = x->n, p = x->p;
@@ -478,9 +498,9 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
         HIP_TRY(launch_cdf(yd, n, cdf, last, err, st));
     }
     tm.end();
-    // thresholds
-    std::vector<int64_t> hsmin(nys);
-    std::vector<double> hkap(nys);
+    // thresholds (fixed arrays: this path allocates no host memory either)
+    int64_t hsmin[255];
+    double hkap[255];
     for (int y = 0; y < nys; ++y) {
         hkap[y] = Ps[y]->kappa;
         hsmin[y] = xyz_smin(n, Ps[y]->kappa, two);
@@ -489,8 +509,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     double *dkap = nullptr;
     XYZ_TRY(ws(c, WS_SMIN, nys, &dsmin));
     XYZ_TRY(ws(c, WS_KAPPA, nys, &dkap));
-    HIP_TRY(hipMemcpyAsync(dsmin, hsmin.data(), sizeof(int64_t) * nys, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dkap, hkap.data(), sizeof(double) * nys, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dsmin, hsmin, sizeof(int64_t) * nys, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dkap, hkap, sizeof(double) * nys, hipMemcpyHostToDevice, st));
     XYZ_TRY(check_err_flag(err, st));
 
     // ---- repetitions, in chunks
@@ -507,7 +527,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
     XYZ_TRY(ws(c, WS_BASE, 3 * ((size_t)chunk * nys + 1), &base));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
-    HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
+    HIP_TRY(launch_zero(scnt, sizeof(unsigned long long), st));
     uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
     Survivor *surv = nullptr;
     XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
@@ -582,7 +602,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 }
                 const uint64_t ncnt = 3ull * nys * nr;
                 XYZ_TRY(ws(c, WS_SKCNT, ncnt + 1, &cnt));
-                HIP_TRY(hipMemsetAsync(cnt + ncnt, 0, sizeof(uint32_t), st));
+                HIP_TRY(launch_zero(cnt + ncnt, sizeof(uint32_t), st));
                 HIP_TRY(launch_sk_products(rkey, rstart, dnr, nr, S, m, nys, cinfo, R * nys, two, mfma, table, cnt,
                                            st));
                 tm.end();
@@ -646,17 +666,49 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     }
 
     // ---- merge repetitions
-    return merge_results(c, x, nys, L, P.rep_offset, surv, surv_done, info, tm, timing, t0, st, outs);
+    return merge_results(c, x, nys, L, P.rep_offset, surv, surv_done, info, tm, timing, t0, st, outs, direct);
 }
 
 namespace {
+
+// One search's result into caller-owned host buffers (xyz_search_noalloc): the pairs, if they
+// fit, and the statistics of every repetition, converted through a small stack buffer.
+xyz_status copy_direct(const unsigned long long *nout, const OutPair *dout, const RepInfo *info, int L,
+                       hipStream_t st, const DirectOut &d)
+{
+    unsigned long long U = 0;
+    HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *d.npairs = (int64_t)U;
+    if ((int64_t)U > d.cap)
+        return fail(XYZ_ENOMEM, "the search found %llu pairs; the pair buffer holds %lld", U, (long long)d.cap);
+    static_assert(sizeof(OutPair) == sizeof(xyz_pair), "OutPair is the layout of xyz_pair");
+    if (U) HIP_TRY(hipMemcpyAsync(d.pairs, dout, sizeof(xyz_pair) * U, hipMemcpyDeviceToHost, st));
+    RepInfo buf[64];
+    for (int l0 = 0; l0 < L; l0 += 64) {
+        const int cnt = std::min(64, L - l0);
+        HIP_TRY(hipMemcpyAsync(buf, info + l0, sizeof(RepInfo) * cnt, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int i = 0; i < cnt; ++i) {
+            xyz_rep_stats &o = d.reps[l0 + i];
+            o.candidates = (int64_t)buf[i].candidates;
+            o.passed = (int64_t)buf[i].passed;
+            o.fresh = (int64_t)buf[i].fresh;
+            o.cmask = buf[i].cmask;
+            o.max_bucket = (int32_t)buf[i].max_bucket;
+            o.reserved = 0;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return XYZ_OK;
+}
 
 // Merge the S survivors of a finished search into one result per response: unique pairs
 // sorted by (j, k) with their first repetition and hits (Algorithm 2, "add to I"), and the
 // per-repetition statistics of info [L][nys].
 xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_offset, const Survivor *surv,
                          uint64_t S, RepInfo *info, Timer &tm, xyz_timing &timing, double t0, hipStream_t st,
-                         xyz_result **outs)
+                         xyz_result **outs, const DirectOut *direct)
 {
     const int64_t n = x->n, p = x->p;
     uint64_t *dk = nullptr, *dk2 = nullptr;
@@ -672,11 +724,12 @@ xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_off
     XYZ_TRY(ws(c, WS_OUT, S, &dout));
     XYZ_TRY(ws(c, WS_NOUT, 1, &nout));
     XYZ_TRY(ws(c, WS_YCNT, nys, &ycnt));
-    HIP_TRY(hipMemsetAsync(ycnt, 0, sizeof(unsigned long long) * nys, st));
+    HIP_TRY(launch_zero(ycnt, sizeof(unsigned long long) * nys, st));
     tm.begin(6);
     HIP_TRY(launch_dedup(surv, S, p, n, nys, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info,
                          (int64_t)rep_offset, st));
     tm.end();
+    if (direct) return copy_direct(nout, dout, info, L, st, *direct);
     unsigned long long U = 0;
     std::vector<unsigned long long> hy(nys);
     HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));
@@ -871,7 +924,7 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     }
     RepInfo *info = nullptr;
     XYZ_TRY(ws(c, WS_INFO, 1, &info));
-    HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo), st));
+    HIP_TRY(launch_zero(info, sizeof(RepInfo), st));
     BruteArgs ba{};
     const int nw = (int)((n + 31) / 32);
     ba.nq = x->W32p >> 2;
@@ -918,7 +971,7 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     uint64_t S = 0;
     for (;;) {
         XYZ_TRY(ws(c, WS_SURV, cap_wg * grid, &surv));
-        HIP_TRY(hipMemsetAsync(wcnt, 0, sizeof(unsigned int) * grid, st));
+        HIP_TRY(launch_zero(wcnt, sizeof(unsigned int) * grid, st));
         ba.surv = surv;
         ba.cap_wg = cap_wg;
         ba.wg_count = wcnt;
@@ -969,7 +1022,7 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     XYZ_TRY(ws(c, WS_OUT, S, &dout));
     XYZ_TRY(ws(c, WS_NOUT, 1, &nout));
     XYZ_TRY(ws(c, WS_YCNT, 1, &ycnt));
-    HIP_TRY(hipMemsetAsync(ycnt, 0, sizeof(unsigned long long), st));
+    HIP_TRY(launch_zero(ycnt, sizeof(unsigned long long), st));
     tm.begin(6);
     HIP_TRY(launch_dedup(dense, S, p, n, 1, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info, 0, st));
     tm.end();
@@ -1285,8 +1338,8 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
     uint32_t *didx = nullptr;
     XYZ_TRY(ws(c, WS_DPI, (size_t)chunk * (dense_index_buckets(p) + 1), &didx));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
-    HIP_TRY(hipMemsetAsync(info, 0, sizeof(RepInfo) * L, st));
-    HIP_TRY(hipMemsetAsync(scnt, 0, sizeof(unsigned long long), st));
+    HIP_TRY(launch_zero(info, sizeof(RepInfo) * L, st));
+    HIP_TRY(launch_zero(scnt, sizeof(unsigned long long), st));
     uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
     Survivor *surv = nullptr;
     XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
@@ -1310,7 +1363,7 @@ extern "C" xyz_status xyz_dense_search(xyz_ctx *c, const xyz_x *x, const void *Y
         tm.end();
         for (bool redo = true; redo;) {
             redo = false;
-            HIP_TRY(hipMemsetAsync(cinfo, 0, sizeof(RepInfo) * nr, st));
+            HIP_TRY(launch_zero(cinfo, sizeof(RepInfo) * nr, st));
             tm.begin(5);
             HIP_TRY(launch_dense_verify(xs, zs, Ks, Vs, didx, p, nr, taub, x->XC, x->W32p, yb, n, smin,
                                         (int64_t)rep_offset + r0, surv, scnt, surv_cap, cinfo, st));

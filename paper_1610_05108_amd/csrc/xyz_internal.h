@@ -262,6 +262,9 @@ hipError_t launch_dense_verify(const int32_t *xs, const int32_t *zs, const uint6
                                uint32_t *idx, int64_t p, int nrep, int64_t tau, const uint32_t *XC, int W32p,
                                const uint32_t *yb, int64_t n, int64_t smin, int64_t rep_abs0, Survivor *surv,
                                unsigned long long *surv_count, uint64_t surv_cap, RepInfo *info, hipStream_t st);
+// Zero `bytes` bytes at p (a multiple of 4, p 4-byte aligned) with a fill kernel: used instead of
+// hipMemsetAsync for every counter and flag of the search path.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 // Set kernel attributes (large dynamic LDS); called once per device.
 hipError_t kernels_init();
 

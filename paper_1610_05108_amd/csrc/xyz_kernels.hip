@@ -2685,6 +2685,19 @@ __global__ void k_dedup_count(const uint32_t *__restrict__ heads_scan, const uin
 
 static inline unsigned grid1(uint64_t work, unsigned per) { return (unsigned)((work + per - 1) / per); }
 
+__global__ __launch_bounds__(256) void k_zero(uint32_t *__restrict__ p, uint64_t count)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (uint64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st)
+{
+    const uint64_t count = bytes / 4;
+    if (count == 0) return hipSuccess;
+    k_zero<<<(unsigned)std::min<uint64_t>(grid1(count, 256), 4096), 256, 0, st>>>((uint32_t *)p, count);
+    return hipGetLastError();
+}
+
 hipError_t kernels_init()
 {
     hipError_t e = hipFuncSetAttribute((const void *)k_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2756,7 +2769,7 @@ hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uin
 
 hipError_t launch_row_absmax(const float *XF, int64_t nF, int64_t n, int64_t p, uint32_t *nu, hipStream_t st)
 {
-    const hipError_t e = hipMemsetAsync(nu, 0, sizeof(uint32_t) * (size_t)n, st);
+    const hipError_t e = launch_zero(nu, sizeof(uint32_t) * (size_t)n, st);
     if (e != hipSuccess) return e;
     const int64_t slices = std::min<int64_t>(std::max<int64_t>(p / 64, 1), 4096);
     const int64_t per = (p + slices - 1) / slices;
@@ -2956,7 +2969,7 @@ hipError_t launch_sk_runs(const uint64_t *K, uint64_t S, uint32_t *heads, uint32
 hipError_t launch_sk_table(const uint64_t *run_key, const uint32_t *nruns, uint32_t nr, uint64_t entries,
                            uint32_t *table, hipStream_t st)
 {
-    hipError_t e = hipMemsetAsync(table, 0, sizeof(uint32_t) * entries, st);
+    hipError_t e = launch_zero(table, sizeof(uint32_t) * entries, st);
     if (e != hipSuccess || nr == 0) return e;
     hipLaunchKernelGGL(k_sk_table, dim3(grid1(nr, 256)), dim3(256), 0, st, run_key, nruns, table);
     return hipGetLastError();

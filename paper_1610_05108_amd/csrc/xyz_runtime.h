@@ -30,6 +30,10 @@ struct xyz_ctx {
     int cu_count = 256;
     int64_t max_chunk = 0;   // repetitions per chunk (0: the default bound); the server lowers it to fit its budget
     xyz_rt::DevBuf ws[xyz_rt::NWS];
+    // Arena mode (xyz_search_noalloc): workspaces are carved from [arena, arena + arena_size)
+    // by a bump pointer instead of being allocated, and are never freed.
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
 };
 
 struct xyz_x {
@@ -61,13 +65,25 @@ xyz_status validate_params(const xyz_x *x, const xyz_params *P, int yfmt);
 xyz_status brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa, uint32_t flags,
                      const int32_t *colsA, int64_t nA, const int32_t *colsB, int64_t nB, hipStream_t st,
                      xyz_result **out);
-// Searches sharing X, m, L, seed, rep_offset and flags (nys > 1 requires +-1 Y and no row table).
-// X may belong to another context on the same device.
+// Caller-owned host buffers that receive one search's result instead of an xyz_result.
+struct DirectOut {
+    xyz_pair *pairs;       // room for cap pairs
+    int64_t cap;
+    int64_t *npairs;       // number of pairs found (also when it exceeds cap)
+    xyz_rep_stats *reps;   // L entries
+};
+// Searches sharing X, m, L, seed, rep_offset and flags (nys > 1 requires +-1 Y and no row table;
+// nys <= 255).  X may belong to another context on the same device.  With direct (nys = 1), the
+// result goes to the caller's buffers and outs is not used.
 xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
-                     const xyz_params *const *Ps, hipStream_t st, xyz_result **outs);
+                     const xyz_params *const *Ps, hipStream_t st, xyz_result **outs,
+                     const DirectOut *direct = nullptr);
 // Repetitions per chunk for p columns and 2^m buckets under the context's limits.
 int64_t chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m);
 // Frees every workspace of the context.
 void ws_release(xyz_ctx *c);
+// Device address of the static scratch array of xyz_search_noalloc on `device` (looked up once
+// per device, with that device current; called by xyz_init).
+xyz_status scratch_setup(int device);
 
 }  // namespace xyz_rt
