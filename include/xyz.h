@@ -49,12 +49,14 @@ typedef int32_t xyz_status;
 #define XYZ_MEM_HOST   0
 #define XYZ_MEM_DEVICE 1
 
-/* X formats.  All are column-major: column j starts at element j * ld. */
+/* X formats.  XYZ_X_I8_PM1, XYZ_X_BITS and XYZ_X_F32 are column-major: column j starts at element
+ * j * ld.  XYZ_X_I8_PM1_ROWMAJOR is row-major: row i starts at element i * ld. */
 #define XYZ_X_I8_PM1 0   /* int8 in {-1, +1}; ld >= n elements */
 #define XYZ_X_BITS   1   /* uint64 words; bit (i % 64) of word i / 64 is 1 iff X_ij = -1; ld >= ceil(n/64) words;
                             bits of rows >= n are ignored */
 #define XYZ_X_F32    2   /* float32, finite; ld >= n elements.  Hashing uses the sign transform
                             (x < 0 -> -1, else +1; Section 3.2), verification uses the values */
+#define XYZ_X_I8_PM1_ROWMAJOR 3  /* int8 in {-1, +1}, row-major (n rows of p entries); ld >= p elements */
 
 /* Y formats */
 #define XYZ_Y_I8_PM1 0   /* int8 in {-1, +1}: rows are sampled uniformly (eq. (6)) */
@@ -149,8 +151,9 @@ void xyz_fini(xyz_ctx *ctx);
 uint64_t xyz_ctx_bytes(const xyz_ctx *ctx);
 
 /* Make X resident on the device in the packed layouts the search reads
- * (term (i) of eq. (8)).  X: n x p column-major in format `fmt` (XYZ_X_*),
- * leading dimension ld (elements, or words for XYZ_X_BITS), host or device
+ * (term (i) of eq. (8)).  X: n x p in format `fmt` (XYZ_X_*: column-major, or
+ * row-major for XYZ_X_I8_PM1_ROWMAJOR), leading dimension ld (elements, or
+ * words for XYZ_X_BITS), host or device
  * memory per `mem`.  n >= 1, 1 <= p < 2^31, n < 2^31.  The caller keeps
  * ownership of X. */
 xyz_status xyz_x_create(xyz_ctx *ctx, const void *X, int fmt, int mem, int64_t n, int64_t p,
@@ -284,8 +287,10 @@ xyz_status xyz_plan(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int m
  * A server owns `workers` threads, each with its own context (workspaces) and
  * HIP stream on the device of ctx.  Requests on resident X (any context of the
  * same device; X must outlive its requests) wait in one FIFO queue; a free
- * worker takes the oldest request whose estimated device bytes fit beside the
- * running ones within hbm_budget_bytes (0: no bound), together with up to
+ * worker takes the oldest request whose estimated device bytes fit within
+ * hbm_budget_bytes (0: no bound) beside what the other workers hold or run
+ * (their workspaces are counted while idle, and a worker keeps at most
+ * budget / workers bytes between groups), together with up to
  * max_batch - 1 queued requests it can share a pass with (same X, m, L, seed,
  * rep_offset and flags, +-1 Y, no row table: one row draw, projection and
  * bucket sort serve them all).  Groups on different workers overlap on the
@@ -300,6 +305,8 @@ typedef struct {
     int32_t queued, inflight;   /* requests waiting / running now */
     uint64_t bytes_inflight;    /* estimated device bytes of running groups */
     double p50_ms, p99_ms, max_ms;  /* submit-to-completion latency of completed requests */
+    uint64_t bytes_held;        /* device bytes the workers' contexts may hold now: the larger of what each
+                                   holds and the estimate of the group it runs */
 } xyz_serve_stats;
 
 xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, int32_t workers, int32_t max_batch,

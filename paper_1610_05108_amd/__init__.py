@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libxyz.so")
 
 XYZ_OK, XYZ_EINVAL, XYZ_ENOMEM, XYZ_EDEVICE, XYZ_EAGAIN, XYZ_ECANCELED, XYZ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 XYZ_MEM_HOST, XYZ_MEM_DEVICE = 0, 1
-XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32 = 0, 1, 2
+XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32, XYZ_X_I8_PM1_ROWMAJOR = 0, 1, 2, 3
 XYZ_Y_I8_PM1, XYZ_Y_F32, XYZ_Y_F64 = 0, 1, 2
 XYZ_TWO_SIDED, XYZ_PROFILE, XYZ_EXACT, XYZ_UNBIASED = 1, 2, 4, 8
 XYZ_MAX_M = 30
@@ -73,7 +73,8 @@ class xyz_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("max_batch", ctypes.c_int32),
                 ("queued", ctypes.c_int32), ("inflight", ctypes.c_int32), ("bytes_inflight", ctypes.c_uint64),
-                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("bytes_held", ctypes.c_uint64)]
 
 
 _lib = None
@@ -217,12 +218,17 @@ def xyz_ctx_bytes(ctx) -> int:
     return int(lib().xyz_ctx_bytes(ctx))
 
 
-def xyz_x_create(ctx, XT, n: int | None = None, stream=None):
+def xyz_x_create(ctx, XT, n: int | None = None, stream=None, row_major: bool = False):
     """Make X resident.  XT is X in column-major order, shape (p, n) for int8 +-1 or
-    float32, or (p, ceil(n/64)) uint64 packed bits (then n must be given)."""
+    float32, or (p, ceil(n/64)) uint64 packed bits (then n must be given).  With
+    row_major, XT is X itself in row-major order: int8 +-1 of shape (n, p)."""
     fmt = _x_format(XT)
     p = int(XT.shape[0])
-    if fmt == XYZ_X_BITS:
+    if row_major:
+        if fmt != XYZ_X_I8_PM1 or XT.ndim != 2:
+            raise ValueError("row-major X must be a 2-D int8 array of shape (n, p)")
+        fmt, n, p, ld = XYZ_X_I8_PM1_ROWMAJOR, int(XT.shape[0]), int(XT.shape[1]), int(XT.shape[1])
+    elif fmt == XYZ_X_BITS:
         if n is None:
             raise ValueError("n is required for packed bits")
         ld = int(XT.shape[1])
@@ -238,6 +244,22 @@ def xyz_x_create(ctx, XT, n: int | None = None, stream=None):
 
 def xyz_x_destroy(x) -> None:
     lib().xyz_x_destroy(x)
+
+
+def xyz_x_n(x) -> int:
+    return int(lib().xyz_x_n(x))
+
+
+def xyz_x_p(x) -> int:
+    return int(lib().xyz_x_p(x))
+
+
+def _check_y(x, Y):
+    """The C side reads n entries of Y: refuse a response of another length."""
+    n = xyz_x_n(x)
+    size = int(Y.numel()) if _is_torch(Y) else int(np.size(Y))
+    if size != n:
+        raise ValueError(f"Y has {size} entries; X has n = {n} rows")
 
 
 def _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased=False):
@@ -275,6 +297,7 @@ def xyz_search(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided
                rep_offset: int = 0, rows=None, profile: bool = False, stream=None, unbiased: bool = False):
     """Algorithm 2 on resident X.  Returns {'pairs', 'reps', 'timing'}.  unbiased:
     hash float32 X with the unbiased transform of Section 3.2 (XYZ_UNBIASED)."""
+    _check_y(x, Y)
     prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased)
     ptr, mem, keep = _ptr(Y)
     h = ctypes.c_void_p()
@@ -293,6 +316,7 @@ def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
         raise ValueError("all Y must share one format")
     ptrs, keeps, mems = [], [], set()
     for Y in Ys:
+        _check_y(x, Y)
         ptr, mem, keep = _ptr(Y)
         ptrs.append(ptr)
         keeps.append(keep)
@@ -321,6 +345,7 @@ def xyz_search_noalloc(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, t
     'npairs' set) when more than pairs_cap pairs are found."""
     if int(L) < 1:
         raise ValueError("L must be >= 1")
+    _check_y(x, Y)
     prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, False, unbiased)
     ptr, mem, keep = _ptr(Y)
     pairs = np.zeros(max(int(pairs_cap), 1), dtype=PAIR_DTYPE)
@@ -341,9 +366,13 @@ def xyz_dense_search(ctx, x, Y, R, tau: int, kappa: float, rep_offset: int = 0, 
     """Algorithm 1 with dense projections: R is (L, n) int32 (one projection vector
     per repetition, sum |R_l| < 2^31), tau the close-pairs threshold on R's grid.
     Returns {'pairs', 'reps', 'timing'} as xyz_search."""
-    Rv = np.ascontiguousarray(R, dtype=np.int32)
-    if Rv.ndim != 2:
-        raise ValueError("R must be (L, n)")
+    R0 = np.asarray(R)
+    if R0.ndim != 2 or R0.shape[1] != xyz_x_n(x):
+        raise ValueError(f"R must be (L, n) with n = {xyz_x_n(x)}; got shape {R0.shape}")
+    if R0.size and (not np.issubdtype(R0.dtype, np.integer) or R0.min() < -(2 ** 31 - 1) or R0.max() > 2 ** 31 - 1):
+        raise ValueError("R must hold integers of magnitude below 2^31")
+    _check_y(x, Y)
+    Rv = np.ascontiguousarray(R0, dtype=np.int32)
     ptr, mem, keep = _ptr(Y)
     h = ctypes.c_void_p()
     _check(lib().xyz_dense_search(ctx, x, ptr, _y_format(Y), mem, Rv.ctypes.data, Rv.shape[0], int(tau),
@@ -356,6 +385,7 @@ def xyz_dense_search(ctx, x, Y, R, tau: int, kappa: float, rep_offset: int = 0, 
 def xyz_bruteforce(ctx, x, Y, kappa: float, colsA=None, colsB=None, two_sided: bool = False,
                    profile: bool = False, stream=None):
     """Exact eq. (1) over colsA x colsB (all columns when None)."""
+    _check_y(x, Y)
     ptr, mem, keep = _ptr(Y)
     a = None if colsA is None else np.ascontiguousarray(colsA, dtype=np.int32)
     b = None if colsB is None else np.ascontiguousarray(colsB, dtype=np.int32)
@@ -395,6 +425,7 @@ def xyz_mstar(gamma: float, n: int, p: int, gammas, total_pairs: float, m_max: i
 
 
 def xyz_sample_strengths(ctx, x, Y, npairs: int, seed: int = 0, stream=None) -> np.ndarray:
+    _check_y(x, Y)
     out = np.zeros(int(npairs), dtype=np.float64)
     ptr, mem, keep = _ptr(Y)
     _check(lib().xyz_sample_strengths(ctx, x, ptr, _y_format(Y), mem, int(npairs), int(seed) & (2 ** 64 - 1),
@@ -405,6 +436,7 @@ def xyz_sample_strengths(ctx, x, Y, npairs: int, seed: int = 0, stream=None) -> 
 
 def xyz_plan(ctx, x, Y, kappa: float, gamma_target: float, eta_target: float = 0.95, two_sided: bool = False,
              stream=None) -> dict:
+    _check_y(x, Y)
     info = xyz_plan_info()
     ptr, mem, keep = _ptr(Y)
     _check(lib().xyz_plan(ctx, x, ptr, _y_format(Y), mem, float(kappa), float(gamma_target), float(eta_target),
@@ -425,6 +457,7 @@ def xyz_serve_submit(server, x, Y, m: int = 0, L: int = 1, kappa: float = 0.0, s
     exact=True asks for the exact search of eq. (1) (m, L, seed, rows ignored)."""
     if _is_torch(Y) and Y.is_cuda:
         raise ValueError("xyz_serve_submit takes Y in host memory")
+    _check_y(x, Y)
     prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, None if exact else rows, False)
     if exact:
         prm.flags |= XYZ_EXACT
@@ -477,8 +510,8 @@ class Context:
         self.h = xyz_init(device, hbm_budget_bytes)
         self._xs = []
 
-    def x_create(self, XT, n=None, stream=None):
-        x = xyz_x_create(self.h, XT, n=n, stream=stream)
+    def x_create(self, XT, n=None, stream=None, row_major=False):
+        x = xyz_x_create(self.h, XT, n=n, stream=stream, row_major=row_major)
         self._xs.append(x)
         return x
 

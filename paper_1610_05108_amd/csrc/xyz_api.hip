@@ -271,9 +271,11 @@ extern "C" xyz_status xyz_x_create(xyz_ctx *c, const void *X, int fmt, int mem, 
     *out = nullptr;
     if (n < 1 || n >= (1ll << 31) || p < 1 || p >= (1ll << 31))
         return fail(XYZ_EINVAL, "shape n=%lld p=%lld out of range", (long long)n, (long long)p);
-    if (fmt != XYZ_X_I8_PM1 && fmt != XYZ_X_BITS && fmt != XYZ_X_F32) return fail(XYZ_EINVAL, "unknown X format %d", fmt);
+    if (fmt != XYZ_X_I8_PM1 && fmt != XYZ_X_BITS && fmt != XYZ_X_F32 && fmt != XYZ_X_I8_PM1_ROWMAJOR)
+        return fail(XYZ_EINVAL, "unknown X format %d", fmt);
     if (mem != XYZ_MEM_HOST && mem != XYZ_MEM_DEVICE) return fail(XYZ_EINVAL, "unknown memory kind %d", mem);
-    const int64_t minld = fmt == XYZ_X_BITS ? (n + 63) / 64 : n;
+    const bool rowmajor = fmt == XYZ_X_I8_PM1_ROWMAJOR;
+    const int64_t minld = fmt == XYZ_X_BITS ? (n + 63) / 64 : (rowmajor ? p : n);
     if (ld < minld) return fail(XYZ_EINVAL, "ld=%lld < %lld", (long long)ld, (long long)minld);
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
@@ -308,7 +310,7 @@ extern "C" xyz_status xyz_x_create(xyz_ctx *c, const void *X, int fmt, int mem, 
     }
     // source on the device
     const size_t esz = fmt == XYZ_X_BITS ? 8 : (fmt == XYZ_X_F32 ? 4 : 1);
-    const size_t src_bytes = ((size_t)(p - 1) * ld + minld) * esz;
+    const size_t src_bytes = ((size_t)((rowmajor ? n : p) - 1) * ld + minld) * esz;
     const void *src = X;
     if (mem == XYZ_MEM_HOST) {
         void *tmp = nullptr;
@@ -323,10 +325,16 @@ extern "C" xyz_status xyz_x_create(xyz_ctx *c, const void *X, int fmt, int mem, 
     if (s != XYZ_OK) return cleanup(s);
     if (launch_zero(err, sizeof(int), st) != hipSuccess) return cleanup(fail(XYZ_EDEVICE, "zeroing the error flag failed"));
     hipError_t e;
-    if (fmt == XYZ_X_I8_PM1) e = launch_pack_x_i8((const int8_t *)src, ld, n, p, x->W32p, x->XC, err, st);
-    else if (fmt == XYZ_X_F32) e = launch_pack_x_f32((const float *)src, ld, n, p, x->W32p, x->XC, x->XF, x->nF, err, st);
-    else e = launch_pack_x_bits((const uint64_t *)src, ld, n, p, x->W32p, x->XC, st);
-    if (e == hipSuccess) e = launch_transpose(x->XC, n, p, x->W32p, x->XR, x->P64, st);
+    if (rowmajor) {
+        // row-major input packs straight into the row layout; the column layout is its transpose
+        e = launch_pack_x_i8_rows((const int8_t *)src, ld, n, p, x->XR, x->P64, err, st);
+        if (e == hipSuccess) e = launch_transpose_rc(x->XR, n, p, x->P64, x->W32p, x->XC, st);
+    } else {
+        if (fmt == XYZ_X_I8_PM1) e = launch_pack_x_i8((const int8_t *)src, ld, n, p, x->W32p, x->XC, err, st);
+        else if (fmt == XYZ_X_F32) e = launch_pack_x_f32((const float *)src, ld, n, p, x->W32p, x->XC, x->XF, x->nF, err, st);
+        else e = launch_pack_x_bits((const uint64_t *)src, ld, n, p, x->W32p, x->XC, st);
+        if (e == hipSuccess) e = launch_transpose(x->XC, n, p, x->W32p, x->XR, x->P64, st);
+    }
     if (e != hipSuccess) return cleanup(fail(XYZ_EDEVICE, "packing X failed: %s", hipGetErrorString(e)));
     s = check_err_flag(err, st);
     if (s != XYZ_OK) return cleanup(s);

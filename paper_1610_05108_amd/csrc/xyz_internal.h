@@ -72,6 +72,12 @@ struct RepInfo {         // per repetition and response, filled on the device
 // X (int8 +-1, column-major, ld) -> XC bits [p][W32p] u32.  err |= 1 on a bad value.
 hipError_t launch_pack_x_i8(const int8_t *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC,
                             int *err, hipStream_t st);
+// X (int8 +-1, row-major, ld >= p) -> XR [n][P64] directly (columns past p: bit 0).  err |= 1 on a bad value.
+hipError_t launch_pack_x_i8_rows(const int8_t *X, int64_t ld, int64_t n, int64_t p, uint64_t *XR, int64_t P64,
+                                 int *err, hipStream_t st);
+// XR [n][P64] -> XC [p][W32p] (the inverse bit transpose; rows past n: bit 0).
+hipError_t launch_transpose_rc(const uint64_t *XR, int64_t n, int64_t p, int64_t P64, int W32p, uint32_t *XC,
+                               hipStream_t st);
 // X (float32, column-major, ld) -> sign bits XC and the zero-padded copy XF [p][nF].  err |= 2 on NaN/Inf.
 hipError_t launch_pack_x_f32(const float *X, int64_t ld, int64_t n, int64_t p, int W32p, uint32_t *XC,
                              float *XF, int64_t nF, int *err, hipStream_t st);

@@ -133,6 +133,54 @@ __global__ __launch_bounds__(256) void k_pack_x_i8(const int8_t *__restrict__ X,
     if (__ballot(bad) && lane == 0) atomicOr(err, 1);
 }
 
+// Row-major int8 X: one wave per (row i, group g of 64 columns); lane l reads
+// entry (i, 64g + l) (64 contiguous bytes per wave) and a ballot forms the
+// row-major word XR[i][g] directly.  Columns past p read as +1 (bit 0).
+__global__ __launch_bounds__(256) void k_pack_x_i8_rows(const int8_t *__restrict__ X, int64_t ld, int64_t n,
+                                                        int64_t p, uint64_t *__restrict__ XR, int64_t P64,
+                                                        int *__restrict__ err)
+{
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= n * P64) return;
+    const int64_t i = wave / P64, g = wave % P64;
+    const unsigned lane = lane_id();
+    const int64_t j = g * 64 + lane;
+    int8_t v = 1;
+    if (j < p) v = X[i * ld + j];
+    const bool bad = v != 1 && v != -1;
+    const unsigned long long w = __ballot(v == -1);
+    if (lane == 0) XR[i * P64 + g] = w;
+    if (__ballot(bad) && lane == 0) atomicOr(err, 1);
+}
+
+// Bit transpose XR -> XC (the inverse of k_transpose).  One wave takes 64
+// columns (row word g) and 128 rows (quad q of every column): lane l loads the
+// words of rows 128q + l and 128q + 64 + l; 128 ballots give each column's 128
+// bits, and lane c writes the quad of column 64g + c as one 16-byte store.
+// Rows past n read as 0.
+__global__ __launch_bounds__(256) void k_transpose_rc(const uint64_t *__restrict__ XR, int64_t n, int64_t p,
+                                                      int64_t P64, int W32p, uint32_t *__restrict__ XC)
+{
+    const int W4 = W32p / 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= P64 * W4) return;
+    const int64_t g = wave / W4;
+    const int q = (int)(wave % W4);
+    const unsigned lane = lane_id();
+    const int64_t r0 = (int64_t)q * 128 + lane;
+    const uint64_t lo = r0 < n ? XR[r0 * P64 + g] : 0ull;
+    const uint64_t hi = r0 + 64 < n ? XR[(r0 + 64) * P64 + g] : 0ull;
+    uint4 out = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+        const unsigned long long a = __ballot((lo >> c) & 1ull);   // rows 128q .. 128q + 63 of column 64g + c
+        const unsigned long long b = __ballot((hi >> c) & 1ull);   // rows 128q + 64 .. 128q + 127
+        if ((int)lane == c) out = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+    }
+    const int64_t j = g * 64 + lane;
+    if (j < p) reinterpret_cast<uint4 *>(XC + j * (int64_t)W32p)[q] = out;
+}
+
 __global__ __launch_bounds__(256) void k_pack_x_f32(const float *__restrict__ X, int64_t ld, int64_t n, int64_t p,
                                                     int W32p, uint32_t *__restrict__ XC, float *__restrict__ XF,
                                                     int64_t nF, int *__restrict__ err)
@@ -2709,6 +2757,22 @@ hipError_t launch_pack_x_i8(const int8_t *X, int64_t ld, int64_t n, int64_t p, i
                             hipStream_t st)
 {
     hipLaunchKernelGGL(k_pack_x_i8, dim3(grid1(p, 4)), dim3(256), 0, st, X, ld, n, p, W32p, XC, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_x_i8_rows(const int8_t *X, int64_t ld, int64_t n, int64_t p, uint64_t *XR, int64_t P64,
+                                 int *err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_x_i8_rows, dim3(grid1((uint64_t)n * (uint64_t)P64, 4)), dim3(256), 0, st, X, ld, n, p,
+                       XR, P64, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_rc(const uint64_t *XR, int64_t n, int64_t p, int64_t P64, int W32p, uint32_t *XC,
+                               hipStream_t st)
+{
+    const uint64_t waves = (uint64_t)P64 * (uint64_t)(W32p / 4);
+    hipLaunchKernelGGL(k_transpose_rc, dim3(grid1(waves, 4)), dim3(256), 0, st, XR, n, p, P64, W32p, XC);
     return hipGetLastError();
 }
 

@@ -49,20 +49,38 @@ struct Request {
 
 size_t y_size(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 1 : (yfmt == XYZ_Y_F32 ? 4 : 8)); }
 
-// Device bytes of one search with `chunk` repetitions per chunk: keys and
-// permutation (8p per repetition), bucket offsets, the tile list (about one
-// 16-byte tile per 24 x 24 candidates, at least p/24 per repetition), the
-// initial survivor buffer and merge scratch, and packed Y.
-uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk)
+// Device bytes of one request with `chunk` repetitions per chunk, from the buffers its path
+// allocates.  Algorithm 2: keys and permutation (8p per repetition), bucket offsets (or the
+// sort path's scratch), the tile list (about one 16-byte tile per 24 x 24 candidates, at least
+// p/24 per repetition), the initial survivor buffer and merge scratch, and packed Y.  The exact
+// search of +-1 data (brute_run): both sides staged in 256-column blocks of the packed columns
+// (2 p n / 8 bytes) with their popcounts, one survivor region of at least 1024 records per
+// workgroup of the persistent launch, and the merge.  The exact search of real data runs the
+// m = 0 search: one bucket of p columns cut into 64 x 64 matrix-core tiles.
+uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk, int yfmt)
 {
-    if (P.flags & XYZ_EXACT)   // survivors, merge scratch and packed Y only
-        return (uint64_t)((double)(1 << 16) * 32 * 2 + (double)x->W32p * 4 + (double)x->nF * 8 + 4096);
-    const double p = (double)x->p, nb = std::ldexp(1.0, P.m);
+    const double p = (double)x->p;
+    const double ybytes = (double)x->W32p * 4 + (double)x->nF * 8 + (double)x->n * 8 + 4096;
+    const double merge = (double)(1 << 16) * (32 + 72);      // initial survivors + dedup scratch per record
+    if (P.flags & XYZ_EXACT) {
+        const bool real = x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1;
+        if (!real) {
+            const double blocks = std::ceil(p / 256.0);
+            const double staged = 2 * blocks * 256.0 * (double)x->W32p * 4 + 2 * blocks * 256.0 * 4;
+            const double grid = 256;                         // workgroups of the persistent launch (cu_count / 8 * 8)
+            const double surv = grid * 1024 * 32 + grid * 12;
+            return (uint64_t)(staged + surv + merge + ybytes);
+        }
+        const double t = std::ceil(p / 64.0);
+        const double tiles = t * (t + 1) / 2;
+        return (uint64_t)(8 * p + 64 + 16 * tiles + 80 + merge + ybytes);
+    }
+    const double nb = std::ldexp(1.0, P.m);
     const double cand = p * (p - 1) / 2 / nb;
     const double tiles = std::max(p / 24.0, cand / 576.0);
     // the sort path (m > 15) replaces the 2^m bucket offsets by about 56 bytes of scratch per column
     const double per_rep = 8 * p + (P.m <= 15 ? 4 * (nb + 1) : 56 * p) + 16 * tiles + 80;
-    const double fixed = (double)(1 << 16) * 32 * 2 + (double)x->W32p * 4 + (double)x->nF * 8 + (double)P.L * 48;
+    const double fixed = merge + ybytes + (double)P.L * 64 + (yfmt != XYZ_Y_I8_PM1 ? (double)x->n * 12 : 0.0);
     return (uint64_t)(per_rep * (double)chunk + fixed);
 }
 
@@ -90,11 +108,24 @@ struct xyz_server {
     bool stopping = false;
     uint64_t bytes_inflight = 0;
     int inflight = 0;
+    std::vector<uint64_t> held;   // device bytes each worker's context held after its last group
+    std::vector<uint64_t> est;    // estimated bytes of the group each worker runs (0: idle)
     xyz_serve_stats st{};
     std::vector<double> lat;
 };
 
 namespace {
+
+// Device bytes the workers' contexts may hold if worker w runs a group of `bytes` now: each
+// running worker its estimate (or more, if its context already holds more), each idle worker
+// what its context holds.  Lock held.
+uint64_t footprint(const xyz_server *s, int w, uint64_t bytes)
+{
+    uint64_t t = 0;
+    for (size_t v = 0; v < s->held.size(); ++v)
+        t += std::max(s->held[v], (int)v == w ? bytes : s->est[v]);
+    return t;
+}
 
 void worker_loop(xyz_server *s, int w)
 {
@@ -106,13 +137,22 @@ void worker_loop(xyz_server *s, int w)
         std::vector<Request *> batch;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [s] {
+            s->cv_work.wait(lk, [s, w] {
                 if (s->stopping) return true;
                 if (s->queue.empty()) return false;
                 const Request *h = s->queue.front();
-                return s->inflight == 0 || s->budget == 0 || s->bytes_inflight + h->bytes <= s->budget;
+                return s->inflight == 0 || s->budget == 0 || footprint(s, w, h->bytes) <= s->budget;
             });
             if (s->stopping) break;
+            if (s->budget && footprint(s, w, s->queue.front()->bytes) > s->budget) {
+                // nothing runs (inflight == 0), yet the idle contexts' workspaces leave no room:
+                // free them all (their threads touch their contexts only after taking a group,
+                // which needs this lock)
+                for (size_t v = 0; v < s->wctx.size(); ++v) {
+                    ws_release(s->wctx[v]);
+                    s->held[v] = s->wctx[v]->used;
+                }
+            }
             Request *h = s->queue.front();
             s->queue.pop_front();
             batch.push_back(h);
@@ -128,6 +168,7 @@ void worker_loop(xyz_server *s, int w)
                 }
             }
             for (Request *r : batch) r->running = true;
+            s->est[w] = bytes;
             s->bytes_inflight += bytes;
             s->inflight += (int)batch.size();
             s->st.batches += 1;
@@ -149,9 +190,13 @@ void worker_loop(xyz_server *s, int w)
                             P0.flags & ~XYZ_EXACT, nullptr, 0, nullptr, 0, stream, outs.data())
                 : run_group(ctx, batch[0]->x, (int)batch.size(), ys.data(), batch[0]->yfmt, XYZ_MEM_HOST,
                             ps.data(), stream, outs.data());
-        if (s->budget && ctx->used > s->budget) ws_release(ctx);
+        // keep at most this worker's share of the budget between groups, so that idle workers
+        // together never hold more than the budget
+        if (s->budget && ctx->used > s->budget / s->wctx.size()) ws_release(ctx);
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            s->held[w] = ctx->used;
+            s->est[w] = 0;
             const double t = now_ms();
             for (size_t q = 0; q < batch.size(); ++q) {
                 Request *r = batch[q];
@@ -199,6 +244,8 @@ extern "C" xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, i
         }
         s->wctx.push_back(c);
     }
+    s->held.assign(workers, 0);
+    s->est.assign(workers, 0);
     for (int w = 0; w < workers; ++w) s->threads.emplace_back(worker_loop, s, w);
     *out = s;
     return XYZ_OK;
@@ -232,15 +279,15 @@ extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void
     xyz_ctx probe{};
     int64_t chunk = (params->flags & XYZ_EXACT) ? 1 : chunk_reps(&probe, params->L, x->p, params->m);
     if (s->budget) {
-        while (chunk > 1 && estimate_bytes(x, r->params, chunk) > s->budget) chunk = (chunk + 1) / 2;
-        if (estimate_bytes(x, r->params, chunk) > s->budget) {
+        while (chunk > 1 && estimate_bytes(x, r->params, chunk, yfmt) > s->budget) chunk = (chunk + 1) / 2;
+        if (estimate_bytes(x, r->params, chunk, yfmt) > s->budget) {
             delete r;
             return fail(XYZ_ENOMEM, "request needs about %llu bytes even one repetition at a time, budget %llu",
-                        (unsigned long long)estimate_bytes(x, *params, 1), (unsigned long long)s->budget);
+                        (unsigned long long)estimate_bytes(x, *params, 1, yfmt), (unsigned long long)s->budget);
         }
     }
     r->chunk = chunk;
-    r->bytes = estimate_bytes(x, r->params, chunk);
+    r->bytes = estimate_bytes(x, r->params, chunk, yfmt);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) {
@@ -322,6 +369,8 @@ extern "C" xyz_status xyz_serve_stats_get(xyz_server *s, xyz_serve_stats *out)
     out->queued = (int32_t)s->queue.size();
     out->inflight = s->inflight;
     out->bytes_inflight = s->bytes_inflight;
+    out->bytes_held = 0;
+    for (size_t v = 0; v < s->held.size(); ++v) out->bytes_held += std::max(s->held[v], s->est[v]);
     if (!s->lat.empty()) {
         std::vector<double> v = s->lat;
         std::sort(v.begin(), v.end());

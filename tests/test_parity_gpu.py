@@ -365,3 +365,75 @@ def test_matrix_tile_fragment_shapes(ctx, n, p, m, L, kappa, two, ybias, seed):
     if ybias == 1.0:
         assert (rr["cmask"] == 0).all()
     assert_same_binary(res, rp, rr)
+
+
+@pytest.mark.parametrize("n,p,ld_pad,device", [(200, 2000, 0, False), (77, 130, 5, False), (1025, 3001, 0, True),
+                                               (64, 64, 64, True), (3, 1, 0, False)])
+def test_rowmajor_int8_input_bit_exact(ctx, n, p, ld_pad, device):
+    """X handed over as int8 +-1 in row-major order (XYZ_X_I8_PM1_ROWMAJOR), from
+    host or device memory and with a leading dimension past p: the search equals
+    the oracle bit for bit, and the exact search equals the one on the same X
+    handed over column-major."""
+    import ctypes
+    import torch
+    d = synthgen.small_binary(n, p, seed=n + p, planted=[(0, p - 1)] if p > 1 else [], flip=0.2)
+    ld = p + ld_pad
+    buf = np.ones((n, ld), dtype=np.int8)
+    buf[:, :p] = d.XT.T
+    _log(f"row-major case n={n} p={p} ld={ld} device={device}")
+    if device:
+        src = torch.from_numpy(buf).to("cuda:0")
+        ptr, mem = src.data_ptr(), xyz.XYZ_MEM_DEVICE
+    else:
+        src = buf
+        ptr, mem = buf.ctypes.data, xyz.XYZ_MEM_HOST
+    h = ctypes.c_void_p()
+    rc = xyz.lib().xyz_x_create(ctx.h, ptr, xyz.XYZ_X_I8_PM1_ROWMAJOR, mem, n, p, ld, None, ctypes.byref(h))
+    assert rc == 0, xyz.lib().xyz_last_error()
+    torch.cuda.synchronize()
+    m, L, kappa = min(6, max(1, n // 20)), 9, 0.05
+    res = ctx.search(h, d.Y, m=m, L=L, kappa=kappa, seed=3)
+    rp, rr = oracle.search(d.XT, d.Y, m, L, kappa, seed=3)
+    assert_same_binary(res, rp, rr)
+    if p > 1:
+        xc = ctx.x_create(d.XT)
+        a = ctx.bruteforce(h, d.Y, -0.1)["pairs"]
+        b = ctx.bruteforce(xc, d.Y, -0.1)["pairs"]
+        assert len(a) == len(b) and all(np.array_equal(a[f], b[f]) for f in ("j", "k", "s"))
+        ctx.x_destroy(xc)
+    xyz.xyz_x_destroy(h)
+
+
+def test_rowmajor_rejects_bad_values(ctx):
+    X = np.ones((40, 70), dtype=np.int8)
+    X[17, 33] = 0
+    with pytest.raises(xyz.XyzError) as ei:
+        ctx.x_create(X, row_major=True)
+    assert ei.value.code == xyz.XYZ_EINVAL
+    import ctypes
+    h = ctypes.c_void_p()
+    ok = np.ones((40, 70), dtype=np.int8)
+    # leading dimension shorter than a row
+    rc = xyz.lib().xyz_x_create(ctx.h, ok.ctypes.data, xyz.XYZ_X_I8_PM1_ROWMAJOR, xyz.XYZ_MEM_HOST, 40, 70, 69, None,
+                                ctypes.byref(h))
+    assert rc == xyz.XYZ_EINVAL
+    x = ctx.x_create(ok, row_major=True)
+    assert xyz.xyz_x_n(x) == 40 and xyz.xyz_x_p(x) == 70
+
+
+def test_binding_checks_sizes_against_x(ctx):
+    """The binding refuses responses and projection matrices whose length does not
+    match n (the C side would read n entries), and weights that do not fit int32."""
+    d = synthgen.small_binary(50, 30, seed=24)
+    x = ctx.x_create(d.XT)
+    with pytest.raises(ValueError):
+        ctx.search(x, d.Y[:49], m=2, L=2, kappa=0.1)
+    with pytest.raises(ValueError):
+        ctx.bruteforce(x, np.concatenate([d.Y, d.Y]), 0.1)
+    with pytest.raises(ValueError):
+        ctx.dense_search(x, d.Y, np.zeros((2, 49), dtype=np.int32), 1, 0.1)
+    wide = np.zeros((1, 50), dtype=np.int64)
+    wide[0, 3] = 1 << 31
+    with pytest.raises(ValueError):
+        ctx.dense_search(x, d.Y, wide, 1, 0.1)
+    ctx.search(x, d.Y, m=2, L=2, kappa=0.1)

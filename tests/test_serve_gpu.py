@@ -157,3 +157,61 @@ def test_exact_requests_in_the_mix(ctx, shared):
         assert np.array_equal(o["pairs"], ref["pairs"]) and len(o["pairs"]) > 0
     for (Y, kw), o in zip(reqs, ox):
         _same(o, ctx.search(x, Y, **kw))
+
+
+def test_budget_bounds_device_memory_with_exact_requests(ctx):
+    """Exact and xyz requests mixed under a budget of about 1.5 exact requests:
+    the exact search stages both sides of X (2 p n / 8 bytes), so admission must
+    count that, and idle workers' workspaces count against the budget too.  The
+    device memory in use (hipMemGetInfo, sampled while the server runs) never
+    exceeds the budget beyond a small allowance for the runtime, and every result
+    equals its stand-alone call."""
+    import torch
+    XT, _ = synthgen.genotype(2000, 60000, seed=33)
+    x = ctx.x_create(XT)
+    n = XT.shape[1]
+    r = np.random.default_rng(11)
+    exact = [(np.where(r.random(n) < 0.5, 1, -1).astype(np.int8), 0.1 + 0.005 * q) for q in range(4)]
+    xyzq = [(np.where(r.random(n) < 0.45, 1, -1).astype(np.int8), dict(m=12, L=8, kappa=0.12, seed=q % 2))
+            for q in range(6)]
+    staged = 2 * 60000 * 2000 // 8
+    budget = int(1.5 * (staged + (16 << 20)))
+    torch.cuda.synchronize()
+    srv = xyz.xyz_serve_start(ctx.h, budget, workers=3, max_batch=4)
+    samples, held = [], []
+    stop = threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            samples.append(torch.cuda.mem_get_info(0)[0])
+            held.append(xyz.xyz_serve_stats_get(srv)["bytes_held"])
+            stop.wait(0.0005)
+
+    base = torch.cuda.mem_get_info(0)[0]
+    th = threading.Thread(target=sampler)
+    th.start()
+    try:
+        te, tx = [], []
+        for q in range(4):
+            te.append(xyz.xyz_serve_submit(srv, x, exact[q][0], kappa=exact[q][1], exact=True))
+            for Y, kw in xyzq[q * 3 // 2:(q + 1) * 3 // 2]:
+                tx.append(xyz.xyz_serve_submit(srv, x, Y, **kw))
+        oe = [xyz.xyz_serve_wait(srv, t) for t in te]
+        ox = [xyz.xyz_serve_wait(srv, t) for t in tx]
+        st = xyz.xyz_serve_stats_get(srv)
+    finally:
+        stop.set()
+        th.join()
+        xyz.xyz_serve_stop(srv)
+    used = base - min(samples)
+    print(f"budget {budget >> 20} MiB, largest device use {used >> 20} MiB, largest accounted {max(held) >> 20} MiB, "
+          f"{len(samples)} samples", flush=True)
+    assert max(held) <= budget
+    assert used <= budget + (48 << 20)
+    assert st["completed"] == 4 + len(tx) and st["failed"] == 0
+    for (Y, k), o in zip(exact, oe):
+        ref = ctx.bruteforce(x, Y, k)
+        assert np.array_equal(o["pairs"], ref["pairs"]) and len(o["pairs"]) > 0
+    for (Y, kw), o in zip(xyzq, ox):
+        _same(o, ctx.search(x, Y, **kw))
+    ctx.x_destroy(x)
