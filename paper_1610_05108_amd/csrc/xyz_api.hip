@@ -533,7 +533,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     XYZ_TRY(ws(c, WS_KEYS, (size_t)chunk * p, &keys));
     if (m <= MAX_M_LDS) XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
     XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
-    XYZ_TRY(ws(c, WS_BASE, 3 * ((size_t)chunk * nys + 1), &base));
+    XYZ_TRY(ws(c, WS_BASE, NLISTS * ((size_t)chunk * nys + 1), &base));
     XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
     HIP_TRY(launch_zero(scnt, sizeof(unsigned long long), st));
     uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
@@ -565,7 +565,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
         bool redo = true;
         while (redo) {
             redo = false;
-            unsigned long long ntiles = 0, nsmall = 0, nmfma = 0;
+            unsigned long long ntiles = 0, nsmall = 0, nmfma = 0, nbig = 0;
             Tile *tiles = nullptr;
             if (m <= MAX_M_LDS) {
                 tm.begin(3);
@@ -573,13 +573,14 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 tm.end();
                 tm.begin(4);
                 HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
-                // list totals at base[K (R nys + 1) + R nys]: popcount, small, matrix-core tiles
+                // list totals at base[K (R nys + 1) + R nys]: popcount, small, matrix-core, big tiles
                 const size_t cnt1 = (size_t)R * nys + 1;
                 HIP_TRY(hipMemcpyAsync(&ntiles, base + cnt1 - 1, sizeof ntiles, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * cnt1 - 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&nmfma, base + 3 * cnt1 - 1, sizeof nmfma, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&nbig, base + 4 * cnt1 - 1, sizeof nbig, hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
-                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
+                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma + nbig), &tiles));
                 HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, mfma, base, tiles, st));
                 tm.end();
             } else {
@@ -608,7 +609,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                     XYZ_TRY(ws(c, WS_SKTAB, (size_t)R << m, &table));
                     HIP_TRY(launch_sk_table(rkey, dnr, nr, (uint64_t)R << m, table, st));
                 }
-                const uint64_t ncnt = 3ull * nys * nr;
+                const uint64_t ncnt = (uint64_t)NLISTS * nys * nr;
                 XYZ_TRY(ws(c, WS_SKCNT, ncnt + 1, &cnt));
                 HIP_TRY(launch_zero(cnt + ncnt, sizeof(uint32_t), st));
                 HIP_TRY(launch_sk_products(rkey, rstart, dnr, nr, S, m, nys, cinfo, R * nys, two, mfma, table, cnt,
@@ -618,16 +619,18 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 // positions of every (list, response, run) in the tile array; list starts and total
                 XYZ_TRY(ws(c, WS_SKHIST, std::max<size_t>(radix_hist_entries(S), (size_t)((ncnt + 1) / 2048 + 16)), &hist));
                 HIP_TRY(launch_scan_u32(cnt, ncnt + 1, hist, st));
-                uint32_t bnd[3] = {0, 0, 0};
+                uint32_t bnd[4] = {0, 0, 0, 0};
                 const uint64_t stride = (uint64_t)nys * nr;
                 HIP_TRY(hipMemcpyAsync(&bnd[0], cnt + stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&bnd[1], cnt + 2 * stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipMemcpyAsync(&bnd[2], cnt + ncnt, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&bnd[2], cnt + 3 * stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(&bnd[3], cnt + ncnt, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipStreamSynchronize(st));
                 ntiles = bnd[0];
                 nsmall = bnd[1] - bnd[0];
                 nmfma = bnd[2] - bnd[1];
-                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma), &tiles));
+                nbig = bnd[3] - bnd[2];
+                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma + nbig), &tiles));
                 HIP_TRY(launch_sk_tiles(rkey, rstart, dnr, nr, S, p, m, nys, cinfo, two, mfma, table, cnt, tiles, st));
                 tm.end();
             }
@@ -636,6 +639,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             va.ntiles = ntiles;
             va.nsmall = nsmall;
             va.nmfma = nmfma;
+            va.nbig = nbig;
             va.perm = perm;
             va.XC = x->XC;
             va.W32p = x->W32p;
@@ -653,14 +657,14 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             va.surv_count = scnt;
             va.surv_cap = surv_cap;
             va.info = cinfo;
-            const int g = (int)std::min<unsigned long long>(std::max(ntiles + nsmall + nmfma, 1ull),
+            const int g = (int)std::min<unsigned long long>(std::max(ntiles + nsmall + nmfma + nbig, 1ull),
                                                             (unsigned long long)grid);
             tm.begin(5);
             if (real) HIP_TRY(launch_verify_real(va, real_x ? 1 : 0, g, st));
             else HIP_TRY(launch_verify_bin(va, g, st));
             tm.end();
-            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0) + (nmfma ? 1 : 0);
-            timing.tiles += (int64_t)(ntiles + nsmall + nmfma);
+            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0) + (nmfma ? 1 : 0) + (nbig ? 1 : 0);
+            timing.tiles += (int64_t)(ntiles + nsmall + nmfma + nbig);
             unsigned long long cnt = 0;
             HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));

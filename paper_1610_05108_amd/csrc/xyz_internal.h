@@ -28,6 +28,12 @@ constexpr uint32_t MTILE_MIN_REAL = 33;
 // MTILE_WIDE is verified as one tile (up to 3 x 2 fragments of 32 x 32), so that neither
 // side is read twice; larger products are cut into MTILE x MTILE tiles.
 constexpr uint32_t MTILE_WIDE = 96;
+// +-1 data: products larger than that whose shorter side has at least BIG_MIN_SHORT columns
+// are verified by one workgroup per block pair of at most BIG_TILE x BIG_TILE columns, with
+// both blocks staged through LDS once (k_verify_lds): the fourth tile list.  A big tile stores
+// its sides minus one (1..BIG_TILE columns in a byte).
+constexpr int BIG_TILE = 256;
+constexpr uint32_t BIG_MIN_SHORT = 33;
 
 struct Tile {            // 16 bytes
     uint32_t rep;        // repetition index relative to the launch's first repetition
@@ -64,6 +70,7 @@ struct RepInfo {         // per repetition and response, filled on the device
     unsigned int max_bucket;
     unsigned int small_tiles; // one-tile bucket products with at most SMALL_TILE_PAIRS pairs
     unsigned long long mfma_tiles; // MTILE x MTILE tiles of products verified on the matrix cores
+    unsigned long long big_tiles;  // BIG_TILE x BIG_TILE block pairs of products staged through LDS
 };
 
 // ------------------------------------------------------------ launchers --
@@ -114,16 +121,18 @@ hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uin
 hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nrep, const int32_t *rows,
                        uint32_t *keys, hipStream_t st);
 // Bucket sort of each repetition's keys (one workgroup per repetition) plus the histogram-only
-// statistics of nys responses (info[r * nys + y]): candidates, tile counts of the three lists
-// (matrix-core tiles only when mfma != 0), max bucket.  offs [nrep][2^m + 1], perm [nrep][p].
+// statistics of nys responses (info[r * nys + y]): candidates, tile counts of the four lists
+// (matrix-core and big tiles only when mfma != 0), max bucket.  offs [nrep][2^m + 1], perm [nrep][p].
 hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info,
                          int two_sided, int mfma, uint32_t *offs, uint32_t *perm, hipStream_t st);
-// Exclusive scans over count = nrep*nys entries into base [3 (count + 1)] (u64): list K
-// (0: popcount tiles, 1: small tiles, 2: matrix-core tiles) at base + K (count + 1), its total
-// at base[K (count + 1) + count].
+// Exclusive scans over count = nrep*nys entries into base [NLISTS (count + 1)] (u64): list K
+// (0: popcount tiles, 1: small tiles, 2: matrix-core tiles, 3: big tiles) at base + K (count + 1),
+// its total at base[K (count + 1) + count].
+constexpr int NLISTS = 4;
 hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st);
 // Emit the tiles of every (repetition, response): popcount tiles first, then small tiles,
-// then matrix-core tiles (MTILE x MTILE), each list ordered by (repetition, response).
+// then matrix-core tiles (MTILE x MTILE), then big tiles, each list ordered by (repetition,
+// response).
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
                         int two_sided, int mfma, const unsigned long long *base, Tile *tiles, hipStream_t st);
 
@@ -143,8 +152,8 @@ constexpr int SK_TABLE_MAX_M = 22;
 hipError_t launch_sk_table(const uint64_t *run_key, const uint32_t *nruns, uint32_t nr, uint64_t entries,
                            uint32_t *table, hipStream_t st);
 // Clears the statistics of info[0..count) (keeping cmask), then per (response, run) counts the
-// tiles of its bucket products in cnt[list][y][rid] (lists: popcount, small, matrix-core;
-// 3 * nys * nr entries) and adds the statistics to info.  table: as above, or null (binary search).
+// tiles of its bucket products in cnt[list][y][rid] (lists: popcount, small, matrix-core, big;
+// NLISTS * nys * nr entries) and adds the statistics to info.  table: as above, or null (binary search).
 hipError_t launch_sk_products(const uint64_t *run_key, const uint32_t *run_start, const uint32_t *nruns, uint32_t nr,
                               uint64_t S, int m, int nys, RepInfo *info, int count, int two_sided, int mfma,
                               const uint32_t *table, uint32_t *cnt, hipStream_t st);
@@ -161,6 +170,7 @@ struct VerifyArgs {
     uint64_t ntiles;         // large tiles: tiles[0, ntiles)
     uint64_t nsmall;         // small tiles: tiles[ntiles, ntiles + nsmall)
     uint64_t nmfma;          // matrix-core tiles: tiles[ntiles + nsmall, ... + nmfma)
+    uint64_t nbig;           // big tiles: tiles[ntiles + nsmall + nmfma, ... + nbig)
     const uint32_t *perm;
     const uint32_t *XC;      // [p][W32p] bits
     int W32p;

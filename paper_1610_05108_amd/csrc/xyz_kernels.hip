@@ -478,7 +478,10 @@ __global__ __launch_bounds__(256) void k_hash_unbiased(const float *__restrict__
 //   kind 3: T tiles of MTILE x MTILE for the matrix cores (mfma = 1, +-1 data with
 //           n < 2^24: both sides at least MTILE_MIN columns, and a product within
 //           MTILE x MTILE_WIDE is one tile; mfma = 2, real data: both sides at least
-//           MTILE_MIN_REAL).
+//           MTILE_MIN_REAL),
+//   kind 4: T block pairs of at most BIG_TILE x BIG_TILE staged through LDS (mfma = 1: a
+//           larger product whose shorter side has at least BIG_MIN_SHORT columns, or a
+//           bucket's own pairs past MTILE columns).
 // A product of two different buckets that is one matrix-core tile (+-1 data): one side of
 // at most MTILE columns, the other of at most MTILE_WIDE.
 XYZ_DEV bool mfma_single(uint32_t a, uint32_t a2, int mfma)
@@ -495,7 +498,10 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
         const unsigned long long c = (unsigned long long)a * a2;
         if (c == 0) return 0;
         const uint32_t mmin = mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN;
-        if (mfma && a >= mmin && a2 >= mmin) {
+        if (mfma == 1 && min(a, a2) >= BIG_MIN_SHORT && !mfma_single(a, a2, mfma)) {
+            kind = 4;
+            T = cdiv_u64(a, BIG_TILE) * cdiv_u64(a2, BIG_TILE);
+        } else if (mfma && a >= mmin && a2 >= mmin) {
             kind = 3;
             T = mfma_single(a, a2, mfma) ? 1 : cdiv_u64(a, MTILE) * cdiv_u64(a2, MTILE);
         } else if (a <= (uint32_t)TILE && a2 <= (uint32_t)TILE && c <= SMALL_TILE_PAIRS) {
@@ -509,7 +515,11 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
     }
     if (b == b2 && a >= 2) {
         const unsigned long long c = (unsigned long long)a * (a - 1) / 2;
-        if (mfma && a >= (mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN_DIAG)) {
+        if (mfma == 1 && a > (uint32_t)MTILE) {
+            kind = 4;
+            const unsigned long long n = cdiv_u64(a, BIG_TILE);
+            T = n * (n + 1) / 2;
+        } else if (mfma && a >= (mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN_DIAG)) {
             kind = 3;
             const unsigned long long n = cdiv_u64(a, MTILE);
             T = n * (n + 1) / 2;
@@ -555,7 +565,7 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
         RepInfo *inf = info + (int64_t)r * nys + y;
         const uint32_t c = (uint32_t)inf->cmask & mask;
         const uint32_t cn = (~c) & mask;
-        unsigned long long cand = 0, cnts[4] = {0, 0, 0, 0};
+        unsigned long long cand = 0, cnts[5] = {0, 0, 0, 0, 0};
         unsigned mx = 0;
         for (int b = threadIdx.x; b < nb; b += 1024) {
             const uint32_t a = cnt[b];
@@ -572,12 +582,14 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
         const unsigned long long tiles = block_sum<1024>(cnts[2], shm);
         const unsigned long long small = block_sum<1024>(cnts[1], shm);
         const unsigned long long mtiles = block_sum<1024>(cnts[3], shm);
+        const unsigned long long btiles = block_sum<1024>(cnts[4], shm);
         mx = block_max<1024>(mx, shmax);
         if (threadIdx.x == 0) {
             inf->candidates = cand;
             inf->tiles = tiles;
             inf->small_tiles = (unsigned)small;
             inf->mfma_tiles = mtiles;
+            inf->big_tiles = btiles;
             inf->max_bucket = mx;
             inf->passed = 0;
             inf->fresh = 0;
@@ -617,9 +629,11 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const RepInfo *__restrict__ 
     const int seg = (count + 1023) / 1024;
     const int i0 = min(count, (int)threadIdx.x * seg), i1 = min(count, i0 + seg);
     auto tiles_of = [&](int list, int i) -> unsigned long long {
-        return list == 0 ? info[i].tiles : (list == 1 ? (unsigned long long)info[i].small_tiles : info[i].mfma_tiles);
+        return list == 0 ? info[i].tiles
+                         : (list == 1 ? (unsigned long long)info[i].small_tiles
+                                      : (list == 2 ? info[i].mfma_tiles : info[i].big_tiles));
     };
-    for (int list = 0; list < 3; ++list) {
+    for (int list = 0; list < NLISTS; ++list) {
         unsigned long long *bs = base + list * (count + 1);
         unsigned long long loc = 0;
         for (int i = i0; i < i1; ++i) loc += tiles_of(list, i);
@@ -678,14 +692,36 @@ XYZ_DEV Tile single_tile(uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1,
     return t;
 }
 
-// Tile number t (tiles of ts x ts, or the one tile of mfma_single) of the product of bucket b
-// and its partner b2.
-XYZ_DEV Tile pair_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t b, uint32_t b2,
-                       const uint32_t *of, int mfma)
+// Block pair (ia, ib) of BIG_TILE columns per side; the sides are stored minus one.
+XYZ_DEV Tile big_tile(uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1, uint32_t a, uint32_t o2, uint32_t a2,
+                      uint32_t ia, uint32_t ib, uint8_t diag)
 {
-    const uint32_t o1 = of[b], a = of[b + 1] - o1;
-    const uint32_t o2 = of[b2], a2 = of[b2 + 1] - o2;
-    if (b != b2) {
+    Tile t;
+    t.rep = r;
+    t.a0 = pbase + o1 + ia * BIG_TILE;
+    t.b0 = pbase + o2 + ib * BIG_TILE;
+    t.na = (uint8_t)(min((uint32_t)BIG_TILE, a - ia * BIG_TILE) - 1);
+    t.nb = (uint8_t)(min((uint32_t)BIG_TILE, a2 - ib * BIG_TILE) - 1);
+    t.diag = diag;
+    t.ysel = (uint8_t)ysel;
+    return t;
+}
+
+// Tile number t of the product of bucket b (o1, a) and its partner b2 (o2, a2): a big block
+// pair (ts = BIG_TILE), a tile of ts x ts, or the one tile of mfma_single.
+XYZ_DEV Tile product_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, bool own, uint32_t o1,
+                          uint32_t a, uint32_t o2, uint32_t a2, int mfma)
+{
+    if (ts == (uint32_t)BIG_TILE) {
+        uint32_t ia, ib;
+        if (own) {
+            tri_index(t, (a + BIG_TILE - 1) / BIG_TILE, ia, ib);
+            return big_tile(r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
+        }
+        const uint32_t nB = (a2 + BIG_TILE - 1) / BIG_TILE;
+        return big_tile(r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
+    }
+    if (!own) {
         if (ts == (uint32_t)MTILE && mfma_single(a, a2, mfma)) return single_tile(r, ysel, pbase, o1, a, o2, a2);
         const uint32_t nB = (a2 + ts - 1) / ts;
         return make_tile(ts, r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
@@ -696,14 +732,29 @@ XYZ_DEV Tile pair_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, uint3
     return make_tile(ts, r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
 }
 
+// Tile number t of the product of bucket b and its partner b2 (offsets of).
+XYZ_DEV Tile pair_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t b, uint32_t b2,
+                       const uint32_t *of, int mfma)
+{
+    const uint32_t o1 = of[b], a = of[b + 1] - o1;
+    const uint32_t o2 = of[b2], a2 = of[b2 + 1] - o2;
+    return product_tile(ts, t, r, ysel, pbase, b == b2, o1, a, o2, a2, mfma);
+}
+
+XYZ_DEV uint32_t kind_tile(int kind)
+{
+    return kind == 4 ? (uint32_t)BIG_TILE : (kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE);
+}
+
 // Bucket products with more tiles than this are emitted by the whole block.
 constexpr unsigned HEAVY_TILES = 64;
 constexpr int HEAVY_CAP = 512;
 
-// Tiles of every (repetition, response) into three regions of one array: the
+// Tiles of every (repetition, response) into four regions of one array: the
 // popcount tiles (TILE) at base0[ry], the small tiles after all popcount tiles
 // at base0[count] + base1[ry], the matrix-core tiles (MTILE) after those at
-// base0[count] + base1[count] + base2[ry] (baseK = base + K (count + 1)).
+// base0[count] + base1[count] + base2[ry], the big tiles (BIG_TILE) last
+// (baseK = base + K (count + 1)).
 __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs, int64_t p, int m, int nys,
                                                const RepInfo *__restrict__ info, int two_sided, int mfma,
                                                const unsigned long long *__restrict__ base, Tile *__restrict__ tiles)
@@ -713,7 +764,8 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     __shared__ unsigned long long hpos[HEAVY_CAP], hcnt_t[HEAVY_CAP];
     __shared__ int hcnt;
     const int ry = blockIdx.x, count = gridDim.x;
-    const unsigned long long *base0 = base, *base1 = base + (count + 1), *base2 = base + 2 * (count + 1);
+    const unsigned long long *base0 = base, *base1 = base + (count + 1), *base2 = base + 2 * (count + 1),
+                             *base3 = base + 3 * (count + 1);
     const int r = ry / nys, y = ry % nys;
     const int nb = 1 << m;
     const uint32_t mask = (uint32_t)(nb - 1);
@@ -724,7 +776,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     if (threadIdx.x == 0) hcnt = 0;
     const int seg = (nb + 255) / 256;
     const int b0 = min(nb, (int)threadIdx.x * seg), b1 = min(nb, b0 + seg);
-    unsigned long long loc[4] = {0, 0, 0, 0};
+    unsigned long long loc[5] = {0, 0, 0, 0, 0};
     for (int b = b0; b < b1; ++b) {
         const uint32_t a = of[b + 1] - of[b];
         for (int side = 0; side < (second ? 2 : 1); ++side) {
@@ -735,10 +787,11 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
             loc[kind] += T;
         }
     }
-    unsigned long long tot, pos[4];
+    unsigned long long tot, pos[5];
     pos[2] = base0[ry] + block_scan_excl<256>(loc[2], shm, &tot);
     pos[1] = base0[count] + base1[ry] + block_scan_excl<256>(loc[1], shm, &tot);
     pos[3] = base0[count] + base1[count] + base2[ry] + block_scan_excl<256>(loc[3], shm, &tot);
+    pos[4] = base0[count] + base1[count] + base2[count] + base3[ry] + block_scan_excl<256>(loc[4], shm, &tot);
     const uint32_t pbase = (uint32_t)((int64_t)r * p);
     for (int b = b0; b < b1; ++b) {
         for (int side = 0; side < (second ? 2 : 1); ++side) {
@@ -747,7 +800,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
             int kind;
             product_tiles(b, b2, of[b + 1] - of[b], of[b2 + 1] - of[b2], mfma, kind, T);
             if (kind == 0) continue;
-            const uint32_t ts = kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE;
+            const uint32_t ts = kind_tile(kind);
             int h = -1;
             if (T > HEAVY_TILES) {
                 h = atomicAdd(&hcnt, 1);
@@ -863,19 +916,20 @@ XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t 
     return cand;
 }
 
-// Per (response y, run): tile counts of the three lists into cnt[list][y][rid], and the
+// Per (response y, run): tile counts of the four lists into cnt[list][y][rid], and the
 // repetition's statistics.  A block takes SK_ITEMS * 256 consecutive items; each thread sums its
 // items per (repetition, response), flushing with atomics only when that changes, and the
 // waves whose lanes end on one (repetition, response) add their sums once.
 constexpr int SK_ITEMS = 16;
 
-XYZ_DEV void sk_flush(RepInfo *info, int64_t key, const unsigned long long v[4], uint32_t mx)
+XYZ_DEV void sk_flush(RepInfo *info, int64_t key, const unsigned long long v[5], uint32_t mx)
 {
     RepInfo *inf = info + key;
     if (v[0]) atomicAdd(&inf->candidates, v[0]);
     if (v[1]) atomicAdd(&inf->tiles, v[1]);
     if (v[2]) atomicAdd(&inf->small_tiles, (unsigned)v[2]);
     if (v[3]) atomicAdd(&inf->mfma_tiles, v[3]);
+    if (v[4]) atomicAdd(&inf->big_tiles, v[4]);
     atomicMax(&inf->max_bucket, mx);
 }
 
@@ -890,7 +944,7 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
     const uint64_t total = (uint64_t)nr * nys;
     const uint64_t base = (uint64_t)blockIdx.x * SK_ITEMS * 256;
     int64_t key = -1;
-    unsigned long long v[4] = {0, 0, 0, 0};
+    unsigned long long v[5] = {0, 0, 0, 0, 0};
     uint32_t mx = 0;
     for (int it = 0; it < SK_ITEMS; ++it) {
         const uint64_t tid = base + (uint64_t)it * 256 + threadIdx.x;
@@ -901,19 +955,21 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
         if (k != key) {
             if (key >= 0) sk_flush(info, key, v, mx);
             key = k;
-            v[0] = v[1] = v[2] = v[3] = 0;
+            v[0] = v[1] = v[2] = v[3] = v[4] = 0;
             mx = 0;
         }
         const uint32_t c = (uint32_t)info[k].cmask & (uint32_t)((1ull << m) - 1);
-        unsigned long long tl[4] = {0, 0, 0, 0};
+        unsigned long long tl[5] = {0, 0, 0, 0, 0};
         v[0] += run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
                              [&](uint32_t, uint32_t, int kind, unsigned long long T) { tl[kind] += T; });
         cnt[0 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[2];
         cnt[1 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[1];
         cnt[2 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[3];
+        cnt[3 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[4];
         v[1] += tl[2];
         v[2] += tl[1];
         v[3] += tl[3];
+        v[4] += tl[4];
         mx = max(mx, run_len(run_start, nr, S, rid));
     }
     // lanes that end on lane 0's (repetition, response) add their sums once per wave
@@ -923,7 +979,7 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], d, 64);
+            for (int q = 0; q < 5; ++q) v[q] += __shfl_xor(v[q], d, 64);
             mx = max(mx, (uint32_t)__shfl_xor(mx, d, 64));
         }
         if (lane_id() == 0) sk_flush(info, k0, v, mx);
@@ -932,8 +988,8 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
     }
 }
 
-// Tiles of every (response, run) at pos[list][y][rid] (exclusive scan over the three lists
-// laid end to end, so the popcount, small and matrix-core lists follow each other).
+// Tiles of every (response, run) at pos[list][y][rid] (exclusive scan over the four lists
+// laid end to end, so the popcount, small, matrix-core and big lists follow each other).
 __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ run_key,
                                                   const uint32_t *__restrict__ run_start,
                                                   const uint32_t *__restrict__ nruns, uint64_t S, int64_t p, int m,
@@ -950,33 +1006,19 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
     const uint32_t c = (uint32_t)info[r * nys + y].cmask & (uint32_t)((1ull << m) - 1);
     const uint32_t pbase = (uint32_t)(r * (uint64_t)p);
     const uint32_t o1 = run_start[rid] - pbase, a = run_len(run_start, nr, S, rid);
-    uint64_t at[4];
+    uint64_t at[5];
     at[2] = pos[0 * cnt_stride + (uint64_t)y * nr + rid];
     at[1] = pos[1 * cnt_stride + (uint64_t)y * nr + rid];
     at[3] = pos[2 * cnt_stride + (uint64_t)y * nr + rid];
+    at[4] = pos[3 * cnt_stride + (uint64_t)y * nr + rid];
     run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
                  [&](uint32_t rid2, uint32_t a2, int kind, unsigned long long T) {
-                     const uint32_t ts = kind == 3 ? (uint32_t)MTILE : (uint32_t)TILE;
+                     const uint32_t ts = kind_tile(kind);
                      const uint32_t o2 = run_start[rid2] - pbase;
                      const bool own = rid2 == rid;
-                     if (kind == 3 && !own && mfma_single(a, a2, mfma)) {
-                         tiles[at[kind]] = single_tile((uint32_t)r, y, pbase, o1, a, o2, a2);
-                         at[kind] += T;
-                         return;
-                     }
-                     const uint32_t nB = (a2 + ts - 1) / ts, nA = (a + ts - 1) / ts;
-                     for (unsigned long long t = 0; t < T; ++t) {
-                         uint32_t ia, ib;
-                         if (own) {
-                             tri_index(t, nA, ia, ib);
-                         } else {
-                             ia = (uint32_t)(t / nB);
-                             ib = (uint32_t)(t % nB);
-                         }
-                         tiles[at[kind] + t] =
-                             make_tile(ts, (uint32_t)r, y, pbase, o1, a, own ? o1 : o2, own ? a : a2, ia, ib,
-                                       (uint8_t)(own && ia == ib));
-                     }
+                     for (unsigned long long t = 0; t < T; ++t)
+                         tiles[at[kind] + t] = product_tile(ts, t, (uint32_t)r, y, pbase, own, o1, a, own ? o1 : o2,
+                                                            own ? a : a2, mfma);
                      at[kind] += T;
                  });
 }
@@ -1000,6 +1042,7 @@ __global__ __launch_bounds__(256) void k_sk_clear_info(RepInfo *__restrict__ inf
     info[i].max_bucket = 0;
     info[i].small_tiles = 0;
     info[i].mfma_tiles = 0;
+    info[i].big_tiles = 0;
 }
 
 // ----------------------------------------------------------- FP4 operands --
@@ -1520,6 +1563,230 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
         case 14: tile_body(t, I3{}, I2{}); break;
         default: break;
         }
+    }
+}
+
+// Big tiles (products of large buckets, kind 4): one workgroup of 8 waves per
+// block pair of at most BIG_TILE x BIG_TILE columns, on the FP4 matrix cores as
+// in the exact search.  Both blocks are gathered from the packed columns once,
+// in chunks of BKQ quads (128 rows each), into LDS: the A side as z = y ^ x,
+// the B side as x with bits 0 and 2 of every nibble swapped, the words of a
+// quad in the order 0, 2, 1, 3 so that lane half h of a fragment reads words h
+// and h + 2 as one 8-byte load.  Eight consecutive threads read the 128
+// contiguous bytes of one column's chunk.  The next chunk's loads are in
+// flight while the waves multiply the current one (two LDS buffers, one
+// barrier per chunk).  Wave (wa, wb) owns A columns 64 wa.. and B columns
+// 128 wb.. as up to 2 x 4 fragments of 32 x 32; positions past the end of a
+// block are staged as copies of its last column, so their products duplicate
+// real ones and the cheap threshold test needs no masks.  Column popcounts are
+// summed by the staging threads over the chunks and reduced across the eight
+// threads of a column with the last chunk.
+constexpr int BKQ = 8;                          // quads per staged chunk (1024 rows)
+constexpr int BROW = BIG_TILE + 1;              // uint4 per LDS row (one quad of every column), padded
+constexpr size_t BIG_LDS = (size_t)2 * 2 * BKQ * BROW * sizeof(uint4);   // [buffer][side][quad][column]
+
+template <bool TWO>
+__global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
+{
+    extern __shared__ uint4 bl[];
+    __shared__ __align__(16) uint32_t bpop[2][2][BIG_TILE];   // [tile parity][side][column] popcounts
+    const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wa = wave >> 1, wb = wave & 1;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int sq = tid & 7, sc = tid >> 3;       // staging: quad sq of columns sc + 64 r, r < 4
+    const int W4 = a.W32p >> 2;
+    const int NC = (W4 + BKQ - 1) / BKQ;
+    const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
+    const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall + a.nmfma);
+    const uint2 *bl2 = reinterpret_cast<const uint2 *>(bl);
+    const int32_t n32 = (int32_t)a.n;
+    int par = 0;
+    for (uint64_t ti = blockIdx.x; ti < a.nbig; ti += gridDim.x, par ^= 1) {
+        const Tile t = tile_from(T4[ti]);
+        const int na = (int)t.na + 1, nb = (int)t.nb + 1;
+        const int FA = (na + 31) >> 5, FB = (nb + 31) >> 5;
+        const int nua = min(max(FA - 2 * wa, 0), 2), nvb = min(max(FB - 4 * wb, 0), 4);
+        const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
+        // this thread's staging slots: column ids (NOCOL: not staged)
+        constexpr uint32_t NOCOL = ~0u;
+        uint32_t col[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int side = r >> 2, c = sc + 64 * (r & 3);
+            const int nside = side ? nb : na, fs = side ? FB : FA;
+            col[r] = c < 32 * fs ? a.perm[(side ? t.b0 : t.a0) + min(c, nside - 1)] : NOCOL;
+        }
+        uint32_t pops[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) pops[r] = 0;
+        uint4 pre[8], ypre;
+        auto load_chunk = [&](int ch) {
+            const int qi = ch * BKQ + sq;
+            const bool in = qi < W4;
+            ypre = in ? y4[qi] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                pre[r] = (in && col[r] != NOCOL) ? XC4[(uint64_t)col[r] * W4 + qi] : make_uint4(0, 0, 0, 0);
+        };
+        // registers -> LDS buffer `buf` (A side z = y ^ x, B side bit-swapped), popcounts; with the
+        // last chunk, the column popcounts are complete: reduce and publish them
+        auto store_chunk = [&](int buf, bool last) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (col[r] == NOCOL) continue;
+                const int side = r >> 2, c = sc + 64 * (r & 3);
+                uint4 v = pre[r];
+                if (side == 0) {
+                    v.x ^= ypre.x;
+                    v.y ^= ypre.y;
+                    v.z ^= ypre.z;
+                    v.w ^= ypre.w;
+                } else {
+                    v.x = swap02(v.x);
+                    v.y = swap02(v.y);
+                    v.z = swap02(v.z);
+                    v.w = swap02(v.w);
+                }
+                pops[r] += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                bl[((buf * 2 + side) * BKQ + sq) * BROW + c] = make_uint4(v.x, v.z, v.y, v.w);
+            }
+            if (last) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    uint32_t v = pops[r];
+                    v += __shfl_xor(v, 1, 64);
+                    v += __shfl_xor(v, 2, 64);
+                    v += __shfl_xor(v, 4, 64);
+                    if (sq == 0 && col[r] != NOCOL) bpop[par][r >> 2][sc + 64 * (r & 3)] = v;
+                }
+            }
+        };
+        v16f acc[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = v16f{};
+        // the products of one chunk; FULL: all 2 x 4 fragments of the wave are inside the block pair
+        auto compute = [&](int ch, int buf, auto full) {
+            constexpr bool FULL = decltype(full)::value;
+            const int nq = min(BKQ, W4 - ch * BKQ);
+            const uint2 *LA = bl2 + (size_t)((buf * 2 + 0) * BKQ) * (2 * BROW) + 2 * (wa * 64 + l32) + h;
+            const uint2 *LB = bl2 + (size_t)((buf * 2 + 1) * BKQ) * (2 * BROW) + 2 * (wb * 128 + l32) + h;
+#pragma unroll
+            for (int q = 0; q < BKQ; ++q) {
+                if (q >= nq) break;
+                uint2 fa[2], fb[4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) fa[u] = LA[q * 2 * BROW + 2 * 32 * u];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) fb[v] = LB[q * 2 * BROW + 2 * 32 * v];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const v8i ea0 = expand_a(k ? fa[0].y : fa[0].x), ea1 = expand_a(k ? fa[1].y : fa[1].x);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const v8i eb = expand_b(k ? fb[v].y : fb[v].x);
+                        if (FULL || (0 < nua && v < nvb)) acc[0][v] = mfma_fp4(ea0, eb, acc[0][v]);
+                        if (FULL || (1 < nua && v < nvb)) acc[1][v] = mfma_fp4(ea1, eb, acc[1][v]);
+                    }
+                }
+            }
+        };
+        load_chunk(0);
+        store_chunk(0, NC == 1);
+        lds_barrier();
+        const bool active = nua > 0 && nvb > 0, full = nua == 2 && nvb == 4;
+        for (int ch = 0; ch < NC; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < NC) load_chunk(ch + 1);
+            if (full) compute(ch, buf, std::true_type{});
+            else if (active) compute(ch, buf, std::false_type{});
+            if (ch + 1 < NC) store_chunk(buf ^ 1, ch + 2 == NC);
+            lds_barrier();
+        }
+        if (!active) continue;
+        // cheap test per fragment: x = 4C - 2|z_a| over the lane's 16 rows against smin - n + 2|x_b|
+        // (and -smin - n + 2|x_b| two-sided), exact in FP32
+        const int32_t smin = (int32_t)a.smin[t.ysel];
+        const uint32_t *popA = bpop[par][0], *popB = bpop[par][1];
+        uint32_t hitmask = 0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u >= nua) break;
+            float tA[16];
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint4 v4 = *reinterpret_cast<const uint4 *>(&popA[wa * 64 + u * 32 + q4 * 8 + h * 4]);
+                tA[4 * q4 + 0] = (float)(2 * v4.x);
+                tA[4 * q4 + 1] = (float)(2 * v4.y);
+                tA[4 * q4 + 2] = (float)(2 * v4.z);
+                tA[4 * q4 + 3] = (float)(2 * v4.w);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (v >= nvb) break;
+                const int32_t pb2 = 2 * (int32_t)popB[wb * 128 + v * 32 + l32];
+                float mx = -1e30f, mn = 1e30f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float x = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
+                    mx = fmaxf(mx, x);
+                    if (TWO) mn = fminf(mn, x);
+                }
+                const bool hit = mx >= (float)(smin - n32 + pb2) || (TWO && mn <= (float)(-smin - n32 + pb2));
+                hitmask |= (hit ? 1u : 0u) << (u * 4 + v);
+            }
+        }
+        if (__ballot(hitmask != 0) == 0) continue;
+        // rare: the fragments that hit are checked pair by pair.  Their counts go through this
+        // wave's slot in the second staging buffer (free until the next tile stores its second
+        // chunk, which follows a barrier that every wave reaches after this pass), so that the
+        // rows are indexed at run time; each lane reads back only what it wrote.
+        float *fbuf = reinterpret_cast<float *>(bl + (size_t)2 * BKQ * BROW) + wave * 16 * 64;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const bool fh = (hitmask >> (u * 4 + v)) & 1u;
+                if (__ballot(fh) == 0) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) fbuf[r * 64 + lane] = acc[u][v][r];
+                const int cb = wb * 128 + v * 32 + l32;
+                const int32_t pb2 = 2 * (int32_t)popB[cb];
+                const int row0 = wa * 64 + u * 32 + h * 4;
+                uint32_t msk = 0;
+                if (fh && cb < nb) {
+#pragma unroll 1
+                    for (int r = 0; r < 16; ++r) {
+                        const int ra = row0 + (r >> 2) * 8 + (r & 3);
+                        const int32_t sv = n32 - 2 * (int32_t)popA[ra] - pb2 + 4 * (int32_t)fbuf[r * 64 + lane];
+                        const bool pass = TWO ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin);
+                        if (pass && ra < na && (!t.diag || ra < cb)) msk |= 1u << r;
+                    }
+                }
+                unsigned long long idx = reserve_survivors(a, t, __popc(msk));
+                if (idx == ~0ull) continue;
+                const uint32_t k = a.perm[t.b0 + min(cb, nb - 1)];
+                while (msk) {
+                    const int r = __ffs(msk) - 1;
+                    msk &= msk - 1;
+                    const int ra = row0 + (r >> 2) * 8 + (r & 3);
+                    const uint32_t j = a.perm[t.a0 + ra];
+                    const int32_t sv = n32 - 2 * (int32_t)popA[ra] - pb2 + 4 * (int32_t)fbuf[r * 64 + lane];
+                    if (idx < a.surv_cap) {
+                        Survivor sr;
+                        sr.j = min(j, k);
+                        sr.k = max(j, k);
+                        sr.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                        sr.s = sv;
+                        sr.value = (double)sv;
+                        sr.ysel = t.ysel;
+                        sr.pad = 0;
+                        a.surv[idx] = sr;
+                    }
+                    ++idx;
+                }
+            }
     }
 }
 
@@ -2750,6 +3017,12 @@ hipError_t kernels_init()
 {
     hipError_t e = hipFuncSetAttribute((const void *)k_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (1 << MAX_M_LDS) * 4);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_verify_lds<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)BIG_LDS);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_verify_lds<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)BIG_LDS);
     return e;
 }
 
@@ -2894,6 +3167,13 @@ hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
     if (a.nmfma)
         hipLaunchKernelGGL(k_verify_mfma, dim3((unsigned)std::min<uint64_t>((a.nmfma + 3) / 4, (uint64_t)grid)),
                            dim3(256), 0, st, a);
+    if (a.nbig) {
+        const unsigned g = (unsigned)std::min<uint64_t>(a.nbig, (uint64_t)std::max(grid / 3, 1));
+        if (a.two_sided)
+            hipLaunchKernelGGL(k_verify_lds<true>, dim3(g), dim3(512), BIG_LDS, st, a);
+        else
+            hipLaunchKernelGGL(k_verify_lds<false>, dim3(g), dim3(512), BIG_LDS, st, a);
+    }
     if (a.nsmall) {
         const uint64_t groups = (a.nsmall + 63) / 64;                  // 64 small tiles per wave step
         hipLaunchKernelGGL(k_verify_small, dim3((unsigned)std::min<uint64_t>(groups, (uint64_t)grid)), dim3(64), 0, st,

@@ -51,9 +51,9 @@ uint64_t fixed_bytes(const xyz_x *x, const xyz_params &P, int yfmt)
 uint64_t per_rep_bytes(const xyz_x *x, int m)
 {
     const uint64_t p = (uint64_t)x->p;
-    uint64_t b = 4 * (uint64_t)std::max(m, 1) + 8 * p + 24;
+    uint64_t b = 4 * (uint64_t)std::max(m, 1) + 8 * p + 8 * NLISTS;
     if (m <= MAX_M_LDS) b += 4 * ((1ull << m) + 1);
-    else b += 60 * p + (m <= SK_TABLE_MAX_M ? 4ull << m : 0);
+    else b += (48 + 4 * NLISTS) * p + (m <= SK_TABLE_MAX_M ? 4ull << m : 0);
     return b;
 }
 

@@ -437,3 +437,23 @@ def test_binding_checks_sizes_against_x(ctx):
     with pytest.raises(ValueError):
         ctx.dense_search(x, d.Y, wide, 1, 0.1)
     ctx.search(x, d.Y, m=2, L=2, kappa=0.1)
+
+
+BIG_CASES = [
+    # n, p, m, L, kappa, two_sided, seed: bucket products past 64 x 96 columns (LDS-staged tiles)
+    (1025, 3000, 2, 4, 0.08, False, 31),     # buckets of ~750: 3 x 3 block pairs, ragged last blocks
+    (2000, 5000, 3, 3, 0.06, True, 32),      # two-sided: partners b ^ c and b ^ ~c
+    (5000, 2100, 1, 3, 0.04, False, 33),     # n = 5000: five staged chunks of 1024 rows
+    (700, 1100, 2, 3, -2.0, False, 34),      # every candidate survives: the pair-by-pair pass everywhere
+    (333, 900, 0, 1, 0.1, False, 35),        # m = 0: one bucket, its own pairs as triangular block pairs
+    (64, 600, 1, 6, 0.2, True, 36),          # one chunk of one quad
+    (4097, 1300, 2, 2, 0.05, False, 37),     # a partial last chunk (33 quads)
+]
+
+
+@pytest.mark.parametrize("n,p,m,L,kappa,two,seed", BIG_CASES)
+def test_big_bucket_products_bit_exact(ctx, n, p, m, L, kappa, two, seed):
+    d = synthgen.small_binary(n, p, seed=seed, planted=[(1, p - 2), (5, 17)], flip=0.3)
+    res, rp, rr = run_both(ctx, d.XT, d.Y, m, L, kappa, seed=seed, two_sided=two)
+    assert_same_binary(res, rp, rr)
+    assert res["reps"]["max_bucket"].max() > 96
