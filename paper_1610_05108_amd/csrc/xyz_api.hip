@@ -521,6 +521,13 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     HIP_TRY(hipMemcpyAsync(dkap, hkap, sizeof(double) * nys, hipMemcpyHostToDevice, st));
     XYZ_TRY(check_err_flag(err, st));
 
+    // column popcounts for the big tiles (+-1 data on the matrix cores)
+    uint32_t *cpop = nullptr;
+    if (mfma == 1) {
+        XYZ_TRY(ws(c, WS_CPOP, (size_t)(nys + 1) * p, &cpop));
+        HIP_TRY(launch_col_pops(x->XC, x->W32p, yb, nys, p, cpop, st));
+    }
+
     // ---- repetitions, in chunks
     const int nb = 1 << m;
     const int64_t chunk = chunk_reps(c, L, p, m);
@@ -646,6 +653,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             va.XF = x->XF;
             va.nF = x->nF;
             va.yb = yb;
+            va.cpop = cpop;
+            va.p = p;
             va.yd = yd;
             va.n = n;
             va.smin = dsmin;

@@ -177,6 +177,8 @@ struct VerifyArgs {
     const float *XF;         // [p][nF] values (continuous X) or null
     int64_t nF;
     const uint32_t *yb;      // [nys][W32p] bits of Y
+    const uint32_t *cpop;    // big tiles: [nys + 1][p] popcounts |y_y ^ x_j| (rows y < nys) and |x_j| (row nys)
+    int64_t p;
     const double *yd;        // [nys][nF] values of Y
     int64_t n;
     const int64_t *smin;     // [nys] integer thresholds (binary data)
@@ -189,6 +191,9 @@ struct VerifyArgs {
     uint64_t surv_cap;
     RepInfo *info;           // [nrep][nys]
 };
+// Column popcounts for the big tiles: cpop[y][j] = |y_y ^ x_j| for y < nys, cpop[nys][j] = |x_j|.
+hipError_t launch_col_pops(const uint32_t *XC, int W32p, const uint32_t *yb, int nys, int64_t p, uint32_t *cpop,
+                           hipStream_t st);
 // Popcount-XOR verification of +-1 candidates: s = n - 2 popcount(y ^ x_j ^ x_k).
 hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st);
 // Binary64 verification of real-valued candidates (x_real: values from XF, else +-1 from XC).

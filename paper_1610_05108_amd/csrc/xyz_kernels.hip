@@ -1570,25 +1570,27 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
 // block pair of at most BIG_TILE x BIG_TILE columns, on the FP4 matrix cores as
 // in the exact search.  Both blocks are gathered from the packed columns once,
 // in chunks of BKQ quads (128 rows each), into LDS: the A side as z = y ^ x,
-// the B side as x with bits 0 and 2 of every nibble swapped, the words of a
-// quad in the order 0, 2, 1, 3 so that lane half h of a fragment reads words h
-// and h + 2 as one 8-byte load.  Eight consecutive threads read the 128
-// contiguous bytes of one column's chunk.  The next chunk's loads are in
-// flight while the waves multiply the current one (two LDS buffers, one
-// barrier per chunk).  Wave (wa, wb) owns A columns 64 wa.. and B columns
-// 128 wb.. as up to 2 x 4 fragments of 32 x 32; positions past the end of a
-// block are staged as copies of its last column, so their products duplicate
-// real ones and the cheap threshold test needs no masks.  Column popcounts are
-// summed by the staging threads over the chunks and reduced across the eight
-// threads of a column with the last chunk.
+// the B side as x.  Lane half h of a fragment needs words h and h + 2 of a
+// quad; they sit side by side in half row h of the quad's LDS row, so a
+// fragment load is two runs of 256 contiguous bytes.  Eight consecutive
+// threads read the 128 contiguous bytes of one column's chunk.  The next
+// chunk's loads are in flight while the waves multiply the current one (two
+// LDS buffers, one barrier per chunk).  The B side's words are expanded into
+// FP4 operands with the shifts that give every product of two set bits the
+// value 1 (expand_b_plain), so the staging does no arithmetic on them; the
+// column popcounts |z_j| and |x_j| come precomputed per search, read with the
+// first chunk.  Wave (wa, wb) owns A columns 64 wa.. and B columns 128 wb.. as
+// up to 2 x 4 fragments of 32 x 32; positions past the end of a block are
+// staged as copies of its last column, so their products duplicate real ones
+// and the cheap threshold test needs no masks.
 constexpr int BKQ = 8;                          // quads per staged chunk (1024 rows)
-constexpr int BROW = BIG_TILE + 1;              // uint4 per LDS row (one quad of every column), padded
-constexpr size_t BIG_LDS = (size_t)2 * 2 * BKQ * BROW * sizeof(uint4);   // [buffer][side][quad][column]
+constexpr int BHROW = BIG_TILE + 1;             // uint2 per LDS half row (words h, h + 2 of every column), padded
+constexpr size_t BIG_LDS = (size_t)2 * 2 * BKQ * 2 * BHROW * sizeof(uint2);   // [buffer][side][quad][half][column]
 
 template <bool TWO>
 __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
 {
-    extern __shared__ uint4 bl[];
+    extern __shared__ uint2 bl[];
     __shared__ __align__(16) uint32_t bpop[2][2][BIG_TILE];   // [tile parity][side][column] popcounts
     const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wa = wave >> 1, wb = wave & 1;
@@ -1598,7 +1600,6 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
     const int NC = (W4 + BKQ - 1) / BKQ;
     const uint4 *XC4 = reinterpret_cast<const uint4 *>(a.XC);
     const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall + a.nmfma);
-    const uint2 *bl2 = reinterpret_cast<const uint2 *>(bl);
     const int32_t n32 = (int32_t)a.n;
     int par = 0;
     for (uint64_t ti = blockIdx.x; ti < a.nbig; ti += gridDim.x, par ^= 1) {
@@ -1617,8 +1618,6 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
             col[r] = c < 32 * fs ? a.perm[(side ? t.b0 : t.a0) + min(c, nside - 1)] : NOCOL;
         }
         uint32_t pops[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) pops[r] = 0;
         uint4 pre[8], ypre;
         auto load_chunk = [&](int ch) {
             const int qi = ch * BKQ + sq;
@@ -1627,10 +1626,15 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
 #pragma unroll
             for (int r = 0; r < 8; ++r)
                 pre[r] = (in && col[r] != NOCOL) ? XC4[(uint64_t)col[r] * W4 + qi] : make_uint4(0, 0, 0, 0);
+            if (ch == 0 && sq == 0) {      // the staged columns' popcounts, stored with the first chunk
+                const uint32_t *pz = a.cpop + (uint64_t)t.ysel * (uint64_t)a.p, *px = a.cpop + (uint64_t)a.nys * a.p;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) pops[r] = col[r] != NOCOL ? (r < 4 ? pz : px)[col[r]] : 0u;
+            }
         };
-        // registers -> LDS buffer `buf` (A side z = y ^ x, B side bit-swapped), popcounts; with the
-        // last chunk, the column popcounts are complete: reduce and publish them
-        auto store_chunk = [&](int buf, bool last) {
+        // registers -> LDS buffer `buf` (A side z = y ^ x), words h and h + 2 into half row h; with
+        // the first chunk, the popcounts
+        auto store_chunk = [&](int buf, bool first) {
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 if (col[r] == NOCOL) continue;
@@ -1641,24 +1645,11 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
                     v.y ^= ypre.y;
                     v.z ^= ypre.z;
                     v.w ^= ypre.w;
-                } else {
-                    v.x = swap02(v.x);
-                    v.y = swap02(v.y);
-                    v.z = swap02(v.z);
-                    v.w = swap02(v.w);
                 }
-                pops[r] += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
-                bl[((buf * 2 + side) * BKQ + sq) * BROW + c] = make_uint4(v.x, v.z, v.y, v.w);
-            }
-            if (last) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    uint32_t v = pops[r];
-                    v += __shfl_xor(v, 1, 64);
-                    v += __shfl_xor(v, 2, 64);
-                    v += __shfl_xor(v, 4, 64);
-                    if (sq == 0 && col[r] != NOCOL) bpop[par][r >> 2][sc + 64 * (r & 3)] = v;
-                }
+                uint2 *row = bl + (size_t)((buf * 2 + side) * BKQ + sq) * (2 * BHROW) + c;
+                row[0] = make_uint2(v.x, v.z);
+                row[BHROW] = make_uint2(v.y, v.w);
+                if (first && sq == 0) bpop[par][side][c] = pops[r];
             }
         };
         v16f acc[2][4];
@@ -1670,22 +1661,22 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
         auto compute = [&](int ch, int buf, auto full) {
             constexpr bool FULL = decltype(full)::value;
             const int nq = min(BKQ, W4 - ch * BKQ);
-            const uint2 *LA = bl2 + (size_t)((buf * 2 + 0) * BKQ) * (2 * BROW) + 2 * (wa * 64 + l32) + h;
-            const uint2 *LB = bl2 + (size_t)((buf * 2 + 1) * BKQ) * (2 * BROW) + 2 * (wb * 128 + l32) + h;
+            const uint2 *LA = bl + (size_t)((buf * 2 + 0) * BKQ) * (2 * BHROW) + h * BHROW + wa * 64 + l32;
+            const uint2 *LB = bl + (size_t)((buf * 2 + 1) * BKQ) * (2 * BHROW) + h * BHROW + wb * 128 + l32;
 #pragma unroll
             for (int q = 0; q < BKQ; ++q) {
                 if (q >= nq) break;
                 uint2 fa[2], fb[4];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) fa[u] = LA[q * 2 * BROW + 2 * 32 * u];
+                for (int u = 0; u < 2; ++u) fa[u] = LA[q * 2 * BHROW + 32 * u];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) fb[v] = LB[q * 2 * BROW + 2 * 32 * v];
+                for (int v = 0; v < 4; ++v) fb[v] = LB[q * 2 * BHROW + 32 * v];
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
                     const v8i ea0 = expand_a(k ? fa[0].y : fa[0].x), ea1 = expand_a(k ? fa[1].y : fa[1].x);
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const v8i eb = expand_b(k ? fb[v].y : fb[v].x);
+                        const v8i eb = expand_b_plain(k ? fb[v].y : fb[v].x);
                         if (FULL || (0 < nua && v < nvb)) acc[0][v] = mfma_fp4(ea0, eb, acc[0][v]);
                         if (FULL || (1 < nua && v < nvb)) acc[1][v] = mfma_fp4(ea1, eb, acc[1][v]);
                     }
@@ -1693,7 +1684,7 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
             }
         };
         load_chunk(0);
-        store_chunk(0, NC == 1);
+        store_chunk(0, true);
         lds_barrier();
         const bool active = nua > 0 && nvb > 0, full = nua == 2 && nvb == 4;
         for (int ch = 0; ch < NC; ++ch) {
@@ -1701,7 +1692,7 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
             if (ch + 1 < NC) load_chunk(ch + 1);
             if (full) compute(ch, buf, std::true_type{});
             else if (active) compute(ch, buf, std::false_type{});
-            if (ch + 1 < NC) store_chunk(buf ^ 1, ch + 2 == NC);
+            if (ch + 1 < NC) store_chunk(buf ^ 1, false);
             lds_barrier();
         }
         if (!active) continue;
@@ -1742,7 +1733,7 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
         // wave's slot in the second staging buffer (free until the next tile stores its second
         // chunk, which follows a barrier that every wave reaches after this pass), so that the
         // rows are indexed at run time; each lane reads back only what it wrote.
-        float *fbuf = reinterpret_cast<float *>(bl + (size_t)2 * BKQ * BROW) + wave * 16 * 64;
+        float *fbuf = reinterpret_cast<float *>(bl + (size_t)2 * BKQ * 2 * BHROW) + wave * 16 * 64;
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -1787,6 +1778,38 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
                     ++idx;
                 }
             }
+    }
+}
+
+// Column popcounts for the big tiles: eight threads per column, each summing
+// every eighth quad (the eight read 128 contiguous bytes at a time), reduced
+// across the eight.  cpop[y][j] = |y_y ^ x_j| for y < nys, cpop[nys][j] = |x_j|.
+__global__ __launch_bounds__(256) void k_col_pops(const uint4 *__restrict__ XC4, int W4, const uint4 *__restrict__ Y4,
+                                                  int nys, int64_t p, uint32_t *__restrict__ cpop)
+{
+    const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
+    const int e = (int)(threadIdx.x & 7);
+    const bool ok = j < p;
+    const uint4 *col = XC4 + (ok ? j : 0) * W4;
+    uint32_t px = 0;
+    for (int q = e; q < W4; q += 8) {
+        const uint4 v = ok ? col[q] : make_uint4(0, 0, 0, 0);
+        px += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+    }
+    px += __shfl_xor(px, 1, 64);
+    px += __shfl_xor(px, 2, 64);
+    px += __shfl_xor(px, 4, 64);
+    if (ok && e == 0) cpop[(int64_t)nys * p + j] = px;
+    for (int y = 0; y < nys; ++y) {
+        uint32_t pz = 0;
+        for (int q = e; q < W4; q += 8) {
+            const uint4 v = ok ? col[q] : make_uint4(0, 0, 0, 0), w = Y4[(int64_t)y * W4 + q];
+            pz += __popc(v.x ^ w.x) + __popc(v.y ^ w.y) + __popc(v.z ^ w.z) + __popc(v.w ^ w.w);
+        }
+        pz += __shfl_xor(pz, 1, 64);
+        pz += __shfl_xor(pz, 2, 64);
+        pz += __shfl_xor(pz, 4, 64);
+        if (ok && e == 0) cpop[(int64_t)y * p + j] = pz;
     }
 }
 
@@ -3179,6 +3202,14 @@ hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
         hipLaunchKernelGGL(k_verify_small, dim3((unsigned)std::min<uint64_t>(groups, (uint64_t)grid)), dim3(64), 0, st,
                            a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_col_pops(const uint32_t *XC, int W32p, const uint32_t *yb, int nys, int64_t p, uint32_t *cpop,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_col_pops, dim3(grid1((uint64_t)p * 8, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const uint4 *>(XC), W32p / 4, reinterpret_cast<const uint4 *>(yb), nys, p, cpop);
     return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ uint64_t fixed_bytes(const xyz_x *x, const xyz_params &P, int yfmt)
     if (yfmt != XYZ_Y_I8_PM1 || (P.flags & XYZ_UNBIASED)) b += round256(n * 8) + round256(n * 4) + 256;
     b += round256((uint64_t)P.L * sizeof(RepInfo));
     b += round256((uint64_t)(1 << 16) * sizeof(Survivor));
+    b += round256(2 * (uint64_t)x->p * 4);                      // column popcounts of the big tiles
     return b;
 }
 

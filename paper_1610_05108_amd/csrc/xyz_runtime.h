@@ -13,7 +13,7 @@ enum Slot {
     WS_XIN, WS_YIN, WS_YB, WS_YD, WS_CDF, WS_LAST, WS_ERR, WS_ROWS, WS_INFO, WS_KEYS, WS_OFFS, WS_PERM, WS_BASE,
     WS_TILES, WS_SURV, WS_SURV2, WS_SCNT, WS_SMIN, WS_KAPPA, WS_DKEYS, WS_DVALS, WS_DKEYS2, WS_DVALS2, WS_HIST,
     WS_HEADS, WS_OUT, WS_NOUT, WS_YCNT, WS_BXA, WS_BXB, WS_BPOP, WS_BCNT, WS_BOFF, WS_SKK, WS_SKK2, WS_SKV, WS_SKV2, WS_SKHIST, WS_SKHEADS,
-    WS_SKRK, WS_SKRS, WS_SKN, WS_SKCNT, WS_SKTAB, WS_NU, WS_DPR, WS_DPW, WS_DPX, WS_DPZ, WS_DPI, NWS
+    WS_SKRK, WS_SKRS, WS_SKN, WS_SKCNT, WS_SKTAB, WS_NU, WS_DPR, WS_DPW, WS_DPX, WS_DPZ, WS_DPI, WS_CPOP, NWS
 };
 
 struct DevBuf {

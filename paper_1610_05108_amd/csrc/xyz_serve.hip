@@ -80,7 +80,8 @@ uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk, int 
     const double tiles = std::max(p / 24.0, cand / 576.0);
     // the sort path (m > 15) replaces the 2^m bucket offsets by about 56 bytes of scratch per column
     const double per_rep = 8 * p + (P.m <= 15 ? 4 * (nb + 1) : 56 * p) + 16 * tiles + 80;
-    const double fixed = merge + ybytes + (double)P.L * 64 + (yfmt != XYZ_Y_I8_PM1 ? (double)x->n * 12 : 0.0);
+    // column popcounts of the big tiles: |x_j| once and |y ^ x_j| per response
+    const double fixed = merge + ybytes + (double)P.L * 64 + (yfmt != XYZ_Y_I8_PM1 ? (double)x->n * 12 : 8.0 * p);
     return (uint64_t)(per_rep * (double)chunk + fixed);
 }
 
