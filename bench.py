@@ -1,29 +1,25 @@
 """Benchmark of the xyz interaction search on one MI355X.
 
-Workload (genotype-shaped binary data standing in for the SNP data of the
-paper's Section 5.3): n = 2000 rows, p = 100,000 columns, minor-allele
-frequencies U[0.05, 0.5]; five data sets (seeds 0-4), each with a +-1
-response from a logistic model with 10 planted pairs and 20 main effects.
-kappa is set per data set so that about 1e4 pairs exceed it (found exactly
-on the GPU before timing).
+Headline workload (the largest single-GPU configuration): n = 5000 rows,
+p = 10^6 Rademacher columns handed over bit-packed (625 MB), one +-1 response
+with 20 planted pairs of exact strength s ~ U[0.15, 0.5], kappa = 0.12.  A
+step answers the search at >= 95 % predicted recall (eq. (9)) of the weakest
+planted pair above kappa.  The candidate plans are xyz with m in {10, 11, 12}
+and L from eq. (15) for that pair, and the exact search of eq. (1) on the FP4
+(e2m1) matrix cores (recall 1); each is timed once and the fastest runs the
+timed steps.  Inputs are resident in HBM before timing; a search includes
+packing Y, row sampling, projection, bucket sort, candidate expansion,
+verification, merging and the copy of the result to the host.  Pairs screened
+per search = p (p - 1) / 2 (the whole search space, as in the paper's
+"interactions screened"); recall is measured against the exact truth.
 
-A step answers all five searches at >= 95 % predicted recall of the planted
-pairs above kappa.  The candidate plans are xyz with m in {8, 10, 12} rows
-and L from eq. (15) for the weakest planted pair above kappa, and the exact
-search of eq. (1) on the FP4 (e2m1) matrix cores (recall 1); each is timed once on
-the first data set and the fastest is used for every step.  Inputs are
-resident in HBM before timing; an xyz search includes packing Y, row
-sampling, projection, bucket sort, candidate expansion, verification,
-merging and the copy of the result to the host.
-
-Prints one JSON line.  Pairs screened per search = p (p - 1) / 2 (the whole
-search space, as in the paper's "interactions screened").  Beside the timed
-steps it reports the large Rademacher workload (xyz against the exact
-search), the continuous workload (sign and unbiased transforms), the serving
-stream and the CPU oracle's rate on a bounded sample.  Separate modes:
---scaling-law (Section 5.2), --lasso (Section 5.4), --dense (Section 5.1:
-dense Gaussian projections against minimal subsampling), --calibrate-copy
-(the reference for the HBM byte counters).
+Prints one JSON line.  Beside the timed steps it reports the genotype-shaped
+workload (n = 2000, p = 10^5, five data sets), the continuous workload (sign
+and unbiased transforms), the serving stream and the CPU oracle's rate on a
+bounded sample (one thread and all threads).  Separate modes: --scaling-law
+(Section 5.2), --lasso (Section 5.4), --dense (Section 5.1: dense Gaussian
+projections against minimal subsampling), --calibrate-copy (the reference for
+the HBM byte counters).
 """
 from __future__ import annotations
 
@@ -64,12 +60,13 @@ def find_kappa(ctx, x, Yd, n, p, target=10_000):
     return kappa, exact
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter profile, or
-    None when the kernel source changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter profile of
+    `workload`, or None when the kernel source changed since the counters were
+    taken (or there is no profile)."""
     import hashlib
     try:
-        with open(os.path.join(ROOT, "profiles", "traffic_genotype_n2000_p100000.json")) as f:
+        with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")) as f:
             t = json.load(f)
         with open(os.path.join(ROOT, "paper_1610_05108_amd", "csrc", "xyz_kernels.hip"), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
@@ -85,23 +82,34 @@ def gamma_of(stat):
     return 0.5 * (1.0 + stat)
 
 
+def host_threads():
+    """Threads for the CPU baseline: this process's CPU share, at most 16."""
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def unpack_bits(bits, n):
+    """(p, ceil(n/64)) uint64 column bits -> (p, n) int8 +-1 (bit 1 = -1)."""
+    u8 = np.ascontiguousarray(bits).view(np.uint8)
+    b = np.unpackbits(u8, axis=1, bitorder="little")[:, :n]
+    return (1 - 2 * b.astype(np.int8)).astype(np.int8)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--seeds", type=int, default=5)
-    ap.add_argument("--p", type=int, default=100_000)
-    ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--plan", choices=["auto", "brute", "xyz"], default="auto",
                     help="auto: time every plan once and keep the fastest")
-    ap.add_argument("--m", type=int, default=None, help="force m of the xyz plan")
-    ap.add_argument("--L", type=int, default=None, help="force L (default: eq. (15) at 95%% recall)")
+    ap.add_argument("--ms", type=str, default="10,11,12", help="m of the xyz plans (L from eq. (15))")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-reps", type=int, default=None)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
-    ap.add_argument("--no-large", action="store_true", help="skip the large Rademacher comparison")
+    ap.add_argument("--no-genotype", action="store_true", help="skip the genotype-shaped workload")
     ap.add_argument("--no-continuous", action="store_true", help="skip the continuous workload")
+    ap.add_argument("--seeds", type=int, default=5, help="data sets of the genotype-shaped workload")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-fresh", type=int, default=32)
     ap.add_argument("--serve-workers", type=int, default=2)
@@ -113,7 +121,8 @@ def main():
     ap.add_argument("--scaling-sims", type=int, default=40)
     ap.add_argument("--lasso", action="store_true",
                     help="only run the regression experiment of Section 5.4 (Lasso with all interactions)")
-    ap.add_argument("--lasso-p", type=str, default="250,500,1000")
+    ap.add_argument("--lasso-p", type=str, default="250,500,750,1000")
+    ap.add_argument("--lasso-settings", type=str, default="1,2")
     ap.add_argument("--dense", action="store_true",
                     help="only Section 5.1: dense Gaussian projections vs minimal subsampling")
     ap.add_argument("--dense-p", type=str, default="1000,10000,100000,1000000")
@@ -145,7 +154,8 @@ def main():
     if args.lasso:
         import paper_1610_05108_amd as xyz
         ctx = xyz.Context(0)
-        print(json.dumps(lasso_leg(ctx, [int(v) for v in args.lasso_p.split(",")])), flush=True)
+        print(json.dumps(lasso_leg(ctx, [int(v) for v in args.lasso_p.split(",")],
+                                   settings=[int(v) for v in args.lasso_settings.split(",")])), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards over repetitions "
@@ -156,129 +166,127 @@ def main():
     import synthgen
     import paper_1610_05108_amd as xyz
 
-    dev = torch.device("cuda:0")
     ctx = xyz.Context(0)
-    n, p = args.n, args.p
-    data = []
-    for seed in range(args.seeds):
-        t0 = time.time()
-        d = synthgen.config2(seed=seed, n=n, p=p)
-        XT = torch.from_numpy(d.XT).to(dev)
-        Yd = torch.from_numpy(d.Y).to(dev)
-        x = ctx.x_create(XT)
-        kappa, exact = find_kappa(ctx, x, Yd, n, p)
-        ex = {(int(a), int(b)): int(s) for a, b, s in zip(exact["j"], exact["k"], exact["s"])}
-        planted_above = [pq for pq in d.planted if pq in ex]
-        data.append(dict(seed=seed, d=d, XT=XT, Y=Yd, x=x, kappa=kappa, exact=ex, planted_above=planted_above))
-        log(f"seed {seed}: kappa={kappa:.4f} truth={len(ex)} planted above kappa={len(planted_above)} "
-            f"({time.time() - t0:.1f}s)")
+    # ---- the headline workload, resident in HBM
+    t0 = time.time()
+    d = synthgen.config3(seed=0)
+    n, p = d.n, d.p
+    kappa = d.params["kappa"]
+    x = xyz.xyz_x_create(ctx.h, d.bits, n=n)
+    Y = torch.from_numpy(d.Y).cuda()
+    torch.cuda.synchronize()
+    log(f"data ready ({time.time() - t0:.1f}s): n={n} p={p}, {len(d.planted)} planted pairs, kappa={kappa}")
+    truth = ctx.bruteforce(x, Y, kappa)["pairs"]
+    ex = {(int(a), int(b)): int(sv) for a, b, sv in zip(truth["j"], truth["k"], truth["s"])}
+    above = [pq for pq in d.planted if pq in ex]
+    gamma_w = min(gamma_of(ex[pq] / n) for pq in above)
+    log(f"exact truth: {len(ex)} pairs above kappa, {len(above)} of them planted; weakest planted gamma {gamma_w:.4f}")
 
-    # candidate plans at >= 95 % predicted recall of the weakest planted pair above kappa:
-    # xyz with m rows and L from eq. (15), or the exact search on matrix cores.
-    strengths = [gamma_of(dd["exact"][pq] / n) for dd in data for pq in dd["planted_above"]]
-    gamma_w = min(strengths) if strengths else 0.6
-    d0 = data[0]
-
-    def L95(m):
-        beta = gamma_w ** m
-        return 1 if beta >= 1.0 else int(math.ceil(math.log(0.05) / math.log(1.0 - beta)))
-
-    def run(plan, dd, profile=False):
+    def run(plan, profile=False):
         if plan[0] == "brute":
-            return ctx.bruteforce(dd["x"], dd["Y"], dd["kappa"], profile=profile)
-        return ctx.search(dd["x"], dd["Y"], m=plan[1], L=plan[2], kappa=dd["kappa"], seed=1000 + dd["seed"],
-                          profile=profile)
+            return ctx.bruteforce(x, Y, kappa, profile=profile)
+        return ctx.search(x, Y, m=plan[1], L=plan[2], kappa=kappa, seed=1, profile=profile)
 
-    if args.m is not None:
-        plans = [("xyz", args.m, args.L if args.L is not None else L95(args.m))]
-    elif args.plan == "brute":
-        plans = [("brute", 0, 1)]
-    elif args.plan == "xyz":
-        plans = [("xyz", m, L95(m)) for m in (8, 10, 12)]
-    else:
-        plans = [("brute", 0, 1)] + [("xyz", m, L95(m)) for m in (8, 10, 12)]
+    def recall_of(res):
+        got = {(int(a), int(b)) for a, b in zip(res["pairs"]["j"], res["pairs"]["k"])}
+        return sum(1 for pq in above if pq in got) / len(above), len(got & set(ex)) / max(len(ex), 1)
+
+    ms_list = [int(v) for v in args.ms.split(",") if v]
+    xyz_plans = [("xyz", m, xyz.xyz_L_for(0.95, gamma_w ** m)) for m in ms_list]
+    plans = {"auto": [("brute", 0, 1)] + xyz_plans, "brute": [("brute", 0, 1)], "xyz": xyz_plans}[args.plan]
     table = []
     for pl in plans:
-        run(pl, d0)
+        run(pl)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run(pl, d0)
+        tt = time.perf_counter()
+        r = run(pl)
         torch.cuda.synchronize()
-        table.append(dict(kind=pl[0], m=pl[1], L=pl[2], ms_per_search=(time.perf_counter() - t0) * 1e3,
-                          predicted_recall=1.0 if pl[0] == "brute" else 1 - (1 - gamma_w ** pl[1]) ** pl[2]))
-    best = min(range(len(plans)), key=lambda i: table[i]["ms_per_search"])
+        dt = time.perf_counter() - tt
+        rec, trec = recall_of(r)
+        table.append(dict(kind=pl[0], m=pl[1], L=pl[2], ms_per_search=dt * 1e3, planted_recall=rec,
+                          predicted_recall_min=1.0 if pl[0] == "brute" else xyz.xyz_eta(gamma_w, pl[1], pl[2])))
+        log(f"plan {pl}: {dt * 1e3:.1f} ms, planted recall {rec:.3f}")
+    best = min(range(len(plans)), key=lambda q: table[q]["ms_per_search"])
     plan = plans[best]
-    log(f"weakest planted strength gamma={gamma_w:.4f}; plans: {table}")
     log(f"running {plan}")
 
-    def step(profile=False):
-        return [run(plan, dd, profile) for dd in data]
-
     for _ in range(args.warmup):
-        step()
+        run(plan)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = None
+    tt = time.perf_counter()
+    out = None
     for _ in range(args.steps):
-        outs = step()
+        out = run(plan)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-
-    # recall of the planted pairs above kappa, and of the whole truth set
-    found = tot = 0
-    tfound = ttot = 0
-    for dd, o in zip(data, outs):
-        got = {(int(a), int(b)) for a, b in zip(o["pairs"]["j"], o["pairs"]["k"])}
-        found += sum(1 for pq in dd["planted_above"] if pq in got)
-        tot += len(dd["planted_above"])
-        tfound += len(got & set(dd["exact"]))
-        ttot += len(dd["exact"])
-    recall = found / tot if tot else float("nan")
-
-    # profiled pass (HIP events inside the library, on the stream the kernels run on)
-    prof = step(profile=True)
-    if plan[0] == "brute":
-        k_ms = sum(o["timing"]["brute_ms"] for o in prof)
-        k_launch = sum(o["timing"]["verify_launches"] for o in prof)
-        work = sum(2.0 * n * o["timing"]["candidates"] for o in prof)       # multiply-adds of eq. (1) over j < k
-        roof = dict(kernel="k_brute", bound="mfma", peak=PEAK_FP4_TFLOPS, unit="TFLOP/s")
-    else:
-        k_ms = sum(o["timing"]["verify_ms"] for o in prof)
-        k_launch = sum(o["timing"]["verify_launches"] for o in prof)
-        work = sum(2.0 * math.ceil(n / 32) * o["timing"]["candidates"] for o in prof)   # XOR + popcount per word
-        roof = dict(kernel="k_verify_bin", bound="alu", peak=PEAK_ALU_TOPS, unit="TOP/s")
-    avg_launch_ms = k_ms / max(k_launch, 1)
-    per_launch = work / max(k_launch, 1)
-    achieved = per_launch / (avg_launch_ms * 1e-3) / 1e12 if k_launch else 0.0
-    roof.update(achieved=achieved, frac=achieved / roof["peak"], traffic=measured_traffic(roof["kernel"]),
-                work_per_launch=per_launch,
-                avg_launch_ms=avg_launch_ms, launches=k_launch)
-    stages = {k: round(sum(o["timing"][k] for o in prof) / len(prof), 4)
-              for k in ("pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms", "dedup_ms",
-                        "brute_ms", "total_ms")}
-
+    ms_per_step = (time.perf_counter() - tt) * 1e3 / args.steps
+    recall, truth_recall = recall_of(out)
     pairs_per_search = p * (p - 1) / 2
-    value = len(data) * pairs_per_search / (ms_per_step * 1e-3)
+    value = pairs_per_search / (ms_per_step * 1e-3)
 
-    large = None
-    if not args.no_large:
-        large = large_binary_leg(ctx)
-        log(f"large binary: {large}")
+    # profiled pass: HIP events recorded by the library on the stream the kernels run on
+    prof = run(plan, profile=True)
+    tm = prof["timing"]
+    workload_id = f"rademacher_n{n}_p{p}"
+    if plan[0] == "brute":
+        flops = 2.0 * n * tm["candidates"]
+        k_ms, k_launch = tm["brute_ms"], max(tm["verify_launches"], 1)
+        dom = dict(kernel="k_brute", bound="mfma", unit="TFLOP/s", peak=PEAK_FP4_TFLOPS)
+        hashr = sortr = None
+    else:
+        m, L = plan[1], plan[2]
+        flops = 2.0 * n * tm["big_candidates"]        # the n-row products of the big tiles' candidates
+        k_ms, k_launch = tm["big_ms"], max(tm["big_launches"], 1)
+        dom = dict(kernel="k_verify_lds", bound="mfma", unit="TFLOP/s", peak=PEAK_FP4_TFLOPS)
+        hb = L * (m * p / 8.0 + 4.0 * p)              # rows of the bit matrix read, keys written
+        sb = L * (8.0 * p + 4.0 * ((1 << m) + 1))     # keys read, permutation and bucket offsets written
+        hashr = dict(kernel="k_hash", bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS,
+                     achieved=hb / (tm["hash_ms"] * 1e-3) / 1e9, bytes_per_search=hb, ms_per_search=tm["hash_ms"])
+        hashr["frac"] = hashr["achieved"] / PEAK_HBM_GBS
+        hashr["traffic"] = measured_traffic("k_hash", workload_id)
+        sortr = dict(kernel="k_bucket", bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS,
+                     achieved=sb / (tm["bucket_ms"] * 1e-3) / 1e9, bytes_per_search=sb, ms_per_search=tm["bucket_ms"])
+        sortr["frac"] = sortr["achieved"] / PEAK_HBM_GBS
+        sortr["traffic"] = measured_traffic("k_bucket", workload_id)
+    achieved = flops / k_launch / (k_ms / k_launch * 1e-3) / 1e12
+    dom.update(achieved=achieved, frac=achieved / dom["peak"], work_per_launch=flops / k_launch,
+               avg_launch_ms=k_ms / k_launch, launches=k_launch, traffic=measured_traffic(dom["kernel"], workload_id))
+    stages = {k: round(tm[k], 3) for k in ("pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms",
+                                           "big_ms", "dedup_ms", "brute_ms", "total_ms")}
+    stages["candidates"] = tm["candidates"]
+    stages["big_candidates"] = tm["big_candidates"]
+    literal = None
+    if plan[0] != "brute" or args.plan == "auto":
+        # the workload's literal parameters (m = 14, L = 500): a parity run, recall as it comes
+        lit = ("xyz", d.params["m"], d.params["L"])
+        run(lit)
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        r = run(lit)
+        torch.cuda.synchronize()
+        rec, _ = recall_of(r)
+        g = [gamma_of(ex[pq] / n) for pq in above]
+        literal = dict(m=lit[1], L=lit[2], ms_per_search=(time.perf_counter() - tt) * 1e3, planted_recall=rec,
+                       predicted_recall_mean=float(np.mean([xyz.xyz_eta(gg, lit[1], lit[2]) for gg in g])))
+    xyz.xyz_x_destroy(x)
+    del Y
+    torch.cuda.synchronize()
 
+    genotype = None
+    if not args.no_genotype:
+        genotype = genotype_leg(ctx, args.seeds)
+        log(f"genotype: {genotype}")
     continuous = None
     if not args.no_continuous:
         continuous = continuous_leg(ctx)
         log(f"continuous: {continuous}")
-
     serving = None
     if not args.no_serve:
         serving = serve_leg(ctx, args.serve_requests, args.serve_fresh, args.serve_workers, seq_sample=32)
         log(f"serving: {serving}")
-
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(data[0], plan[1], plan[2], n, p, args.cpu_reps)
+        cpu = cpu_baseline(d, plan, kappa)
+        log(f"cpu: {cpu}")
 
     line = {
         "metric": "interaction pairs screened/s at >=95% planted recall; p50/p99 request latency",
@@ -291,24 +299,83 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp4-e2m1/fp32-acc" if plan[0] == "brute" else "u32",
+        "dtype": "fp4-e2m1/fp32-acc",
         "data": "synthetic",
-        "config": {"workload": f"genotype-shaped binary search n={n} p={p}, {len(data)} data sets "
-                               f"(seeds 0-{len(data) - 1}), kappa for 1e4 survivors",
-                   "searches_per_step": len(data), "plan": plan[0], "m": plan[1], "L": plan[2],
-                   "kappa": [round(dd["kappa"], 6) for dd in data]},
-        "recall": {"planted_predicted_min": table[best]["predicted_recall"], "planted_measured": recall,
-                   "planted_pairs_above_kappa": tot, "truth_set_recall": tfound / ttot if ttot else None},
+        "config": {"workload": f"large binary: Rademacher bits n={n} p={p}, 20 planted pairs of strength "
+                               f"U[0.15,0.5], kappa={kappa}, one search per step at >=95% predicted recall "
+                               f"of the weakest planted pair",
+                   "searches_per_step": 1, "plan": plan[0], "m": plan[1], "L": plan[2], "kappa": kappa},
+        "recall": {"planted_predicted_min": table[best]["predicted_recall_min"], "planted_measured": recall,
+                   "planted_pairs_above_kappa": len(above), "weakest_planted_gamma": gamma_w,
+                   "truth_set_recall": truth_recall, "truth_set_size": len(ex)},
         "plans_ms_per_search": table,
         "stages_ms_per_search": stages,
-        "roofline": roof,
+        "roofline": dom,
+        "roofline_hash": hashr,
+        "roofline_sort": sortr,
+        "literal_parameters": literal,
         "cpu_baseline": cpu,
         "serving": serving,
-        "large_binary": large,
+        "genotype": genotype,
         "continuous": continuous,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def genotype_leg(ctx, seeds, n=2000, p=100_000):
+    """The genotype-shaped workload (stands in for the SNP data of Section 5.3):
+    `seeds` data sets of n = 2000, p = 10^5, minor-allele frequencies U[0.05,
+    0.5], +-1 responses from a logistic model with 10 planted pairs; kappa per
+    data set so that about 1e4 pairs exceed it (found exactly on the GPU).  Each
+    data set is searched at >= 95 % predicted recall of the weakest planted pair
+    above kappa; the plans are the exact search and xyz with m in {8, 10, 12}
+    (L from eq. (15)), each timed once on data set 0, and the fastest answers all
+    data sets; pairs/s over the data sets, recall against the exact truth."""
+    import torch
+    import synthgen
+    import paper_1610_05108_amd as xyz
+    data = []
+    for seed in range(seeds):
+        d = synthgen.config2(seed=seed, n=n, p=p)
+        x = ctx.x_create(torch.from_numpy(d.XT).cuda())
+        Yd = torch.from_numpy(d.Y).cuda()
+        kappa, exact = find_kappa(ctx, x, Yd, n, p)
+        ex = {(int(a), int(b)): int(sv) for a, b, sv in zip(exact["j"], exact["k"], exact["s"])}
+        data.append(dict(seed=seed, x=x, Y=Yd, kappa=kappa, ex=ex, planted=[pq for pq in d.planted if pq in ex]))
+    gamma_w = min(gamma_of(dd["ex"][pq] / n) for dd in data for pq in dd["planted"])
+
+    def run(plan, dd):
+        if plan[0] == "brute":
+            return ctx.bruteforce(dd["x"], dd["Y"], dd["kappa"])
+        return ctx.search(dd["x"], dd["Y"], m=plan[1], L=plan[2], kappa=dd["kappa"], seed=1000 + dd["seed"])
+
+    plans = [("brute", 0, 1)] + [("xyz", m, xyz.xyz_L_for(0.95, gamma_w ** m)) for m in (8, 10, 12)]
+    table = []
+    for pl in plans:
+        run(pl, data[0])
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        run(pl, data[0])
+        torch.cuda.synchronize()
+        table.append(dict(kind=pl[0], m=pl[1], L=pl[2], ms_per_search=(time.perf_counter() - tt) * 1e3))
+    plan = plans[min(range(len(plans)), key=lambda q: table[q]["ms_per_search"])]
+    torch.cuda.synchronize()
+    tt = time.perf_counter()
+    outs = [run(plan, dd) for dd in data]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - tt
+    found = tot = 0
+    for dd, o in zip(data, outs):
+        got = {(int(a), int(b)) for a, b in zip(o["pairs"]["j"], o["pairs"]["k"])}
+        found += sum(1 for pq in dd["planted"] if pq in got)
+        tot += len(dd["planted"])
+    for dd in data:
+        ctx.x_destroy(dd["x"])
+    return {"workload": f"genotype-shaped binary n={n} p={p}, {seeds} data sets, kappa for 1e4 survivors",
+            "plan": plan, "plans_ms_per_search": table, "weakest_planted_gamma": gamma_w,
+            "ms_per_search": dt * 1e3 / len(data), "pairs_per_s": len(data) * p * (p - 1) / 2 / dt,
+            "planted_found": found, "planted_above_kappa": tot}
 
 
 def pct(v, q):
@@ -459,45 +526,6 @@ def serve_leg(ctx, count, fresh_count, workers, seq_sample):
         "model": {"exact_pair_rows_per_s": rate_exact, "verify_candidate_words_per_s": rate_verify,
                   "s_per_rep_column": rep_cost},
     }
-
-
-def large_binary_leg(ctx):
-    """The large Rademacher workload (n=5000, p=10^6, 20 planted pairs of strength
-    U[0.15, 0.5], bit-packed) with its configured xyz parameters (m=14, L=500,
-    kappa=0.12) against the exact matrix-core search, each timed on its second run.
-    Recall: planted pairs above kappa reported; predicted: eq. (9) at each planted
-    pair's measured strength."""
-    import torch
-    import synthgen
-    import paper_1610_05108_amd as xyz
-    d = synthgen.config3(seed=0)
-    x = xyz.xyz_x_create(ctx.h, d.bits, n=d.n)
-    Y = torch.from_numpy(d.Y).cuda()
-    m, L, kappa = 14, 500, 0.12
-    out = {"workload": f"Rademacher bits n={d.n} p={d.p}, {len(d.planted)} planted pairs, kappa={kappa}"}
-    ex = None
-    for name in ("exact", "xyz"):
-        for rep in range(2):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if name == "exact":
-                r = ctx.bruteforce(x, Y, kappa)
-            else:
-                r = ctx.search(x, Y, m=m, L=L, kappa=kappa, seed=rep)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-        got = {(int(a), int(b)): int(s) for a, b, s in zip(r["pairs"]["j"], r["pairs"]["k"], r["pairs"]["s"])}
-        if name == "exact":
-            ex = got
-        above = [pq for pq in d.planted if pq in ex]
-        out[name] = {"ms": dt * 1e3, "planted_found": sum(1 for pq in above if pq in got),
-                     "planted_above_kappa": len(above)}
-    g = [0.5 * (1 + ex[pq] / d.n) for pq in d.planted if pq in ex]
-    eta = [1 - (1 - gg ** m) ** L for gg in g]
-    out["xyz"].update(m=m, L=L, predicted_recall_min=min(eta), predicted_recall_mean=sum(eta) / len(eta))
-    out["speedup_xyz_over_exact"] = out["exact"]["ms"] / out["xyz"]["ms"]
-    xyz.xyz_x_destroy(x)
-    return out
 
 
 def scaling_law_leg(ctx, n, ps, gammas, sims, gamma0=0.55):
@@ -729,28 +757,56 @@ def lasso_leg(ctx, ps, n=1000, settings=(1, 2), nlam=12):
             "data": "synthetic, settings 1-2 of Section 5.4", "points": out}
 
 
-def cpu_baseline(dd, m, L, n, p, reps=None):
-    """The CPU oracle on a bounded sample of the same workload: the first
-    `reps` repetitions of one search (same data, m, kappa), scaled to pairs/s."""
+def cpu_baseline(d, plan, kappa, ps=40_000, budget_s=12.0):
+    """The CPU oracle on a bounded sample of the headline workload: its first `ps`
+    columns (all n rows), run with the timed plan's method -- the oracle's
+    Algorithm 2 at the plan's m (repetitions, each screening a 1/L share of the
+    sample's pairs), or its brute force of eq. (1) -- on one thread, then on all
+    threads of this process's CPU share (independent repetition ranges, or
+    column blocks, one oracle call per thread).  Each rate is scaled to the
+    pairs screened per second."""
+    import concurrent.futures as cf
     import oracle
-    d = dd["d"]
-    if m == 0:
-        # exact search: time the oracle's brute force on the first p' columns (all p'(p'-1)/2 pairs)
-        ps = 4000
+    XT = unpack_bits(d.bits[:ps], d.n)
+    pairs = ps * (ps - 1) / 2
+    nth = host_threads()
+    out = {"unit": "pairs/s", "kind": "oracle", "threads_available": nth}
+    if plan[0] == "brute":
+        # brute force over column blocks; one block pair per call
+        blk = 4000
         t0 = time.perf_counter()
-        oracle.brute(d.XT[:ps], d.Y, dd["kappa"])
-        t = time.perf_counter() - t0
-        return {"value": ps * (ps - 1) / 2 / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-                "sample": f"brute force of eq. (1) over the first {ps} columns of one data set "
-                          f"(seed {dd['seed']}), {t:.1f} s"}
-    reps = reps or 3
+        oracle.brute(XT[:blk], d.Y, kappa)
+        t1 = time.perf_counter() - t0
+        rate1 = blk * (blk - 1) / 2 / t1
+        parts = [XT[q * blk // 2:(q + 2) * blk // 2] for q in range(nth)]
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(nth) as ex:
+            list(ex.map(lambda a: oracle.brute(a, d.Y, kappa), parts))
+        tn = time.perf_counter() - t0
+        raten = sum(len(a) * (len(a) - 1) / 2 for a in parts) / tn
+        out.update(value=rate1, cores=1, value_all_threads=raten, cores_all_threads=nth,
+                   sample=f"brute force of eq. (1) over {blk}-column blocks of the first {ps} columns "
+                          f"(n={d.n}): 1 thread {t1:.1f} s, {nth} threads {tn:.1f} s")
+        return out
+    m, L = plan[1], plan[2]
     t0 = time.perf_counter()
-    oracle.search(d.XT, d.Y, m, reps, dd["kappa"], seed=1000 + dd["seed"])
-    t = time.perf_counter() - t0
-    # each repetition screens a 1/L share of the search space
-    rate = p * (p - 1) / 2 * (reps / L) / t
-    return {"value": rate, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} of {L} repetitions of one search (seed {dd['seed']}, m={m}), {t:.1f} s"}
+    reps = 0
+    while time.perf_counter() - t0 < budget_s / 2 or reps == 0:
+        oracle.search(XT, d.Y, m, 1, kappa, seed=1, rep_offset=reps)
+        reps += 1
+    t1 = time.perf_counter() - t0
+    rate1 = pairs * (reps / L) / t1
+    per = max(1, reps // 2)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nth) as ex:
+        list(ex.map(lambda w: oracle.search(XT, d.Y, m, per, kappa, seed=1, rep_offset=1000 + w * per), range(nth)))
+    tn = time.perf_counter() - t0
+    raten = pairs * (nth * per / L) / tn
+    out.update(value=rate1, cores=1, value_all_threads=raten, cores_all_threads=nth,
+               sample=f"the oracle's Algorithm 2 (m={m}, a 1/{L} share of the pairs per repetition) on the first "
+                      f"{ps} of {d.p} columns (n={d.n}): {reps} repetitions on 1 thread in {t1:.1f} s, "
+                      f"{nth} x {per} repetitions on {nth} threads in {tn:.1f} s")
+    return out
 
 
 if __name__ == "__main__":

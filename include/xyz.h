@@ -137,6 +137,10 @@ typedef struct {
     int64_t verify_launches;
     int64_t candidates;   /* sum of candidates over repetitions */
     int64_t tiles;        /* verification tiles processed */
+    double big_ms;        /* the part of verify_ms spent on products of large buckets (LDS-staged block pairs on
+                             the matrix cores) */
+    int64_t big_launches;
+    int64_t big_candidates;   /* candidates verified in those products */
 } xyz_timing;
 
 /* Library version string (static storage). */

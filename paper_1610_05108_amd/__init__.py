@@ -60,7 +60,8 @@ class xyz_timing(ctypes.Structure):
     _fields_ = [(name, ctypes.c_double) for name in
                 ("total_ms", "pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms",
                  "dedup_ms", "brute_ms")] + [("verify_launches", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                                             ("tiles", ctypes.c_int64)]
+                                             ("tiles", ctypes.c_int64), ("big_ms", ctypes.c_double),
+                                             ("big_launches", ctypes.c_int64), ("big_candidates", ctypes.c_int64)]
 
 
 class xyz_plan_info(ctypes.Structure):

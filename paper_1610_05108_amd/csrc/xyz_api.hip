@@ -89,15 +89,17 @@ struct Timer {
         marks.push_back({open_stage, {open_ev, e}});
         open_ev = nullptr;
     }
-    // stage ids: 0 pack, 1 sample, 2 hash, 3 bucket, 4 tiles, 5 verify, 6 dedup, 7 brute
+    // stage ids: 0 pack, 1 sample, 2 hash, 3 bucket, 4 tiles, 5 verify, 6 dedup, 7 brute, 8 big tiles
+    // (counted in verify as well)
     void collect(xyz_timing &t)
     {
         for (auto &m : marks) {
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, m.second.first, m.second.second);
-            double *dst[8] = {&t.pack_ms, &t.sample_ms, &t.hash_ms, &t.bucket_ms,
-                              &t.tiles_ms, &t.verify_ms, &t.dedup_ms, &t.brute_ms};
-            if (m.first >= 0 && m.first < 8) *dst[m.first] += ms;
+            double *dst[9] = {&t.pack_ms, &t.sample_ms, &t.hash_ms, &t.bucket_ms,
+                              &t.tiles_ms, &t.verify_ms, &t.dedup_ms, &t.brute_ms, &t.big_ms};
+            if (m.first >= 0 && m.first < 9) *dst[m.first] += ms;
+            if (m.first == 8) t.verify_ms += ms;
             pool.push_back(m.second.first);
             pool.push_back(m.second.second);
         }
@@ -672,6 +674,12 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             if (real) HIP_TRY(launch_verify_real(va, real_x ? 1 : 0, g, st));
             else HIP_TRY(launch_verify_bin(va, g, st));
             tm.end();
+            if (nbig) {
+                tm.begin(8);
+                HIP_TRY(launch_verify_big(va, g, st));
+                tm.end();
+                timing.big_launches += 1;
+            }
             timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0) + (nmfma ? 1 : 0) + (nbig ? 1 : 0);
             timing.tiles += (int64_t)(ntiles + nsmall + nmfma + nbig);
             unsigned long long cnt = 0;
@@ -762,9 +770,13 @@ xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_off
     if (U) HIP_TRY(hipMemcpyAsync(all.data(), dout, sizeof(xyz_pair) * U, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     tm.collect(timing);
-    int64_t cand_total = 0;
-    for (auto &ri : hinfo) cand_total += (int64_t)ri.candidates;
+    int64_t cand_total = 0, big_total = 0;
+    for (auto &ri : hinfo) {
+        cand_total += (int64_t)ri.candidates;
+        big_total += (int64_t)ri.big_pairs;
+    }
     timing.candidates = cand_total;
+    timing.big_candidates = big_total;
     timing.total_ms = now_ms() - t0;
 
     size_t off = 0;

@@ -71,6 +71,7 @@ struct RepInfo {         // per repetition and response, filled on the device
     unsigned int small_tiles; // one-tile bucket products with at most SMALL_TILE_PAIRS pairs
     unsigned long long mfma_tiles; // MTILE x MTILE tiles of products verified on the matrix cores
     unsigned long long big_tiles;  // BIG_TILE x BIG_TILE block pairs of products staged through LDS
+    unsigned long long big_pairs;  // candidate pairs of those products
 };
 
 // ------------------------------------------------------------ launchers --
@@ -194,8 +195,11 @@ struct VerifyArgs {
 // Column popcounts for the big tiles: cpop[y][j] = |y_y ^ x_j| for y < nys, cpop[nys][j] = |x_j|.
 hipError_t launch_col_pops(const uint32_t *XC, int W32p, const uint32_t *yb, int nys, int64_t p, uint32_t *cpop,
                            hipStream_t st);
-// Popcount-XOR verification of +-1 candidates: s = n - 2 popcount(y ^ x_j ^ x_k).
+// Popcount-XOR verification of +-1 candidates: s = n - 2 popcount(y ^ x_j ^ x_k) (popcount, small
+// and matrix-core tiles).
 hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st);
+// The big tiles of +-1 candidates (LDS-staged block pairs on the FP4 matrix cores).
+hipError_t launch_verify_big(const VerifyArgs &a, int grid, hipStream_t st);
 // Binary64 verification of real-valued candidates (x_real: values from XF, else +-1 from XC).
 hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStream_t st);
 

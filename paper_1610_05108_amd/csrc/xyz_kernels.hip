@@ -565,7 +565,7 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
         RepInfo *inf = info + (int64_t)r * nys + y;
         const uint32_t c = (uint32_t)inf->cmask & mask;
         const uint32_t cn = (~c) & mask;
-        unsigned long long cand = 0, cnts[5] = {0, 0, 0, 0, 0};
+        unsigned long long cand = 0, cnts[5] = {0, 0, 0, 0, 0}, bigc = 0;
         unsigned mx = 0;
         for (int b = threadIdx.x; b < nb; b += 1024) {
             const uint32_t a = cnt[b];
@@ -574,8 +574,10 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
                 const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
                 unsigned long long T;
                 int kind;
-                cand += product_tiles((uint32_t)b, b2, a, cnt[b2], mfma, kind, T);
+                const unsigned long long c = product_tiles((uint32_t)b, b2, a, cnt[b2], mfma, kind, T);
+                cand += c;
                 cnts[kind] += T;
+                if (kind == 4) bigc += c;
             }
         }
         cand = block_sum<1024>(cand, shm);
@@ -583,6 +585,7 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
         const unsigned long long small = block_sum<1024>(cnts[1], shm);
         const unsigned long long mtiles = block_sum<1024>(cnts[3], shm);
         const unsigned long long btiles = block_sum<1024>(cnts[4], shm);
+        const unsigned long long bpairs = block_sum<1024>(bigc, shm);
         mx = block_max<1024>(mx, shmax);
         if (threadIdx.x == 0) {
             inf->candidates = cand;
@@ -590,6 +593,7 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
             inf->small_tiles = (unsigned)small;
             inf->mfma_tiles = mtiles;
             inf->big_tiles = btiles;
+            inf->big_pairs = bpairs;
             inf->max_bucket = mx;
             inf->passed = 0;
             inf->fresh = 0;
@@ -910,8 +914,9 @@ XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t 
         const uint32_t a2 = b2 == b ? a : run_len(run_start, nr, S, (uint32_t)rid2);
         unsigned long long T;
         int kind;
-        cand += product_tiles(b, b2, a, a2, mfma, kind, T);
-        if (kind) f((uint32_t)rid2, a2, kind, T);
+        const unsigned long long c = product_tiles(b, b2, a, a2, mfma, kind, T);
+        cand += c;
+        if (kind) f((uint32_t)rid2, a2, kind, T, c);
     }
     return cand;
 }
@@ -922,9 +927,10 @@ XYZ_DEV unsigned long long run_products(const uint64_t *run_key, const uint32_t 
 // waves whose lanes end on one (repetition, response) add their sums once.
 constexpr int SK_ITEMS = 16;
 
-XYZ_DEV void sk_flush(RepInfo *info, int64_t key, const unsigned long long v[5], uint32_t mx)
+XYZ_DEV void sk_flush(RepInfo *info, int64_t key, const unsigned long long v[6], uint32_t mx)
 {
     RepInfo *inf = info + key;
+    if (v[5]) atomicAdd(&inf->big_pairs, v[5]);
     if (v[0]) atomicAdd(&inf->candidates, v[0]);
     if (v[1]) atomicAdd(&inf->tiles, v[1]);
     if (v[2]) atomicAdd(&inf->small_tiles, (unsigned)v[2]);
@@ -944,7 +950,7 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
     const uint64_t total = (uint64_t)nr * nys;
     const uint64_t base = (uint64_t)blockIdx.x * SK_ITEMS * 256;
     int64_t key = -1;
-    unsigned long long v[5] = {0, 0, 0, 0, 0};
+    unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
     uint32_t mx = 0;
     for (int it = 0; it < SK_ITEMS; ++it) {
         const uint64_t tid = base + (uint64_t)it * 256 + threadIdx.x;
@@ -955,13 +961,16 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
         if (k != key) {
             if (key >= 0) sk_flush(info, key, v, mx);
             key = k;
-            v[0] = v[1] = v[2] = v[3] = v[4] = 0;
+            v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = 0;
             mx = 0;
         }
         const uint32_t c = (uint32_t)info[k].cmask & (uint32_t)((1ull << m) - 1);
-        unsigned long long tl[5] = {0, 0, 0, 0, 0};
+        unsigned long long tl[5] = {0, 0, 0, 0, 0}, bp = 0;
         v[0] += run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
-                             [&](uint32_t, uint32_t, int kind, unsigned long long T) { tl[kind] += T; });
+                             [&](uint32_t, uint32_t, int kind, unsigned long long T, unsigned long long pc) {
+                                 tl[kind] += T;
+                                 if (kind == 4) bp += pc;
+                             });
         cnt[0 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[2];
         cnt[1 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[1];
         cnt[2 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[3];
@@ -970,6 +979,7 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
         v[2] += tl[1];
         v[3] += tl[3];
         v[4] += tl[4];
+        v[5] += bp;
         mx = max(mx, run_len(run_start, nr, S, rid));
     }
     // lanes that end on lane 0's (repetition, response) add their sums once per wave
@@ -979,7 +989,7 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) v[q] += __shfl_xor(v[q], d, 64);
+            for (int q = 0; q < 6; ++q) v[q] += __shfl_xor(v[q], d, 64);
             mx = max(mx, (uint32_t)__shfl_xor(mx, d, 64));
         }
         if (lane_id() == 0) sk_flush(info, k0, v, mx);
@@ -1012,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
     at[3] = pos[2 * cnt_stride + (uint64_t)y * nr + rid];
     at[4] = pos[3 * cnt_stride + (uint64_t)y * nr + rid];
     run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
-                 [&](uint32_t rid2, uint32_t a2, int kind, unsigned long long T) {
+                 [&](uint32_t rid2, uint32_t a2, int kind, unsigned long long T, unsigned long long) {
                      const uint32_t ts = kind_tile(kind);
                      const uint32_t o2 = run_start[rid2] - pbase;
                      const bool own = rid2 == rid;
@@ -1043,6 +1053,7 @@ __global__ __launch_bounds__(256) void k_sk_clear_info(RepInfo *__restrict__ inf
     info[i].small_tiles = 0;
     info[i].mfma_tiles = 0;
     info[i].big_tiles = 0;
+    info[i].big_pairs = 0;
 }
 
 // ----------------------------------------------------------- FP4 operands --
@@ -3190,13 +3201,6 @@ hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st)
     if (a.nmfma)
         hipLaunchKernelGGL(k_verify_mfma, dim3((unsigned)std::min<uint64_t>((a.nmfma + 3) / 4, (uint64_t)grid)),
                            dim3(256), 0, st, a);
-    if (a.nbig) {
-        const unsigned g = (unsigned)std::min<uint64_t>(a.nbig, (uint64_t)std::max(grid / 3, 1));
-        if (a.two_sided)
-            hipLaunchKernelGGL(k_verify_lds<true>, dim3(g), dim3(512), BIG_LDS, st, a);
-        else
-            hipLaunchKernelGGL(k_verify_lds<false>, dim3(g), dim3(512), BIG_LDS, st, a);
-    }
     if (a.nsmall) {
         const uint64_t groups = (a.nsmall + 63) / 64;                  // 64 small tiles per wave step
         hipLaunchKernelGGL(k_verify_small, dim3((unsigned)std::min<uint64_t>(groups, (uint64_t)grid)), dim3(64), 0, st,
@@ -3210,6 +3214,18 @@ hipError_t launch_col_pops(const uint32_t *XC, int W32p, const uint32_t *yb, int
 {
     hipLaunchKernelGGL(k_col_pops, dim3(grid1((uint64_t)p * 8, 256)), dim3(256), 0, st,
                        reinterpret_cast<const uint4 *>(XC), W32p / 4, reinterpret_cast<const uint4 *>(yb), nys, p, cpop);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_big(const VerifyArgs &a, int grid, hipStream_t st)
+{
+    if (a.nbig) {
+        const unsigned g = (unsigned)std::min<uint64_t>(a.nbig, (uint64_t)std::max(grid / 3, 1));
+        if (a.two_sided)
+            hipLaunchKernelGGL(k_verify_lds<true>, dim3(g), dim3(512), BIG_LDS, st, a);
+        else
+            hipLaunchKernelGGL(k_verify_lds<false>, dim3(g), dim3(512), BIG_LDS, st, a);
+    }
     return hipGetLastError();
 }
 
