@@ -366,7 +366,7 @@ int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m)
     // path's scratch (two key/value buffers, heads, runs and per-run tile counts)
     const int64_t per_rep = m <= MAX_M_LDS ? 8 * p + 4 * ((1ll << m) + 1)
                                            : 64 * p + (m <= SK_TABLE_MAX_M ? 4 * (1ll << m) : 0);
-    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(2ll << 30) / per_rep));
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(8ll << 30) / per_rep));   // 8 GiB of 288
     chunk = std::min<int64_t>(chunk, 65535);                                           // grid y of k_hash
     if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
     return std::max<int64_t>(chunk, 1);
