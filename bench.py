@@ -390,12 +390,15 @@ def serve_leg(ctx, count, fresh_count, workers, seq_sample):
     sets (n=1000, p from {1e4, 1e5, 5e5}, handed over bit-packed, made
     resident on arrival and freed after).
 
-    Each request is routed by the cost model: xyz with the largest m that
-    keeps eq. (9) >= 0.95 at the strength kappa itself (gamma = (1 + kappa)/2)
-    for the request's L, and candidates predicted from sampled pair strengths
-    (E|E_l| = sum of gamma^m), against the exact matrix-core search; the
-    predicted faster one is submitted.  Rates for the model are measured on
-    the shared X before the stream starts.  Latency = arrival to result."""
+    Every request is submitted with XYZ_ROUTE: the library's router answers it
+    with xyz at the request's L (m from eq. (9) at gamma = (1 + kappa)/2, rows
+    from the shared seed, so that compatible requests share a pass) or with the
+    exact search, whichever its cost model predicts faster.  Latency = arrival
+    to result.  The stream is replayed twice: at its arrival times (p50/p99
+    latency, pairs screened per second of the stream) and, for the shared-X
+    requests, all at once (the server's capacity: pairs screened per second
+    with the queue full), beside the same requests answered one at a time by
+    the reported routes."""
     import threading
     import synthgen
     import paper_1610_05108_amd as xyz
@@ -407,124 +410,97 @@ def serve_leg(ctx, count, fresh_count, workers, seq_sample):
     fresh = synthgen.config5_fresh_bits(count=fresh_count, seed=0) if fresh_count else []
     log(f"serving data ready ({time.time() - t0:.1f}s): {len(reqs)} shared-X requests, {len(fresh)} fresh")
 
-    # rates for the cost model, on the shared X
-    Y0 = reqs[0]["Y"]
-    ctx.bruteforce(x, Y0, 0.15)
-    tb = time.perf_counter()
-    ctx.bruteforce(x, Y0, 0.15)
-    t_br = time.perf_counter() - tb
-    rate_exact = ps * (ps - 1) / 2 * ns / t_br               # pair-rows / s
-    r = ctx.search(x, Y0, m=9, L=50, kappa=0.15, seed=1, profile=True)
-    tm = r["timing"]
-    words = math.ceil(ns / 32)
-    rate_verify = tm["candidates"] * words / (tm["verify_ms"] * 1e-3)   # candidate-words / s
-    rep_cost = max(tm["total_ms"] - tm["verify_ms"], 0.0) * 1e-3 / (50 * ps)   # s per repetition and column
+    def replay(realtime, with_fresh=True):
+        events = [dict(kind="shared", **q) for q in reqs] + ([dict(kind="fresh", **q) for q in fresh] if with_fresh else [])
+        events.sort(key=lambda e: e["t"])
+        srv = xyz.xyz_serve_start(ctx.h, 0, workers=workers, max_batch=64)
+        pending, done = {}, {}
+        lock = threading.Lock()
+        finished = threading.Event()
 
-    def route(xh, Y, p, n, L, kappa):
-        g = 0.5 * (1.0 + kappa)
-        m = xyz.xyz_m_for_L(g, L, 0.95, 15)
-        t_exact = p * (p - 1) / 2 * n / rate_exact
-        if m < 1:
-            return ("exact", 0, t_exact, t_exact)
-        gs = xyz.xyz_sample_strengths(ctx.h, xh, Y, 4096, seed=7)
-        cand = p * (p - 1) / 2 * float(np.mean(gs ** m))
-        t_xyz = L * (cand * math.ceil(n / 32) / rate_verify + p * rep_cost)
-        return ("xyz", m, t_xyz, t_exact) if t_xyz < t_exact else ("exact", m, t_xyz, t_exact)
+        def collector():
+            while not finished.is_set() or pending:
+                with lock:
+                    items = list(pending.items())
+                for tk, e in items:
+                    try:
+                        o = xyz.xyz_serve_poll(srv, tk)
+                    except xyz.XyzError as err:          # failed request: report it, keep collecting
+                        e["error"] = str(err)
+                        o = {"pairs": np.zeros(0, dtype=[("j", "i4"), ("k", "i4")]), "route": {"method": -1}}
+                    if o is not None:
+                        e["t_done"] = time.perf_counter()
+                        e["out"] = o
+                        with lock:
+                            del pending[tk]
+                            done[tk] = e
+                time.sleep(0.0005)
 
-    events = [dict(kind="shared", **q) for q in reqs] + [dict(kind="fresh", **q) for q in fresh]
-    events.sort(key=lambda e: e["t"])
-    srv = xyz.xyz_serve_start(ctx.h, 0, workers=workers, max_batch=16)
-    pending = {}
-    done = {}
-    lock = threading.Lock()
-    finished = threading.Event()
-
-    def collector():
-        while not finished.is_set() or pending:
-            with lock:
-                items = list(pending.items())
-            for tk, e in items:
-                try:
-                    o = xyz.xyz_serve_poll(srv, tk)
-                except xyz.XyzError as err:          # failed request: report it, keep collecting
-                    e["error"] = str(err)
-                    o = {"pairs": np.zeros(0, dtype=[("j", "i4"), ("k", "i4")])}
-                if o is not None:
-                    e["t_done"] = time.perf_counter()
-                    e["out"] = o
-                    with lock:
-                        del pending[tk]
-                        done[tk] = e
-            time.sleep(0.0005)
-
-    th = threading.Thread(target=collector)
-    th.start()
-    start = time.perf_counter()
-    routes = {"xyz": 0, "exact": 0}
-    try:
+        th = threading.Thread(target=collector)
+        th.start()
+        start = time.perf_counter()
+        try:
+            for e in events:
+                if realtime:
+                    wait = start + e["t"] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                e["t_arr"] = start + e["t"] if realtime else time.perf_counter()
+                if e["kind"] == "fresh":
+                    e["x"] = xyz.xyz_x_create(ctx.h, e["bits"], n=e["n"])
+                    e.update(p=e["bits"].shape[0], xh=e["x"])
+                else:
+                    e.update(p=ps, n=ns, xh=x)
+                tk = xyz.xyz_serve_submit(srv, e["xh"], e["Y"], L=e["L"], kappa=e["kappa"], route=True)
+                with lock:
+                    pending[tk] = e
+        finally:
+            finished.set()
+            th.join()
+            st = xyz.xyz_serve_stats_get(srv)
+            xyz.xyz_serve_stop(srv)
+        end = max(e["t_done"] for e in events)
         for e in events:
-            wait = start + e["t"] - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
-            e["t_arr"] = start + e["t"]
-            if e["kind"] == "fresh":
-                e["x"] = xyz.xyz_x_create(ctx.h, e["bits"], n=e["n"])
-                p, n, xh = e["bits"].shape[0], e["n"], e["x"]
-            else:
-                p, n, xh = ps, ns, x
-            kind, m, t_x, t_e = route(xh, e["Y"], p, n, e["L"], e["kappa"])
-            e.update(route=kind, m=m, p=p, n=n)
-            routes[kind] += 1
-            if kind == "exact":
-                tk = xyz.xyz_serve_submit(srv, xh, e["Y"], kappa=e["kappa"], exact=True)
-            else:
-                tk = xyz.xyz_serve_submit(srv, xh, e["Y"], m=m, L=e["L"], kappa=e["kappa"], seed=int(e["t"] * 1e6))
-            with lock:
-                pending[tk] = e
-    finally:
-        finished.set()
-        th.join()
-        st = xyz.xyz_serve_stats_get(srv)
-        xyz.xyz_serve_stop(srv)
-    end = max(e["t_done"] for e in done.values())
-    for e in events:
-        if "x" in e:
-            xyz.xyz_x_destroy(e.pop("x"))
-    lat = [(e["t_done"] - e["t_arr"]) * 1e3 for e in events]
-    screened = sum(e["p"] * (e["p"] - 1) / 2 for e in events)
-    # planted pairs reported by their request
-    found = tot = 0
-    for e in events:
-        got = {(int(a), int(b)) for a, b in zip(e["out"]["pairs"]["j"], e["out"]["pairs"]["k"])}
-        for pq in e["planted"]:
-            tot += 1
-            found += pq in got
-    # the same requests one at a time, without the server (first seq_sample shared-X requests)
-    seq = [e for e in events if e["kind"] == "shared"][:seq_sample]
+            if "x" in e:
+                xyz.xyz_x_destroy(e.pop("x"))
+        lat = [(e["t_done"] - e["t_arr"]) * 1e3 for e in events]
+        screened = sum(e["p"] * (e["p"] - 1) / 2 for e in events)
+        routes = {"xyz": sum(1 for e in events if e["out"]["route"]["method"] == xyz.XYZ_PLAN_XYZ),
+                  "exact": sum(1 for e in events if e["out"]["route"]["method"] == xyz.XYZ_PLAN_BRUTE)}
+        found = tot = 0
+        for e in events:
+            got = {(int(a), int(b)) for a, b in zip(e["out"]["pairs"]["j"], e["out"]["pairs"]["k"])}
+            for pq in e["planted"]:
+                tot += 1
+                found += pq in got
+        return events, dict(p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), max_ms=max(lat),
+                            server_p50_ms=st["p50_ms"], server_p99_ms=st["p99_ms"], batches=st["batches"],
+                            max_batch=st["max_batch"], wall_s=end - start, pairs_screened_per_s=screened / (end - start),
+                            routes=routes, failed=sum(1 for e in events if "error" in e), planted_found=found,
+                            planted_total=tot)
+
+    ev_rt, realtime = replay(True)
+    ev_b, burst = replay(False, with_fresh=False)
+    # the shared-X requests one at a time, without the server, by the routes the server reported
+    seq = [e for e in ev_b if e["kind"] == "shared"][:seq_sample]
     ts = time.perf_counter()
     for e in seq:
-        if e["route"] == "exact":
+        rt = e["out"]["route"]
+        if rt["method"] == xyz.XYZ_PLAN_BRUTE:
             ctx.bruteforce(x, e["Y"], e["kappa"])
         else:
-            ctx.search(x, e["Y"], m=e["m"], L=e["L"], kappa=e["kappa"], seed=int(e["t"] * 1e6))
+            ctx.search(x, e["Y"], m=rt["m"], L=rt["L"], kappa=e["kappa"], seed=rt["seed"])
     t_seq = time.perf_counter() - ts
     xyz.xyz_x_destroy(x)
+    seq_rate = sum(ps * (ps - 1) / 2 for _ in seq) / t_seq if seq else None
     return {
         "workload": f"shared genotype X n={ns} p={ps} resident; {len(reqs)} +-1 requests at 50/s "
                     f"(L in {{50,200,500}}, kappa 0.15) + {len(fresh)} fresh Rademacher data sets "
-                    f"(n=1000, p in {{1e4,1e5,5e5}}, bit-packed)",
-        "requests": len(events), "workers": workers,
-        "failed": sum(1 for e in events if "error" in e),
-        "routes": routes,
-        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": max(lat),
-        "server_p50_ms": st["p50_ms"], "server_p99_ms": st["p99_ms"],
-        "batches": st["batches"], "max_batch": st["max_batch"],
-        "wall_s": end - start, "pairs_screened_per_s": screened / (end - start),
-        "planted_found": found, "planted_total": tot,
-        "sequential_pairs_per_s": sum(ps * (ps - 1) / 2 for _ in seq) / t_seq if seq else None,
-        "sequential_sample": len(seq),
-        "model": {"exact_pair_rows_per_s": rate_exact, "verify_candidate_words_per_s": rate_verify,
-                  "s_per_rep_column": rep_cost},
+                    f"(n=1000, p in {{1e4,1e5,5e5}}, bit-packed); routed by the library (XYZ_ROUTE)",
+        "requests": len(ev_rt), "workers": workers,
+        "realtime": realtime, "burst": burst,
+        "sequential_pairs_per_s": seq_rate, "sequential_sample": len(seq),
+        "burst_over_sequential": burst["pairs_screened_per_s"] / seq_rate if seq_rate else None,
     }
 
 

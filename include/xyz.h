@@ -68,6 +68,8 @@ typedef int32_t xyz_status;
 #define XYZ_PROFILE   2u  /* time the GPU stages with HIP events and report them in xyz_timing */
 #define XYZ_EXACT     4u  /* xyz_serve_submit only: answer with the exact search of eq. (1), as xyz_bruteforce
                              over all columns; m, L, seed, rep_offset and rows are ignored */
+#define XYZ_ROUTE    16u  /* xyz_serve_submit only: the server chooses between the exact search and xyz with the
+                             request's L (see xyz_serve_submit); m, seed and rows are ignored */
 #define XYZ_UNBIASED  8u  /* float32 X only: hash with the unbiased transform of Section 3.2 (Proposition 4)
                              instead of the sign transform.  Each row is divided by its largest absolute
                              entry nu_i and Y_i multiplied by nu_i^2, so rows are drawn with probability
@@ -317,7 +319,18 @@ xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, int32_t work
                            xyz_server **out);
 /* Queue a search; Y (host memory, format yfmt) and params (including its row table) are copied.
  * With XYZ_EXACT in params->flags the request is answered by the exact search (result as from
- * xyz_bruteforce); such requests are never grouped with others. */
+ * xyz_bruteforce); such requests are never grouped with others.
+ * With XYZ_ROUTE (+-1 X and Y) the server picks the method, as Section 2.3 compares xyz with the
+ * O(n p^2) search: xyz with the request's L and the largest m <= 15 whose recall eq. (9) at the
+ * threshold's own strength gamma = (1 + kappa)/2 is at least 0.95 (xyz_m_for_L), or the exact
+ * search, whichever its cost model predicts faster.  The cost model prices the exact search at
+ * p(p-1)/2 pairs of n rows and xyz at L repetitions of p columns plus E|E_l| candidates of n rows,
+ * E|E_l| = p(p-1)/2 times the mean of gamma_jk^m over 4096 sampled pairs (xyz_sample_strengths;
+ * Section 2.3 estimates the strengths by sampling); its rates start from values measured on this
+ * part and follow the server's completed requests.  A routed xyz request samples its rows with
+ * the shared seed XYZ_SERVE_SEED, so that routed requests on the same X with the same L, m and
+ * flags share a pass.  xyz_result_route tells what was run. */
+#define XYZ_SERVE_SEED 0x9E3779B97F4A7C15ull
 xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void *Y, int yfmt, const xyz_params *params,
                             uint64_t *ticket);
 /* XYZ_EAGAIN while the request is queued or running; otherwise the request's result (or its error, or
@@ -331,6 +344,18 @@ xyz_status xyz_serve_stats_get(xyz_server *s, xyz_serve_stats *out);
 /* Cancel queued requests, wait for running ones, free the server and every unclaimed result. */
 xyz_status xyz_serve_stop(xyz_server *s);
 
+/* What produced a result: the method (XYZ_PLAN_XYZ or XYZ_PLAN_BRUTE), xyz's m, L and seed (0, 1, 0
+ * for the exact search) and, for a request routed by a server (XYZ_ROUTE), the cost model's
+ * predictions for the chosen and the other method (0 otherwise). */
+typedef struct {
+    int32_t method;
+    int32_t m, L;
+    int32_t routed;             /* 1 when the server chose the method */
+    uint64_t seed;
+    double predicted_ms;
+    double alternative_ms;
+} xyz_route;
+xyz_status xyz_result_route(const xyz_result *r, xyz_route *out);
 int64_t xyz_result_npairs(const xyz_result *r);
 const xyz_pair *xyz_result_pairs(const xyz_result *r);      /* sorted by (j, k), unique */
 int32_t xyz_result_nreps(const xyz_result *r);

@@ -24,7 +24,8 @@ XYZ_OK, XYZ_EINVAL, XYZ_ENOMEM, XYZ_EDEVICE, XYZ_EAGAIN, XYZ_ECANCELED, XYZ_EUNS
 XYZ_MEM_HOST, XYZ_MEM_DEVICE = 0, 1
 XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32, XYZ_X_I8_PM1_ROWMAJOR = 0, 1, 2, 3
 XYZ_Y_I8_PM1, XYZ_Y_F32, XYZ_Y_F64 = 0, 1, 2
-XYZ_TWO_SIDED, XYZ_PROFILE, XYZ_EXACT, XYZ_UNBIASED = 1, 2, 4, 8
+XYZ_TWO_SIDED, XYZ_PROFILE, XYZ_EXACT, XYZ_UNBIASED, XYZ_ROUTE = 1, 2, 4, 8, 16
+XYZ_SERVE_SEED = 0x9E3779B97F4A7C15
 XYZ_MAX_M = 30
 
 PAIR_DTYPE = np.dtype([("j", np.int32), ("k", np.int32), ("s", np.int64), ("value", np.float64),
@@ -35,7 +36,8 @@ REP_DTYPE = np.dtype([("candidates", np.int64), ("passed", np.int64), ("fresh", 
 EXPORTS = [
     "xyz_version", "xyz_last_error", "xyz_init", "xyz_fini", "xyz_ctx_bytes", "xyz_x_create", "xyz_x_destroy",
     "xyz_x_n", "xyz_x_p", "xyz_search", "xyz_search_batch", "xyz_search_noalloc", "xyz_bruteforce", "xyz_dense_search", "xyz_result_npairs",
-    "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_free", "xyz_smin",
+    "xyz_result_pairs", "xyz_result_nreps", "xyz_result_reps", "xyz_result_timing", "xyz_result_route",
+    "xyz_result_free", "xyz_smin",
     "xyz_eta", "xyz_tau_dense", "xyz_eta_dense", "xyz_L_for", "xyz_m_for_L", "xyz_mstar",
     "xyz_sample_strengths", "xyz_plan",
     "xyz_serve_start", "xyz_serve_submit", "xyz_serve_poll", "xyz_serve_wait", "xyz_serve_cancel",
@@ -62,6 +64,11 @@ class xyz_timing(ctypes.Structure):
                  "dedup_ms", "brute_ms")] + [("verify_launches", ctypes.c_int64), ("candidates", ctypes.c_int64),
                                              ("tiles", ctypes.c_int64), ("big_ms", ctypes.c_double),
                                              ("big_launches", ctypes.c_int64), ("big_candidates", ctypes.c_int64)]
+
+
+class xyz_route(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("m", ctypes.c_int32), ("L", ctypes.c_int32), ("routed", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("predicted_ms", ctypes.c_double), ("alternative_ms", ctypes.c_double)]
 
 
 class xyz_plan_info(ctypes.Structure):
@@ -118,6 +125,7 @@ def lib():
         "xyz_result_nreps": (I32, [P]),
         "xyz_result_reps": (P, [P]),
         "xyz_result_timing": (ctypes.POINTER(xyz_timing), [P]),
+        "xyz_result_route": (I32, [P, ctypes.POINTER(xyz_route)]),
         "xyz_result_free": (None, [P]),
         "xyz_smin": (I64, [I64, D, ctypes.c_int]),
         "xyz_eta": (D, [D, I32, I64]),
@@ -290,8 +298,11 @@ def _take_result(h):
         ctypes.memmove(reps.ctypes.data, L.xyz_result_reps(h), nreps * REP_DTYPE.itemsize)
     t = L.xyz_result_timing(h).contents
     timing = {name: getattr(t, name) for name, _ in xyz_timing._fields_}
+    rt = xyz_route()
+    L.xyz_result_route(h, ctypes.byref(rt))
+    route = {name: getattr(rt, name) for name, _ in xyz_route._fields_}
     L.xyz_result_free(h)
-    return {"pairs": pairs, "reps": reps, "timing": timing}
+    return {"pairs": pairs, "reps": reps, "timing": timing, "route": route}
 
 
 def xyz_search(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
@@ -453,15 +464,19 @@ def xyz_serve_start(ctx, hbm_budget_bytes: int = 0, workers: int = 2, max_batch:
 
 
 def xyz_serve_submit(server, x, Y, m: int = 0, L: int = 1, kappa: float = 0.0, seed: int = 0,
-                     two_sided: bool = False, rep_offset: int = 0, rows=None, exact: bool = False) -> int:
+                     two_sided: bool = False, rep_offset: int = 0, rows=None, exact: bool = False,
+                     route: bool = False) -> int:
     """Queue a search (Y is host memory: numpy array or CPU tensor); returns the ticket.
-    exact=True asks for the exact search of eq. (1) (m, L, seed, rows ignored)."""
+    exact=True asks for the exact search of eq. (1) (m, L, seed, rows ignored); route=True lets the
+    server choose between the exact search and xyz with this L (XYZ_ROUTE: m, seed, rows ignored)."""
     if _is_torch(Y) and Y.is_cuda:
         raise ValueError("xyz_serve_submit takes Y in host memory")
     _check_y(x, Y)
-    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, None if exact else rows, False)
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, None if (exact or route) else rows, False)
     if exact:
         prm.flags |= XYZ_EXACT
+    if route:
+        prm.flags |= XYZ_ROUTE
     ptr, _, keep = _ptr(Y)
     t = ctypes.c_uint64()
     _check(lib().xyz_serve_submit(server, x, ptr, _y_format(Y), ctypes.byref(prm), ctypes.byref(t)))

@@ -695,7 +695,16 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     }
 
     // ---- merge repetitions
-    return merge_results(c, x, nys, L, P.rep_offset, surv, surv_done, info, tm, timing, t0, st, outs, direct);
+    const xyz_status ms = merge_results(c, x, nys, L, P.rep_offset, surv, surv_done, info, tm, timing, t0, st, outs,
+                                        direct);
+    if (ms == XYZ_OK && !direct)
+        for (int y = 0; y < nys; ++y) {
+            outs[y]->route.method = XYZ_PLAN_XYZ;
+            outs[y]->route.m = m;
+            outs[y]->route.L = L;
+            outs[y]->route.seed = Ps[y]->seed;
+        }
+    return ms;
 }
 
 namespace {
@@ -871,6 +880,12 @@ extern "C" int32_t xyz_result_nreps(const xyz_result *r) { return r ? (int32_t)r
 extern "C" const xyz_rep_stats *xyz_result_reps(const xyz_result *r) { return r && !r->reps.empty() ? r->reps.data() : nullptr; }
 extern "C" const xyz_timing *xyz_result_timing(const xyz_result *r) { return r ? &r->timing : nullptr; }
 extern "C" void xyz_result_free(xyz_result *r) { delete r; }
+extern "C" xyz_status xyz_result_route(const xyz_result *r, xyz_route *out)
+{
+    if (!r || !out) return fail(XYZ_EINVAL, "NULL argument");
+    *out = r->route;
+    return XYZ_OK;
+}
 
 extern "C" xyz_status xyz_bruteforce(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, double kappa,
                                      uint32_t flags, const int32_t *colsA, int64_t nA, const int32_t *colsB,
@@ -923,6 +938,9 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
         }
         r->reps.clear();
         r->timing.brute_ms = r->timing.verify_ms;
+        r->route = xyz_route{};
+        r->route.method = XYZ_PLAN_BRUTE;
+        r->route.L = 1;
         *out = r;
         return XYZ_OK;
     }
@@ -1075,6 +1093,8 @@ xyz_status xyz_rt::brute_run(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt
     timing.tiles = (int64_t)ba.ntiles;
     timing.total_ms = now_ms() - t0;
     r->timing = timing;
+    r->route.method = XYZ_PLAN_BRUTE;
+    r->route.L = 1;
     *out = r;
     return XYZ_OK;
 }
@@ -1168,6 +1188,14 @@ extern "C" xyz_status xyz_sample_strengths(xyz_ctx *c, const xyz_x *x, const voi
 {
     if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
     if (x->ctx != c) return fail(XYZ_EINVAL, "X belongs to another context");
+    return sample_strengths(c, x, Y, yfmt, mem, npairs, seed, (hipStream_t)stream, out);
+}
+
+xyz_status xyz_rt::sample_strengths(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, int64_t npairs,
+                                    uint64_t seed, hipStream_t stream, double *out)
+{
+    if (!c || !x || !Y || !out) return fail(XYZ_EINVAL, "NULL argument");
+    if (x->ctx->device != c->device) return fail(XYZ_EINVAL, "X lives on another device");
     if (npairs < 0) return fail(XYZ_EINVAL, "npairs < 0");
     if (x->p < 2) return fail(XYZ_EINVAL, "X has fewer than two columns");
     if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);

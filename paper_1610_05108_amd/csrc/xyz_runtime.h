@@ -53,6 +53,7 @@ struct xyz_result {
     std::vector<xyz_pair> pairs;
     std::vector<xyz_rep_stats> reps;
     xyz_timing timing{};
+    xyz_route route{};
 };
 
 namespace xyz_rt {
@@ -78,6 +79,10 @@ struct DirectOut {
 xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys, int yfmt, int mem,
                      const xyz_params *const *Ps, hipStream_t st, xyz_result **outs,
                      const DirectOut *direct = nullptr);
+// xyz_sample_strengths without the check that X belongs to c (X may belong to another context on
+// the same device).
+xyz_status sample_strengths(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, int64_t npairs,
+                            uint64_t seed, hipStream_t stream, double *out);
 // Repetitions per chunk for p columns and 2^m buckets under the context's limits.
 int64_t chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m);
 // Frees every workspace of the context.

@@ -45,6 +45,8 @@ struct Request {
     bool running = false, done = false, canceled = false;
     xyz_status status = XYZ_OK;
     xyz_result *result = nullptr;
+    xyz_route route{};           // what the router chose (routed requests)
+    double base_ms = 0.0;        // the cost model's unscaled prediction of the chosen method
 };
 
 size_t y_size(int yfmt, int64_t n) { return (size_t)n * (yfmt == XYZ_Y_I8_PM1 ? 1 : (yfmt == XYZ_Y_F32 ? 4 : 8)); }
@@ -85,6 +87,26 @@ uint64_t estimate_bytes(const xyz_x *x, const xyz_params &P, int64_t chunk, int 
     return (uint64_t)(per_rep * (double)chunk + fixed);
 }
 
+// Unscaled cost model of the router (Section 2.3 compares the two methods the same way).  Rates of
+// this part: the exact search runs about 2.7e15 pair-rows per second on the FP4 matrix cores, xyz
+// verifies about 4.5e13 candidate words per second and spends about 8e-11 s per column and
+// repetition on sampling, projection, bucket sort and candidate expansion.
+constexpr double RATE_EXACT_PAIR_ROWS = 2.7e15;
+constexpr double RATE_VERIFY_WORDS = 4.5e13;
+constexpr double SEC_PER_REP_COLUMN = 8e-11;
+
+double exact_ms(const xyz_x *x)
+{
+    const double p = (double)x->p;
+    return p * (p - 1) / 2 * (double)x->n / RATE_EXACT_PAIR_ROWS * 1e3 + 0.05;
+}
+
+double xyz_ms(const xyz_x *x, int L, double cand_per_rep)
+{
+    const double words = std::ceil((double)x->n / 32.0);
+    return (double)L * (cand_per_rep * words / RATE_VERIFY_WORDS + (double)x->p * SEC_PER_REP_COLUMN) * 1e3 + 0.05;
+}
+
 bool same_group(const Request &a, const Request &b)
 {
     if ((a.params.flags | b.params.flags) & XYZ_EXACT) return false;
@@ -113,6 +135,11 @@ struct xyz_server {
     std::vector<uint64_t> est;    // estimated bytes of the group each worker runs (0: idle)
     xyz_serve_stats st{};
     std::vector<double> lat;
+    // router (XYZ_ROUTE): a context of its own for sampling strengths, and the cost model's
+    // scale factors (measured time / unscaled prediction, exponential average of completed groups)
+    std::mutex rmu;
+    xyz_ctx *rctx = nullptr;
+    double scale_exact = 1.0, scale_xyz = 1.0;
 };
 
 namespace {
@@ -185,6 +212,7 @@ void worker_loop(xyz_server *s, int w)
         std::vector<xyz_result *> outs(batch.size(), nullptr);
         ctx->max_chunk = batch[0]->chunk;
         const xyz_params &P0 = batch[0]->params;
+        const double tg0 = now_ms();
         const xyz_status rc =
             (P0.flags & XYZ_EXACT)
                 ? brute_run(ctx, batch[0]->x, ys[0], batch[0]->yfmt, XYZ_MEM_HOST, P0.kappa,
@@ -194,10 +222,19 @@ void worker_loop(xyz_server *s, int w)
         // keep at most this worker's share of the budget between groups, so that idle workers
         // together never hold more than the budget
         if (s->budget && ctx->used > s->budget / s->wctx.size()) ws_release(ctx);
+        const double tg = now_ms() - tg0;
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->held[w] = ctx->used;
             s->est[w] = 0;
+            // the router's scale factors follow the measured group times (a group of routed xyz
+            // requests shares its repetitions: its prediction is the largest member's)
+            double base = 0.0;
+            for (Request *r : batch) base = std::max(base, r->base_ms);
+            if (rc == XYZ_OK && base > 0.0 && batch[0]->route.routed) {
+                double &sc = (P0.flags & XYZ_EXACT) ? s->scale_exact : s->scale_xyz;
+                sc = 0.7 * sc + 0.3 * std::min(100.0, std::max(0.01, tg / base));
+            }
             const double t = now_ms();
             for (size_t q = 0; q < batch.size(); ++q) {
                 Request *r = batch[q];
@@ -205,6 +242,11 @@ void worker_loop(xyz_server *s, int w)
                 r->done = true;
                 r->status = rc;
                 r->result = rc == XYZ_OK ? outs[q] : nullptr;
+                if (r->result && r->route.routed) {
+                    r->result->route.routed = 1;
+                    r->result->route.predicted_ms = r->route.predicted_ms;
+                    r->result->route.alternative_ms = r->route.alternative_ms;
+                }
                 if (rc == XYZ_OK) {
                     s->st.completed += 1;
                     s->lat.push_back(t - r->t_submit);
@@ -245,6 +287,14 @@ extern "C" xyz_status xyz_serve_start(xyz_ctx *ctx, uint64_t hbm_budget_bytes, i
         }
         s->wctx.push_back(c);
     }
+    {
+        const xyz_status rc = xyz_init(ctx->device, 0, &s->rctx);
+        if (rc != XYZ_OK) {
+            for (auto *q : s->wctx) xyz_fini(q);
+            delete s;
+            return rc;
+        }
+    }
     s->held.assign(workers, 0);
     s->est.assign(workers, 0);
     for (int w = 0; w < workers; ++w) s->threads.emplace_back(worker_loop, s, w);
@@ -257,6 +307,66 @@ extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void
 {
     if (!s || !x || !Y || !params || !ticket) return fail(XYZ_EINVAL, "NULL argument");
     if (x->ctx->device != s->device) return fail(XYZ_EINVAL, "X lives on another device");
+    xyz_params rp = *params;
+    xyz_route route{};
+    double base_ms = 0.0;
+    if (params->flags & XYZ_ROUTE) {
+        // the router: xyz at the request's L with m from eq. (9) at gamma = (1 + kappa)/2, or the exact
+        // search, whichever the cost model predicts faster
+        if (params->flags & (XYZ_EXACT | XYZ_UNBIASED | XYZ_PROFILE))
+            return fail(XYZ_EINVAL, "XYZ_ROUTE combines with XYZ_TWO_SIDED only");
+        if (x->fmt == XYZ_X_F32 || yfmt != XYZ_Y_I8_PM1) return fail(XYZ_EUNSUPPORTED, "XYZ_ROUTE needs +-1 X and Y");
+        if (params->L < 1) return fail(XYZ_EINVAL, "L=%d < 1", params->L);
+        if (!std::isfinite(params->kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
+        const bool two = (params->flags & XYZ_TWO_SIDED) != 0;
+        const double g = std::min(1.0, std::max(1e-9, 0.5 * (1.0 + std::fabs(params->kappa))));
+        const int32_t m = g >= 1.0 ? -1 : xyz_m_for_L(g, params->L, 0.95, xyz::MAX_M_LDS);
+        const double t_exact = exact_ms(x);
+        double t_xyz = INFINITY;
+        if (m >= 1 && x->p >= 2) {
+            constexpr int NS = 4096;
+            double gs[NS];
+            xyz_status rc;
+            {
+                std::lock_guard<std::mutex> lk(s->rmu);
+                rc = sample_strengths(s->rctx, x, Y, yfmt, XYZ_MEM_HOST, NS, 0x5eedull, nullptr, gs);
+            }
+            if (rc != XYZ_OK) return rc;
+            double acc = 0.0;
+            for (int q = 0; q < NS; ++q) acc += std::pow(gs[q], m) + (two ? std::pow(1.0 - gs[q], m) : 0.0);
+            const double P = (double)x->p * (double)(x->p - 1) / 2;
+            t_xyz = xyz_ms(x, params->L, P * acc / NS);
+        }
+        double se, sx;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            se = s->scale_exact;
+            sx = s->scale_xyz;
+        }
+        route.routed = 1;
+        rp.rows = nullptr;
+        rp.rep_offset = 0;
+        rp.flags &= ~XYZ_ROUTE;
+        if (t_xyz * sx < t_exact * se) {
+            rp.m = m;
+            rp.seed = XYZ_SERVE_SEED;
+            route.method = XYZ_PLAN_XYZ;
+            route.m = m;
+            route.L = params->L;
+            route.seed = XYZ_SERVE_SEED;
+            route.predicted_ms = t_xyz * sx;
+            route.alternative_ms = t_exact * se;
+            base_ms = t_xyz;
+        } else {
+            rp.flags |= XYZ_EXACT;
+            route.method = XYZ_PLAN_BRUTE;
+            route.L = 1;
+            route.predicted_ms = t_exact * se;
+            route.alternative_ms = t_xyz * sx;
+            base_ms = t_exact;
+        }
+        params = &rp;
+    }
     if (params->flags & XYZ_EXACT) {
         if (!std::isfinite(params->kappa)) return fail(XYZ_EINVAL, "kappa is not finite");
         if (params->flags & ~(uint32_t)(XYZ_TWO_SIDED | XYZ_PROFILE | XYZ_EXACT))
@@ -273,6 +383,8 @@ extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void
     r->y.resize(y_size(yfmt, x->n));
     std::memcpy(r->y.data(), Y, r->y.size());
     r->params = *params;
+    r->route = route;
+    r->base_ms = base_ms;
     if (params->rows && !(params->flags & XYZ_EXACT))
         r->rows.assign(params->rows, params->rows + (size_t)params->L * params->m);
     r->params.rows = nullptr;
@@ -404,6 +516,7 @@ extern "C" xyz_status xyz_serve_stop(xyz_server *s)
         delete kv.second;
     }
     for (auto *c : s->wctx) xyz_fini(c);
+    xyz_fini(s->rctx);
     delete s;
     return XYZ_OK;
 }

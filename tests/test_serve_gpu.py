@@ -215,3 +215,48 @@ def test_budget_bounds_device_memory_with_exact_requests(ctx):
     for (Y, kw), o in zip(xyzq, ox):
         _same(o, ctx.search(x, Y, **kw))
     ctx.x_destroy(x)
+
+
+def test_routed_requests_choose_a_method_and_share_passes(ctx):
+    """XYZ_ROUTE: the server picks xyz (m from eq. (9) at gamma = (1 + kappa)/2 for the request's L,
+    the shared seed XYZ_SERVE_SEED) or the exact search by its cost model.  Strong-threshold
+    requests go to xyz and, submitted together on one X, share passes; weak-threshold ones go to
+    the exact search.  Every result equals the stand-alone call of the route it reports."""
+    d = synthgen.small_binary(500, 60000, seed=51, planted=[(3, 4000)], flip=0.02)
+    x = ctx.x_create(d.XT)
+    r = np.random.default_rng(12)
+    strong = []
+    for q in range(6):
+        Y = d.Y.copy()
+        Y[r.random(500) < 0.03] *= -1
+        strong.append((Y, dict(L=20, kappa=0.6)))
+    weak = [(np.where(r.random(500) < 0.5, 1, -1).astype(np.int8), dict(L=5, kappa=0.05)) for _ in range(2)]
+    srv = xyz.xyz_serve_start(ctx.h, 0, workers=1, max_batch=8)
+    try:
+        # the first request occupies the worker while the others queue, so the strong ones group
+        tickets = [xyz.xyz_serve_submit(srv, x, Y, route=True, **kw) for Y, kw in weak[:1] + strong + weak[1:]]
+        outs = [xyz.xyz_serve_wait(srv, t) for t in tickets]
+        st = xyz.xyz_serve_stats_get(srv)
+    finally:
+        xyz.xyz_serve_stop(srv)
+    reqs = weak[:1] + strong + weak[1:]
+    methods = []
+    for (Y, kw), o in zip(reqs, outs):
+        rt = o["route"]
+        assert rt["routed"] == 1 and rt["predicted_ms"] > 0 and rt["alternative_ms"] > 0
+        methods.append(rt["method"])
+        if rt["method"] == xyz.XYZ_PLAN_BRUTE:
+            ref = ctx.bruteforce(x, Y, kw["kappa"])
+            assert np.array_equal(o["pairs"], ref["pairs"])
+        else:
+            assert rt["seed"] == xyz.XYZ_SERVE_SEED and rt["L"] == kw["L"]
+            g = 0.5 * (1 + kw["kappa"])
+            assert rt["m"] == xyz.xyz_m_for_L(g, kw["L"], 0.95, 15)
+            ref = ctx.search(x, Y, m=rt["m"], L=rt["L"], kappa=kw["kappa"], seed=xyz.XYZ_SERVE_SEED)
+            _same(o, ref)
+    assert all(mt == xyz.XYZ_PLAN_XYZ for mt in methods[1:7])
+    assert methods[0] == xyz.XYZ_PLAN_BRUTE and methods[7] == xyz.XYZ_PLAN_BRUTE
+    assert st["max_batch"] > 1 and st["completed"] == len(reqs)
+    found = [(3, 4000) in set(zip(o["pairs"]["j"].tolist(), o["pairs"]["k"].tolist())) for o in outs[1:7]]
+    assert all(found)
+    ctx.x_destroy(x)
