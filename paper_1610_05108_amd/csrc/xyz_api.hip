@@ -543,7 +543,9 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     if (m <= MAX_M_LDS) XYZ_TRY(ws(c, WS_OFFS, (size_t)chunk * (nb + 1), &offs));
     XYZ_TRY(ws(c, WS_PERM, (size_t)chunk * p, &perm));
     XYZ_TRY(ws(c, WS_BASE, NLISTS * ((size_t)chunk * nys + 1), &base));
-    XYZ_TRY(ws(c, WS_SCNT, 1, &scnt));
+    // scnt[0]: survivors so far; scnt[1..4]: the chunk's four tile-list sizes (m <= MAX_M_LDS),
+    // read back with the survivor count in one transfer per chunk
+    XYZ_TRY(ws(c, WS_SCNT, 1 + NLISTS, &scnt));
     HIP_TRY(launch_zero(scnt, sizeof(unsigned long long), st));
     uint64_t surv_cap = std::max<uint64_t>(c->ws[WS_SURV].bytes / sizeof(Survivor), 1 << 16);
     Survivor *surv = nullptr;
@@ -576,22 +578,24 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             redo = false;
             unsigned long long ntiles = 0, nsmall = 0, nmfma = 0, nbig = 0;
             Tile *tiles = nullptr;
-            if (m <= MAX_M_LDS) {
+            // m <= MAX_M_LDS: the list sizes stay on the device; the tile list has the capacity
+            // it has (grown when a chunk overflows it) and the verification kernels read the sizes
+            const bool device_counts = m <= MAX_M_LDS;
+            uint64_t tile_cap = 0;
+            if (device_counts) {
                 tm.begin(3);
                 HIP_TRY(launch_bucket(keys, p, m, R, nys, cinfo, two, mfma, offs, perm, st));
                 tm.end();
                 tm.begin(4);
-                HIP_TRY(launch_tile_scan(cinfo, R * nys, base, st));
-                // list totals at base[K (R nys + 1) + R nys]: popcount, small, matrix-core, big tiles
-                const size_t cnt1 = (size_t)R * nys + 1;
-                HIP_TRY(hipMemcpyAsync(&ntiles, base + cnt1 - 1, sizeof ntiles, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipMemcpyAsync(&nsmall, base + 2 * cnt1 - 1, sizeof nsmall, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipMemcpyAsync(&nmfma, base + 3 * cnt1 - 1, sizeof nmfma, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipMemcpyAsync(&nbig, base + 4 * cnt1 - 1, sizeof nbig, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipStreamSynchronize(st));
-                XYZ_TRY(ws(c, WS_TILES, (size_t)(ntiles + nsmall + nmfma + nbig), &tiles));
-                HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, mfma, base, tiles, st));
+                HIP_TRY(launch_tile_scan(cinfo, R * nys, base, scnt + 1, st));
+                tile_cap = std::max<uint64_t>(c->ws[WS_TILES].bytes / sizeof(Tile), 1 << 16);
+                XYZ_TRY(ws(c, WS_TILES, (size_t)tile_cap, &tiles));
+                HIP_TRY(launch_tiles(offs, p, m, R, nys, cinfo, two, mfma, base, tiles, tile_cap, st));
                 tm.end();
+                // launch bounds only (matrix-core tiles need mfma, big tiles +-1 data)
+                ntiles = nsmall = tile_cap;
+                nmfma = mfma ? tile_cap : 0;
+                nbig = mfma == 1 ? tile_cap : 0;
             } else {
                 // m > MAX_M_LDS: sort the keys, take runs of equal keys as buckets
                 const uint64_t S = (uint64_t)R * (uint64_t)p;
@@ -668,6 +672,10 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             va.surv_count = scnt;
             va.surv_cap = surv_cap;
             va.info = cinfo;
+            if (device_counts) {
+                va.dcnt = scnt + 1;
+                va.tile_cap = tile_cap;
+            }
             const int g = (int)std::min<unsigned long long>(std::max(ntiles + nsmall + nmfma + nbig, 1ull),
                                                             (unsigned long long)grid);
             tm.begin(5);
@@ -678,13 +686,24 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 tm.begin(8);
                 HIP_TRY(launch_verify_big(va, g, st));
                 tm.end();
-                timing.big_launches += 1;
             }
-            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0) + (nmfma ? 1 : 0) + (nbig ? 1 : 0);
-            timing.tiles += (int64_t)(ntiles + nsmall + nmfma + nbig);
-            unsigned long long cnt = 0;
-            HIP_TRY(hipMemcpyAsync(&cnt, scnt, sizeof cnt, hipMemcpyDeviceToHost, st));
+            // the one transfer of the chunk: the survivor count and (device_counts) the list sizes
+            unsigned long long hc[1 + NLISTS] = {0, ntiles, nsmall, nmfma, nbig};
+            HIP_TRY(hipMemcpyAsync(hc, scnt, sizeof(unsigned long long) * (device_counts ? 1 + NLISTS : 1),
+                                   hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            const unsigned long long cnt = hc[0];
+            ntiles = hc[1], nsmall = hc[2], nmfma = hc[3], nbig = hc[4];
+            const uint64_t need = ntiles + nsmall + nmfma + nbig;
+            if (device_counts && need > tile_cap) {
+                // nothing was verified: grow the list and redo the chunk
+                XYZ_TRY(ws(c, WS_TILES, (size_t)need, &tiles));
+                redo = true;
+                continue;
+            }
+            if (nbig) timing.big_launches += 1;
+            timing.verify_launches += (ntiles ? 1 : 0) + (nsmall && !real ? 1 : 0) + (nmfma ? 1 : 0) + (nbig ? 1 : 0);
+            timing.tiles += (int64_t)need;
             if (cnt > surv_cap) {
                 XYZ_TRY(grow_survivors(c, cnt, surv_done, scnt, &surv, &surv_cap, st));
                 redo = true;

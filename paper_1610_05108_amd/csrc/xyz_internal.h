@@ -128,14 +128,17 @@ hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int n
                          int two_sided, int mfma, uint32_t *offs, uint32_t *perm, hipStream_t st);
 // Exclusive scans over count = nrep*nys entries into base [NLISTS (count + 1)] (u64): list K
 // (0: popcount tiles, 1: small tiles, 2: matrix-core tiles, 3: big tiles) at base + K (count + 1),
-// its total at base[K (count + 1) + count].
+// its total at base[K (count + 1) + count] and, if totals is not NULL, at totals[K].
 constexpr int NLISTS = 4;
-hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st);
+hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, unsigned long long *totals,
+                            hipStream_t st);
 // Emit the tiles of every (repetition, response): popcount tiles first, then small tiles,
 // then matrix-core tiles (MTILE x MTILE), then big tiles, each list ordered by (repetition,
 // response).
+// Tiles past cap are not written.
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
-                        int two_sided, int mfma, const unsigned long long *base, Tile *tiles, hipStream_t st);
+                        int two_sided, int mfma, const unsigned long long *base, Tile *tiles, uint64_t cap,
+                        hipStream_t st);
 
 // Bucketing for m > MAX_M_LDS (keys sorted instead of counted in LDS):
 // sort the nrep * p keys by (repetition, key) with the radix sort (K, V, K2, V2: scratch of
@@ -172,6 +175,12 @@ struct VerifyArgs {
     uint64_t nsmall;         // small tiles: tiles[ntiles, ntiles + nsmall)
     uint64_t nmfma;          // matrix-core tiles: tiles[ntiles + nsmall, ... + nmfma)
     uint64_t nbig;           // big tiles: tiles[ntiles + nsmall + nmfma, ... + nbig)
+    // With dcnt set, the four list sizes are read on the device (dcnt[0..3]: popcount, small,
+    // matrix-core, big; the tile scan's totals) instead of the fields above, which then only
+    // bound the launch grids; a kernel does nothing when the sizes sum past tile_cap (the host
+    // then grows the list and reruns the chunk).
+    const unsigned long long *dcnt;
+    uint64_t tile_cap;
     const uint32_t *perm;
     const uint32_t *XC;      // [p][W32p] bits
     int W32p;

@@ -627,7 +627,8 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
 }
 
 __global__ __launch_bounds__(1024) void k_tile_scan(const RepInfo *__restrict__ info, int count,
-                                                    unsigned long long *__restrict__ base)
+                                                    unsigned long long *__restrict__ base,
+                                                    unsigned long long *__restrict__ totals)
 {
     __shared__ unsigned long long shm[17];
     const int seg = (count + 1023) / 1024;
@@ -647,7 +648,10 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const RepInfo *__restrict__ 
             bs[i] = pre;
             pre += tiles_of(list, i);
         }
-        if (threadIdx.x == 0) bs[count] = tot;
+        if (threadIdx.x == 0) {
+            bs[count] = tot;
+            if (totals) totals[list] = tot;
+        }
         __syncthreads();
     }
 }
@@ -761,7 +765,8 @@ constexpr int HEAVY_CAP = 512;
 // (baseK = base + K (count + 1)).
 __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs, int64_t p, int m, int nys,
                                                const RepInfo *__restrict__ info, int two_sided, int mfma,
-                                               const unsigned long long *__restrict__ base, Tile *__restrict__ tiles)
+                                               const unsigned long long *__restrict__ base, Tile *__restrict__ tiles,
+                                               uint64_t cap)
 {
     __shared__ unsigned long long shm[5];
     __shared__ uint32_t hb[HEAVY_CAP], hb2[HEAVY_CAP], hts[HEAVY_CAP];
@@ -817,7 +822,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
                 }
             }
             if (h < 0 || h >= HEAVY_CAP)
-                for (unsigned long long t = 0; t < T; ++t)
+                for (unsigned long long t = 0; t < T && pos[kind] + t < cap; ++t)
                     tiles[pos[kind] + t] = pair_tile(ts, t, r, y, pbase, b, b2, of, mfma);
             pos[kind] += T;
         }
@@ -826,7 +831,7 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
     const int nh = min(hcnt, HEAVY_CAP);
     for (int h = 0; h < nh; ++h) {
         const unsigned long long T = hcnt_t[h], p0 = hpos[h];
-        for (unsigned long long t = threadIdx.x; t < T; t += 256)
+        for (unsigned long long t = threadIdx.x; t < T && p0 + t < cap; t += 256)
             tiles[p0 + t] = pair_tile(hts[h], t, r, y, pbase, hb[h], hb2[h], of, mfma);
     }
 }
@@ -1136,6 +1141,19 @@ XYZ_DEV v16f mfma_fp4_plane(v8i a, v8i b, v16f c, int pl)
 // B holds x_b, so the inner loop is one XOR and one popcount-accumulate per
 // pair and 32-bit word.  RA = ceil(na/8), RB = ceil(nb/8) are wave-uniform.
 
+// The list sizes of a verification launch whose sizes live on the device (VerifyArgs::dcnt): all
+// four zero when the lists exceed the tile array, whose overflow the host resolves by rerunning.
+XYZ_DEV void load_counts(VerifyArgs &a)
+{
+    if (!a.dcnt) return;
+    const unsigned long long n0 = a.dcnt[0], n1 = a.dcnt[1], n2 = a.dcnt[2], n3 = a.dcnt[3];
+    const bool fits = n0 + n1 + n2 + n3 <= a.tile_cap;
+    a.ntiles = fits ? n0 : 0;
+    a.nsmall = fits ? n1 : 0;
+    a.nmfma = fits ? n2 : 0;
+    a.nbig = fits ? n3 : 0;
+}
+
 // Candidate pairs of a tile (positions a < b only on a diagonal tile).
 XYZ_DEV uint32_t tile_pairs(const Tile &t)
 {
@@ -1276,8 +1294,10 @@ XYZ_DEV void verify_bin_tile(const Tile &t, const uint32_t *colA, const uint32_t
             }
 }
 
-__global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a)
+__global__ __launch_bounds__(64) void k_verify_bin(VerifyArgs a0)
 {
+    VerifyArgs a = a0;
+    load_counts(a);
     __shared__ uint4 As[TILE][LDS4];
     __shared__ uint4 Bs[TILE][LDS4];
     __shared__ uint32_t colA[TILE], colB[TILE];
@@ -1343,8 +1363,10 @@ XYZ_DEV void swap16(uint4 &lo, uint4 &hi)
     hi = make_uint4(x[1], y[1], z[1], w[1]);
 }
 
-__global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a)
+__global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a0)
 {
+    VerifyArgs a = a0;
+    load_counts(a);
     __shared__ __align__(16) float zpop2[4][MTILE_WIDE];  // per wave: 2|z_a| of the tile's A columns
     const unsigned lane = lane_id();
     const int h = (int)(lane >> 5), c = (int)(lane & 31);
@@ -1599,8 +1621,10 @@ constexpr int BHROW = BIG_TILE + 1;             // uint2 per LDS half row (words
 constexpr size_t BIG_LDS = (size_t)2 * 2 * BKQ * 2 * BHROW * sizeof(uint2);   // [buffer][side][quad][half][column]
 
 template <bool TWO>
-__global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a)
+__global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a0)
 {
+    VerifyArgs a = a0;
+    load_counts(a);
     extern __shared__ uint2 bl[];
     __shared__ __align__(16) uint32_t bpop[2][2][BIG_TILE];   // [tile parity][side][column] popcounts
     const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1864,8 +1888,10 @@ XYZ_DEV int first_above(uint32_t v, uint32_t x)
     return L;
 }
 
-__global__ __launch_bounds__(64) void k_verify_small(VerifyArgs a)
+__global__ __launch_bounds__(64) void k_verify_small(VerifyArgs a0)
 {
+    VerifyArgs a = a0;
+    load_counts(a);
     __shared__ uint4 Cs[SG_COLS][SLDS4];
     const unsigned lane = lane_id();
     const int W4 = a.W32p >> 2;
@@ -2251,8 +2277,10 @@ XYZ_DEV void verify_real_mfma_tile(const Tile &t, const uint32_t *colA, const ui
 // 64 x 64 tiles of large products of real data, on the FP64 matrix cores (a kernel
 // of its own: its accumulators and 64-row LDS tiles would cut the occupancy of
 // the 32 x 32 kernel).
-__global__ __launch_bounds__(64) void k_verify_real_mfma(VerifyArgs a, int x_real)
+__global__ __launch_bounds__(64) void k_verify_real_mfma(VerifyArgs a0, int x_real)
 {
+    VerifyArgs a = a0;
+    load_counts(a);
     __shared__ double As[MTILE][CR + 1];
     __shared__ double Bs[MTILE][CR + 1];
     __shared__ uint32_t colA[MTILE], colB[MTILE];
@@ -2289,8 +2317,10 @@ __global__ __launch_bounds__(64) void k_verify_real_mfma(VerifyArgs a, int x_rea
     }
 }
 
-__global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a, int x_real)
+__global__ __launch_bounds__(64) void k_verify_real(VerifyArgs a0, int x_real)
 {
+    VerifyArgs a = a0;
+    load_counts(a);
     __shared__ double As[TILE][CR + 1];
     __shared__ double Bs[TILE][CR + 1];
     __shared__ uint32_t colA[TILE], colB[TILE];
@@ -3179,17 +3209,19 @@ hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int n
     return hipGetLastError();
 }
 
-hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, hipStream_t st)
+hipError_t launch_tile_scan(const RepInfo *info, int count, unsigned long long *base, unsigned long long *totals,
+                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, info, count, base);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, info, count, base, totals);
     return hipGetLastError();
 }
 
 hipError_t launch_tiles(const uint32_t *offs, int64_t p, int m, int nrep, int nys, const RepInfo *info,
-                        int two_sided, int mfma, const unsigned long long *base, Tile *tiles, hipStream_t st)
+                        int two_sided, int mfma, const unsigned long long *base, Tile *tiles, uint64_t cap,
+                        hipStream_t st)
 {
     hipLaunchKernelGGL(k_tiles, dim3(nrep * nys), dim3(256), 0, st, offs, p, m, nys, info, two_sided, mfma, base,
-                       tiles);
+                       tiles, cap);
     return hipGetLastError();
 }
 

@@ -113,6 +113,21 @@ def test_survivor_buffer_growth(ctx):
     assert_same_binary(res, rp, rr)
 
 
+def test_tile_list_growth():
+    """More tiles in a chunk than the initial tile list of a fresh context holds: the
+    verification kernels see the overflow on the device and verify nothing, the library
+    grows the list and redoes the chunk; a second search reuses the grown list."""
+    d = synthgen.small_binary(64, 40000, seed=41, planted=[(1, 39998)], flip=0.05)
+    c = xyz.Context(0)
+    try:
+        for it in range(2):
+            res, rp, rr = run_both(c, d.XT, d.Y, 12, 20, 0.5, seed=41)
+            assert res["timing"]["tiles"] > 1 << 16
+            assert_same_binary(res, rp, rr)
+    finally:
+        c.close()
+
+
 def test_split_repetitions_match_full_run(ctx):
     d = synthgen.small_binary(300, 1200, seed=16, planted=[(1, 2)], flip=0.1)
     x = ctx.x_create(d.XT)
