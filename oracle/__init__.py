@@ -55,8 +55,8 @@ def lib():
         L.xo_search_ex.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
-                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
-                                   ctypes.c_void_p]
+                                   ctypes.c_double, ctypes.POINTER(ctypes.c_void_p),
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.xo_brute.restype = ctypes.c_int
         L.xo_brute.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
@@ -131,13 +131,15 @@ def _take_pairs(ptr, npairs):
 
 
 def search(XT, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
-           rep_offset: int = 0, rows=None, unbiased: bool = False):
+           rep_offset: int = 0, rows=None, unbiased: bool = False, cap: float = 0.0):
     """Algorithm 2 run by the oracle.  Returns (pairs, reps) structured arrays.
 
     XT: (p, n) int8 +-1 or real; Y: (n,) int8 +-1 or real.  rows: optional
     (L, m) int32 table of row indices replacing the sampler.  unbiased (real X
     only): the unbiased transform of Section 3.2 with row scaling instead of
-    the sign transform.
+    the sign transform.  cap (unbiased only; 0: none): entries are capped at
+    +-cap, rounded to float32, before the transform (Section 3.2's remark on
+    capping).
     """
     XT_, xk = _x_arg(XT)
     Y_, yk = _y_arg(Y)
@@ -151,7 +153,7 @@ def search(XT, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool =
     cnt = ctypes.c_int64()
     rc = lib().xo_search_ex(XT_.ctypes.data, xk, Y_.ctypes.data, yk, n, p, m, L, float(kappa),
                             seed & (2**64 - 1), int(bool(two_sided)), rep_offset, rp, int(bool(unbiased)),
-                            ctypes.byref(out), ctypes.byref(cnt), reps.ctypes.data)
+                            float(cap), ctypes.byref(out), ctypes.byref(cnt), reps.ctypes.data)
     if rc != 0:
         raise OracleError(f"xo_search failed ({rc})")
     return _take_pairs(out.value, cnt.value), reps[:L]

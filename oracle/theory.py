@@ -95,13 +95,18 @@ def gamma_example_unweighted(sigma2: float) -> float:
     return 0.5 * (1.0 + math.erf(1.0 / math.sqrt(2.0 * sigma2)))
 
 
-def gamma_unbiased(XT: np.ndarray, Y: np.ndarray, j: int, k: int, scale: bool = True) -> float:
+def gamma_unbiased(XT: np.ndarray, Y: np.ndarray, j: int, k: int, scale: bool = True, cap=None) -> float:
     """Proposition 4 (Section 3.2): strength under the unbiased transform,
     1/2 + sum_i Y_i X_ij X_ik / (2 ||Y||_1).  With ``scale`` the rows are first
     divided by nu_i = max_j |X_ij| and Y_i multiplied by nu_i^2 (the remark after
     Proposition 4), which leaves the numerator unchanged and turns the
-    denominator into 2 sum_i |Y_i| nu_i^2."""
+    denominator into 2 sum_i |Y_i| nu_i^2.  With ``cap`` the entries are first
+    capped at +-cap (Section 3.2's remark on capping), cap rounded to float32:
+    the proposition then holds for the capped matrix."""
     X = np.asarray(XT, dtype=np.float64)
+    if cap is not None:
+        c = float(np.float32(cap))
+        X = np.minimum(np.maximum(X, -c), c)
     Y = np.asarray(Y, dtype=np.float64)
     num = float(np.sum(Y * X[j] * X[k]))
     w = np.abs(Y)

@@ -28,7 +28,10 @@
  *    after Proposition 4), so rows are drawn with probability proportional to
  *    |Y_i| nu_i^2, and every sampled entry becomes +1 with probability
  *    (1 + X_ij / nu_i) / 2, drawn afresh for each repetition, draw and column;
- *    the Z side uses the same draw, Z~_ij = sgn(Y_i) X~_ij.
+ *    the Z side uses the same draw, Z~_ij = sgn(Y_i) X~_ij.  Optionally the
+ *    entries are first capped at +-c (Section 3.2's remark on capping): the
+ *    transform, the row maxima and the row weights then all see the capped
+ *    entries min(max(X_ij, -c), c).
  *
  * Readings where the paper leaves a choice (each is also listed in the
  * design notes of the repository):
@@ -56,7 +59,11 @@
  *    (u * 2) * nu_i < (nu_i + X_ij) * 2^24 (u / 2^24 < (1 + X_ij / nu_i) / 2
  *    without a division), and with probability 1/2 (u < 2^23) on a row whose
  *    entries are all zero (nu_i = 0; such a row is drawn only from a row table);
- *    the row weights are |Y_i| * (nu_i * nu_i), summed left to right.
+ *    the row weights are |Y_i| * (nu_i * nu_i), summed left to right;
+ *  - the cap c of the unbiased transform is taken in float32, as X is: c is
+ *    the caller's value rounded to the nearest float32, so that every capped
+ *    entry is a float32 value; the strength check stays eq. (1) on the
+ *    original, uncapped X.
  */
 #define _GNU_SOURCE
 #include <stdint.h>
@@ -296,15 +303,27 @@ static int cmp_record(const void *pa, const void *pb)
  * the sampler.  Outputs malloc'ed arrays (free with xo_free); reps must hold
  * L entries.
  */
+/* Entry x capped at +-c (c = +inf: unchanged). */
+static double capped(double x, double c)
+{
+    return x > c ? c : (x < -c ? -c : x);
+}
+
 /* transform: 0 = sign transform of real X (or +-1 X as is), 1 = unbiased
- * transform of real X (Section 3.2). */
+ * transform of real X (Section 3.2).  cap (transform 1 only): 0 for none,
+ * else the entries are capped at +-cap (rounded to float32) before the
+ * transform. */
 int xo_search_ex(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, int64_t p,
                  int m, int L, double kappa, uint64_t seed, int two_sided, int rep_offset,
-                 const int32_t *rows_in, int transform, xo_pair **out_pairs, int64_t *out_npairs, xo_rep *reps)
+                 const int32_t *rows_in, int transform, double cap, xo_pair **out_pairs, int64_t *out_npairs,
+                 xo_rep *reps)
 {
     if (n <= 0 || p <= 0 || m < 0 || m > 64 || L < 0 || !(kappa == kappa) || isinf(kappa))
         return XO_EINVAL;
     if (transform != 0 && (transform != 1 || xkind != 1)) return XO_EINVAL;
+    if (!(cap >= 0.0) || (cap != 0.0 && transform != 1)) return XO_EINVAL;
+    const double c = cap == 0.0 ? INFINITY : (double)(float)cap;
+    if (!(c > 0.0)) return XO_EINVAL;
     const int8_t *Xb = (const int8_t *)Xv; const double *Xd = (const double *)Xv;
     const int8_t *Yb = (const int8_t *)Yv; const double *Yd = (const double *)Yv;
     int binary = (xkind == 0 && ykind == 0);
@@ -362,7 +381,10 @@ int xo_search_ex(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n
         if (!nu || !wrow) { free(Xs); free(Z); free(Ys); free(Ydw); free(Xdw); free(nu); free(wrow); return XO_ENOMEM; }
         for (int64_t i = 0; i < n; i++) {
             double v = 0.0;
-            for (int64_t j = 0; j < p; j++) if (fabs(Xd[j * n + i]) > v) v = fabs(Xd[j * n + i]);
+            for (int64_t j = 0; j < p; j++) {
+                double a = fabs(capped(Xd[j * n + i], c));
+                if (a > v) v = a;
+            }
             nu[i] = v;
             wrow[i] = fabs(ykind == 0 ? (double)Yb[i] : Yd[i]) * (v * v);
         }
@@ -400,7 +422,7 @@ int xo_search_ex(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n
             for (int t = 0; t < m; t++) {
                 if (transform == 1) {
                     int64_t i = rows[t];
-                    int8_t xt = unbiased_sign(seed, l, t, j, Xd[j * n + i], nu[i]);
+                    int8_t xt = unbiased_sign(seed, l, t, j, capped(Xd[j * n + i], c), nu[i]);
                     tx[j * m + t] = xt;
                     tz[j * m + t] = (int8_t)(Ys[i] * xt);
                 } else {
@@ -478,7 +500,7 @@ int xo_search(const void *Xv, int xkind, const void *Yv, int ykind, int64_t n, i
               int m, int L, double kappa, uint64_t seed, int two_sided, int rep_offset,
               const int32_t *rows_in, xo_pair **out_pairs, int64_t *out_npairs, xo_rep *reps)
 {
-    return xo_search_ex(Xv, xkind, Yv, ykind, n, p, m, L, kappa, seed, two_sided, rep_offset, rows_in, 0,
+    return xo_search_ex(Xv, xkind, Yv, ykind, n, p, m, L, kappa, seed, two_sided, rep_offset, rows_in, 0, 0.0,
                         out_pairs, out_npairs, reps);
 }
 

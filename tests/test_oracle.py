@@ -391,6 +391,84 @@ def test_unbiased_transform_collision_rate_is_proposition_4(m):
     assert abs(theory.gamma_unbiased(XT, Y, 0, 1) - theory.gamma_unbiased(XT, Y, 0, 1, scale=False)) > 0.05
 
 
+@pytest.mark.parametrize("m", [1, 2])
+def test_capped_unbiased_collision_rate_is_proposition_4_of_capped_x(m):
+    """Capping before the unbiased transform (Section 3.2): the pair's collision
+    frequency equals Proposition 4's strength of the capped matrix to the power
+    m.  Capping that reached only the transform, only the row maxima or only
+    the row weights, or no capping at all, moves the rate by more than ten times
+    the tolerance on this data (column 2 holds outliers of +-8 on eight rows,
+    capped at 1)."""
+    r = np.random.default_rng(21)
+    n = 40
+    XT = r.uniform(-1, 1, size=(3, n)).astype(np.float32)
+    XT[2, :8] = np.where(r.random(8) < 0.5, -8.0, 8.0)    # outliers set the maxima of rows 0..7
+    XT[1] = (0.8 * XT[0] + 0.2 * r.uniform(-1, 1, size=n)).astype(np.float32)
+    Y = (XT[0].astype(np.float64) * XT[1] + 0.1 * r.standard_normal(n)).astype(np.float32)
+    L = 40_000
+    cap = 1.0
+    _, reps = oracle.search(XT, Y, m, L, 10.0, seed=6, unbiased=True, cap=cap)
+    pairs = ((0, 1), (0, 2), (1, 2))
+    want = sum(theory.gamma_unbiased(XT, Y, a, b, cap=cap) ** m for a, b in pairs)
+    got = float(reps["candidates"].mean())
+    se = math.sqrt(3 * 0.25 / L)
+    assert abs(got - want) < 5 * se, (got, want)
+    uncapped = sum(theory.gamma_unbiased(XT, Y, a, b) ** m for a, b in pairs)
+    assert abs(uncapped - want) > 10 * se, (uncapped, want)
+    # capping that reaches only the transform or only the row weights: the per-row collision
+    # probability 1/2 + sgn(Y_i) x_a x_b / (2 nu_i^2) under row weights |Y_i| nu_i^2
+    Xr = XT.astype(np.float64)
+    Xc = np.clip(Xr, -cap, cap)
+    nu_raw, nu_cap = np.abs(Xr).max(axis=0), np.abs(Xc).max(axis=0)
+
+    def rate(X, nu_draw, nu_scale):
+        w = np.abs(Y) * nu_draw ** 2
+        w = w / w.sum()
+        return sum(float(np.sum(w * (0.5 + np.sign(Y) * X[a] * X[b] / (2 * nu_scale ** 2)))) ** m
+                   for a, b in pairs)
+
+    assert abs(rate(Xc, nu_cap, nu_cap) - want) < 1e-9
+    for wrong in (rate(Xr, nu_raw, nu_raw), rate(Xc, nu_raw, nu_cap), rate(Xc, nu_cap, nu_raw)):
+        assert abs(wrong - want) > 10 * se, (wrong, want)
+
+
+def test_capped_unbiased_below_every_entry_is_the_sign_transform():
+    """A cap below every |X_ij| leaves X~_ij = sgn(X_ij) with probability one and
+    row weights |Y_i| c^2: with c a power of two the capped unbiased search is
+    the sign-transform search exactly (Section 3.2 relates capping at small c to
+    the sign transform)."""
+    d = synthgen.small_continuous(60, 40, seed=22, planted=[(2, 9), (4, 31)])
+    XT = d.XT.astype(np.float32)
+    assert np.abs(XT).min() > 2.0 ** -20
+    for two in (False, True):
+        a = oracle.search(XT, d.Y, 6, 12, 0.15, seed=8, two_sided=two, unbiased=True, cap=2.0 ** -20)
+        b = oracle.search(XT, d.Y, 6, 12, 0.15, seed=8, two_sided=two)
+        assert np.array_equal(a[0], b[0])
+        for f in ("candidates", "passed", "cmask", "max_bucket", "fresh"):
+            assert np.array_equal(a[1][f], b[1][f]), f
+        assert a[1]["candidates"].sum() > 0
+
+
+def test_capped_unbiased_above_every_entry_changes_nothing():
+    d = synthgen.small_continuous(50, 30, seed=23, planted=[(1, 4)])
+    XT = d.XT.astype(np.float32)
+    big = float(np.abs(XT).max())
+    a = oracle.search(XT, d.Y, 5, 8, 0.2, seed=3, unbiased=True, cap=big)
+    b = oracle.search(XT, d.Y, 5, 8, 0.2, seed=3, unbiased=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # a cap just below the largest entry changes the draws
+    c = oracle.search(XT, d.Y, 5, 8, 0.2, seed=3, unbiased=True, cap=0.5 * big)
+    assert not np.array_equal(a[1]["candidates"], c[1]["candidates"])
+
+
+def test_cap_rejected_without_unbiased_or_negative():
+    d = synthgen.small_continuous(20, 10, seed=24)
+    with pytest.raises(oracle.OracleError):
+        oracle.search(d.XT, d.Y, 3, 2, 0.2, cap=1.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.search(d.XT, d.Y, 3, 2, 0.2, unbiased=True, cap=-1.0)
+
+
 def test_unbiased_strength_uniform_example_is_13_18():
     """Section 3.2 prints 13/18 as the limit of the true pair's strength under the
     unbiased transform for X ~ Uniform(-1, 1) and Y = X_j X_k without noise."""
