@@ -79,7 +79,10 @@ typedef int32_t xyz_status;
                              seed = output 1 + l*2^16 + t of SplitMix64 seeded with seed ^ 0x2545F4914F6CDD1D;
                              column j: top 24 bits u of that stream's output 1 + j; +1 exactly when, in
                              binary64, (u * 2) * nu_i < (nu_i + X_ij) * 2^24; on an all-zero row, when
-                             u < 2^23).  The strength check stays eq. (1) on the original X and Y.
+                             u < 2^23).  With xyz_params.cap > 0 the entries are first capped at
+                             +-cap (Section 3.2's remark on capping; cap rounded to float32): nu_i, the
+                             row weights and the transform then use min(max(X_ij, -cap), cap).  The
+                             strength check stays eq. (1) on the original X and Y.
                              XYZ_EUNSUPPORTED for int8 or bit-packed X. */
 
 #define XYZ_MAX_M 30      /* largest supported number of sampled rows per repetition */
@@ -101,6 +104,9 @@ typedef struct {
     int32_t rep_offset;   /* index of the first repetition (split or resumed runs); >= 0 */
     const int32_t *rows;  /* optional host table of L*m row indices in [0, n) replacing the sampler;
                              repetition l uses rows[l*m .. l*m+m-1] */
+    double cap;           /* XYZ_UNBIASED only: 0 for no capping, else cap |X_ij| at cap (> 0, finite or
+                             +inf, at least the smallest positive float32) before the transform;
+                             XYZ_EINVAL otherwise */
 } xyz_params;
 
 /* One reported pair.  For +-1 data s is exact and stat = s/n (binary64

@@ -55,7 +55,7 @@ class XyzError(RuntimeError):
 class xyz_params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("L", ctypes.c_int32), ("kappa", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("rep_offset", ctypes.c_int32),
-                ("rows", ctypes.c_void_p)]
+                ("rows", ctypes.c_void_p), ("cap", ctypes.c_double)]
 
 
 class xyz_timing(ctypes.Structure):
@@ -271,8 +271,9 @@ def _check_y(x, Y):
         raise ValueError(f"Y has {size} entries; X has n = {n} rows")
 
 
-def _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased=False):
+def _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased=False, cap=0.0):
     prm = xyz_params()
+    prm.cap = float(cap)
     prm.m, prm.L, prm.kappa, prm.seed = int(m), int(L), float(kappa), int(seed) & (2 ** 64 - 1)
     prm.flags = ((XYZ_TWO_SIDED if two_sided else 0) | (XYZ_PROFILE if profile else 0) |
                  (XYZ_UNBIASED if unbiased else 0))
@@ -306,11 +307,13 @@ def _take_result(h):
 
 
 def xyz_search(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
-               rep_offset: int = 0, rows=None, profile: bool = False, stream=None, unbiased: bool = False):
+               rep_offset: int = 0, rows=None, profile: bool = False, stream=None, unbiased: bool = False,
+               cap: float = 0.0):
     """Algorithm 2 on resident X.  Returns {'pairs', 'reps', 'timing'}.  unbiased:
-    hash float32 X with the unbiased transform of Section 3.2 (XYZ_UNBIASED)."""
+    hash float32 X with the unbiased transform of Section 3.2 (XYZ_UNBIASED);
+    cap > 0 caps the entries at +-cap first (xyz_params.cap)."""
     _check_y(x, Y)
-    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased)
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, profile, unbiased, cap)
     ptr, mem, keep = _ptr(Y)
     h = ctypes.c_void_p()
     _check(lib().xyz_search(ctx, x, ptr, _y_format(Y), mem, ctypes.byref(prm), _stream(stream, Y), ctypes.byref(h)))
@@ -340,7 +343,7 @@ def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
     for q, kw in enumerate(params):
         prm, kr = _params(kw["m"], kw["L"], kw["kappa"], kw.get("seed", 0), kw.get("two_sided", False),
                           kw.get("rep_offset", 0), kw.get("rows"), kw.get("profile", False),
-                          kw.get("unbiased", False))
+                          kw.get("unbiased", False), kw.get("cap", 0.0))
         arr[q] = prm
         keep_rows.append(kr)
     yp = (ctypes.c_void_p * nY)(*ptrs)
@@ -351,14 +354,15 @@ def xyz_search_batch(ctx, x, Ys, params: list, stream=None):
 
 
 def xyz_search_noalloc(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
-                       rep_offset: int = 0, rows=None, stream=None, unbiased: bool = False, pairs_cap: int = 1 << 16):
+                       rep_offset: int = 0, rows=None, stream=None, unbiased: bool = False, pairs_cap: int = 1 << 16,
+                       cap: float = 0.0):
     """xyz_search through the entry point that allocates no memory (workspaces in the library's
     static device scratch).  Returns {'pairs', 'reps'}; raises XyzError (code XYZ_ENOMEM, with
     'npairs' set) when more than pairs_cap pairs are found."""
     if int(L) < 1:
         raise ValueError("L must be >= 1")
     _check_y(x, Y)
-    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, False, unbiased)
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, rep_offset, rows, False, unbiased, cap)
     ptr, mem, keep = _ptr(Y)
     pairs = np.zeros(max(int(pairs_cap), 1), dtype=PAIR_DTYPE)
     reps = np.zeros(int(L), dtype=REP_DTYPE)

@@ -9,6 +9,7 @@
 #include "xyz_runtime.h"
 
 #include <algorithm>
+#include <limits>
 #include <cstdarg>
 #include <chrono>
 #include <cmath>
@@ -393,6 +394,11 @@ xyz_status xyz_rt::validate_params(const xyz_x *x, const xyz_params *P, int yfmt
         return fail(XYZ_EINVAL, "unknown flags 0x%x", P->flags);
     if ((P->flags & XYZ_UNBIASED) && x->fmt != XYZ_X_F32)
         return fail(XYZ_EUNSUPPORTED, "the unbiased transform needs float32 X");
+    if (P->cap != 0.0) {
+        if (!(P->flags & XYZ_UNBIASED)) return fail(XYZ_EINVAL, "cap applies to the unbiased transform only");
+        if (!(P->cap > 0.0) || !((float)P->cap > 0.0f))
+            return fail(XYZ_EINVAL, "cap=%g: must be positive and at least the smallest positive float32", P->cap);
+    }
     if (yfmt != XYZ_Y_I8_PM1 && yfmt != XYZ_Y_F32 && yfmt != XYZ_Y_F64) return fail(XYZ_EINVAL, "unknown Y format %d", yfmt);
     if (P->rows) {
         const int64_t cnt = (int64_t)P->L * P->m;
@@ -478,6 +484,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     const bool real_x = x->fmt == XYZ_X_F32;
     const bool real = real_x || real_y;
     const bool unbiased = (P.flags & XYZ_UNBIASED) != 0 && real_x;
+    // Section 3.2's capping of the unbiased transform, in float32 like X (+inf: none)
+    const float cap_f = P.cap > 0.0 ? (float)P.cap : std::numeric_limits<float>::infinity();
     // large bucket products go to the matrix cores in 64 x 64 tiles: FP4 with exact FP32
     // counts for +-1 data (n < 2^24, mfma = 1), FP64 for real data (mfma = 2)
     const int mfma = real ? 2 : (n < (1 << 24) ? 1 : 0);
@@ -500,7 +508,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
         XYZ_TRY(ws(c, WS_NU, (size_t)n, &nu));
         XYZ_TRY(ws(c, WS_CDF, (size_t)n, &cdf));
         XYZ_TRY(ws(c, WS_LAST, 1, &last));
-        HIP_TRY(launch_row_absmax(x->XF, x->nF, n, p, nu, st));
+        HIP_TRY(launch_row_absmax(x->XF, x->nF, n, p, cap_f, nu, st));
         HIP_TRY(launch_cdf_unbiased(yd, nu, n, cdf, last, err, st));
     } else if (real_y && m > 0) {
         XYZ_TRY(ws(c, WS_CDF, (size_t)n, &cdf));
@@ -569,7 +577,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
         tm.end();
         tm.begin(2);
         if (unbiased && m > 0)
-            HIP_TRY(launch_hash_unbiased(x->XF, x->nF, p, m, R, rows, nu, P.seed, rep_abs0, keys, st));
+            HIP_TRY(launch_hash_unbiased(x->XF, x->nF, p, m, R, rows, nu, cap_f, P.seed, rep_abs0, keys, st));
         else
             HIP_TRY(launch_hash(x->XR, x->P64, p, m, R, rows, keys, st));
         tm.end();
@@ -869,7 +877,7 @@ extern "C" xyz_status xyz_search_batch(xyz_ctx *c, const xyz_x *x, int32_t nY, c
             for (int r = q + 1; r < nY && grp.size() < 255; ++r) {
                 const xyz_params &b = params[r];
                 if (!done[r] && !b.rows && b.m == a.m && b.L == a.L && b.seed == a.seed &&
-                    b.rep_offset == a.rep_offset && b.flags == a.flags)
+                    b.rep_offset == a.rep_offset && b.flags == a.flags && b.cap == a.cap)
                     grp.push_back(r);
             }
         std::vector<const void *> ys;

@@ -107,11 +107,14 @@ hipError_t launch_cdf(const double *yd, int64_t n, double *cdf, int64_t *last, i
 // weights |yd_i| * (nu_i * nu_i) in binary64 (ascending i, last = last row of
 // positive weight), and the keys of nrep repetitions from the transformed
 // entries of the sampled rows (draws keyed by seed and rep0 + r).
-hipError_t launch_row_absmax(const float *XF, int64_t nF, int64_t n, int64_t p, uint32_t *nu, hipStream_t st);
+// nu_i = max_j min(|X_ij|, cap) as float bits (cap = +inf: no capping).
+hipError_t launch_row_absmax(const float *XF, int64_t nF, int64_t n, int64_t p, float cap, uint32_t *nu,
+                             hipStream_t st);
 hipError_t launch_cdf_unbiased(const double *yd, const uint32_t *nu, int64_t n, double *cdf, int64_t *last, int *err,
                                hipStream_t st);
 hipError_t launch_hash_unbiased(const float *XF, int64_t nF, int64_t p, int m, int nrep, const int32_t *rows,
-                                const uint32_t *nu, uint64_t seed, int64_t rep0, uint32_t *keys, hipStream_t st);
+                                const uint32_t *nu, float cap, uint64_t seed, int64_t rep0, uint32_t *keys,
+                                hipStream_t st);
 // Row draws for repetitions [rep0, rep0 + nrep): rows [nrep][m].  weighted: cdf/last used.
 hipError_t launch_sample(uint64_t seed, int64_t rep0, int nrep, int m, int64_t n, int weighted, const double *cdf,
                          const int64_t *last, int32_t *rows, hipStream_t st);

@@ -20,6 +20,7 @@
 #include "xyz_internal.h"
 
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 
 namespace xyz {
@@ -321,15 +322,17 @@ __global__ void k_cdf(const double *__restrict__ yd, int64_t n, double *__restri
 // independently for every repetition, draw and column.
 
 // nu_i as float bits: non-negative floats order like their bit patterns, so an
-// integer atomic max over |x| bits is the float max.  Thread (i, column slice).
+// integer atomic max over |x| bits is the float max.  Entries capped at +-cap
+// (+inf: none) count as capped.  Thread (i, column slice).
 __global__ __launch_bounds__(256) void k_row_absmax(const float *__restrict__ XF, int64_t nF, int64_t n, int64_t p,
-                                                    int64_t cols_per, uint32_t *__restrict__ nu)
+                                                    int64_t cols_per, uint32_t capb, uint32_t *__restrict__ nu)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j0 = (int64_t)blockIdx.y * cols_per, j1 = min(p, j0 + cols_per);
     uint32_t mb = 0;
     for (int64_t j = j0; j < j1; ++j) mb = max(mb, __float_as_uint(XF[j * nF + i]) & 0x7FFFFFFFu);
+    mb = min(mb, capb);
     if (mb) atomicMax(&nu[i], mb);
 }
 
@@ -439,8 +442,8 @@ constexpr uint64_t UNB_STREAM = 0x2545F4914F6CDD1Dull;
 
 __global__ __launch_bounds__(256) void k_hash_unbiased(const float *__restrict__ XF, int64_t nF, int64_t p, int m,
                                                        const int32_t *__restrict__ rows,
-                                                       const uint32_t *__restrict__ nu, uint64_t seed, int64_t rep0,
-                                                       uint32_t *__restrict__ keys)
+                                                       const uint32_t *__restrict__ nu, float cap, uint64_t seed,
+                                                       int64_t rep0, uint32_t *__restrict__ keys)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(256) void k_hash_unbiased(const float *__restrict__
     if (j >= p) return;
     uint32_t key = 0;
     for (int t = 0; t < m; ++t) {
-        const double x = (double)XF[j * nF + rr[t]];
+        const double x = (double)fminf(fmaxf(XF[j * nF + rr[t]], -cap), cap);
         const double v = (double)nus[t];
         const uint64_t u = splitmix64_at(ss[t], 1ull + (uint64_t)j) >> 40;
         const bool plus = v > 0.0 ? __dmul_rn(__dmul_rn((double)u, 2.0), v) < __dmul_rn(__dadd_rn(v, x), 16777216.0)
@@ -3168,13 +3171,17 @@ hipError_t launch_cmask(const int32_t *rows, int nrep, int m, int nys, const uin
     return hipGetLastError();
 }
 
-hipError_t launch_row_absmax(const float *XF, int64_t nF, int64_t n, int64_t p, uint32_t *nu, hipStream_t st)
+hipError_t launch_row_absmax(const float *XF, int64_t nF, int64_t n, int64_t p, float cap, uint32_t *nu,
+                             hipStream_t st)
 {
     const hipError_t e = launch_zero(nu, sizeof(uint32_t) * (size_t)n, st);
     if (e != hipSuccess) return e;
     const int64_t slices = std::min<int64_t>(std::max<int64_t>(p / 64, 1), 4096);
     const int64_t per = (p + slices - 1) / slices;
-    hipLaunchKernelGGL(k_row_absmax, dim3(grid1(n, 256), (unsigned)slices), dim3(256), 0, st, XF, nF, n, p, per, nu);
+    uint32_t capb;
+    std::memcpy(&capb, &cap, sizeof capb);
+    hipLaunchKernelGGL(k_row_absmax, dim3(grid1(n, 256), (unsigned)slices), dim3(256), 0, st, XF, nF, n, p, per, capb,
+                       nu);
     return hipGetLastError();
 }
 
@@ -3186,10 +3193,11 @@ hipError_t launch_cdf_unbiased(const double *yd, const uint32_t *nu, int64_t n, 
 }
 
 hipError_t launch_hash_unbiased(const float *XF, int64_t nF, int64_t p, int m, int nrep, const int32_t *rows,
-                                const uint32_t *nu, uint64_t seed, int64_t rep0, uint32_t *keys, hipStream_t st)
+                                const uint32_t *nu, float cap, uint64_t seed, int64_t rep0, uint32_t *keys,
+                                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hash_unbiased, dim3(grid1(p, 256), nrep), dim3(256), 0, st, XF, nF, p, m, rows, nu, seed,
-                       rep0, keys);
+    hipLaunchKernelGGL(k_hash_unbiased, dim3(grid1(p, 256), nrep), dim3(256), 0, st, XF, nF, p, m, rows, nu, cap,
+                       seed, rep0, keys);
     return hipGetLastError();
 }
 

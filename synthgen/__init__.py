@@ -23,6 +23,7 @@ stands in for it) and Gaussian continuous designs (Section 5.4).
 from __future__ import annotations
 
 import dataclasses
+import math
 import numpy as np
 
 __all__ = [
@@ -227,15 +228,57 @@ def scaling_y(bits: np.ndarray, n: int, agree: int, seed: int) -> np.ndarray:
     return (x0 * x1 * sign).astype(np.int8)
 
 
+def dag_gaussian(n: int, p: int, r, mean_parents: float = 10.0):
+    """Rows i.i.d. N(0, Sigma) with Sigma from a random DAG (Section 5.4, setting 3).
+
+    Nodes come in a random order; node t takes Poisson(mean_parents) parents
+    (at most t) drawn uniformly among the earlier nodes, and is their linear
+    combination with weights U[0, 1] plus independent centred Gaussian noise of
+    variance 0.1 times the variance of that combination; a node without
+    parents is N(0, 1).  Every column is then divided by its population
+    standard deviation, so Sigma is a correlation matrix.  Returns (X float32
+    (n, p), Sigma float64 (p, p))."""
+    order = r.permutation(p)
+    S = np.zeros((p, p))                        # covariance in generation order
+    Z = np.empty((n, p))
+    for t in range(p):
+        k = min(t, int(r.poisson(mean_parents))) if t else 0
+        if k == 0:
+            S[t, t] = 1.0
+            Z[:, t] = r.standard_normal(n)
+            continue
+        pa = r.choice(t, size=k, replace=False)
+        w = r.uniform(0.0, 1.0, size=k)
+        v = float(w @ S[np.ix_(pa, pa)] @ w)     # variance from the direct parents
+        c = S[:t][:, pa] @ w
+        S[:t, t] = c
+        S[t, :t] = c
+        S[t, t] = 1.1 * v
+        Z[:, t] = Z[:, pa] @ w + math.sqrt(0.1 * v) * r.standard_normal(n)
+    sd = np.sqrt(np.diag(S))
+    X = np.empty((n, p), dtype=np.float32)
+    X[:, order] = (Z / sd).astype(np.float32)
+    C = S / sd[:, None] / sd[None, :]
+    Sigma = np.empty((p, p))
+    Sigma[np.ix_(order, order)] = C
+    return X, Sigma
+
+
 def lasso_setting(n: int, p: int, setting: int, seed: int = 0):
-    """Regression data of Section 5.4, settings 1 and 2 (Sigma = I): X ~ N(0, I)
-    float32 (n, p); 20 main effects and 10 interactions with magnitudes
-    U[2, 6] and random signs, mu = 0, eps ~ N(0, 1).  Setting 1 is
-    hierarchical (interactions drawn among pairs of main effects), setting 2
-    strictly non-hierarchical (interactions among the other columns).
+    """Regression data of Section 5.4: X float32 (n, p) with rows N(0, Sigma);
+    20 main effects and 10 interactions with magnitudes U[2, 6] and random
+    signs, mu = 0, eps ~ N(0, 1).  Setting 1 (Sigma = I) is hierarchical
+    (interactions drawn among pairs of main effects), setting 2 (Sigma = I)
+    strictly non-hierarchical (interactions among the other columns), setting
+    3 is setting 2 on the correlated design of dag_gaussian.
     Returns (X, Y, mains {j: beta}, inters {(j, k): theta})."""
+    if setting not in (1, 2, 3):
+        raise ValueError(f"setting {setting}: Section 5.4 has settings 1, 2 and 3")
     r = _rng(seed, 23 + setting)
-    X = r.standard_normal((n, p)).astype(np.float32)
+    if setting == 3:
+        X, _ = dag_gaussian(n, p, r)
+    else:
+        X = r.standard_normal((n, p)).astype(np.float32)
     cols = r.permutation(p)
     main = [int(j) for j in cols[:20]]
     pool = main if setting == 1 else [int(j) for j in cols[20:]]

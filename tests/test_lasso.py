@@ -73,3 +73,28 @@ def test_binary_design_matches_full_lasso():
     assert (3, 7) in path.inter[-1]
     # squares of +-1 columns are constant: never selected
     assert all(j != k for j, k in path.inter[-1])
+
+
+def test_dag_design_setting_3():
+    """Section 5.4, setting 3: rows N(0, Sigma) with Sigma from a random DAG whose
+    nodes are linear in their parents plus noise of 10 % of the parents'
+    variance.  Sigma is a correlation matrix, the sample correlation of many
+    rows converges to it, and the design is strongly correlated (most columns
+    have another column with correlation above 0.9)."""
+    import synthgen
+    r = np.random.default_rng(3)
+    X, S = synthgen.dag_gaussian(100_000, 80, r)
+    assert np.allclose(np.diag(S), 1.0) and np.allclose(S, S.T)
+    assert np.linalg.eigvalsh(S).min() > 0
+    E = np.corrcoef(X.T.astype(np.float64))
+    assert np.abs(E - S).max() < 0.02
+    strong = (np.abs(S) > 0.9).sum(1) - 1
+    assert np.mean(strong > 0) > 0.7 and np.median(strong) >= 2
+    # a node with parents explains 1/1.1 of its variance by them: some column's
+    # best linear fit from all the others has R^2 of at least 0.909
+    Sinv = np.linalg.inv(S)
+    r2 = 1.0 - 1.0 / np.diag(Sinv)
+    assert r2.max() > 1 / 1.1 - 1e-9
+    Xs, Ys, mains, inters = synthgen.lasso_setting(300, 60, 3, seed=4)
+    assert Xs.shape == (300, 60) and Xs.dtype == np.float32 and len(mains) == 20 and len(inters) == 10
+    assert all(j not in mains and k not in mains for j, k in inters)

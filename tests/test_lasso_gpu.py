@@ -80,3 +80,20 @@ def test_gpu_screen_path_equals_exact(ctx, binary):
     ref = lasso_interactions(X, Y, lambdas, _exact_screen(X))
     _same_path(gpu, ref)
     _kkt_full(X, Y, gpu)
+
+
+def test_gpu_screen_path_equals_exact_correlated_design(ctx):
+    """Section 5.4's setting 3: the non-hierarchical model on the strongly
+    correlated DAG design, where products of columns correlated with the true
+    pairs also predict Y; the screened path must still equal the exact one."""
+    import synthgen
+    X, Y, mains, inters = synthgen.lasso_setting(400, 40, 3, seed=7)
+    Xc = X.astype(np.float64) - X.mean(0)
+    lam_max = float(np.abs(Xc.T @ (Y - Y.mean())).max() / 400)
+    lambdas = list(lam_max * np.array([1.0, 0.5, 0.25, 0.12]))
+    x = ctx.x_create(np.ascontiguousarray(X.T))
+    gpu = lasso_interactions(X, Y, lambdas, xyz_screen(ctx, x, m=2, L=200, seed=1))
+    ref = lasso_interactions(X, Y, lambdas, _exact_screen(X))
+    _same_path(gpu, ref)
+    _kkt_full(X, Y, gpu)
+    assert len(gpu.inter[-1]) > 0

@@ -118,10 +118,13 @@ def test_tile_list_growth():
     verification kernels see the overflow on the device and verify nothing, the library
     grows the list and redoes the chunk; a second search reuses the grown list."""
     d = synthgen.small_binary(64, 40000, seed=41, planted=[(1, 39998)], flip=0.05)
+    rp, rr = oracle.search(d.XT, d.Y, 12, 80, 0.5, seed=41)
     c = xyz.Context(0)
     try:
+        x = c.x_create(d.XT)
         for it in range(2):
-            res, rp, rr = run_both(c, d.XT, d.Y, 12, 20, 0.5, seed=41)
+            _log(f"tile list growth: search {it}")
+            res = c.search(x, d.Y, m=12, L=80, kappa=0.5, seed=41)
             assert res["timing"]["tiles"] > 1 << 16
             assert_same_binary(res, rp, rr)
     finally:

@@ -84,3 +84,35 @@ def test_unbiased_needs_float_x(ctx):
     x = ctx.x_create(d.XT)
     with pytest.raises(xyz.XyzError):
         ctx.search(x, d.Y, m=4, L=2, kappa=0.1, unbiased=True)
+
+
+@pytest.mark.parametrize("cap,two,m", [(1.0, False, 6), (0.37, True, 9), (3.0, False, 17)])
+def test_capped_unbiased_matches_oracle(ctx, cap, two, m):
+    """Capping before the unbiased transform (Section 3.2's remark): rows with
+    outliers of +-6 on every fifth row; the cap (0.37 is not a float32 value,
+    so both sides round it alike) reaches the row maxima, the row weights and
+    the transform.  m = 17 takes the sort path."""
+    d = synthgen.small_continuous(240, 700, seed=30, planted=[(0, 1), (7, 40)], noise=0.8)
+    XT = d.XT.copy()
+    XT[::5, ::5] = np.where(XT[::5, ::5] < 0, -6.0, 6.0)
+    x = ctx.x_create(XT)
+    res = ctx.search(x, d.Y, m=m, L=7, kappa=0.2, seed=5, two_sided=two, unbiased=True, cap=cap)
+    rp, rr = oracle.search(XT, d.Y, m, 7, 0.2, seed=5, two_sided=two, unbiased=True, cap=cap)
+    assert_same_real(res, rp, rr, 0.2, 240)
+    plain = ctx.search(x, d.Y, m=m, L=7, kappa=0.2, seed=5, two_sided=two, unbiased=True)
+    assert not np.array_equal(plain["reps"]["candidates"], res["reps"]["candidates"])
+
+
+def test_cap_checks(ctx):
+    d = synthgen.small_continuous(60, 50, seed=31)
+    x = ctx.x_create(d.XT)
+    for kw in ({"cap": 1.0}, {"cap": -1.0, "unbiased": True}, {"cap": float("nan"), "unbiased": True},
+               {"cap": 1e-60, "unbiased": True}):
+        with pytest.raises(xyz.XyzError):
+            ctx.search(x, d.Y, m=4, L=2, kappa=0.1, **kw)
+    # a cap above every entry changes nothing
+    big = float(np.abs(d.XT).max())
+    a = ctx.search(x, d.Y, m=5, L=4, kappa=0.1, seed=2, unbiased=True, cap=big)
+    b = ctx.search(x, d.Y, m=5, L=4, kappa=0.1, seed=2, unbiased=True)
+    assert np.array_equal(a["reps"]["candidates"], b["reps"]["candidates"])
+    assert np.array_equal(a["pairs"], b["pairs"])
