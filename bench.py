@@ -28,6 +28,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -106,6 +107,9 @@ def main():
                     help="auto: time every plan once and keep the fastest")
     ap.add_argument("--ms", type=str, default="10,11,12", help="m of the xyz plans (L from eq. (15))")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="search with the default launch shapes (no xyz_autotune)")
+    ap.add_argument("--tune-cache", type=str, default=os.path.join(tempfile.gettempdir(), "xyz_tune_cache.txt"),
+                    help="cache file of tuned launch shapes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-genotype", action="store_true", help="skip the genotype-shaped workload")
     ap.add_argument("--no-continuous", action="store_true", help="skip the continuous workload")
@@ -196,6 +200,11 @@ def main():
     plans = {"auto": [("brute", 0, 1)] + xyz_plans, "brute": [("brute", 0, 1)], "xyz": xyz_plans}[args.plan]
     table = []
     for pl in plans:
+        tuning = None
+        if pl[0] == "xyz" and not args.no_tune:
+            # launch shapes timed once per search shape (untimed setup; reused from the cache file)
+            tuning = ctx.autotune(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1, cache_path=args.tune_cache)
+            log(f"tuning {pl}: {tuning}")
         run(pl)
         torch.cuda.synchronize()
         tt = time.perf_counter()
@@ -204,7 +213,8 @@ def main():
         dt = time.perf_counter() - tt
         rec, trec = recall_of(r)
         table.append(dict(kind=pl[0], m=pl[1], L=pl[2], ms_per_search=dt * 1e3, planted_recall=rec,
-                          predicted_recall_min=1.0 if pl[0] == "brute" else xyz.xyz_eta(gamma_w, pl[1], pl[2])))
+                          predicted_recall_min=1.0 if pl[0] == "brute" else xyz.xyz_eta(gamma_w, pl[1], pl[2]),
+                          tuning=tuning))
         log(f"plan {pl}: {dt * 1e3:.1f} ms, planted recall {rec:.3f}")
     best = min(range(len(plans)), key=lambda q: table[q]["ms_per_search"])
     plan = plans[best]

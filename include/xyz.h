@@ -45,6 +45,7 @@ typedef int32_t xyz_status;
 #define XYZ_EAGAIN       (-4)  /* serving: the request is not finished yet */
 #define XYZ_ECANCELED    (-5)  /* serving: the request was cancelled or the server stopped */
 #define XYZ_EUNSUPPORTED (-6)  /* valid request outside what the library implements */
+#define XYZ_EINTERNAL    (-7)  /* an internal consistency check failed (a bug in the library) */
 
 #define XYZ_MEM_HOST   0
 #define XYZ_MEM_DEVICE 1
@@ -204,6 +205,30 @@ xyz_status xyz_search_batch(xyz_ctx *ctx, const xyz_x *x, int32_t nY, const void
 xyz_status xyz_search_noalloc(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem,
                               const xyz_params *params, void *stream, xyz_pair *pairs, int64_t pairs_cap,
                               int64_t *npairs, xyz_rep_stats *reps);
+
+/* Launch shapes of Algorithm 2 that do not change a search's result: how many repetitions one
+ * chunk holds (its workspace budget: keys, permutations and bucket offsets; more repetitions per
+ * chunk give the hash and bucket launches more workgroups) and the workgroups per compute unit of
+ * the tile-verification and big-tile launches. */
+typedef struct {
+    double chunk_gib;          /* workspace budget of one chunk, GiB (default 8) */
+    int32_t verify_wg_per_cu;  /* tile-verification launches (default 24) */
+    int32_t big_wg_per_cu;     /* big-tile launch (default 8) */
+    int32_t from_cache;        /* 1: read from the cache file, nothing was timed */
+    int32_t variants;          /* searches timed (0 when read from the cache) */
+    double ms;                 /* wall time of the search under the chosen shapes, ms (as recorded) */
+} xyz_tuning;
+
+/* Times the search (x, Y, params) under a few launch shapes, one choice at a time from the
+ * defaults, and keeps the fastest for every later search of the same shape in the context: the
+ * same device architecture and compute units, n, p, m, X and Y formats, XYZ_TWO_SIDED and
+ * XYZ_UNBIASED.  cache_path (or NULL): a text file of tuned shapes; when it holds this shape the
+ * record is used and nothing is timed, else the choice is added to it (written to cache_path.tmp,
+ * then renamed).  The search runs several times (params as xyz_search, without XYZ_PROFILE);
+ * every run must give the same pairs (XYZ_EINTERNAL otherwise).  Chunk budgets above the default
+ * are tried only with room in free device memory.  out: the choice. */
+xyz_status xyz_autotune(xyz_ctx *ctx, const xyz_x *x, const void *Y, int yfmt, int mem, const xyz_params *params,
+                        void *stream, const char *cache_path, xyz_tuning *out);
 
 /* Exact search of eq. (1) over the pairs (a, b), a in colsA, b in colsB,
  * a != b, reported once as (min, max) (brute force, FP4 e2m1 matrix cores for

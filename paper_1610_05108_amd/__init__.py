@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxyz.so")
 
 XYZ_OK, XYZ_EINVAL, XYZ_ENOMEM, XYZ_EDEVICE, XYZ_EAGAIN, XYZ_ECANCELED, XYZ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+XYZ_EINTERNAL = -7
 XYZ_MEM_HOST, XYZ_MEM_DEVICE = 0, 1
 XYZ_X_I8_PM1, XYZ_X_BITS, XYZ_X_F32, XYZ_X_I8_PM1_ROWMAJOR = 0, 1, 2, 3
 XYZ_Y_I8_PM1, XYZ_Y_F32, XYZ_Y_F64 = 0, 1, 2
@@ -41,7 +42,7 @@ EXPORTS = [
     "xyz_eta", "xyz_tau_dense", "xyz_eta_dense", "xyz_L_for", "xyz_m_for_L", "xyz_mstar",
     "xyz_sample_strengths", "xyz_plan",
     "xyz_serve_start", "xyz_serve_submit", "xyz_serve_poll", "xyz_serve_wait", "xyz_serve_cancel",
-    "xyz_serve_stats_get", "xyz_serve_stop",
+    "xyz_serve_stats_get", "xyz_serve_stop", "xyz_autotune",
 ]
 XYZ_PLAN_XYZ, XYZ_PLAN_BRUTE = 0, 1
 
@@ -69,6 +70,12 @@ class xyz_timing(ctypes.Structure):
 class xyz_route(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("m", ctypes.c_int32), ("L", ctypes.c_int32), ("routed", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("predicted_ms", ctypes.c_double), ("alternative_ms", ctypes.c_double)]
+
+
+class xyz_tuning(ctypes.Structure):
+    _fields_ = [("chunk_gib", ctypes.c_double), ("verify_wg_per_cu", ctypes.c_int32),
+                ("big_wg_per_cu", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("variants", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class xyz_plan_info(ctypes.Structure):
@@ -118,6 +125,8 @@ def lib():
         "xyz_search_noalloc": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(xyz_params), P, P, I64,
                                      ctypes.POINTER(I64), P]),
         "xyz_bruteforce": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, D, U32, P, I64, P, I64, P, ctypes.POINTER(P)]),
+        "xyz_autotune": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(xyz_params), P, ctypes.c_char_p,
+                               ctypes.POINTER(xyz_tuning)]),
         "xyz_dense_search": (I32, [P, P, P, ctypes.c_int, ctypes.c_int, P, I32, I64, D, I32, U32, P,
                                    ctypes.POINTER(P)]),
         "xyz_result_npairs": (I64, [P]),
@@ -377,6 +386,22 @@ def xyz_search_noalloc(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, t
     return {"pairs": pairs[:int(npairs.value)].copy(), "reps": reps}
 
 
+def xyz_autotune(ctx, x, Y, m: int, L: int, kappa: float, seed: int = 0, two_sided: bool = False,
+                 unbiased: bool = False, cap: float = 0.0, cache_path=None, stream=None):
+    """Time the search's launch shapes once (xyz_autotune) and keep the fastest for later searches of
+    the same shape in the context; cache_path: text file of tuned shapes read before timing and
+    updated after.  Returns the choice as a dict (from_cache = 1 when nothing was timed)."""
+    _check_y(x, Y)
+    prm, keep_rows = _params(m, L, kappa, seed, two_sided, 0, None, False, unbiased, cap)
+    ptr, mem, keep = _ptr(Y)
+    out = xyz_tuning()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().xyz_autotune(ctx, x, ptr, _y_format(Y), mem, ctypes.byref(prm), _stream(stream, Y), path,
+                              ctypes.byref(out)))
+    del keep, keep_rows
+    return {name: getattr(out, name) for name, _ in xyz_tuning._fields_}
+
+
 def xyz_dense_search(ctx, x, Y, R, tau: int, kappa: float, rep_offset: int = 0, profile: bool = False,
                      stream=None):
     """Algorithm 1 with dense projections: R is (L, n) int32 (one projection vector
@@ -549,6 +574,9 @@ class Context:
 
     def search_noalloc(self, x, Y, **kw):
         return xyz_search_noalloc(self.h, x, Y, **kw)
+
+    def autotune(self, x, Y, **kw):
+        return xyz_autotune(self.h, x, Y, **kw)
 
     def search_batch(self, x, Ys, params, stream=None):
         return xyz_search_batch(self.h, x, Ys, params, stream=stream)

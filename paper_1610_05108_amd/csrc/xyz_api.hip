@@ -40,19 +40,6 @@ xyz_status xyz_rt::fail(xyz_status code, const char *fmt, ...)
 
 namespace {
 
-#define HIP_TRY(expr)                                                                                       \
-    do {                                                                                                    \
-        hipError_t e_ = (expr);                                                                             \
-        if (e_ != hipSuccess) return fail(XYZ_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
-                                          __FILE__, __LINE__);                                              \
-    } while (0)
-
-#define XYZ_TRY(expr)                  \
-    do {                               \
-        xyz_status s_ = (expr);        \
-        if (s_ != XYZ_OK) return s_;   \
-    } while (0)
-
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 // HIP events around the stages of one call, summed after the final sync.
@@ -253,6 +240,7 @@ extern "C" xyz_status xyz_init(int device, uint64_t hbm_budget_bytes, xyz_ctx **
     c->device = device;
     c->budget = hbm_budget_bytes;
     c->cu_count = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     *out = c;
     return XYZ_OK;
 }
@@ -359,7 +347,7 @@ extern "C" void xyz_x_destroy(xyz_x *x)
 extern "C" int64_t xyz_x_n(const xyz_x *x) { return x ? x->n : 0; }
 extern "C" int64_t xyz_x_p(const xyz_x *x) { return x ? x->p : 0; }
 
-int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m)
+int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m, int64_t chunk_bytes)
 {
     int64_t chunk = std::min<int64_t>(L, 4096);
     chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((1ll << 32) - 1) / p));   // u32 positions in perm
@@ -367,7 +355,7 @@ int64_t xyz_rt::chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m)
     // path's scratch (two key/value buffers, heads, runs and per-run tile counts)
     const int64_t per_rep = m <= MAX_M_LDS ? 8 * p + 4 * ((1ll << m) + 1)
                                            : 64 * p + (m <= SK_TABLE_MAX_M ? 4 * (1ll << m) : 0);
-    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)(8ll << 30) / per_rep));   // 8 GiB of 288
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, chunk_bytes / per_rep));   // default 8 GiB of 288
     chunk = std::min<int64_t>(chunk, 65535);                                           // grid y of k_hash
     if (c->max_chunk > 0) chunk = std::min<int64_t>(chunk, c->max_chunk);
     return std::max<int64_t>(chunk, 1);
@@ -540,7 +528,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
 
     // ---- repetitions, in chunks
     const int nb = 1 << m;
-    const int64_t chunk = chunk_reps(c, L, p, m);
+    const Knobs kn = knobs_for(c, x, m, yfmt, P.flags);
+    const int64_t chunk = chunk_reps(c, L, p, m, kn.chunk_bytes);
     RepInfo *info = nullptr;
     XYZ_TRY(ws(c, WS_INFO, (size_t)L * nys, &info));
     int32_t *rows = nullptr;
@@ -559,7 +548,8 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     Survivor *surv = nullptr;
     XYZ_TRY(ws(c, WS_SURV, surv_cap, &surv));
     uint64_t surv_done = 0;
-    const int grid = std::max(1, c->cu_count * 24);
+    const int grid = std::max(1, c->cu_count * kn.verify_per_cu);
+    const int big_grid = std::max(1, c->cu_count * kn.big_per_cu);
 
     for (int64_t r0 = 0; r0 < L; r0 += chunk) {
         const int R = (int)std::min<int64_t>(chunk, L - r0);
@@ -692,7 +682,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             tm.end();
             if (nbig) {
                 tm.begin(8);
-                HIP_TRY(launch_verify_big(va, g, st));
+                HIP_TRY(launch_verify_big(va, big_grid, st));
                 tm.end();
             }
             // the one transfer of the chunk: the survivor count and (device_counts) the list sizes

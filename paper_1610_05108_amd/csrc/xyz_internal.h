@@ -210,7 +210,8 @@ hipError_t launch_col_pops(const uint32_t *XC, int W32p, const uint32_t *yb, int
 // Popcount-XOR verification of +-1 candidates: s = n - 2 popcount(y ^ x_j ^ x_k) (popcount, small
 // and matrix-core tiles).
 hipError_t launch_verify_bin(const VerifyArgs &a, int grid, hipStream_t st);
-// The big tiles of +-1 candidates (LDS-staged block pairs on the FP4 matrix cores).
+// The big tiles of +-1 candidates (LDS-staged block pairs on the FP4 matrix cores), on at most
+// grid workgroups.
 hipError_t launch_verify_big(const VerifyArgs &a, int grid, hipStream_t st);
 // Binary64 verification of real-valued candidates (x_real: values from XF, else +-1 from XC).
 hipError_t launch_verify_real(const VerifyArgs &a, int x_real, int grid, hipStream_t st);

@@ -3260,7 +3260,7 @@ hipError_t launch_col_pops(const uint32_t *XC, int W32p, const uint32_t *yb, int
 hipError_t launch_verify_big(const VerifyArgs &a, int grid, hipStream_t st)
 {
     if (a.nbig) {
-        const unsigned g = (unsigned)std::min<uint64_t>(a.nbig, (uint64_t)std::max(grid / 3, 1));
+        const unsigned g = (unsigned)std::min<uint64_t>(a.nbig, (uint64_t)std::max(grid, 1));
         if (a.two_sided)
             hipLaunchKernelGGL(k_verify_lds<true>, dim3(g), dim3(512), BIG_LDS, st, a);
         else

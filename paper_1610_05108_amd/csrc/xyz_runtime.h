@@ -5,7 +5,23 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <vector>
+
+// Return from the enclosing xyz_status function on a failed HIP call (XYZ_EDEVICE, with the
+// call and its error as the last-error message) or on a failed library call.
+#define HIP_TRY(expr)                                                                                       \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess) return fail(XYZ_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                              \
+    } while (0)
+
+#define XYZ_TRY(expr)                  \
+    do {                               \
+        xyz_status s_ = (expr);        \
+        if (s_ != XYZ_OK) return s_;   \
+    } while (0)
 
 namespace xyz_rt {
 
@@ -21,6 +37,21 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Launch-shape choices of a search that do not change its result: the workspace budget of
+// one chunk of repetitions and the workgroups per compute unit of the verification launches.
+struct Knobs {
+    int64_t chunk_bytes = 8ll << 30;
+    int verify_per_cu = 24;
+    int big_per_cu = 8;
+};
+
+// A tuned choice for one shape of search (xyz_autotune).
+struct Tuned {
+    std::string key;
+    Knobs k;
+    double ms = 0.0;
+};
+
 }  // namespace xyz_rt
 
 struct xyz_ctx {
@@ -34,6 +65,10 @@ struct xyz_ctx {
     // by a bump pointer instead of being allocated, and are never freed.
     char *arena = nullptr;
     size_t arena_size = 0, arena_used = 0;
+    // Tuned launch shapes by search shape (xyz_autotune), and the shape the tuner is timing.
+    std::string arch;
+    std::vector<xyz_rt::Tuned> tuned;
+    const xyz_rt::Knobs *force_knobs = nullptr;
 };
 
 struct xyz_x {
@@ -83,8 +118,13 @@ xyz_status run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *const *Ys,
 // the same device).
 xyz_status sample_strengths(xyz_ctx *c, const xyz_x *x, const void *Y, int yfmt, int mem, int64_t npairs,
                             uint64_t seed, hipStream_t stream, double *out);
-// Repetitions per chunk for p columns and 2^m buckets under the context's limits.
-int64_t chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m);
+// Repetitions per chunk for p columns and 2^m buckets under the context's limits and a chunk
+// budget of chunk_bytes.
+int64_t chunk_reps(const xyz_ctx *c, int64_t L, int64_t p, int m, int64_t chunk_bytes = 8ll << 30);
+// Key of a search shape in the tuning table and cache file.
+std::string tune_key(const xyz_ctx *c, const xyz_x *x, int m, int yfmt, uint32_t flags);
+// The launch shapes of a search: the tuner's forced choice, a tuned entry, or the defaults.
+Knobs knobs_for(const xyz_ctx *c, const xyz_x *x, int m, int yfmt, uint32_t flags);
 // Frees every workspace of the context.
 void ws_release(xyz_ctx *c);
 // Device address of the static scratch array of xyz_search_noalloc on `device` (looked up once
