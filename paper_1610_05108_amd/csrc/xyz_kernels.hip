@@ -1616,9 +1616,13 @@ __global__ __launch_bounds__(256, 2) void k_verify_mfma(VerifyArgs a0)
 // value 1 (expand_b_plain), so the staging does no arithmetic on them; the
 // column popcounts |z_j| and |x_j| come precomputed per search, read with the
 // first chunk.  Wave (wa, wb) owns A columns 64 wa.. and B columns 128 wb.. as
-// up to 2 x 4 fragments of 32 x 32; positions past the end of a block are
-// staged as copies of its last column, so their products duplicate real ones
-// and the cheap threshold test needs no masks.
+// up to 2 x 4 fragments of 32 x 32.  All 256 positions of both blocks are
+// staged, those past the end of a block as copies of its last column, so the
+// loads and stores carry no conditions and the products of the extra
+// positions duplicate real ones (the cheap threshold test needs no masks);
+// quads past the last are clamped and never read.  A workgroup runs tiles
+// in turn: under the products of a tile's last chunk it reads the next
+// tile's column ids and first chunk, so a tile's start waits for no memory.
 constexpr int BKQ = 8;                          // quads per staged chunk (1024 rows)
 constexpr int BHROW = BIG_TILE + 1;             // uint2 per LDS half row (words h, h + 2 of every column), padded
 constexpr size_t BIG_LDS = (size_t)2 * 2 * BKQ * 2 * BHROW * sizeof(uint2);   // [buffer][side][quad][half][column]
@@ -1640,56 +1644,60 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a0)
     const uint4 *T4 = reinterpret_cast<const uint4 *>(a.tiles + a.ntiles + a.nsmall + a.nmfma);
     const int32_t n32 = (int32_t)a.n;
     int par = 0;
-    for (uint64_t ti = blockIdx.x; ti < a.nbig; ti += gridDim.x, par ^= 1) {
-        const Tile t = tile_from(T4[ti]);
-        const int na = (int)t.na + 1, nb = (int)t.nb + 1;
-        const int FA = (na + 31) >> 5, FB = (nb + 31) >> 5;
-        const int nua = min(max(FA - 2 * wa, 0), 2), nvb = min(max(FB - 4 * wb, 0), 4);
-        const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)t.ysel * a.W32p);
-        // this thread's staging slots: column ids (NOCOL: not staged)
-        constexpr uint32_t NOCOL = ~0u;
-        uint32_t col[8];
+    uint64_t ti = blockIdx.x;
+    if (ti >= a.nbig) return;
+    // this thread's staging slots: column ids, every slot of the 256 x 256 block pair staged
+    // (positions past the end of a block as copies of its last column); loads and stores are
+    // unconditional, quads past the last are clamped and never read
+    uint32_t col[8];
+    uint32_t pops[8];
+    uint4 pre[8], ypre;
+    auto stage_cols = [&](const Tile &tt) {
+        const int na_ = (int)tt.na + 1, nb_ = (int)tt.nb + 1;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int side = r >> 2, c = sc + 64 * (r & 3);
-            const int nside = side ? nb : na, fs = side ? FB : FA;
-            col[r] = c < 32 * fs ? a.perm[(side ? t.b0 : t.a0) + min(c, nside - 1)] : NOCOL;
+            col[r] = a.perm[(side ? tt.b0 : tt.a0) + min(c, (side ? nb_ : na_) - 1)];
         }
-        uint32_t pops[8];
-        uint4 pre[8], ypre;
-        auto load_chunk = [&](int ch) {
-            const int qi = ch * BKQ + sq;
-            const bool in = qi < W4;
-            ypre = in ? y4[qi] : make_uint4(0, 0, 0, 0);
+    };
+    auto load_chunk = [&](const Tile &tt, int ch) {
+        const uint4 *y4 = reinterpret_cast<const uint4 *>(a.yb + (int64_t)tt.ysel * a.W32p);
+        const int qi = min(ch * BKQ + sq, W4 - 1);
+        ypre = y4[qi];
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
-                pre[r] = (in && col[r] != NOCOL) ? XC4[(uint64_t)col[r] * W4 + qi] : make_uint4(0, 0, 0, 0);
-            if (ch == 0 && sq == 0) {      // the staged columns' popcounts, stored with the first chunk
-                const uint32_t *pz = a.cpop + (uint64_t)t.ysel * (uint64_t)a.p, *px = a.cpop + (uint64_t)a.nys * a.p;
+        for (int r = 0; r < 8; ++r) pre[r] = XC4[(uint64_t)col[r] * W4 + qi];
+        if (ch == 0 && sq == 0) {      // the staged columns' popcounts, stored with the first chunk
+            const uint32_t *pz = a.cpop + (uint64_t)tt.ysel * (uint64_t)a.p, *px = a.cpop + (uint64_t)a.nys * a.p;
 #pragma unroll
-                for (int r = 0; r < 8; ++r) pops[r] = col[r] != NOCOL ? (r < 4 ? pz : px)[col[r]] : 0u;
+            for (int r = 0; r < 8; ++r) pops[r] = (r < 4 ? pz : px)[col[r]];
+        }
+    };
+    // registers -> LDS buffer `buf` (A side z = y ^ x), words h and h + 2 into half row h; with
+    // the first chunk, the popcounts
+    auto store_chunk = [&](int buf, bool first) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int side = r >> 2, c = sc + 64 * (r & 3);
+            uint4 v = pre[r];
+            if (side == 0) {
+                v.x ^= ypre.x;
+                v.y ^= ypre.y;
+                v.z ^= ypre.z;
+                v.w ^= ypre.w;
             }
-        };
-        // registers -> LDS buffer `buf` (A side z = y ^ x), words h and h + 2 into half row h; with
-        // the first chunk, the popcounts
-        auto store_chunk = [&](int buf, bool first) {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                if (col[r] == NOCOL) continue;
-                const int side = r >> 2, c = sc + 64 * (r & 3);
-                uint4 v = pre[r];
-                if (side == 0) {
-                    v.x ^= ypre.x;
-                    v.y ^= ypre.y;
-                    v.z ^= ypre.z;
-                    v.w ^= ypre.w;
-                }
-                uint2 *row = bl + (size_t)((buf * 2 + side) * BKQ + sq) * (2 * BHROW) + c;
-                row[0] = make_uint2(v.x, v.z);
-                row[BHROW] = make_uint2(v.y, v.w);
-                if (first && sq == 0) bpop[par][side][c] = pops[r];
-            }
-        };
+            uint2 *row = bl + (size_t)((buf * 2 + side) * BKQ + sq) * (2 * BHROW) + c;
+            row[0] = make_uint2(v.x, v.z);
+            row[BHROW] = make_uint2(v.y, v.w);
+            if (first && sq == 0) bpop[par][side][c] = pops[r];
+        }
+    };
+    Tile t = tile_from(T4[ti]);
+    stage_cols(t);
+    load_chunk(t, 0);
+    for (;;) {
+        const int na = (int)t.na + 1, nb = (int)t.nb + 1;
+        const int FA = (na + 31) >> 5, FB = (nb + 31) >> 5;
+        const int nua = min(max(FA - 2 * wa, 0), 2), nvb = min(max(FB - 4 * wb, 0), 4);
         v16f acc[2][4];
 #pragma unroll
         for (int u = 0; u < 2; ++u)
@@ -1721,101 +1729,115 @@ __global__ __launch_bounds__(512) void k_verify_lds(VerifyArgs a0)
                 }
             }
         };
-        load_chunk(0);
-        store_chunk(0, true);
+        store_chunk(0, true);             // chunk 0 of this tile, loaded during the previous tile
         lds_barrier();
         const bool active = nua > 0 && nvb > 0, full = nua == 2 && nvb == 4;
+        const uint64_t tn_i = ti + gridDim.x;
+        const bool more = tn_i < a.nbig;
+        Tile tn = t;
         for (int ch = 0; ch < NC; ++ch) {
             const int buf = ch & 1;
-            if (ch + 1 < NC) load_chunk(ch + 1);
+            if (ch + 1 < NC) {
+                load_chunk(t, ch + 1);
+            } else if (more) {            // the next tile's columns and first chunk, under this chunk's products
+                tn = tile_from(T4[tn_i]);
+                stage_cols(tn);
+                load_chunk(tn, 0);
+            }
             if (full) compute(ch, buf, std::true_type{});
             else if (active) compute(ch, buf, std::false_type{});
             if (ch + 1 < NC) store_chunk(buf ^ 1, false);
             lds_barrier();
         }
-        if (!active) continue;
-        // cheap test per fragment: x = 4C - 2|z_a| over the lane's 16 rows against smin - n + 2|x_b|
-        // (and -smin - n + 2|x_b| two-sided), exact in FP32
-        const int32_t smin = (int32_t)a.smin[t.ysel];
-        const uint32_t *popA = bpop[par][0], *popB = bpop[par][1];
-        uint32_t hitmask = 0;
+        do {
+            if (!active) break;
+            // cheap test per fragment: x = 4C - 2|z_a| over the lane's 16 rows against smin - n + 2|x_b|
+            // (and -smin - n + 2|x_b| two-sided), exact in FP32
+            const int32_t smin = (int32_t)a.smin[t.ysel];
+            const uint32_t *popA = bpop[par][0], *popB = bpop[par][1];
+            uint32_t hitmask = 0;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (u >= nua) break;
-            float tA[16];
+            for (int u = 0; u < 2; ++u) {
+                if (u >= nua) break;
+                float tA[16];
 #pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const uint4 v4 = *reinterpret_cast<const uint4 *>(&popA[wa * 64 + u * 32 + q4 * 8 + h * 4]);
-                tA[4 * q4 + 0] = (float)(2 * v4.x);
-                tA[4 * q4 + 1] = (float)(2 * v4.y);
-                tA[4 * q4 + 2] = (float)(2 * v4.z);
-                tA[4 * q4 + 3] = (float)(2 * v4.w);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                if (v >= nvb) break;
-                const int32_t pb2 = 2 * (int32_t)popB[wb * 128 + v * 32 + l32];
-                float mx = -1e30f, mn = 1e30f;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float x = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
-                    mx = fmaxf(mx, x);
-                    if (TWO) mn = fminf(mn, x);
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const uint4 v4 = *reinterpret_cast<const uint4 *>(&popA[wa * 64 + u * 32 + q4 * 8 + h * 4]);
+                    tA[4 * q4 + 0] = (float)(2 * v4.x);
+                    tA[4 * q4 + 1] = (float)(2 * v4.y);
+                    tA[4 * q4 + 2] = (float)(2 * v4.z);
+                    tA[4 * q4 + 3] = (float)(2 * v4.w);
                 }
-                const bool hit = mx >= (float)(smin - n32 + pb2) || (TWO && mn <= (float)(-smin - n32 + pb2));
-                hitmask |= (hit ? 1u : 0u) << (u * 4 + v);
-            }
-        }
-        if (__ballot(hitmask != 0) == 0) continue;
-        // rare: the fragments that hit are checked pair by pair.  Their counts go through this
-        // wave's slot in the second staging buffer (free until the next tile stores its second
-        // chunk, which follows a barrier that every wave reaches after this pass), so that the
-        // rows are indexed at run time; each lane reads back only what it wrote.
-        float *fbuf = reinterpret_cast<float *>(bl + (size_t)2 * BKQ * 2 * BHROW) + wave * 16 * 64;
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v) {
+                    if (v >= nvb) break;
+                    const int32_t pb2 = 2 * (int32_t)popB[wb * 128 + v * 32 + l32];
+                    float mx = -1e30f, mn = 1e30f;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const bool fh = (hitmask >> (u * 4 + v)) & 1u;
-                if (__ballot(fh) == 0) continue;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) fbuf[r * 64 + lane] = acc[u][v][r];
-                const int cb = wb * 128 + v * 32 + l32;
-                const int32_t pb2 = 2 * (int32_t)popB[cb];
-                const int row0 = wa * 64 + u * 32 + h * 4;
-                uint32_t msk = 0;
-                if (fh && cb < nb) {
-#pragma unroll 1
                     for (int r = 0; r < 16; ++r) {
-                        const int ra = row0 + (r >> 2) * 8 + (r & 3);
-                        const int32_t sv = n32 - 2 * (int32_t)popA[ra] - pb2 + 4 * (int32_t)fbuf[r * 64 + lane];
-                        const bool pass = TWO ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin);
-                        if (pass && ra < na && (!t.diag || ra < cb)) msk |= 1u << r;
+                        const float x = __builtin_fmaf(4.0f, acc[u][v][r], -tA[r]);
+                        mx = fmaxf(mx, x);
+                        if (TWO) mn = fminf(mn, x);
                     }
-                }
-                unsigned long long idx = reserve_survivors(a, t, __popc(msk));
-                if (idx == ~0ull) continue;
-                const uint32_t k = a.perm[t.b0 + min(cb, nb - 1)];
-                while (msk) {
-                    const int r = __ffs(msk) - 1;
-                    msk &= msk - 1;
-                    const int ra = row0 + (r >> 2) * 8 + (r & 3);
-                    const uint32_t j = a.perm[t.a0 + ra];
-                    const int32_t sv = n32 - 2 * (int32_t)popA[ra] - pb2 + 4 * (int32_t)fbuf[r * 64 + lane];
-                    if (idx < a.surv_cap) {
-                        Survivor sr;
-                        sr.j = min(j, k);
-                        sr.k = max(j, k);
-                        sr.rep = (uint32_t)(a.rep_abs0 + t.rep);
-                        sr.s = sv;
-                        sr.value = (double)sv;
-                        sr.ysel = t.ysel;
-                        sr.pad = 0;
-                        a.surv[idx] = sr;
-                    }
-                    ++idx;
+                    const bool hit = mx >= (float)(smin - n32 + pb2) || (TWO && mn <= (float)(-smin - n32 + pb2));
+                    hitmask |= (hit ? 1u : 0u) << (u * 4 + v);
                 }
             }
+            if (__ballot(hitmask != 0) == 0) break;
+            // rare: the fragments that hit are checked pair by pair.  Their counts go through this
+            // wave's slot in the second staging buffer (free until the next tile stores its second
+            // chunk, which follows a barrier that every wave reaches after this pass), so that the
+            // rows are indexed at run time; each lane reads back only what it wrote.
+            float *fbuf = reinterpret_cast<float *>(bl + (size_t)2 * BKQ * 2 * BHROW) + wave * 16 * 64;
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const bool fh = (hitmask >> (u * 4 + v)) & 1u;
+                    if (__ballot(fh) == 0) continue;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) fbuf[r * 64 + lane] = acc[u][v][r];
+                    const int cb = wb * 128 + v * 32 + l32;
+                    const int32_t pb2 = 2 * (int32_t)popB[cb];
+                    const int row0 = wa * 64 + u * 32 + h * 4;
+                    uint32_t msk = 0;
+                    if (fh && cb < nb) {
+#pragma unroll 1
+                        for (int r = 0; r < 16; ++r) {
+                            const int ra = row0 + (r >> 2) * 8 + (r & 3);
+                            const int32_t sv = n32 - 2 * (int32_t)popA[ra] - pb2 + 4 * (int32_t)fbuf[r * 64 + lane];
+                            const bool pass = TWO ? ((sv < 0 ? -sv : sv) >= smin) : (sv >= smin);
+                            if (pass && ra < na && (!t.diag || ra < cb)) msk |= 1u << r;
+                        }
+                    }
+                    unsigned long long idx = reserve_survivors(a, t, __popc(msk));
+                    if (idx == ~0ull) continue;
+                    const uint32_t k = a.perm[t.b0 + min(cb, nb - 1)];
+                    while (msk) {
+                        const int r = __ffs(msk) - 1;
+                        msk &= msk - 1;
+                        const int ra = row0 + (r >> 2) * 8 + (r & 3);
+                        const uint32_t j = a.perm[t.a0 + ra];
+                        const int32_t sv = n32 - 2 * (int32_t)popA[ra] - pb2 + 4 * (int32_t)fbuf[r * 64 + lane];
+                        if (idx < a.surv_cap) {
+                            Survivor sr;
+                            sr.j = min(j, k);
+                            sr.k = max(j, k);
+                            sr.rep = (uint32_t)(a.rep_abs0 + t.rep);
+                            sr.s = sv;
+                            sr.value = (double)sv;
+                            sr.ysel = t.ysel;
+                            sr.pad = 0;
+                            a.surv[idx] = sr;
+                        }
+                        ++idx;
+                    }
+                }
+        } while (0);
+        if (!more) break;
+        ti = tn_i;
+        t = tn;
+        par ^= 1;
     }
 }
 
