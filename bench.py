@@ -61,10 +61,12 @@ def find_kappa(ctx, x, Yd, n, p, target=10_000):
     return kappa, exact
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed counter profile of
-    `workload`, or None when the kernel source changed since the counters were
-    taken (or there is no profile)."""
+def measured_traffic(kernel, workload, m, L, share=1.0):
+    """HBM bytes of `kernel` in one search (m, L) of `workload`, times `share`,
+    from the committed counter profile of that search (FETCH_SIZE and
+    WRITE_SIZE summed over the kernel's dispatches, scaled by what the counters
+    read for a plain device copy); None when the kernel source changed since
+    the counters were taken, the profile is of another plan, or there is none."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")) as f:
@@ -73,10 +75,13 @@ def measured_traffic(kernel, workload):
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
     except OSError:
         return None
-    k = t.get(kernel)
-    if sha != t.get("kernels_source_sha256_16") or not k or k.get("fetch_kib") is None or k.get("write_kib") is None:
+    k = t.get("kernels", {}).get(kernel)
+    srch = t.get("search", {})
+    if sha != t.get("kernels_source_sha256_16") or not k or srch.get("m") != m or srch.get("L") != L:
         return None
-    return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0
+    if k.get("fetch_kib") is None or k.get("write_kib") is None:
+        return None
+    return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0 * share
 
 
 def gamma_of(stat):
@@ -130,6 +135,10 @@ def main():
     ap.add_argument("--dense", action="store_true",
                     help="only Section 5.1: dense Gaussian projections vs minimal subsampling")
     ap.add_argument("--dense-p", type=str, default="1000,10000,100000,1000000")
+    ap.add_argument("--profile-search", action="store_true",
+                    help="only the headline data, its exact truth and one xyz search (m = first of --ms, L for "
+                         "95%% recall, default launch shapes), after a warm-up search and a marker fill kernel: "
+                         "the run the HBM byte counters are taken on")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -197,6 +206,22 @@ def main():
 
     ms_list = [int(v) for v in args.ms.split(",") if v]
     xyz_plans = [("xyz", m, xyz.xyz_L_for(0.95, gamma_w ** m)) for m in ms_list]
+    if args.profile_search:
+        # a warm-up search (workspaces grow, the first chunk may be redone), then a fill kernel that
+        # marks where the counted search starts in the profile, then the counted search
+        pl = xyz_plans[0]
+        ctx.search(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1)
+        torch.cuda.synchronize()
+        torch.full((256,), 7, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        r = ctx.search(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1)
+        torch.cuda.synchronize()
+        tm = r["timing"]
+        print(json.dumps({"profile_search": {"m": pl[1], "L": pl[2], "seed": 1, "n": n, "p": p,
+                                             "candidates": tm["candidates"], "big_candidates": tm["big_candidates"],
+                                             "big_launches": tm["big_launches"], "pairs": int(len(r["pairs"]))}}),
+              flush=True)
+        return
     plans = {"auto": [("brute", 0, 1)] + xyz_plans, "brute": [("brute", 0, 1)], "xyz": xyz_plans}[args.plan]
     table = []
     for pl in plans:
@@ -252,14 +277,17 @@ def main():
         hashr = dict(kernel="k_hash", bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS,
                      achieved=hb / (tm["hash_ms"] * 1e-3) / 1e9, bytes_per_search=hb, ms_per_search=tm["hash_ms"])
         hashr["frac"] = hashr["achieved"] / PEAK_HBM_GBS
-        hashr["traffic"] = measured_traffic("k_hash", workload_id)
+        hashr["traffic"] = measured_traffic("k_hash", workload_id, m, L)
         sortr = dict(kernel="k_bucket", bound="hbm", unit="GB/s", peak=PEAK_HBM_GBS,
                      achieved=sb / (tm["bucket_ms"] * 1e-3) / 1e9, bytes_per_search=sb, ms_per_search=tm["bucket_ms"])
         sortr["frac"] = sortr["achieved"] / PEAK_HBM_GBS
-        sortr["traffic"] = measured_traffic("k_bucket", workload_id)
+        sortr["traffic"] = measured_traffic("k_bucket", workload_id, m, L)
     achieved = flops / k_launch / (k_ms / k_launch * 1e-3) / 1e12
+    traffic = None
+    if plan[0] != "brute":
+        traffic = measured_traffic(dom["kernel"], workload_id, plan[1], plan[2], 1.0 / k_launch)
     dom.update(achieved=achieved, frac=achieved / dom["peak"], work_per_launch=flops / k_launch,
-               avg_launch_ms=k_ms / k_launch, launches=k_launch, traffic=measured_traffic(dom["kernel"], workload_id))
+               avg_launch_ms=k_ms / k_launch, launches=k_launch, traffic=traffic)
     stages = {k: round(tm[k], 3) for k in ("pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms",
                                            "big_ms", "dedup_ms", "brute_ms", "total_ms")}
     stages["candidates"] = tm["candidates"]

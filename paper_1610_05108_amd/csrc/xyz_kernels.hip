@@ -411,25 +411,36 @@ __global__ __launch_bounds__(256) void k_cmask(const int32_t *__restrict__ rows,
 
 // ------------------------------------------------------------------- hash --
 
-// key_j = sum_t bit(X_{r_t, j}) << t.  One thread per column; the row words
-// are shared by the 64 lanes of a wave (one broadcast load per row).
+// key_j = sum_t bit(X_{r_t, j}) << t.  Four consecutive columns per thread, so
+// that a workgroup reads whole 128-byte lines of every sampled row (1024
+// columns) and writes its keys as 16-byte stores.
+constexpr int HASH_COLS = 4;
+
 __global__ __launch_bounds__(256) void k_hash(const uint64_t *__restrict__ XR, int64_t P64, int64_t p, int m,
                                               const int32_t *__restrict__ rows, uint32_t *__restrict__ keys)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * HASH_COLS;
     const int r = blockIdx.y;
     __shared__ int32_t rr[32];
     if (threadIdx.x < (unsigned)m) rr[threadIdx.x] = rows[(int64_t)r * m + threadIdx.x];
     __syncthreads();
-    if (j >= p) return;
-    const int64_t w = j >> 6;
-    const unsigned sh = (unsigned)(j & 63);
-    uint32_t key = 0;
+    if (j0 >= p) return;
+    const int64_t w = j0 >> 6;
+    const unsigned sh = (unsigned)(j0 & 63);          // the four columns share one word
+    uint32_t k[HASH_COLS] = {0, 0, 0, 0};
     for (int t = 0; t < m; ++t) {
-        const uint64_t word = XR[(int64_t)rr[t] * P64 + w];
-        key |= (uint32_t)((word >> sh) & 1ull) << t;
+        const uint32_t nib = (uint32_t)(XR[(int64_t)rr[t] * P64 + w] >> sh);
+#pragma unroll
+        for (int i = 0; i < HASH_COLS; ++i) k[i] |= ((nib >> i) & 1u) << t;
     }
-    keys[(int64_t)r * p + j] = key;
+    uint32_t *kr = keys + (int64_t)r * p;
+    if ((p & 3) == 0) {
+        *reinterpret_cast<uint4 *>(kr + j0) = make_uint4(k[0], k[1], k[2], k[3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < HASH_COLS; ++i)
+            if (j0 + i < p) kr[j0 + i] = k[i];
+    }
 }
 
 // Keys under the unbiased transform: thread (column j, repetition r); bit t is
@@ -541,9 +552,12 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
 
 constexpr int BKU = 8;       // keys per thread and round in k_bucket
 
+// k_bucket's scatter in chunks of `ch` keys (a multiple of 1024 BKU, 0: direct scatter):
+// the chunk is counting-sorted by key in LDS first, so that the ids of one bucket leave
+// as one contiguous run instead of one 4-byte write each.
 __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ keys, int64_t p, int m, int nys,
                                                  RepInfo *__restrict__ info, int two_sided, int mfma,
-                                                 uint32_t *__restrict__ offs, uint32_t *__restrict__ perm)
+                                                 uint32_t *__restrict__ offs, uint32_t *__restrict__ perm, int ch)
 {
     extern __shared__ uint32_t cnt[];
     __shared__ unsigned long long shm[17];
@@ -619,7 +633,62 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
     if (threadIdx.x == 0) of[nb] = (uint32_t)p;
     __syncthreads();
     uint32_t *pr = perm + (int64_t)r * p;
-    for (int64_t j0 = threadIdx.x; j0 < p; j0 += 1024 * BKU) {
+    if (ch > 0) {
+        // cnt: next free position of every bucket; lo: the chunk's exclusive prefix of counts (lo[nb]:
+        // the chunk's length); cur: placement cursors; sid / skey: the chunk's ids and keys in key order
+        uint32_t *lo = cnt + nb, *cur = lo + nb + 1, *sid = cur + nb;
+        uint16_t *skey = reinterpret_cast<uint16_t *>(sid + ch);
+        for (int64_t c0 = 0; c0 < p; c0 += ch) {
+            const int len = (int)(p - c0 < ch ? p - c0 : (int64_t)ch);
+            const uint32_t *kc = kr + c0;
+            for (int b = threadIdx.x; b < nb; b += 1024) cur[b] = 0;
+            __syncthreads();
+            for (int i0 = threadIdx.x; i0 < len; i0 += 1024 * BKU) {
+                uint32_t kv[BKU];
+#pragma unroll
+                for (int u = 0; u < BKU; ++u) kv[u] = i0 + u * 1024 < len ? kc[i0 + u * 1024] : ~0u;
+#pragma unroll
+                for (int u = 0; u < BKU; ++u)
+                    if (kv[u] != ~0u) atomicAdd(&cur[kv[u]], 1u);
+            }
+            __syncthreads();
+            unsigned long long lloc = 0;
+            for (int b = b0; b < b1; ++b) lloc += cur[b];
+            unsigned long long ltot;
+            unsigned long long lpre = block_scan_excl<1024>(lloc, shm, &ltot);
+            for (int b = b0; b < b1; ++b) {
+                const uint32_t c1 = cur[b];
+                lo[b] = (uint32_t)lpre;
+                cur[b] = (uint32_t)lpre;
+                lpre += c1;
+            }
+            if (threadIdx.x == 0) lo[nb] = (uint32_t)len;
+            __syncthreads();
+            // the chunk's keys again (from L2), each placed at its bucket's cursor
+            for (int i0 = threadIdx.x; i0 < len; i0 += 1024 * BKU) {
+                uint32_t kv[BKU];
+#pragma unroll
+                for (int u = 0; u < BKU; ++u) kv[u] = i0 + u * 1024 < len ? kc[i0 + u * 1024] : ~0u;
+#pragma unroll
+                for (int u = 0; u < BKU; ++u)
+                    if (kv[u] != ~0u) {
+                        const uint32_t slot = atomicAdd(&cur[kv[u]], 1u);
+                        sid[slot] = (uint32_t)(c0 + i0 + u * 1024);
+                        skey[slot] = (uint16_t)kv[u];
+                    }
+            }
+            __syncthreads();
+            // consecutive slots of a bucket go to consecutive positions of its range
+            for (int s = threadIdx.x; s < len; s += 1024) {
+                const uint32_t b = skey[s];
+                pr[cnt[b] + (uint32_t)s - lo[b]] = sid[s];
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < nb; b += 1024) cnt[b] += lo[b + 1] - lo[b];
+            __syncthreads();
+        }
+    }
+    for (int64_t j0 = threadIdx.x; ch == 0 && j0 < p; j0 += 1024 * BKU) {
         uint32_t kv[BKU];
 #pragma unroll
         for (int u = 0; u < BKU; ++u) kv[u] = j0 + u * 1024 < p ? kr[j0 + u * 1024] : ~0u;
@@ -3226,16 +3295,22 @@ hipError_t launch_hash_unbiased(const float *XF, int64_t nF, int64_t p, int m, i
 hipError_t launch_hash(const uint64_t *XR, int64_t P64, int64_t p, int m, int nrep, const int32_t *rows,
                        uint32_t *keys, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hash, dim3(grid1(p, 256), nrep), dim3(256), 0, st, XR, P64, p, m, rows, keys);
+    hipLaunchKernelGGL(k_hash, dim3(grid1(p, 256 * HASH_COLS), nrep), dim3(256), 0, st, XR, P64, p, m, rows, keys);
     return hipGetLastError();
 }
 
 hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int nys, RepInfo *info, int two_sided,
                          int mfma, uint32_t *offs, uint32_t *perm, hipStream_t st)
 {
-    const size_t lds = (size_t)4 << m;
+    // chunked scatter while the bucket counters, the chunk's offsets and cursors and a chunk of
+    // at least 4096 ids and keys fit in 120 KiB of LDS (m <= 12); direct scatter above
+    const int nb = 1 << m;
+    const size_t base = (size_t)4 * (3 * (size_t)nb + 1), budget = (size_t)120 << 10;
+    int ch = 0;
+    if (base + 6 * 4096 <= budget) ch = (int)std::min<size_t>((budget - base) / 6 / 1024 * 1024, 65536);
+    const size_t lds = ch ? base + 6 * (size_t)ch : (size_t)4 << m;
     hipLaunchKernelGGL(k_bucket, dim3(nrep), dim3(1024), lds, st, keys, p, m, nys, info, two_sided, mfma, offs,
-                       perm);
+                       perm, ch);
     return hipGetLastError();
 }
 
