@@ -551,6 +551,7 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
 }
 
 constexpr int BKU = 8;       // keys per thread and round in k_bucket
+constexpr size_t BUCKET_LDS = (size_t)148 << 10;   // dynamic LDS of k_bucket's chunked scatter (of 160 KiB)
 
 // k_bucket's scatter in chunks of `ch` keys (a multiple of 1024 BKU, 0: direct scatter):
 // the chunk is counting-sorted by key in LDS first, so that the ids of one bucket leave
@@ -635,9 +636,10 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
     uint32_t *pr = perm + (int64_t)r * p;
     if (ch > 0) {
         // cnt: next free position of every bucket; lo: the chunk's exclusive prefix of counts (lo[nb]:
-        // the chunk's length); cur: placement cursors; sid / skey: the chunk's ids and keys in key order
+        // the chunk's length); cur: placement cursors; sid / skey: the chunk's ids and keys in key
+        // order; kin: the chunk's keys as read
         uint32_t *lo = cnt + nb, *cur = lo + nb + 1, *sid = cur + nb;
-        uint16_t *skey = reinterpret_cast<uint16_t *>(sid + ch);
+        uint16_t *skey = reinterpret_cast<uint16_t *>(sid + ch), *kin = skey + ch;
         for (int64_t c0 = 0; c0 < p; c0 += ch) {
             const int len = (int)(p - c0 < ch ? p - c0 : (int64_t)ch);
             const uint32_t *kc = kr + c0;
@@ -649,7 +651,10 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
                 for (int u = 0; u < BKU; ++u) kv[u] = i0 + u * 1024 < len ? kc[i0 + u * 1024] : ~0u;
 #pragma unroll
                 for (int u = 0; u < BKU; ++u)
-                    if (kv[u] != ~0u) atomicAdd(&cur[kv[u]], 1u);
+                    if (kv[u] != ~0u) {
+                        atomicAdd(&cur[kv[u]], 1u);
+                        kin[i0 + u * 1024] = (uint16_t)kv[u];
+                    }
             }
             __syncthreads();
             unsigned long long lloc = 0;
@@ -664,18 +669,12 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
             }
             if (threadIdx.x == 0) lo[nb] = (uint32_t)len;
             __syncthreads();
-            // the chunk's keys again (from L2), each placed at its bucket's cursor
-            for (int i0 = threadIdx.x; i0 < len; i0 += 1024 * BKU) {
-                uint32_t kv[BKU];
-#pragma unroll
-                for (int u = 0; u < BKU; ++u) kv[u] = i0 + u * 1024 < len ? kc[i0 + u * 1024] : ~0u;
-#pragma unroll
-                for (int u = 0; u < BKU; ++u)
-                    if (kv[u] != ~0u) {
-                        const uint32_t slot = atomicAdd(&cur[kv[u]], 1u);
-                        sid[slot] = (uint32_t)(c0 + i0 + u * 1024);
-                        skey[slot] = (uint16_t)kv[u];
-                    }
+            // each key placed at its bucket's cursor
+            for (int i = threadIdx.x; i < len; i += 1024) {
+                const uint32_t key = kin[i];
+                const uint32_t slot = atomicAdd(&cur[key], 1u);
+                sid[slot] = (uint32_t)(c0 + i);
+                skey[slot] = (uint16_t)key;
             }
             __syncthreads();
             // consecutive slots of a bucket go to consecutive positions of its range
@@ -3174,7 +3173,7 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st)
 hipError_t kernels_init()
 {
     hipError_t e = hipFuncSetAttribute((const void *)k_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (1 << MAX_M_LDS) * 4);
+                                       (int)std::max<size_t>((size_t)4 << MAX_M_LDS, BUCKET_LDS));
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_verify_lds<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)BIG_LDS);
@@ -3303,12 +3302,14 @@ hipError_t launch_bucket(const uint32_t *keys, int64_t p, int m, int nrep, int n
                          int mfma, uint32_t *offs, uint32_t *perm, hipStream_t st)
 {
     // chunked scatter while the bucket counters, the chunk's offsets and cursors and a chunk of
-    // at least 4096 ids and keys fit in 120 KiB of LDS (m <= 12); direct scatter above
+    // ids and 16-bit keys fit in BUCKET_LDS with runs of at least two ids per bucket on average
+    // (m <= 12); direct scatter above
     const int nb = 1 << m;
-    const size_t base = (size_t)4 * (3 * (size_t)nb + 1), budget = (size_t)120 << 10;
+    const size_t base = (size_t)4 * (3 * (size_t)nb + 1), budget = BUCKET_LDS;
     int ch = 0;
-    if (base + 6 * 4096 <= budget) ch = (int)std::min<size_t>((budget - base) / 6 / 1024 * 1024, 65536);
-    const size_t lds = ch ? base + 6 * (size_t)ch : (size_t)4 << m;
+    if (base + 8 * 4096 <= budget) ch = (int)std::min<size_t>((budget - base) / 8 / 1024 * 1024, 65536);
+    if (ch < 2 * nb) ch = 0;
+    const size_t lds = ch ? base + 8 * (size_t)ch : (size_t)4 << m;
     hipLaunchKernelGGL(k_bucket, dim3(nrep), dim3(1024), lds, st, keys, p, m, nys, info, two_sided, mfma, offs,
                        perm, ch);
     return hipGetLastError();
