@@ -139,7 +139,12 @@ struct xyz_server {
     // scale factors (measured time / unscaled prediction, exponential average of completed groups)
     std::mutex rmu;
     xyz_ctx *rctx = nullptr;
-    double scale_exact = 1.0, scale_xyz = 1.0;
+    // measured over predicted time per method, by resident X: requests on one X calibrate each
+    // other, and a small data set whose fixed costs dominate does not skew the scale of a large one
+    struct Scales {
+        double exact = 1.0, xyz = 1.0;
+    };
+    std::unordered_map<const xyz_x *, Scales> scales;
 };
 
 namespace {
@@ -227,13 +232,15 @@ void worker_loop(xyz_server *s, int w)
             std::lock_guard<std::mutex> lk(s->mu);
             s->held[w] = ctx->used;
             s->est[w] = 0;
-            // the router's scale factors follow the measured group times (a group of routed xyz
-            // requests shares its repetitions: its prediction is the largest member's)
+            // the router's scale factors of this X follow the measured group times (a group of
+            // routed xyz requests shares its row draws and bucket sort but verifies every member:
+            // its prediction is the sum of the members', an upper bound)
             double base = 0.0;
-            for (Request *r : batch) base = std::max(base, r->base_ms);
+            for (Request *r : batch) base += r->base_ms;
             if (rc == XYZ_OK && base > 0.0 && batch[0]->route.routed) {
-                double &sc = (P0.flags & XYZ_EXACT) ? s->scale_exact : s->scale_xyz;
-                sc = 0.7 * sc + 0.3 * std::min(100.0, std::max(0.01, tg / base));
+                auto &sc = s->scales[batch[0]->x];
+                double &f = (P0.flags & XYZ_EXACT) ? sc.exact : sc.xyz;
+                f = 0.7 * f + 0.3 * std::min(100.0, std::max(0.01, tg / base));
             }
             const double t = now_ms();
             for (size_t q = 0; q < batch.size(); ++q) {
@@ -340,8 +347,9 @@ extern "C" xyz_status xyz_serve_submit(xyz_server *s, const xyz_x *x, const void
         double se, sx;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            se = s->scale_exact;
-            sx = s->scale_xyz;
+            const auto it = s->scales.find(x);
+            se = it == s->scales.end() ? 1.0 : it->second.exact;
+            sx = it == s->scales.end() ? 1.0 : it->second.xyz;
         }
         route.routed = 1;
         rp.rows = nullptr;
