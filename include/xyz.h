@@ -150,6 +150,10 @@ typedef struct {
                              the matrix cores) */
     int64_t big_launches;
     int64_t big_candidates;   /* candidates verified in those products */
+    int64_t chunks;           /* chunks of repetitions the search ran (each stage launches once per chunk) */
+    int64_t host_syncs;       /* host waits on the stream during the search: one per chunk (three for m > 15),
+                                 one after the inputs are checked, two for the merged result, and one more
+                                 per chunk redone when a tile list or the survivor buffer grew */
 } xyz_timing;
 
 /* Library version string (static storage). */

@@ -64,7 +64,8 @@ class xyz_timing(ctypes.Structure):
                 ("total_ms", "pack_ms", "sample_ms", "hash_ms", "bucket_ms", "tiles_ms", "verify_ms",
                  "dedup_ms", "brute_ms")] + [("verify_launches", ctypes.c_int64), ("candidates", ctypes.c_int64),
                                              ("tiles", ctypes.c_int64), ("big_ms", ctypes.c_double),
-                                             ("big_launches", ctypes.c_int64), ("big_candidates", ctypes.c_int64)]
+                                             ("big_launches", ctypes.c_int64), ("big_candidates", ctypes.c_int64),
+                                             ("chunks", ctypes.c_int64), ("host_syncs", ctypes.c_int64)]
 
 
 class xyz_route(ctypes.Structure):

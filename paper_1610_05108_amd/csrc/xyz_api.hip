@@ -186,12 +186,21 @@ xyz_status err_flag_status(int h)
     return XYZ_OK;
 }
 
-xyz_status check_err_flag(int *d_err, hipStream_t st)
+xyz_status check_err_flag(int *d_err, hipStream_t st, xyz_ctx *c = nullptr)
 {
     int h = 0;
     HIP_TRY(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (c) ++c->syncs;
     return err_flag_status(h);
+}
+
+// A host wait on the stream within a search (counted in xyz_timing.host_syncs).
+xyz_status host_wait(xyz_ctx *c, hipStream_t st)
+{
+    ++c->syncs;
+    HIP_TRY(hipStreamSynchronize(st));
+    return XYZ_OK;
 }
 
 double now_ms()
@@ -444,13 +453,13 @@ xyz_status grow_survivors(xyz_ctx *c, unsigned long long cnt, uint64_t done, uns
     Survivor *tmp = nullptr;
     XYZ_TRY(ws(c, WS_SURV2, done, &tmp));
     if (done) HIP_TRY(hipMemcpyAsync(tmp, *surv, done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(host_wait(c, st));
     XYZ_TRY(ws(c, WS_SURV, ncap, surv));
     if (done) HIP_TRY(hipMemcpyAsync(*surv, tmp, done * sizeof(Survivor), hipMemcpyDeviceToDevice, st));
     *cap = ncap;
     const unsigned long long keep = done;
     HIP_TRY(hipMemcpyAsync(scnt, &keep, sizeof keep, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(host_wait(c, st));
     return XYZ_OK;
 }
 
@@ -464,6 +473,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
 {
     if (nys < 1 || nys > 255 || (direct && nys != 1)) return fail(XYZ_EINVAL, "group of %d searches", nys);
     const double t0 = now_ms();
+    c->syncs = 0;
     const xyz_params &P = *Ps[0];
     const int64_t n = x->n, p = x->p;
     const int m = P.m, L = P.L;
@@ -517,7 +527,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
     XYZ_TRY(ws(c, WS_KAPPA, nys, &dkap));
     HIP_TRY(hipMemcpyAsync(dsmin, hsmin, sizeof(int64_t) * nys, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dkap, hkap, sizeof(double) * nys, hipMemcpyHostToDevice, st));
-    XYZ_TRY(check_err_flag(err, st));
+    XYZ_TRY(check_err_flag(err, st, c));
 
     // column popcounts for the big tiles (+-1 data on the matrix cores)
     uint32_t *cpop = nullptr;
@@ -553,6 +563,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
 
     for (int64_t r0 = 0; r0 < L; r0 += chunk) {
         const int R = (int)std::min<int64_t>(chunk, L - r0);
+        timing.chunks += 1;
         const int64_t rep_abs0 = (int64_t)P.rep_offset + r0;
         RepInfo *cinfo = info + (size_t)r0 * nys;
         tm.begin(1);
@@ -614,7 +625,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 HIP_TRY(launch_sk_runs(Ks, S, heads, hist, rkey, rstart, dnr, st));
                 uint32_t nr = 0;
                 HIP_TRY(hipMemcpyAsync(&nr, dnr, sizeof nr, hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipStreamSynchronize(st));
+                XYZ_TRY(host_wait(c, st));
                 uint32_t *table = nullptr;
                 if (m <= SK_TABLE_MAX_M) {
                     XYZ_TRY(ws(c, WS_SKTAB, (size_t)R << m, &table));
@@ -636,7 +647,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
                 HIP_TRY(hipMemcpyAsync(&bnd[1], cnt + 2 * stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&bnd[2], cnt + 3 * stride, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
                 HIP_TRY(hipMemcpyAsync(&bnd[3], cnt + ncnt, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipStreamSynchronize(st));
+                XYZ_TRY(host_wait(c, st));
                 ntiles = bnd[0];
                 nsmall = bnd[1] - bnd[0];
                 nmfma = bnd[2] - bnd[1];
@@ -689,7 +700,7 @@ xyz_status xyz_rt::run_group(xyz_ctx *c, const xyz_x *x, int nys, const void *co
             unsigned long long hc[1 + NLISTS] = {0, ntiles, nsmall, nmfma, nbig};
             HIP_TRY(hipMemcpyAsync(hc, scnt, sizeof(unsigned long long) * (device_counts ? 1 + NLISTS : 1),
                                    hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
+            XYZ_TRY(host_wait(c, st));
             const unsigned long long cnt = hc[0];
             ntiles = hc[1], nsmall = hc[2], nmfma = hc[3], nbig = hc[4];
             const uint64_t need = ntiles + nsmall + nmfma + nbig;
@@ -728,12 +739,12 @@ namespace {
 
 // One search's result into caller-owned host buffers (xyz_search_noalloc): the pairs, if they
 // fit, and the statistics of every repetition, converted through a small stack buffer.
-xyz_status copy_direct(const unsigned long long *nout, const OutPair *dout, const RepInfo *info, int L,
-                       hipStream_t st, const DirectOut &d)
+xyz_status copy_direct(xyz_ctx *c, const unsigned long long *nout, const OutPair *dout, const RepInfo *info,
+                       int L, hipStream_t st, const DirectOut &d)
 {
     unsigned long long U = 0;
     HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(host_wait(c, st));
     *d.npairs = (int64_t)U;
     if ((int64_t)U > d.cap)
         return fail(XYZ_ENOMEM, "the search found %llu pairs; the pair buffer holds %lld", U, (long long)d.cap);
@@ -743,7 +754,7 @@ xyz_status copy_direct(const unsigned long long *nout, const OutPair *dout, cons
     for (int l0 = 0; l0 < L; l0 += 64) {
         const int cnt = std::min(64, L - l0);
         HIP_TRY(hipMemcpyAsync(buf, info + l0, sizeof(RepInfo) * cnt, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        XYZ_TRY(host_wait(c, st));
         for (int i = 0; i < cnt; ++i) {
             xyz_rep_stats &o = d.reps[l0 + i];
             o.candidates = (int64_t)buf[i].candidates;
@@ -754,7 +765,7 @@ xyz_status copy_direct(const unsigned long long *nout, const OutPair *dout, cons
             o.reserved = 0;
         }
     }
-    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(host_wait(c, st));
     return XYZ_OK;
 }
 
@@ -784,17 +795,17 @@ xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_off
     HIP_TRY(launch_dedup(surv, S, p, n, nys, dk, dv, dk2, dv2, hist, heads, dout, nout, ycnt, info,
                          (int64_t)rep_offset, st));
     tm.end();
-    if (direct) return copy_direct(nout, dout, info, L, st, *direct);
+    if (direct) return copy_direct(c, nout, dout, info, L, st, *direct);
     unsigned long long U = 0;
     std::vector<unsigned long long> hy(nys);
     HIP_TRY(hipMemcpyAsync(&U, nout, sizeof U, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(hy.data(), ycnt, sizeof(unsigned long long) * nys, hipMemcpyDeviceToHost, st));
     std::vector<RepInfo> hinfo((size_t)L * nys);
     HIP_TRY(hipMemcpyAsync(hinfo.data(), info, sizeof(RepInfo) * hinfo.size(), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(host_wait(c, st));
     std::vector<xyz_pair> all(U);
     if (U) HIP_TRY(hipMemcpyAsync(all.data(), dout, sizeof(xyz_pair) * U, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    XYZ_TRY(host_wait(c, st));
     tm.collect(timing);
     int64_t cand_total = 0, big_total = 0;
     for (auto &ri : hinfo) {
@@ -804,6 +815,7 @@ xyz_status merge_results(xyz_ctx *c, const xyz_x *x, int nys, int L, int rep_off
     timing.candidates = cand_total;
     timing.big_candidates = big_total;
     timing.total_ms = now_ms() - t0;
+    timing.host_syncs = c->syncs;
 
     size_t off = 0;
     for (int y = 0; y < nys; ++y) {

@@ -69,6 +69,7 @@ struct xyz_ctx {
     std::string arch;
     std::vector<xyz_rt::Tuned> tuned;
     const xyz_rt::Knobs *force_knobs = nullptr;
+    int64_t syncs = 0;   // host waits on the stream since the current search started
 };
 
 struct xyz_x {

@@ -131,6 +131,28 @@ def test_tile_list_growth():
         c.close()
 
 
+def test_one_host_wait_per_chunk():
+    """The LDS bucket path waits on the stream once per chunk of repetitions
+    (survivor count and tile-list sizes in one transfer), plus once after the
+    inputs are checked and twice for the merged result; the sort path (m > 15)
+    three times per chunk.  L = 4500 spans two chunks of at most 4096."""
+    d = synthgen.small_binary(64, 1500, seed=42, planted=[(3, 1400)], flip=0.05)
+    c = xyz.Context(0)
+    try:
+        x = c.x_create(d.XT)
+        for m, per_chunk in ((8, 1), (16, 3)):
+            for it in range(2):          # the first search may grow its workspaces and redo a chunk
+                res = c.search(x, d.Y, m=m, L=4500, kappa=0.5, seed=3)
+            t = res["timing"]
+            _log(f"m={m}: chunks {t['chunks']}, host waits {t['host_syncs']}")
+            assert t["chunks"] == 2
+            assert t["host_syncs"] == per_chunk * t["chunks"] + 3
+        small = c.search(x, d.Y, m=6, L=5, kappa=0.5, seed=3)
+        assert small["timing"]["chunks"] == 1 and small["timing"]["host_syncs"] <= 5
+    finally:
+        c.close()
+
+
 def test_split_repetitions_match_full_run(ctx):
     d = synthgen.small_binary(300, 1200, seed=16, planted=[(1, 2)], flip=0.1)
     x = ctx.x_create(d.XT)
