@@ -503,6 +503,31 @@ XYZ_DEV bool mfma_single(uint32_t a, uint32_t a2, int mfma)
     return mfma == 1 && ((a <= (uint32_t)MTILE && a2 <= MTILE_WIDE) || (a <= MTILE_WIDE && a2 <= (uint32_t)MTILE));
 }
 
+// Thin strips of a big product of two buckets: a side past BIG_TILE columns whose remainder
+// after its full blocks is shorter than THIN_MAX leaves that remainder to matrix-core tiles
+// (MTILE wide) instead of block pairs of its own, which would keep most of a workgroup idle.
+constexpr uint32_t THIN_MAX = 64;
+
+XYZ_DEV uint32_t thin_cols(uint32_t s)
+{
+    const uint32_t r = s % (uint32_t)BIG_TILE;
+    return (s > (uint32_t)BIG_TILE && r < THIN_MAX) ? r : 0u;
+}
+
+// Matrix-core tiles of the thin strips of a big product (a x a2): A's remainder against all of
+// B, then B's remainder against A's blocks.
+XYZ_DEV unsigned long long thin_tiles(uint32_t a, uint32_t a2)
+{
+    const uint32_t ra = thin_cols(a), rb = thin_cols(a2);
+    return (ra ? cdiv_u64(a2, MTILE) : 0) + (rb ? cdiv_u64(a - ra, MTILE) : 0);
+}
+
+// Candidate pairs of a big product that its block pairs hold.
+XYZ_DEV unsigned long long big_block_pairs(uint32_t a, uint32_t a2)
+{
+    return (unsigned long long)(a - thin_cols(a)) * (a2 - thin_cols(a2));
+}
+
 XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, uint32_t a2, int mfma, int &kind,
                                          unsigned long long &T)
 {
@@ -513,8 +538,8 @@ XYZ_DEV unsigned long long product_tiles(uint32_t b, uint32_t b2, uint32_t a, ui
         if (c == 0) return 0;
         const uint32_t mmin = mfma == 2 ? MTILE_MIN_REAL : MTILE_MIN;
         if (mfma == 1 && min(a, a2) >= BIG_MIN_SHORT && !mfma_single(a, a2, mfma)) {
-            kind = 4;
-            T = cdiv_u64(a, BIG_TILE) * cdiv_u64(a2, BIG_TILE);
+            kind = 4;      // block pairs here; the thin strips' tiles (thin_tiles) join the matrix-core list
+            T = cdiv_u64(a - thin_cols(a), BIG_TILE) * cdiv_u64(a2 - thin_cols(a2), BIG_TILE);
         } else if (mfma && a >= mmin && a2 >= mmin) {
             kind = 3;
             T = mfma_single(a, a2, mfma) ? 1 : cdiv_u64(a, MTILE) * cdiv_u64(a2, MTILE);
@@ -595,7 +620,14 @@ __global__ __launch_bounds__(1024) void k_bucket(const uint32_t *__restrict__ ke
                 const unsigned long long c = product_tiles((uint32_t)b, b2, a, cnt[b2], mfma, kind, T);
                 cand += c;
                 cnts[kind] += T;
-                if (kind == 4) bigc += c;
+                if (kind == 4) {
+                    if (b2 != (uint32_t)b) {
+                        cnts[3] += thin_tiles(a, cnt[b2]);
+                        bigc += big_block_pairs(a, cnt[b2]);
+                    } else {
+                        bigc += c;
+                    }
+                }
             }
         }
         cand = block_sum<1024>(cand, shm);
@@ -797,8 +829,9 @@ XYZ_DEV Tile product_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, ui
             tri_index(t, (a + BIG_TILE - 1) / BIG_TILE, ia, ib);
             return big_tile(r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
         }
-        const uint32_t nB = (a2 + BIG_TILE - 1) / BIG_TILE;
-        return big_tile(r, ysel, pbase, o1, a, o2, a2, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
+        const uint32_t ea = a - thin_cols(a), eb = a2 - thin_cols(a2);   // sides without thin strips
+        const uint32_t nB = (eb + BIG_TILE - 1) / BIG_TILE;
+        return big_tile(r, ysel, pbase, o1, ea, o2, eb, (uint32_t)(t / nB), (uint32_t)(t % nB), 0);
     }
     if (!own) {
         if (ts == (uint32_t)MTILE && mfma_single(a, a2, mfma)) return single_tile(r, ysel, pbase, o1, a, o2, a2);
@@ -809,6 +842,32 @@ XYZ_DEV Tile product_tile(uint32_t ts, uint64_t t, uint32_t r, uint32_t ysel, ui
     uint32_t ia, ib;
     tri_index(t, T, ia, ib);
     return make_tile(ts, r, ysel, pbase, o1, a, o1, a, ia, ib, (uint8_t)(ia == ib));
+}
+
+// Thin-strip tile number t of the big product of (o1, a) and (o2, a2) (see thin_tiles).
+XYZ_DEV Tile thin_tile(uint64_t t, uint32_t r, uint32_t ysel, uint32_t pbase, uint32_t o1, uint32_t a, uint32_t o2,
+                       uint32_t a2)
+{
+    const uint32_t ra = thin_cols(a), rb = thin_cols(a2);
+    const uint64_t ta = ra ? cdiv_u64(a2, MTILE) : 0;
+    Tile tl;
+    tl.rep = r;
+    tl.diag = 0;
+    tl.ysel = (uint8_t)ysel;
+    if (t < ta) {
+        const uint32_t j = (uint32_t)t * MTILE;
+        tl.a0 = pbase + o1 + (a - ra);
+        tl.na = (uint8_t)ra;
+        tl.b0 = pbase + o2 + j;
+        tl.nb = (uint8_t)min((uint32_t)MTILE, a2 - j);
+    } else {
+        const uint32_t i = (uint32_t)(t - ta) * MTILE;
+        tl.a0 = pbase + o1 + i;
+        tl.na = (uint8_t)min((uint32_t)MTILE, a - ra - i);
+        tl.b0 = pbase + o2 + (a2 - rb);
+        tl.nb = (uint8_t)rb;
+    }
+    return tl;
 }
 
 // Tile number t of the product of bucket b and its partner b2 (offsets of).
@@ -863,8 +922,10 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
             const uint32_t b2 = (uint32_t)b ^ (side ? cn : c);
             unsigned long long T;
             int kind;
-            product_tiles(b, b2, a, of[b2 + 1] - of[b2], mfma, kind, T);
+            const uint32_t a2 = of[b2 + 1] - of[b2];
+            product_tiles(b, b2, a, a2, mfma, kind, T);
             loc[kind] += T;
+            if (kind == 4 && b2 != (uint32_t)b) loc[3] += thin_tiles(a, a2);
         }
     }
     unsigned long long tot, pos[5];
@@ -896,6 +957,13 @@ __global__ __launch_bounds__(256) void k_tiles(const uint32_t *__restrict__ offs
                 for (unsigned long long t = 0; t < T && pos[kind] + t < cap; ++t)
                     tiles[pos[kind] + t] = pair_tile(ts, t, r, y, pbase, b, b2, of, mfma);
             pos[kind] += T;
+            if (kind == 4 && b2 != (uint32_t)b) {
+                const uint32_t a = of[b + 1] - of[b], a2 = of[b2 + 1] - of[b2];
+                const unsigned long long Tt = thin_tiles(a, a2);
+                for (unsigned long long t = 0; t < Tt && pos[3] + t < cap; ++t)
+                    tiles[pos[3] + t] = thin_tile(t, r, y, pbase, of[b], a, of[b2], a2);
+                pos[3] += Tt;
+            }
         }
     }
     __syncthreads();
@@ -1042,10 +1110,18 @@ __global__ __launch_bounds__(256) void k_sk_products(const uint64_t *__restrict_
         }
         const uint32_t c = (uint32_t)info[k].cmask & (uint32_t)((1ull << m) - 1);
         unsigned long long tl[5] = {0, 0, 0, 0, 0}, bp = 0;
+        const uint32_t a = run_len(run_start, nr, S, rid);
         v[0] += run_products(run_key, run_start, nr, S, m, rid, c, two_sided, mfma, table,
-                             [&](uint32_t, uint32_t, int kind, unsigned long long T, unsigned long long pc) {
+                             [&](uint32_t rid2, uint32_t a2, int kind, unsigned long long T, unsigned long long pc) {
                                  tl[kind] += T;
-                                 if (kind == 4) bp += pc;
+                                 if (kind == 4) {
+                                     if (rid2 != rid) {
+                                         tl[3] += thin_tiles(a, a2);
+                                         bp += big_block_pairs(a, a2);
+                                     } else {
+                                         bp += pc;
+                                     }
+                                 }
                              });
         cnt[0 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[2];
         cnt[1 * cnt_stride + (uint64_t)y * nr + rid] = (uint32_t)tl[1];
@@ -1106,6 +1182,12 @@ __global__ __launch_bounds__(256) void k_sk_tiles(const uint64_t *__restrict__ r
                          tiles[at[kind] + t] = product_tile(ts, t, (uint32_t)r, y, pbase, own, o1, a, own ? o1 : o2,
                                                             own ? a : a2, mfma);
                      at[kind] += T;
+                     if (kind == 4 && !own) {
+                         const unsigned long long Tt = thin_tiles(a, a2);
+                         for (unsigned long long t = 0; t < Tt; ++t)
+                             tiles[at[3] + t] = thin_tile(t, (uint32_t)r, y, pbase, o1, a, o2, a2);
+                         at[3] += Tt;
+                     }
                  });
 }
 

@@ -488,6 +488,8 @@ BIG_CASES = [
     (333, 900, 0, 1, 0.1, False, 35),        # m = 0: one bucket, its own pairs as triangular block pairs
     (64, 600, 1, 6, 0.2, True, 36),          # one chunk of one quad
     (4097, 1300, 2, 2, 0.05, False, 37),     # a partial last chunk (33 quads)
+    (700, 8400, 5, 2, 0.12, False, 38),      # buckets of ~262: thin remainders go to matrix-core strips
+    (300, 2200, 3, 3, 0.1, True, 39),        # buckets of ~275, two-sided: strips on both sides
 ]
 
 
