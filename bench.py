@@ -66,7 +66,8 @@ def measured_traffic(kernel, workload, m, L, share=1.0):
     from the committed counter profile of that search (FETCH_SIZE and
     WRITE_SIZE summed over the kernel's dispatches, scaled by what the counters
     read for a plain device copy); None when the kernel source changed since
-    the counters were taken, the profile is of another plan, or there is none."""
+    the counters were taken, no profiled search has this plan, or there is no
+    profile."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")) as f:
@@ -75,9 +76,11 @@ def measured_traffic(kernel, workload, m, L, share=1.0):
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
     except OSError:
         return None
-    k = t.get("kernels", {}).get(kernel)
-    srch = t.get("search", {})
-    if sha != t.get("kernels_source_sha256_16") or not k or srch.get("m") != m or srch.get("L") != L:
+    srch = [q for q in t.get("searches", []) if q.get("m") == m and q.get("L") == L]
+    if sha != t.get("kernels_source_sha256_16") or not srch:
+        return None
+    k = srch[0].get("kernels", {}).get(kernel)
+    if not k:
         return None
     if k.get("fetch_kib") is None or k.get("write_kib") is None:
         return None
@@ -136,8 +139,8 @@ def main():
                     help="only Section 5.1: dense Gaussian projections vs minimal subsampling")
     ap.add_argument("--dense-p", type=str, default="1000,10000,100000,1000000")
     ap.add_argument("--profile-search", action="store_true",
-                    help="only the headline data, its exact truth and one xyz search (m = first of --ms, L for "
-                         "95%% recall, default launch shapes), after a warm-up search and a marker fill kernel: "
+                    help="only the headline data, its exact truth and, per m of --ms, one xyz search (L for 95%% "
+                         "recall, default launch shapes) between two marker fill kernels, after a warm-up search: "
                          "the run the HBM byte counters are taken on")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
@@ -207,20 +210,24 @@ def main():
     ms_list = [int(v) for v in args.ms.split(",") if v]
     xyz_plans = [("xyz", m, xyz.xyz_L_for(0.95, gamma_w ** m)) for m in ms_list]
     if args.profile_search:
-        # a warm-up search (workspaces grow, the first chunk may be redone), then a fill kernel that
-        # marks where the counted search starts in the profile, then the counted search
-        pl = xyz_plans[0]
-        ctx.search(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1)
-        torch.cuda.synchronize()
-        torch.full((256,), 7, dtype=torch.int32, device="cuda")
-        torch.cuda.synchronize()
-        r = ctx.search(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1)
-        torch.cuda.synchronize()
-        tm = r["timing"]
-        print(json.dumps({"profile_search": {"m": pl[1], "L": pl[2], "seed": 1, "n": n, "p": p,
-                                             "candidates": tm["candidates"], "big_candidates": tm["big_candidates"],
-                                             "big_launches": tm["big_launches"], "pairs": int(len(r["pairs"]))}}),
-              flush=True)
+        # per plan: a warm-up search (workspaces grow, the first chunk may be redone), a fill kernel
+        # that marks where the counted search starts in the profile, the counted search, and a
+        # fill kernel that marks its end
+        def marker():
+            torch.cuda.synchronize()
+            torch.full((256,), 7, dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+        for pl in xyz_plans:
+            ctx.search(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1)
+            marker()
+            r = ctx.search(x, Y, m=pl[1], L=pl[2], kappa=kappa, seed=1)
+            marker()
+            tm = r["timing"]
+            print(json.dumps({"profile_search": {"m": pl[1], "L": pl[2], "seed": 1, "n": n, "p": p,
+                                                 "candidates": tm["candidates"],
+                                                 "big_candidates": tm["big_candidates"],
+                                                 "big_launches": tm["big_launches"], "pairs": int(len(r["pairs"]))}}),
+                  flush=True)
         return
     plans = {"auto": [("brute", 0, 1)] + xyz_plans, "brute": [("brute", 0, 1)], "xyz": xyz_plans}[args.plan]
     table = []
