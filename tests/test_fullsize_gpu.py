@@ -140,6 +140,38 @@ def test_large_binary_full_search(ctx, rademacher_large):
             assert s / d.n > kappa
 
 
+def test_large_binary_headline_plan(ctx, rademacher_large):
+    """The plan the benchmark times on this workload (m = 12, where nearly all candidates lie in
+    block pairs of two buckets of about 244 columns), 24 repetitions: every repetition's
+    candidate count exact, every reported value exact, and a planted pair is reported exactly
+    when it collides in some repetition (its keys differ by the repetition's Y key) and its
+    statistic passes kappa; no other pair of the data comes near kappa."""
+    d, x = rademacher_large
+    m, L, kappa, seed = 12, 24, 0.12, 1
+    r = ctx.search(x, d.Y, m=m, L=L, kappa=kappa, seed=seed)
+    assert r["timing"]["big_launches"] >= 1 and r["timing"]["big_candidates"] > 0
+    planted = [tuple(sorted(pq)) for pq in d.planted]
+    collides = {pq: False for pq in planted}
+    for l in range(L):
+        rows = oracle.draw_rows(d.n, seed, l, m)
+        neg = ((d.bits[:, rows >> 6] >> (rows & 63).astype(np.uint64)) & np.uint64(1)).astype(bool)
+        cbits = d.Y[rows] < 0
+        assert int(r["reps"]["candidates"][l]) == _candidates(neg, cbits, m), l
+        key = (neg.astype(np.int64) << np.arange(m, dtype=np.int64)).sum(axis=1)
+        c = int((cbits.astype(np.int64) << np.arange(m, dtype=np.int64)).sum())
+        for (j, k) in planted:
+            collides[(j, k)] |= int(key[j] ^ key[k]) == c
+    found = _pairs_set(r)
+    for (j, k), s in zip(zip(r["pairs"]["j"].tolist(), r["pairs"]["k"].tolist()), r["pairs"]["s"].tolist()):
+        assert s == oracle.pair_value(_unpack_cols(d, (j, k)), d.Y, 0, 1)
+    want = set()
+    for (j, k) in planted:
+        s = oracle.pair_value(_unpack_cols(d, (j, k)), d.Y, 0, 1)
+        if collides[(j, k)] and s / d.n > kappa:
+            want.add((j, k))
+    assert found == want
+
+
 def test_large_binary_exact_blocks(ctx, rademacher_large):
     """The exact search on 20 random 50k x 50k column blocks: the pairs it reports are
     exactly the planted pairs inside the block (a random pair at s/n > 0.12 with
