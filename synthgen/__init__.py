@@ -450,6 +450,21 @@ def small_binary(n: int, p: int, seed: int, planted=(), flip: float = 0.0, y_bia
     return Dataset(n, p, XT, Y, [tuple(sorted(pq)) for pq in planted], {})
 
 
+def long_binary(n: int, p: int, seed: int, pair=(0, 1), share: float = 0.3) -> Dataset:
+    """Rademacher problem with long columns (vectorised, for n in the millions).
+
+    Y_i = X_ia X_ib for the planted pair (a, b) on a random ``share`` of the
+    rows, uniform on {+1, -1} elsewhere.
+    """
+    XT = rademacher(n, p, seed)
+    r = _rng(seed, 23)
+    Y = np.where(r.random(n) < 0.5, 1, -1).astype(np.int8)
+    on = r.random(n) < share
+    a, b = pair
+    Y[on] = XT[a, on] * XT[b, on]
+    return Dataset(n, p, XT, Y, [tuple(sorted(pair))], {})
+
+
 def small_continuous(n: int, p: int, seed: int, planted=(), noise: float = 1.0) -> Dataset:
     """Small Gaussian problem: Y = sum of planted X_a X_b + noise * N(0,1)."""
     XT = gaussian(n, p, seed)

@@ -36,6 +36,30 @@ def test_tiny_shapes(ctx, n, p, m, L, kappa):
     assert_same_binary(res, rp, rr)
 
 
+@pytest.mark.parametrize("n", [(1 << 24) - 1, (1 << 24) + 1])
+def test_rows_at_the_fp32_limit(ctx, n):
+    """Columns of 2^24 - 1 rows (the longest whose counts the FP32 matrix-core accumulators hold
+    exactly) and of 2^24 + 1 rows (past it the search counts on the vector units): with m = 2 on
+    24 columns the whole search equals the oracle's; with m = 0 every pair of 80 columns is a
+    candidate (one bucket, block-pair tiles below the limit) and is reported with its exact
+    value (kappa below every statistic)."""
+    d = synthgen.long_binary(n, 80, seed=5, pair=(3, 17), share=0.3)
+    res, rp, rr = run_both(ctx, np.ascontiguousarray(d.XT[:24]), d.Y, 2, 2, -2.0, seed=1)
+    assert_same_binary(res, rp, rr)
+    x = ctx.x_create(d.XT)
+    r = ctx.search(x, d.Y, m=0, L=1, kappa=-2.0, seed=1)
+    assert len(r["pairs"]) == 80 * 79 // 2
+    assert int(r["reps"]["candidates"][0]) == 80 * 79 // 2
+    assert (r["timing"]["big_launches"] >= 1) == (n < (1 << 24))
+    pos = {(int(j), int(k)): q for q, (j, k) in enumerate(zip(r["pairs"]["j"], r["pairs"]["k"]))}
+    rng = np.random.default_rng(0)
+    check = [(3, 17)] + [tuple(sorted(rng.choice(80, size=2, replace=False).tolist())) for _ in range(30)]
+    for j, k in check:
+        assert int(r["pairs"]["s"][pos[(j, k)]]) == oracle.pair_value(d.XT, d.Y, j, k), (j, k)
+    s_planted = int(r["pairs"]["s"][pos[(3, 17)]])
+    assert s_planted > 0.25 * n                    # the planted pair stands out (share 0.3)
+
+
 def test_one_giant_bucket(ctx):
     """Every column equal: every key is the same, one bucket holds all p columns
     (products split into many tiles, all three tile lists possible)."""
