@@ -42,7 +42,9 @@ def test_rows_at_the_fp32_limit(ctx, n):
     exactly) and of 2^24 + 1 rows (past it the search counts on the vector units): with m = 2 on
     24 columns the whole search equals the oracle's; with m = 0 every pair of 80 columns is a
     candidate (one bucket, block-pair tiles below the limit) and is reported with its exact
-    value (kappa below every statistic)."""
+    value (kappa below every statistic), and a threshold placed at the planted pair's own value
+    keeps it (smin = s) or drops it (smin = s + 1): the FP32 filter in front of the exact integer
+    test rounds monotonically, so it never drops a pair the integer test keeps."""
     d = synthgen.long_binary(n, 80, seed=5, pair=(3, 17), share=0.3)
     res, rp, rr = run_both(ctx, np.ascontiguousarray(d.XT[:24]), d.Y, 2, 2, -2.0, seed=1)
     assert_same_binary(res, rp, rr)
@@ -58,6 +60,12 @@ def test_rows_at_the_fp32_limit(ctx, n):
         assert int(r["pairs"]["s"][pos[(j, k)]]) == oracle.pair_value(d.XT, d.Y, j, k), (j, k)
     s_planted = int(r["pairs"]["s"][pos[(3, 17)]])
     assert s_planted > 0.25 * n                    # the planted pair stands out (share 0.3)
+    # the threshold at the planted pair's value: kept at smin = s, dropped at smin = s + 1 (every
+    # other pair lies near 0)
+    lo = ctx.search(x, d.Y, m=0, L=1, kappa=(s_planted - 0.5) / n, seed=1)
+    hi = ctx.search(x, d.Y, m=0, L=1, kappa=(s_planted + 0.5) / n, seed=1)
+    assert [(int(j), int(k)) for j, k in zip(lo["pairs"]["j"], lo["pairs"]["k"])] == [(3, 17)]
+    assert len(hi["pairs"]) == 0
 
 
 def test_one_giant_bucket(ctx):
